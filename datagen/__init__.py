@@ -1,0 +1,207 @@
+"""Seeded synthetic edge-list generators.
+
+This module only draws inputs. It holds none of the join-project arithmetic, so
+the CPU oracle and the GPU path can both be fed from it without sharing any of
+the method's code. Every generator is deterministic in its seed (numpy PCG64).
+
+Relations are binary and returned as two int32 numpy arrays ``(a, y)``: the
+first column is the free variable (x, z or x_i), the second the join variable y
+(the paper's problem statement, Section 2.1).
+
+Workload shapes (the paper's datasets are not available, so these stand in):
+
+* ``uniform_edges``: i.i.d. uniform (x, y) on a square, first n distinct kept.
+* ``zipf_edges``: x uniform over ``n_x`` ids; the y *rank* follows a truncated
+  Zipf(s) rank-frequency law over ``n_y`` ids, mapped to ids through a seeded
+  permutation of its own (two relations drawn with different seeds therefore
+  have independent y-degree orders); first n distinct (x, y) in draw order.
+* ``communities``: c disjoint communities of m x-ids times g y-ids with edge
+  probability p (the community structure of the paper's Example 1).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "uniform_edges",
+    "zipf_edges",
+    "communities",
+    "random_small",
+    "selfjoin_c1",
+    "twopath_c2",
+    "star_c3",
+    "batch_c4",
+    "selector_instance",
+]
+
+
+def _first_distinct(draw, n: int, n_y: int, rng, max_rounds: int = 64):
+    """Draw (x, y) batches with ``draw(rng, m)`` until ``n`` distinct pairs exist.
+
+    Keeps the first ``n`` distinct pairs in draw order.
+    """
+    xs = np.empty(0, dtype=np.int64)
+    ys = np.empty(0, dtype=np.int64)
+    for _ in range(max_rounds):
+        have = 0
+        if xs.size:
+            key = xs * n_y + ys
+            _, first = np.unique(key, return_index=True)
+            have = first.size
+            if have >= n:
+                first.sort()
+                first = first[:n]
+                return xs[first].astype(np.int32), ys[first].astype(np.int32)
+        m = max(1024, int((n - have) * 1.15) + 16)
+        bx, by = draw(rng, m)
+        xs = np.concatenate([xs, bx.astype(np.int64)])
+        ys = np.concatenate([ys, by.astype(np.int64)])
+    raise RuntimeError("could not draw enough distinct pairs; domain too small")
+
+
+def uniform_edges(n: int, n_x: int, n_y: int, seed: int):
+    """First ``n`` distinct (x, y) of i.i.d. uniform draws on [0,n_x) x [0,n_y)."""
+    if n > n_x * n_y:
+        raise ValueError("n exceeds the number of possible pairs")
+    rng = np.random.default_rng(seed)
+
+    def draw(r, m):
+        return r.integers(0, n_x, m), r.integers(0, n_y, m)
+
+    return _first_distinct(draw, n, n_y, rng)
+
+
+def zipf_table(n_y: int, s: float) -> np.ndarray:
+    """CDF of the truncated rank-frequency Zipf law P(rank=k) ~ k^-s, k=1..n_y."""
+    w = np.arange(1, n_y + 1, dtype=np.float64) ** (-s)
+    cdf = np.cumsum(w)
+    cdf /= cdf[-1]
+    return cdf
+
+
+def zipf_edges(n: int, n_x: int, n_y: int, s: float, seed: int):
+    """x uniform in [0,n_x), y = perm(Zipf(s) rank over n_y), first n distinct."""
+    rng = np.random.default_rng(seed)
+    cdf = zipf_table(n_y, s)
+    perm = rng.permutation(n_y)
+
+    def draw(r, m):
+        x = r.integers(0, n_x, m)
+        rank = np.searchsorted(cdf, r.random(m), side="right")
+        rank = np.minimum(rank, n_y - 1)
+        return x, perm[rank]
+
+    return _first_distinct(draw, n, n_y, rng)
+
+
+def communities(c: int, m: int, g: int, p: float, seed: int):
+    """c disjoint communities: x-block i (m ids) joined to y-block i (g ids).
+
+    Each of the m*g possible edges of a community is present with probability
+    p; every x and every y of a community is guaranteed at least one edge.
+    """
+    rng = np.random.default_rng(seed)
+    xs, ys = [], []
+    for i in range(c):
+        mask = rng.random((m, g)) < p
+        # guarantee no isolated vertex inside a community
+        mask[np.arange(m), rng.integers(0, g, m)] = True
+        mask[rng.integers(0, m, g), np.arange(g)] = True
+        a, b = np.nonzero(mask)
+        xs.append(a + i * m)
+        ys.append(b + i * g)
+    return (np.concatenate(xs).astype(np.int32), np.concatenate(ys).astype(np.int32))
+
+
+def random_small(n: int, n_x: int, n_y: int, seed: int, dup: bool = False, signed: bool = False):
+    """Tiny random relation for brute-force checks.
+
+    With ``dup`` some rows are repeated (bag input); with ``signed`` the ids are
+    spread over the whole int32 range including negatives and the extremes.
+    """
+    rng = np.random.default_rng(seed)
+    x = rng.integers(0, n_x, n)
+    y = rng.integers(0, n_y, n)
+    if signed:
+        xmap = rng.choice(np.arange(-(2**31), 2**31, 2**21, dtype=np.int64), n_x, replace=False)
+        ymap = rng.choice(np.arange(-(2**31), 2**31, 2**21, dtype=np.int64), n_y, replace=False)
+        xmap[0] = -(2**31)
+        ymap[-1] = 2**31 - 1
+        x, y = xmap[x], ymap[y]
+    if dup and n > 0:
+        k = max(1, n // 4)
+        idx = rng.integers(0, n, k)
+        x = np.concatenate([x, x[idx]])
+        y = np.concatenate([y, y[idx]])
+        p = rng.permutation(x.size)
+        x, y = x[p], y[p]
+    return x.astype(np.int32), y.astype(np.int32)
+
+
+# ----------------------------------------------------------------------------
+# Named workloads
+# ----------------------------------------------------------------------------
+
+def selfjoin_c1(seed: int = 1):
+    """Self-join input: 2,000 distinct (x, y), both uniform in [0, 500)."""
+    return uniform_edges(2000, 500, 500, seed)
+
+
+def twopath_c2(scale: float = 1.0):
+    """Two-path input pair: |R|=|S|=10M, 1M x/z ids, 200K y ids, Zipf(1.1) y.
+
+    ``scale`` shrinks every size proportionally (for tests on the CPU).
+    Seeds 2 (R) and 3 (S).
+    """
+    n = int(10_000_000 * scale)
+    nx = max(1, int(1_000_000 * scale))
+    ny = max(1, int(200_000 * scale))
+    r = zipf_edges(n, nx, ny, 1.1, seed=2)
+    s = zipf_edges(n, nx, ny, 1.1, seed=3)
+    return r, s
+
+
+def star_c3(scale: float = 1.0):
+    """Star input: three relations of 2M edges, 500K x ids, 100K y ids, Zipf(1.3)."""
+    n = int(2_000_000 * scale)
+    nx = max(1, int(500_000 * scale))
+    ny = max(1, int(100_000 * scale))
+    return [zipf_edges(n, nx, ny, 1.3, seed=4 + i) for i in range(3)]
+
+
+def batch_c4(n_inst: int = 512, lo: float = 1e3, hi: float = 1e6, seed0: int = 1000):
+    """Batched set: instance i has E_i ~ log-uniform[lo,hi] edges per relation.
+
+    The Zipf exponent is U[0.6,1.6]; |dom x| = |dom z| = ceil(E/10) and
+    |dom y| = ceil(E/50) (the same ratios as the single two-path input).
+    Returns a list of ((rx, ry), (sz, sy)) tuples.
+    """
+    out = []
+    for i in range(n_inst):
+        rng = np.random.default_rng(seed0 + i)
+        e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+        s = float(rng.uniform(0.6, 1.6))
+        nx = max(2, -(-e // 10))
+        ny = max(2, -(-e // 50))
+        e = min(e, nx * ny // 2)
+        sub = int(rng.integers(0, 2**31 - 1))
+        r = zipf_edges(e, nx, ny, s, seed=sub)
+        t = zipf_edges(e, nx, ny, s, seed=sub + 1)
+        out.append((r, t))
+    return out
+
+
+def selector_instance(i: int, lo: float = 1e5, hi: float = 2e7, seed0: int = 10_000,
+                      scale: float = 1.0):
+    """Instance i of the threshold-selector set: |R|=|S| log-uniform in [lo,hi].
+
+    Zipf exponent U[0.5,1.8]; domains in the same ratios as the batched set.
+    """
+    rng = np.random.default_rng(seed0 + i)
+    e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi)))) * scale))
+    s = float(rng.uniform(0.5, 1.8))
+    nx = max(2, -(-e // 10))
+    ny = max(2, -(-e // 50))
+    e = min(e, nx * ny // 2)
+    sub = int(rng.integers(0, 2**31 - 1))
+    return zipf_edges(e, nx, ny, s, seed=sub), zipf_edges(e, nx, ny, s, seed=sub + 1), s

@@ -1,0 +1,327 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle (plain C, full join then sort-distinct) is checked against things
+other than itself: brute force over all candidate pairs by set intersection,
+the paper's worked examples, closed forms, and invariants the paper states.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import reference as ref
+from tests.conftest import load_golden
+
+
+# ---------------------------------------------------------------------------
+# Brute force: for every candidate pair, test whether the neighbour sets meet.
+# This is a different algorithm from the oracle's full join + sort.
+# ---------------------------------------------------------------------------
+
+def brute_two_path(rx, ry, sz, sy):
+    nx, nz = {}, {}
+    for a, b in zip(np.asarray(rx).tolist(), np.asarray(ry).tolist()):
+        nx.setdefault(a, set()).add(b)
+    for c, b in zip(np.asarray(sz).tolist(), np.asarray(sy).tolist()):
+        nz.setdefault(c, set()).add(b)
+    out = sorted((a, c) for a in nx for c in nz if nx[a] & nz[c])
+    return out
+
+
+def brute_star(rels):
+    nbr = []
+    for a, b in rels:
+        m = {}
+        for p, q in zip(np.asarray(a).tolist(), np.asarray(b).tolist()):
+            m.setdefault(p, set()).add(q)
+        nbr.append(m)
+    out = []
+    for t in itertools.product(*[sorted(m) for m in nbr]):
+        common = set.intersection(*[nbr[i][t[i]] for i in range(len(t))])
+        if common:
+            out.append(t)
+    return sorted(out)
+
+
+def as_pairs(x, z):
+    return list(zip(x.tolist(), z.tolist()))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_two_path_matches_brute_force(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(0, 60))
+    nx, ny = int(rng.integers(1, 12)), int(rng.integers(1, 12))
+    rx, ry = datagen.random_small(n, nx, ny, seed, dup=bool(seed % 2), signed=bool(seed % 3 == 0))
+    sz, sy = datagen.random_small(int(rng.integers(0, 60)), nx, ny, seed + 1000,
+                                  dup=bool(seed % 2), signed=bool(seed % 3 == 0))
+    if seed % 3 == 0:
+        # share the y ids with R so the signed case still joins
+        sy = ry[rng.integers(0, max(ry.size, 1), sy.size)] if ry.size else sy
+    x, z = oracle.two_path(rx, ry, sz, sy)
+    assert as_pairs(x, z) == brute_two_path(rx, ry, sz, sy)
+    # sorted, distinct
+    key = x.astype(np.int64) * (2**32) + z.astype(np.int64)
+    assert np.all(np.diff(key) > 0)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_star_matches_brute_force(seed):
+    rng = np.random.default_rng(200 + seed)
+    k = 2 + seed % 3
+    rels = [datagen.random_small(int(rng.integers(0, 25)), 6, 5, seed * 10 + i, dup=True) for i in range(k)]
+    t = oracle.star(rels)
+    assert [tuple(r) for r in t.tolist()] == brute_star(rels)
+
+
+def test_two_path_empty_and_disjoint():
+    e = np.zeros(0, np.int32)
+    x, z = oracle.two_path(e, e, e, e)
+    assert x.size == 0 and z.size == 0
+    x, z = oracle.two_path([1, 2], [5, 6], [3], [7])  # no common y
+    assert x.size == 0
+    assert oracle.join_size([1, 2], [5, 6], [3], [7]) == 0
+
+
+def test_extreme_ids():
+    lo, hi = -(2**31), 2**31 - 1
+    rx = np.array([lo, hi, 0, lo], np.int32)
+    ry = np.array([hi, lo, hi, lo], np.int32)
+    x, z = oracle.two_path(rx, ry, rx, ry)
+    assert as_pairs(x, z) == brute_two_path(rx, ry, rx, ry)
+    assert x[0] == lo  # signed order
+
+
+# ---------------------------------------------------------------------------
+# The worked examples (Section 3.1 and 3.2)
+# ---------------------------------------------------------------------------
+
+def _example_two_path():
+    rows = load_golden("two_path_example.txt")
+    R = [(int(a), int(b), int(c)) for t, a, b, c in (r for r in rows if r[0] == "R")]
+    S = [(int(a), int(b), int(c)) for t, a, b, c in (r for r in rows if r[0] == "S")]
+    mats = {r[0]: np.array(list(map(int, r[1:]))).reshape(3, 3) for r in rows if r[0] in ("M1", "M2", "M")}
+    return R, S, mats
+
+
+def test_worked_example_two_path_output():
+    R, S, _ = _example_two_path()
+    rx, ry = np.array([r[0] for r in R]), np.array([r[1] for r in R])
+    sz, sy = np.array([s[0] for s in S]), np.array([s[1] for s in S])
+    x, z = oracle.two_path(rx, ry, sz, sy)
+    assert as_pairs(x, z) == brute_two_path(rx, ry, sz, sy)
+    # derived from the figure by brute force: 26 distinct pairs, J = 35
+    assert len(x) == 26
+    assert oracle.join_size(rx, ry, sz, sy) == 35
+
+
+def test_worked_example_partition_and_matrices():
+    """At Delta1 = Delta2 = 2 the figure's coloured edges are R^- and S^-,
+    and the heavy matrices are the printed M1 and M2."""
+    R, S, mats = _example_two_path()
+    rx, ry = np.array([r[0] for r in R]), np.array([r[1] for r in R])
+    sz, sy = np.array([s[0] for s in S]), np.array([s[1] for s in S])
+    st = ref.two_path_stats(rx, ry, sz, sy, 2, 2)
+    assert st["X"] == [4, 5, 6] and st["Y"] == [4, 5, 6] and st["Z"] == [4, 5, 6]
+    xh, yh, zh = set(st["X"]), set(st["Y"]), set(st["Z"])
+    for a, b, light in R:
+        assert (not (a in xh and b in yh)) == bool(light), (a, b)
+    for c, b, light in S:
+        assert (not (c in zh and b in yh)) == bool(light), (c, b)
+    np.testing.assert_array_equal(st["M1"], mats["M1"])
+    np.testing.assert_array_equal(st["M2"], mats["M2"])
+    # The product of the printed matrices: every entry but [6][6] as printed.
+    M = st["M"]
+    P = mats["M"]
+    mask = np.ones((3, 3), bool)
+    mask[2, 2] = False
+    np.testing.assert_array_equal(M[mask], P[mask])
+    assert M[2, 2] == 1 and P[2, 2] == 3  # misprint; both nonzero
+    assert (M > 0).all() and (P > 0).all()  # the Boolean support agrees
+    # light witnesses: 19 distinct pairs; union with the 9 heavy pairs is 26
+    assert st["J_L"] == 19 and len(st["light_pairs"]) == 19
+    assert st["nnz_heavy"] == 9
+    assert len(st["light_pairs"] | st["heavy_pairs"]) == 26
+    assert st["light_pairs"] & st["heavy_pairs"] == {(4, 4), (6, 6)}
+
+
+def test_worked_example_star():
+    R, S, _ = _example_two_path()
+    rows = load_golden("star_example.txt")
+    T = [(int(r[1]), int(r[2])) for r in rows if r[0] == "T"]
+    U = [(int(r[1]), int(r[2])) for r in rows if r[0] == "U"]
+    rel = lambda E: (np.array([e[0] for e in E]), np.array([e[1] for e in E]))
+    Rr, Sr, Tr, Ur = rel([r[:2] for r in R]), rel([s[:2] for s in S]), rel(T), rel(U)
+    t3 = oracle.star([Rr, Sr, Tr])
+    assert [tuple(r) for r in t3.tolist()] == brute_star([Rr, Sr, Tr])
+    assert len(t3) == 80
+    t4 = oracle.star([Rr, Sr, Tr, Ur])
+    assert [tuple(r) for r in t4.tolist()] == brute_star([Rr, Sr, Tr, Ur])
+    assert len(t4) == 237
+    # The printed V rows (4,5), (6,6) and W columns follow the V/W definition
+    # (membership of every (a_i, y) in R_i); the printed V row (4,4) does not.
+    def adj(rr):
+        m = {}
+        for a, b in zip(*rr):
+            m.setdefault(int(a), set()).add(int(b))
+        return m
+    aR, aS, aT, aU = adj(Rr), adj(Sr), adj(Tr), adj(Ur)
+    for r in rows:
+        if r[0] in ("V", "W"):
+            a, c = int(r[1]), int(r[2])
+            bits = [int(v) for v in r[3:]]
+            first, second = (aR, aS) if r[0] == "V" else (aT, aU)
+            expect = [int(b in first[a] and b in second[c]) for b in (4, 5, 6)]
+            if r[0] == "V" and (a, c) == (4, 4):
+                assert expect == [1, 0, 0] and bits == [1, 1, 1]
+            else:
+                assert expect == bits, r
+
+
+# ---------------------------------------------------------------------------
+# Closed forms
+# ---------------------------------------------------------------------------
+
+def test_communities_closed_form():
+    """Example 1: c disjoint communities of m x values fully connected through
+    their community's y values give c*m^2 self-join pairs."""
+    c, m = 5, 7
+    x, y = datagen.communities(c, m, 4, 1.0, seed=3)
+    ox, oz = oracle.two_path(x, y, x, y)
+    assert len(ox) == c * m * m
+    # sparse communities: pairs never cross communities, so at most c*m^2
+    xs, ys = datagen.communities(c, m, 4, 0.3, seed=3)
+    sx, sz = oracle.two_path(xs, ys, xs, ys)
+    assert len(sx) <= c * m * m and np.all(sx // m == sz // m)
+    # star over full communities: every in-community triple, c*m^3
+    xf, yf = datagen.communities(3, 4, 3, 1.0, seed=1)
+    assert len(oracle.star([(xf, yf)] * 3)) == 3 * 4 ** 3
+
+
+def test_complete_bipartite_and_single_y():
+    X = np.arange(7)
+    Z = np.arange(100, 105)
+    Y = np.arange(3)
+    rx, ry = np.repeat(X, Y.size), np.tile(Y, X.size)
+    sz, sy = np.repeat(Z, Y.size), np.tile(Y, Z.size)
+    x, z = oracle.two_path(rx, ry, sz, sy)
+    assert len(x) == X.size * Z.size
+    # single shared y: |X| * |Z|
+    x, z = oracle.two_path(X, np.zeros(7), Z, np.zeros(5))
+    assert len(x) == 35
+
+
+def test_perfect_matching_is_diagonal():
+    n = 50
+    rng = np.random.default_rng(5)
+    x = rng.permutation(n)
+    y = rng.permutation(n)
+    ox, oz = oracle.two_path(x, y, x, y)
+    assert np.array_equal(ox, np.arange(n)) and np.array_equal(oz, np.arange(n))
+
+
+# ---------------------------------------------------------------------------
+# Invariants stated in the paper
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_selfjoin_symmetry_bounds_and_duplicates(seed):
+    x, y = datagen.uniform_edges(300, 60, 40, seed)
+    ox, oz = oracle.two_path(x, y, x, y)
+    pairs = set(as_pairs(ox, oz))
+    assert all((c, a) in pairs for a, c in pairs)  # symmetric
+    dom = np.unique(x)
+    assert all((a, a) in pairs for a in dom.tolist())  # full diagonal
+    J = oracle.join_size(x, y, x, y)
+    n = len(x)
+    # Section 5: |dom x| <= |OUT| <= min(|dom x|^2, J) and J <= N sqrt(|OUT|)
+    assert dom.size <= len(pairs) <= min(dom.size ** 2, J)
+    assert J <= n * np.sqrt(len(pairs)) + 1e-9
+    # idempotent under repeated rows
+    x2 = np.concatenate([x, x[: 50]])
+    y2 = np.concatenate([y, y[: 50]])
+    dx, dz = oracle.two_path(x2, y2, x2, y2)
+    assert np.array_equal(dx, ox) and np.array_equal(dz, oz)
+    assert oracle.join_size(x2, y2, x2, y2) == J
+
+
+def test_monotone_under_insertion():
+    x, y = datagen.uniform_edges(200, 40, 30, 9)
+    a, b = oracle.two_path(x[:150], y[:150], x[:150], y[:150])
+    c, d = oracle.two_path(x, y, x, y)
+    assert set(as_pairs(a, b)) <= set(as_pairs(c, d))
+
+
+def test_join_size_matches_enumeration():
+    for seed in range(5):
+        rx, ry = datagen.random_small(80, 15, 10, seed, dup=True)
+        sz, sy = datagen.random_small(70, 15, 10, seed + 50, dup=True)
+        er = set(zip(rx.tolist(), ry.tolist()))
+        es = set(zip(sz.tolist(), sy.tolist()))
+        J = sum(1 for a, b in er for c, d in es if b == d)
+        assert oracle.join_size(rx, ry, sz, sy) == J
+
+
+@pytest.mark.parametrize("d1,d2", [(1, 1), (1, 3), (2, 2), (3, 1), (5, 5), (1000, 1000)])
+def test_partition_is_exact_at_any_threshold(d1, d2):
+    """Correctness argument of Section 3.1: the light output unioned with the
+    heavy product's support is the query result whatever the thresholds, and
+    light plus heavy witnesses partition the full join."""
+    rx, ry = datagen.random_small(120, 25, 12, 31)
+    sz, sy = datagen.random_small(110, 25, 12, 32)
+    st = ref.two_path_stats(rx, ry, sz, sy, d1, d2)
+    x, z = oracle.two_path(rx, ry, sz, sy)
+    assert sorted(st["light_pairs"] | st["heavy_pairs"]) == as_pairs(x, z)
+    assert st["J_L"] + st["J_H"] == st["J"] == oracle.join_size(rx, ry, sz, sy)
+    for rule in (ref.Y_RULE_MAX, ref.Y_RULE_R_ONLY):
+        s2 = ref.two_path_stats(rx, ry, sz, sy, d1, d2, y_rule=rule)
+        assert sorted(s2["light_pairs"] | s2["heavy_pairs"]) == as_pairs(x, z)
+
+
+@pytest.mark.parametrize("d1,d2", [(1, 1), (2, 1), (2, 3), (100, 100)])
+def test_star_partition_is_exact(d1, d2):
+    rels = [datagen.random_small(40, 8, 6, 70 + i) for i in range(3)]
+    st = ref.star_stats(rels, d1, d2)
+    t = oracle.star(rels)
+    assert sorted(st["light"] | st["heavy"]) == [tuple(r) for r in t.tolist()]
+    assert st["J_L"] + st["J_H"] == st["J"]
+
+
+# ---------------------------------------------------------------------------
+# Lemma 3 closed forms against a direct minimisation of the idealised cost
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,out", [(1e6, 1e3), (1e6, 1e5), (1e6, 1e6), (1e6, 3e7), (1e5, 1e9)])
+def test_lemma3_minimiser(n, out):
+    d1, d2 = ref.theory_thresholds(n, out)
+    f0 = ref.idealized_cost(n, out, d1, d2)
+    grid = np.exp(np.linspace(0, np.log(n), 400))
+    best = min(ref.idealized_cost(n, out, a, b) for a in grid for b in grid)
+    assert f0 <= best * (1 + 1e-3)
+
+
+def test_k3_example_exponents():
+    """Section 3.2 example (k=3, OUT = N^(3/2)): D2 = N^(6/16), D1 = N^(7/16)
+    balance N D1^2 = OUT D2 = (N/D2)^3 (the omega = 2 product cost with
+    beta = N/D1), giving N^(15/8)."""
+    N = 1e8
+    out = N ** 1.5
+    d2 = N ** (6 / 16)
+    d1 = N ** (7 / 16)
+    a = N * d1 ** 2
+    b = out * d2
+    c = (N / d2) ** 2 * (N / d1) * (N / d2) / (N / d1)  # M(U,V,W) = UVW/beta
+    assert np.isclose(np.log(a), np.log(b)) and np.isclose(np.log(b), np.log(c))
+    assert np.isclose(np.log(a) / np.log(N), 15 / 8)
+
+
+def test_out_estimate_within_bounds():
+    for seed in range(3):
+        x, y = datagen.uniform_edges(400, 80, 50, seed)
+        ox, _ = oracle.two_path(x, y, x, y)
+        J = oracle.join_size(x, y, x, y)
+        dom = np.unique(x).size
+        est = ref.out_estimate(dom, dom, J, len(x))
+        assert dom <= est <= min(dom * dom, J)
