@@ -1,0 +1,201 @@
+/*
+ * jp.h: C ABI of libjoinproject, an MI355X (gfx950) implementation of the
+ * join-project method of "Fast Join Project Query Evaluation using Matrix
+ * Multiplication" (Deep, Hu, Koutris).
+ *
+ * Queries (paper Section 2.1):
+ *   two-path  Q(x,z)      = R(x,y), S(z,y)           projected on (x,z)
+ *   star      Q(x1..xk)   = R1(x1,y), ..., Rk(xk,y)   projected on (x1..xk)
+ * The result is the set of distinct output tuples.  The method (Algorithm 1,
+ * Section 3.1; star: Section 3.2) splits each relation at integer degree
+ * thresholds Delta1 (on the join variable y) and Delta2 (on the free
+ * variables); light tuples are joined by per-y expansion followed by
+ * duplicate removal, heavy tuples through a 0/1 matrix product whose nonzero
+ * entries are the heavy output, and the two outputs are unioned.  Thresholds
+ * are given by the caller or chosen automatically (Section 5, Algorithm 2, or
+ * Lemma 3's closed forms).  The result does not depend on the thresholds.
+ *
+ * Conventions for every call:
+ *  - Relation columns are DEVICE pointers to int32 values on the handle's
+ *    device, borrowed for the duration of the call, never written.  Any int32
+ *    value is a valid id.  Rows may repeat (relations are sets: repeats do
+ *    not change the result).  A column may be NULL only when its length is 0.
+ *  - All device work is ordered on the handle's stream (jp_set_stream); a
+ *    call returns after the output size is known (the host waits on the
+ *    stream), with the output data possibly still being written in stream
+ *    order.
+ *  - Output tuples are distinct and sorted ascending, lexicographically by
+ *    signed int32, stored as structure-of-arrays int32 device columns owned
+ *    by the library until jp_result_free.
+ *  - No C++ exception crosses this boundary.  On any status other than JP_OK
+ *    no result is returned (*out is set to NULL), nothing leaks, and
+ *    jp_last_error(h) describes the failure.
+ *  - A handle must not be used by two threads at the same time.
+ */
+#ifndef JP_H
+#define JP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JP_ABI_VERSION 1
+
+typedef enum jp_status {
+    JP_OK = 0,
+    JP_EINVAL = 1,      /* bad argument: NULL with n > 0, n < 0, k out of range, Delta < 1 */
+    JP_ENOMEM = 2,      /* device allocation failed */
+    JP_EHIP = 3,        /* a HIP runtime call failed; message has hipGetErrorString */
+    JP_ECAPACITY = 4,   /* a caller-supplied capacity was too small; the needed size is reported */
+    JP_EPRECISION = 5,  /* a reduced-precision product was requested where counts could exceed its exact range */
+    JP_EINTERNAL = 6    /* internal consistency check failed */
+} jp_status;
+
+/* How the thresholds (Delta1, Delta2) are chosen. */
+typedef enum jp_strategy {
+    JP_STRATEGY_AUTO_COST = 0,  /* Algorithm 2 (Section 5) with device-calibrated constants */
+    JP_STRATEGY_THEORY = 1,     /* Lemma 3 closed forms from N and the estimated |OUT| */
+    JP_STRATEGY_FIXED = 2,      /* use options.delta1 / options.delta2 as given */
+    JP_STRATEGY_LIGHT_ONLY = 3, /* no heavy part: every tuple is light (Delta = infinity) */
+    JP_STRATEGY_AUTO_MLP = 4    /* learned selector; falls back to AUTO_COST without weights */
+} jp_strategy;
+
+/* Kernel used for the heavy 0/1 matrix product. */
+typedef enum jp_bmm_kind {
+    JP_BMM_AUTO = 0,     /* int8 MFMA unless the planner prefers the popcount kernel */
+    JP_BMM_I8_MFMA = 1,  /* int8 inputs, int32 accumulation on the matrix cores */
+    JP_BMM_BITPOP = 2    /* bit-packed rows, AND + popcount on the vector units */
+} jp_bmm_kind;
+
+/* Which y-degree decides whether y is heavy (two-path).  MAX: y is heavy when
+ * its degree in R or in S exceeds Delta1; R_ONLY: its degree in R. */
+typedef enum jp_y_rule { JP_Y_RULE_MAX = 0, JP_Y_RULE_R_ONLY = 1 } jp_y_rule;
+
+/* Duplicate-removal strategy for the light witnesses (Section 6,
+ * "Deduplication": append-then-sort or a dense per-x marker vector). */
+typedef enum jp_dedup {
+    JP_DEDUP_AUTO = 0,     /* per-x segments: sort small ones on chip, dense bitmap for large ones */
+    JP_DEDUP_GLOBAL = 1,   /* one device-wide radix sort of all witnesses, then unique */
+    JP_DEDUP_SEGMENTED = 2 /* same as AUTO */
+} jp_dedup;
+
+#define JP_DELTA_INF INT64_MAX
+
+typedef struct jp_options {
+    int64_t delta1;     /* FIXED only: threshold on y degrees, >= 1 (JP_DELTA_INF allowed) */
+    int64_t delta2;     /* FIXED only: threshold on x / z degrees, >= 1 (JP_DELTA_INF allowed) */
+    int32_t strategy;   /* jp_strategy */
+    int32_t bmm;        /* jp_bmm_kind */
+    int32_t y_rule;     /* jp_y_rule */
+    int32_t dedup;      /* jp_dedup */
+    uint64_t seed;      /* seed of the sampled output-size estimate */
+    uint64_t flags;     /* JP_FLAG_* */
+} jp_options;
+
+#define JP_FLAG_TIMING 1ull /* record per-phase device times (HIP events) */
+
+/* Statistics of one evaluation.  Sizes refer to the relations after duplicate
+ * removal and after dropping tuples whose y appears in only one relation. */
+typedef struct jp_stats {
+    int64_t n_r, n_s;            /* edges kept (two-path); star: n_r = sum over relations */
+    int64_t dom_x, dom_y, dom_z; /* distinct values kept; star: dom_x, dom_z = product terms unused */
+    int64_t delta1, delta2;      /* thresholds used (JP_DELTA_INF for light only) */
+    int32_t strategy;            /* strategy that produced them */
+    int32_t bmm;                 /* kernel used for the heavy product (jp_bmm_kind) */
+    int32_t dedup;               /* jp_dedup actually used */
+    int32_t arity;               /* output arity */
+    int64_t u, v, w;             /* heavy x / y / z counts (star: u = rows of V, w = rows of W) */
+    int64_t J;                   /* full join size (witness count) */
+    int64_t J_L;                 /* light witnesses enumerated */
+    int64_t J_H;                 /* heavy witnesses (covered by the product) */
+    int64_t nnz_heavy;           /* nonzero entries of the heavy product */
+    int64_t n_out;               /* distinct output tuples */
+    double bmm_ops;              /* 2*u*v*w (star: 2*u1*u2*v*u3) */
+    double ms_ingest;            /* index build: dedup, semijoin, ranks, CSR, degrees */
+    double ms_plan;              /* threshold choice + partition */
+    double ms_light;             /* light witness enumeration */
+    double ms_heavy;             /* heavy matrix build + product */
+    double ms_bmm;               /* the product kernel alone */
+    double ms_dedup;             /* duplicate removal, union, output */
+    double ms_total;             /* whole call, device time */
+} jp_stats;
+
+typedef struct jp_handle jp_handle;
+typedef struct jp_result jp_result;
+
+/* Create a handle bound to HIP device `device`.  *h receives the handle. */
+jp_status jp_create(jp_handle **h, int device);
+
+/* Destroy a handle and release its cached device memory.  NULL is a no-op.
+ * Results created by the handle stay valid until freed. */
+void jp_destroy(jp_handle *h);
+
+/* Order all later device work of this handle on `stream` (a hipStream_t; NULL
+ * means the default stream). */
+jp_status jp_set_stream(jp_handle *h, void *stream);
+
+/* Message describing the last non-OK status returned for this handle. */
+const char *jp_last_error(const jp_handle *h);
+
+/* Fill *opt with the defaults: AUTO_COST, AUTO kernels, MAX y rule. */
+void jp_default_options(jp_options *opt);
+
+/*
+ * Two-path join-project (Algorithm 1, Section 3.1).
+ * R = (r_x[i], r_y[i]) for i < n_r and S = (s_z[i], s_y[i]) for i < n_s.
+ * opt may be NULL (defaults).  With strategy FIXED, delta1 and delta2 must be
+ * >= 1.  On JP_OK, *out holds a result of arity 2: column 0 = x, column 1 = z.
+ */
+jp_status jp_two_path(jp_handle *h,
+                      const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                      const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+                      const jp_options *opt, jp_result **out);
+
+/*
+ * Star join-project Q*_k (Section 3.2), 2 <= k <= 3.  Relation i has columns
+ * x[i], y[i] of n[i] rows (host arrays of device pointers).  On JP_OK, *out
+ * holds a result of arity k; column i holds x_i.
+ */
+jp_status jp_star(jp_handle *h, int k,
+                  const int32_t *const *x, const int32_t *const *y, const int64_t *n,
+                  const jp_options *opt, jp_result **out);
+
+/* Number of tuples and arity of a result. */
+jp_status jp_result_size(const jp_result *r, int64_t *n_tuples, int32_t *arity);
+
+/* Borrow the result's device columns: cols[i] receives column i (arity
+ * entries).  Valid until jp_result_free. */
+jp_status jp_result_columns(const jp_result *r, const int32_t **cols);
+
+/* Copy the result into caller-allocated device columns (arity pointers, each
+ * with room for n_tuples int32), ordered on the handle's stream. */
+jp_status jp_result_copy(jp_handle *h, const jp_result *r, int32_t *const *cols);
+
+/* Statistics of the evaluation that produced r. */
+jp_status jp_result_stats(const jp_result *r, jp_stats *s);
+
+/* Release a result.  NULL is a no-op. */
+void jp_result_free(jp_result *r);
+
+/*
+ * Heavy-product kernel on its own (Algorithm 1, lines 4-6; Section 2.2's
+ * Boolean matrix product): A is u x k and Bt is w x k, both 0/1 int8
+ * row-major device matrices with row stride `ld` bytes (ld >= k, ld a
+ * multiple of 64, padding bytes zero).  For every (i, j) with
+ * sum_t A[i][t] * Bt[j][t] > 0 the pair (i, j) is written to rows[] / cols[]
+ * (device int32 arrays of capacity `cap`), in no particular order, and the
+ * count to *nnz.  If the count exceeds cap, JP_ECAPACITY is returned with
+ * *nnz = the needed count (only cap pairs written).  `kind` selects the
+ * kernel (jp_bmm_kind).  *ms receives the product kernel's device time.
+ */
+jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt,
+                         int64_t u, int64_t w, int64_t k, int64_t ld, int32_t kind,
+                         int32_t *rows, int32_t *cols, int64_t cap, int64_t *nnz, double *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JP_H */

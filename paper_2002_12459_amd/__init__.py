@@ -1,0 +1,303 @@
+"""MI355X (gfx950) join-project: Python binding of libjoinproject.
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch provides device memory and the current stream.  The
+binding refuses to run when the native library is missing (no fallback).
+
+    import paper_2002_12459_amd as jp
+    x, z = jp.two_path(rx, ry, sz, sy)                # AUTO_COST thresholds
+    x, z = jp.two_path(rx, ry, sz, sy, delta1=44, delta2=44)
+    t = jp.star([(x1, y1), (x2, y2), (x3, y3)])       # tuple columns
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+__all__ = [
+    "LIB_PATH", "JoinProjectError", "Handle", "Result", "two_path", "star", "bool_matmul",
+    "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libjoinproject.so")
+
+DELTA_INF = 2**63 - 1
+STRATEGY = {"auto": 0, "cost": 0, "theory": 1, "fixed": 2, "light": 3, "mlp": 4}
+BMM = {"auto": 0, "i8": 1, "bitpop": 2}
+Y_RULE = {"max": 0, "r_only": 1}
+DEDUP = {"auto": 0, "global": 1, "segmented": 2}
+STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ECAPACITY",
+          5: "JP_EPRECISION", 6: "JP_EINTERNAL"}
+FLAG_TIMING = 1
+
+
+class JoinProjectError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("delta1", ctypes.c_int64), ("delta2", ctypes.c_int64), ("strategy", ctypes.c_int32),
+                ("bmm", ctypes.c_int32), ("y_rule", ctypes.c_int32), ("dedup", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_r", "n_s", "dom_x", "dom_y", "dom_z", "delta1", "delta2")] + \
+               [(n, ctypes.c_int32) for n in ("strategy", "bmm", "dedup", "arity")] + \
+               [(n, ctypes.c_int64) for n in ("u", "v", "w", "J", "J_L", "J_H", "nnz_heavy", "n_out")] + \
+               [(n, ctypes.c_double) for n in ("bmm_ops", "ms_ingest", "ms_plan", "ms_light", "ms_heavy",
+                                               "ms_bmm", "ms_dedup", "ms_total")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+_lock = threading.Lock()
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2002_12459_amd.build.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        lib.jp_create.argtypes = [ctypes.POINTER(P), ctypes.c_int]
+        lib.jp_destroy.argtypes = [P]
+        lib.jp_destroy.restype = None
+        lib.jp_set_stream.argtypes = [P, P]
+        lib.jp_last_error.argtypes = [P]
+        lib.jp_last_error.restype = ctypes.c_char_p
+        lib.jp_default_options.argtypes = [ctypes.POINTER(Options)]
+        lib.jp_default_options.restype = None
+        lib.jp_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        lib.jp_star.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64),
+                                ctypes.POINTER(Options), ctypes.POINTER(P)]
+        lib.jp_result_size.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32)]
+        lib.jp_result_columns.argtypes = [P, ctypes.POINTER(P)]
+        lib.jp_result_copy.argtypes = [P, P, ctypes.POINTER(P)]
+        lib.jp_result_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        lib.jp_result_free.argtypes = [P]
+        lib.jp_result_free.restype = None
+        lib.jp_bool_matmul.argtypes = [P, P, P, i64, i64, i64, i64, ctypes.c_int32, P, P, i64,
+                                       ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        for f in ("jp_create", "jp_set_stream", "jp_two_path", "jp_star", "jp_result_size",
+                  "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul"):
+            getattr(lib, f).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _col(t, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.int32:
+        raise TypeError(f"{name} must be int32")
+    if t.dim() != 1 or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous 1-D tensor")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr() if t.numel() else 0)
+
+
+class Result:
+    """A library-owned result; columns stay valid until ``free()``."""
+
+    def __init__(self, handle, ptr):
+        self._h = handle
+        self._p = ptr
+        lib = _load()
+        n = ctypes.c_int64()
+        a = ctypes.c_int32()
+        lib.jp_result_size(ptr, ctypes.byref(n), ctypes.byref(a))
+        self.n = n.value
+        self.arity = a.value
+        s = Stats()
+        lib.jp_result_stats(ptr, ctypes.byref(s))
+        self.stats = s.as_dict()
+
+    def to_torch(self):
+        """Copy the columns into new int32 torch tensors (stream-ordered)."""
+        torch = _torch()
+        dev = torch.device("cuda", self._h.device)
+        cols = [torch.empty(self.n, dtype=torch.int32, device=dev) for _ in range(self.arity)]
+        if self.n:
+            arr = (ctypes.c_void_p * self.arity)(*[c.data_ptr() for c in cols])
+            self._h._check(_load().jp_result_copy(self._h._p, self._p, arr))
+        return cols
+
+    def free(self):
+        if self._p:
+            _load().jp_result_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Handle:
+    """One library handle per device; work goes to torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        lib = _load()
+        self.device = device
+        p = ctypes.c_void_p()
+        st = lib.jp_create(ctypes.byref(p), device)
+        if st != 0:
+            raise JoinProjectError(st, f"jp_create({device}) failed")
+        self._p = p
+
+    def _check(self, st):
+        if st != 0:
+            raise JoinProjectError(st, _load().jp_last_error(self._p).decode())
+
+    def _bind_stream(self):
+        torch = _torch()
+        s = torch.cuda.current_stream(self.device)
+        self._check(_load().jp_set_stream(self._p, ctypes.c_void_p(s.cuda_stream)))
+
+    def _options(self, delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed):
+        o = Options()
+        _load().jp_default_options(ctypes.byref(o))
+        if delta1 is not None or delta2 is not None:
+            if strategy in (None, "auto"):
+                strategy = "fixed"
+            o.delta1 = DELTA_INF if delta1 is None else int(delta1)
+            o.delta2 = DELTA_INF if delta2 is None else int(delta2)
+        if strategy is not None:
+            o.strategy = STRATEGY[strategy]
+        o.bmm = BMM[bmm]
+        o.y_rule = Y_RULE[y_rule]
+        o.dedup = DEDUP[dedup]
+        if seed is not None:
+            o.seed = seed
+        o.flags = FLAG_TIMING if timing else 0
+        return o
+
+    def two_path_result(self, rx, ry, sz, sy, delta1=None, delta2=None, strategy=None, bmm="auto",
+                        y_rule="max", dedup="auto", timing=False, seed=None) -> Result:
+        rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+        if rx.numel() != ry.numel() or sz.numel() != sy.numel():
+            raise ValueError("column lengths differ")
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed)
+        out = ctypes.c_void_p()
+        self._check(_load().jp_two_path(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(),
+                                        ctypes.byref(o), ctypes.byref(out)))
+        return Result(self, out)
+
+    def two_path(self, rx, ry, sz, sy, **kw):
+        r = self.two_path_result(rx, ry, sz, sy, **kw)
+        try:
+            x, z = r.to_torch()
+            return x, z, r.stats
+        finally:
+            r.free()
+
+    def star_result(self, rels, delta1=None, delta2=None, strategy=None, bmm="auto", dedup="auto",
+                    timing=False, seed=None) -> Result:
+        k = len(rels)
+        cols = [(_col(a, f"x{i}"), _col(b, f"y{i}")) for i, (a, b) in enumerate(rels)]
+        for a, b in cols:
+            if a.numel() != b.numel():
+                raise ValueError("column lengths differ")
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, "max", dedup, timing, seed)
+        xs = (ctypes.c_void_p * k)(*[_ptr(a) for a, _ in cols])
+        ys = (ctypes.c_void_p * k)(*[_ptr(b) for _, b in cols])
+        ns = (ctypes.c_int64 * k)(*[a.numel() for a, _ in cols])
+        out = ctypes.c_void_p()
+        self._check(_load().jp_star(self._p, k, xs, ys, ns, ctypes.byref(o), ctypes.byref(out)))
+        return Result(self, out)
+
+    def star(self, rels, **kw):
+        r = self.star_result(rels, **kw)
+        try:
+            return r.to_torch(), r.stats
+        finally:
+            r.free()
+
+    def bool_matmul(self, A, Bt, k=None, kind="i8", cap=None):
+        """Nonzero coordinates of A @ Bt.T for 0/1 int8 device matrices (rows
+        padded to a multiple of 128 bytes).  Returns (rows, cols, ms)."""
+        torch = _torch()
+        if A.dtype != torch.int8 or Bt.dtype != torch.int8 or not (A.is_cuda and Bt.is_cuda):
+            raise TypeError("A and Bt must be int8 CUDA tensors")
+        if A.dim() != 2 or Bt.dim() != 2 or A.shape[1] != Bt.shape[1]:
+            raise ValueError("A and Bt must be 2-D with equal row length")
+        A = A.contiguous()
+        Bt = Bt.contiguous()
+        u, ld = A.shape
+        w = Bt.shape[0]
+        k = ld if k is None else k
+        if cap is None:
+            cap = u * w
+        self._bind_stream()
+        rows = torch.empty(max(cap, 1), dtype=torch.int32, device=A.device)
+        cols = torch.empty(max(cap, 1), dtype=torch.int32, device=A.device)
+        nnz = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._check(_load().jp_bool_matmul(self._p, _ptr(A), _ptr(Bt), u, w, k, ld, BMM[kind], _ptr(rows),
+                                           _ptr(cols), cap, ctypes.byref(nnz), ctypes.byref(ms)))
+        return rows[: nnz.value], cols[: nnz.value], ms.value
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _load().jp_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles = {}
+
+
+def default_handle(device: int | None = None) -> Handle:
+    torch = _torch()
+    if device is None:
+        device = torch.cuda.current_device()
+    h = _handles.get(device)
+    if h is None:
+        h = _handles[device] = Handle(device)
+    return h
+
+
+def two_path(rx, ry, sz, sy, **kw):
+    """Distinct (x, z) of Q(x,z) = R(x,y), S(z,y) as two sorted int32 tensors."""
+    x, z, _ = default_handle(rx.device.index).two_path(rx, ry, sz, sy, **kw)
+    return x, z
+
+
+def star(rels, **kw):
+    """Distinct tuples of the star query, as a list of k sorted int32 columns."""
+    cols, _ = default_handle(rels[0][0].device.index).star(rels, **kw)
+    return cols
+
+
+def bool_matmul(A, Bt, **kw):
+    return default_handle(A.device.index).bool_matmul(A, Bt, **kw)

@@ -1,0 +1,271 @@
+// C ABI of libjoinproject: argument validation, device/stream binding,
+// exception-to-status translation and result ownership.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <memory>
+#include <string>
+
+#include "pipeline.hpp"
+
+struct jp_handle {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::shared_ptr<jp::Allocator> alloc;
+    int num_cus = 256;
+    std::string err;
+};
+
+namespace {
+
+// Makes the handle's device current for the scope of one call.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) JP_HIP(hipSetDevice(dev));
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+jp::Ctx make_ctx(jp_handle *h) {
+    jp::Ctx c;
+    c.stream = h->stream;
+    c.alloc = h->alloc;
+    c.device = h->device;
+    c.num_cus = h->num_cus;
+    return c;
+}
+
+template <class F>
+jp_status guarded(jp_handle *h, F f) {
+    try {
+        DeviceScope ds(h->device);
+        f();
+        h->err.clear();
+        return JP_OK;
+    } catch (const jp::Error &e) {
+        h->err = e.msg;
+        (void)hipGetLastError();
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        h->err = "host allocation failed";
+        return JP_ENOMEM;
+    } catch (...) {
+        h->err = "unexpected internal error";
+        return JP_EINTERNAL;
+    }
+}
+
+bool bad_col(const void *p, int64_t n) { return n < 0 || (n > 0 && p == nullptr); }
+
+jp_status validate_options(jp_handle *h, const jp_options &o) {
+    if (o.strategy < JP_STRATEGY_AUTO_COST || o.strategy > JP_STRATEGY_AUTO_MLP) {
+        h->err = "unknown strategy";
+        return JP_EINVAL;
+    }
+    if (o.strategy == JP_STRATEGY_FIXED && (o.delta1 < 1 || o.delta2 < 1)) {
+        h->err = "FIXED thresholds must be >= 1";
+        return JP_EINVAL;
+    }
+    if (o.bmm < JP_BMM_AUTO || o.bmm > JP_BMM_BITPOP || o.y_rule < JP_Y_RULE_MAX ||
+        o.y_rule > JP_Y_RULE_R_ONLY || o.dedup < JP_DEDUP_AUTO || o.dedup > JP_DEDUP_SEGMENTED) {
+        h->err = "bad option value";
+        return JP_EINVAL;
+    }
+    return JP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void jp_default_options(jp_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->strategy = JP_STRATEGY_AUTO_COST;
+    opt->bmm = JP_BMM_AUTO;
+    opt->y_rule = JP_Y_RULE_MAX;
+    opt->dedup = JP_DEDUP_AUTO;
+    opt->seed = 0x9e3779b97f4a7c15ull;
+}
+
+jp_status jp_create(jp_handle **out, int device) {
+    if (!out) return JP_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        (void)hipGetLastError();
+        return device < 0 ? JP_EINVAL : JP_EHIP;
+    }
+    auto h = std::make_unique<jp_handle>();
+    h->device = device;
+    h->alloc = std::make_shared<jp::Allocator>(device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        h->num_cus = cus;
+    *out = h.release();
+    return JP_OK;
+}
+
+void jp_destroy(jp_handle *h) {
+    if (!h) return;
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(h->device);
+        (void)hipStreamSynchronize(h->stream);
+        h->alloc->release_cached();
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    delete h;
+}
+
+jp_status jp_set_stream(jp_handle *h, void *stream) {
+    if (!h) return JP_EINVAL;
+    return guarded(h, [&] {
+        hipStream_t s = (hipStream_t)stream;
+        if (s != h->stream) {
+            // cached blocks were last used on the old stream
+            JP_HIP(hipStreamSynchronize(h->stream));
+            h->stream = s;
+        }
+    });
+}
+
+const char *jp_last_error(const jp_handle *h) { return h ? h->err.c_str() : "null handle"; }
+
+jp_status jp_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                      const int32_t *s_y, int64_t n_s, const jp_options *opt, jp_result **out) {
+    if (!h) return JP_EINVAL;
+    if (!out) {
+        h->err = "out is NULL";
+        return JP_EINVAL;
+    }
+    *out = nullptr;
+    if (bad_col(r_x, n_r) || bad_col(r_y, n_r) || bad_col(s_z, n_s) || bad_col(s_y, n_s)) {
+        h->err = "relation column is NULL or its length is negative";
+        return JP_EINVAL;
+    }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    jp_result *r = nullptr;
+    jp_status st = guarded(h, [&] { r = jp::run_two_path(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o); });
+    if (st == JP_OK) *out = r;
+    return st;
+}
+
+jp_status jp_star(jp_handle *h, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
+                  const jp_options *opt, jp_result **out) {
+    if (!h) return JP_EINVAL;
+    if (!out) {
+        h->err = "out is NULL";
+        return JP_EINVAL;
+    }
+    *out = nullptr;
+    if (k < 2 || k > 3 || !x || !y || !n) {
+        h->err = "k must be 2 or 3 and x, y, n non-NULL";
+        return JP_EINVAL;
+    }
+    for (int i = 0; i < k; ++i)
+        if (bad_col(x[i], n[i]) || bad_col(y[i], n[i])) {
+            h->err = "relation column is NULL or its length is negative";
+            return JP_EINVAL;
+        }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    jp_result *r = nullptr;
+    jp_status st = guarded(h, [&] { r = jp::run_star(make_ctx(h), k, x, y, n, o); });
+    if (st == JP_OK) *out = r;
+    return st;
+}
+
+jp_status jp_result_size(const jp_result *r, int64_t *n_tuples, int32_t *arity) {
+    if (!r) return JP_EINVAL;
+    if (n_tuples) *n_tuples = r->n;
+    if (arity) *arity = r->arity;
+    return JP_OK;
+}
+
+jp_status jp_result_columns(const jp_result *r, const int32_t **cols) {
+    if (!r || !cols) return JP_EINVAL;
+    for (int i = 0; i < r->arity; ++i) cols[i] = r->cols[i].get();
+    return JP_OK;
+}
+
+jp_status jp_result_copy(jp_handle *h, const jp_result *r, int32_t *const *cols) {
+    if (!h) return JP_EINVAL;
+    if (!r || !cols) {
+        h->err = "result or column array is NULL";
+        return JP_EINVAL;
+    }
+    for (int i = 0; i < r->arity; ++i)
+        if (r->n > 0 && !cols[i]) {
+            h->err = "destination column is NULL";
+            return JP_EINVAL;
+        }
+    return guarded(h, [&] {
+        for (int i = 0; i < r->arity; ++i)
+            if (r->n > 0)
+                JP_HIP(hipMemcpyAsync(cols[i], r->cols[i].get(), (size_t)r->n * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, h->stream));
+    });
+}
+
+jp_status jp_result_stats(const jp_result *r, jp_stats *s) {
+    if (!r || !s) return JP_EINVAL;
+    *s = r->stats;
+    return JP_OK;
+}
+
+void jp_result_free(jp_result *r) { delete r; }
+
+jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t k,
+                         int64_t ld, int32_t kind, int32_t *rows, int32_t *cols, int64_t cap, int64_t *nnz,
+                         double *ms) {
+    if (!h) return JP_EINVAL;
+    if (u < 0 || w < 0 || k < 0 || cap < 0 || !nnz || ld < k || ld % jp::kBmmPadK != 0 ||
+        bad_col(A, u * ld) || bad_col(Bt, w * ld) || bad_col(rows, cap) || bad_col(cols, cap) ||
+        kind < JP_BMM_AUTO || kind > JP_BMM_BITPOP) {
+        h->err = "bad argument to jp_bool_matmul (ld must be >= k and a multiple of 128)";
+        return JP_EINVAL;
+    }
+    int64_t count = 0;
+    double t = 0;
+    jp_status st = guarded(h, [&] {
+        jp::Ctx c = make_ctx(h);
+        jp::DBuf<unsigned long long> cnt = c.buf<unsigned long long>(1);
+        hipEvent_t e0, e1;
+        JP_HIP(hipEventCreate(&e0));
+        JP_HIP(hipEventCreate(&e1));
+        JP_HIP(hipEventRecord(e0, c.stream));
+        jp::bool_matmul_pairs(c, A, Bt, u, w, ld, kind, rows, cols, cap, cnt.get());
+        JP_HIP(hipEventRecord(e1, c.stream));
+        unsigned long long v = c.load(cnt.get());
+        float f = 0;
+        JP_HIP(hipEventElapsedTime(&f, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        count = (int64_t)v;
+        t = f;
+    });
+    if (st != JP_OK) return st;
+    *nnz = count;
+    if (ms) *ms = t;
+    if (count > cap) {
+        h->err = "capacity too small for the nonzero count";
+        return JP_ECAPACITY;
+    }
+    return JP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,230 @@
+// Host-side infrastructure shared by every translation unit of libjoinproject:
+// error propagation, a caching device allocator, RAII device buffers, the
+// per-call execution context and device-time phase markers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/jp.h"
+
+namespace jp {
+
+// Internal failures travel as exceptions and are turned into a status at the
+// C boundary; nothing throws across it.
+struct Error {
+    jp_status st;
+    std::string msg;
+};
+
+[[noreturn]] inline void fail(jp_status st, const std::string &msg) { throw Error{st, msg}; }
+
+#define JP_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            ::jp::fail(JP_EHIP, std::string(#call) + " failed: " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define JP_CHECK(cond, st, msg)                       \
+    do {                                              \
+        if (!(cond)) ::jp::fail((st), (msg));         \
+    } while (0)
+
+// Caching device allocator.  Blocks are rounded (powers of two below 1 MiB,
+// 2 MiB multiples above), kept on release, and reused best-fit for requests
+// at least 2/3 of their size.  When hipMalloc fails the cache is emptied and
+// the request retried once.  All blocks are used on one stream at a time, so
+// reuse after release is ordered by that stream.
+class Allocator {
+  public:
+    explicit Allocator(int device) : device_(device) {}
+    ~Allocator() { release_cached(); }
+
+    void *alloc(size_t bytes) {
+        if (bytes == 0) bytes = 1;
+        size_t r = round(bytes);
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = free_.lower_bound(r);
+        if (it != free_.end() && it->first * 2 <= r * 3) {
+            void *p = it->second;
+            live_[p] = it->first;
+            cached_ -= it->first;
+            free_.erase(it);
+            return p;
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, r);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            release_cached_locked();
+            e = hipMalloc(&p, r);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                fail(JP_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed");
+            }
+        }
+        live_[p] = r;
+        return p;
+    }
+
+    void release(void *p) {
+        if (!p) return;
+        std::lock_guard<std::mutex> g(mu_);
+        auto it = live_.find(p);
+        if (it == live_.end()) return;
+        free_.emplace(it->second, p);
+        cached_ += it->second;
+        live_.erase(it);
+    }
+
+    void release_cached() {
+        std::lock_guard<std::mutex> g(mu_);
+        release_cached_locked();
+    }
+
+    int device() const { return device_; }
+
+  private:
+    static size_t round(size_t b) {
+        if (b <= (1u << 20)) {
+            size_t r = 256;
+            while (r < b) r <<= 1;
+            return r;
+        }
+        const size_t g = 2u << 20;
+        return (b + g - 1) / g * g;
+    }
+    void release_cached_locked() {
+        for (auto &kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        cached_ = 0;
+    }
+
+    int device_;
+    std::mutex mu_;
+    std::multimap<size_t, void *> free_;
+    std::unordered_map<void *, size_t> live_;
+    size_t cached_ = 0;
+};
+
+// Owning device buffer of n elements of T from an Allocator.
+template <class T>
+class DBuf {
+  public:
+    DBuf() = default;
+    DBuf(std::shared_ptr<Allocator> a, size_t n) : a_(std::move(a)), n_(n) {
+        p_ = static_cast<T *>(a_->alloc(n * sizeof(T)));
+    }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept { swap(o); }
+    DBuf &operator=(DBuf &&o) noexcept {
+        reset();
+        swap(o);
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void reset() {
+        if (p_ && a_) a_->release(p_);
+        p_ = nullptr;
+        n_ = 0;
+    }
+    T *get() const { return p_; }
+    size_t size() const { return n_; }
+    T *release_ptr() {
+        T *p = p_;
+        p_ = nullptr;
+        n_ = 0;
+        return p;
+    }
+
+  private:
+    void swap(DBuf &o) {
+        std::swap(a_, o.a_);
+        std::swap(p_, o.p_);
+        std::swap(n_, o.n_);
+    }
+    std::shared_ptr<Allocator> a_;
+    T *p_ = nullptr;
+    size_t n_ = 0;
+};
+
+// Execution context of one call: device, stream, allocator, chip size.
+struct Ctx {
+    hipStream_t stream = nullptr;
+    std::shared_ptr<Allocator> alloc;
+    int device = 0;
+    int num_cus = 256;
+    size_t lds_bytes = 160 * 1024;
+
+    template <class T>
+    DBuf<T> buf(size_t n) const {
+        return DBuf<T>(alloc, n);
+    }
+    void sync() const { JP_HIP(hipStreamSynchronize(stream)); }
+    template <class T>
+    T load(const T *dev) const {  // small device-to-host read, waits on the stream
+        T v;
+        JP_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, stream));
+        sync();
+        return v;
+    }
+    template <class T>
+    void load_n(T *host, const T *dev, size_t n) const {
+        if (!n) return;
+        JP_HIP(hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, stream));
+        sync();
+    }
+    template <class T>
+    void zero(T *dev, size_t n) const {
+        if (n) JP_HIP(hipMemsetAsync(dev, 0, n * sizeof(T), stream));
+    }
+};
+
+// Device-time phase markers (HIP events on the call's stream).
+class Timeline {
+  public:
+    Timeline(const Ctx &c, bool on) : c_(c), on_(on) {}
+    ~Timeline() {
+        for (auto e : ev_) (void)hipEventDestroy(e);
+    }
+    int mark() {
+        if (!on_) return -1;
+        hipEvent_t e;
+        JP_HIP(hipEventCreate(&e));
+        JP_HIP(hipEventRecord(e, c_.stream));
+        ev_.push_back(e);
+        return (int)ev_.size() - 1;
+    }
+    double ms(int a, int b) const {
+        if (!on_ || a < 0 || b < 0) return 0.0;
+        JP_HIP(hipEventSynchronize(ev_[b]));
+        float t = 0;
+        JP_HIP(hipEventElapsedTime(&t, ev_[a], ev_[b]));
+        return t;
+    }
+
+  private:
+    const Ctx &c_;
+    bool on_;
+    std::vector<hipEvent_t> ev_;
+};
+
+inline int bits_for(uint64_t max_value) {  // bits needed to hold values 0..max_value
+    int b = 0;
+    while (b < 64 && (max_value >> b)) ++b;
+    return b;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace jp

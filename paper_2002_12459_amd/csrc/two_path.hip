@@ -1,0 +1,611 @@
+// Two-path join-project Q(x,z) = R(x,y), S(z,y) (Algorithm 1, Section 3.1).
+//
+//  ingest     relations become sets (duplicate rows dropped), tuples whose y
+//             is missing from the other relation are dropped, ids get dense
+//             order-preserving ranks, R is indexed x-major and S y-major
+//             (Section 5, "Indexing relations"), degrees and J are computed.
+//  plan       thresholds (Delta1, Delta2) from the planner.
+//  partition  x heavy iff deg_R(x) > Delta2, z heavy iff deg_S(z) > Delta2,
+//             y heavy iff its key degree > Delta1 (one y classification shared
+//             by R and S).  Light witnesses are exactly the disjoint classes
+//             (R^- join S) and (R^+ join S^-): an R tuple with light x or
+//             light y meets all of N_S(y); a heavy R tuple meets only the
+//             light z of N_S(y).
+//  light      per R tuple, its witness list is expanded into packed keys
+//             (x_rank << bz | z_rank); the output index space is cut evenly
+//             across workgroups.
+//  heavy      M1 (heavy x by heavy y) and M2^T (heavy z by heavy y) as int8,
+//             their 0/1 product's nonzeros appended as keys.
+//  union      one radix sort of light + heavy keys over the significant bits,
+//             then unique + unrank into the sorted distinct output.
+#include <climits>
+
+#include "pipeline.hpp"
+#include "prims.hpp"
+
+namespace jp {
+namespace {
+
+__global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int *out) {
+    int mn = INT_MAX, mx = INT_MIN;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int v = a[i];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        int a2 = __shfl_xor(mn, o), b2 = __shfl_xor(mx, o);
+        mn = a2 < mn ? a2 : mn;
+        mx = b2 > mx ? b2 : mx;
+    }
+    if (lane_id() == 0) {
+        atomicMin(&out[0], mn);
+        atomicMax(&out[1], mx);
+    }
+}
+
+void minmax(const Ctx &c, const int32_t *a, int64_t n, int *out) {
+    if (n <= 0) return;
+    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 4);
+    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, c.stream, a, n, out);
+    JP_HIP(hipGetLastError());
+}
+
+// Light witness expansion.  Block b produces outputs [b*4096, b*4096+4096);
+// each output index finds its R tuple by binary search in the tuple offsets
+// and reads z from that tuple's list (all of N_S(y), or the light-z part of
+// N_S(y) for a heavy tuple).  Consecutive lanes read consecutive list entries
+// and write consecutive keys.
+constexpr int kExpBlock = 256;
+constexpr int kExpItems = 16;
+constexpr int64_t kExpTile = kExpBlock * kExpItems;
+
+struct ExpandArgs {
+    const int64_t *eoff;    // exclusive offsets of the per-tuple witness counts (n_e)
+    int64_t n_e, J_L;
+    const int32_t *r_xr;    // x rank of each R tuple
+    const int32_t *adj_r;   // y rank of each R tuple
+    const int64_t *off_y;   // S y-major offsets
+    const int32_t *adj_s;   // S z ranks
+    const int32_t *hx_of_x; // heavy id of x or -1 (nullptr: no heavy part)
+    const int32_t *hy_of_y; // heavy id of y or -1
+    const int64_t *lz_off;  // light-z list offsets per heavy y
+    const int32_t *lz_adj;  // light-z lists
+    int bz;
+    uint64_t *out;
+    int64_t *err;           // set when an index falls outside its list
+};
+
+__global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
+    const int64_t o0 = (int64_t)blockIdx.x * kExpTile;
+    const int64_t olast = std::min<int64_t>(o0 + kExpTile, a.J_L) - 1;
+    const int64_t lo = upper_bound_dev(a.eoff, (int64_t)0, a.n_e, o0) - 1;
+    const int64_t hi = upper_bound_dev(a.eoff, lo, a.n_e, olast);
+#pragma unroll 4
+    for (int j = 0; j < kExpItems; ++j) {
+        const int64_t o = o0 + (int64_t)j * kExpBlock + threadIdx.x;
+        if (o > olast) break;
+        const int64_t e = upper_bound_dev(a.eoff, lo, hi, o) - 1;
+        const int64_t t = o - a.eoff[e];
+        const int32_t x = a.r_xr[e], y = a.adj_r[e];
+        int32_t z;
+        bool heavy_tuple = false;
+        int32_t hy = -1;
+        if (a.hx_of_x) {
+            hy = a.hy_of_y[y];
+            heavy_tuple = hy >= 0 && a.hx_of_x[x] >= 0;
+        }
+        int64_t b0, b1;
+        const int32_t *list;
+        if (heavy_tuple) {
+            b0 = a.lz_off[hy];
+            b1 = a.lz_off[hy + 1];
+            list = a.lz_adj;
+        } else {
+            b0 = a.off_y[y];
+            b1 = a.off_y[y + 1];
+            list = a.adj_s;
+        }
+        if (t < 0 || b0 + t >= b1) {
+            *a.err = 1;
+            a.out[o] = 0;
+            continue;
+        }
+        z = list[b0 + t];
+        a.out[o] = ((uint64_t)(uint32_t)x << a.bz) | (uint64_t)(uint32_t)z;
+    }
+}
+
+}  // namespace
+
+jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                        const int32_t *sy, int64_t ns, const jp_options &o) {
+    const bool timing = (o.flags & JP_FLAG_TIMING) != 0;
+    Timeline tl(c, timing);
+    const int ev_start = tl.mark();
+    auto res = std::make_unique<jp_result>();
+    res->alloc = c.alloc;
+    res->arity = 2;
+    jp_stats &st = res->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.arity = 2;
+    st.delta1 = st.delta2 = JP_DELTA_INF;
+    st.strategy = o.strategy;
+    st.dedup = JP_DEDUP_GLOBAL;
+
+    auto finish_empty = [&]() {
+        res->n = 0;
+        res->cols[0] = c.buf<int32_t>(1);
+        res->cols[1] = c.buf<int32_t>(1);
+        return res.release();
+    };
+    if (nr == 0 || ns == 0) return finish_empty();
+
+    DBuf<int64_t> scal = c.buf<int64_t>(32);  // device scalars
+    int64_t *S = scal.get();
+
+    // ---- ranges of the id columns --------------------------------------------
+    DBuf<int> mmb = c.buf<int>(8);
+    int *mm = mmb.get();
+    for_each(c, 4, [=] __device__(int64_t i) {
+        mm[2 * i] = INT_MAX;
+        mm[2 * i + 1] = INT_MIN;
+    });
+    minmax(c, rx, nr, mm + 0);
+    minmax(c, ry, nr, mm + 2);
+    minmax(c, sz, ns, mm + 4);
+    minmax(c, sy, ns, mm + 6);
+    int hmm[8];
+    c.load_n(hmm, mm, 8);
+    const int64_t xmin = hmm[0], xmax = hmm[1], zmin = hmm[4], zmax = hmm[5];
+    const int64_t ymin = std::min(hmm[2], hmm[6]), ymax = std::max(hmm[3], hmm[7]);
+    const int xb = bits_for((uint64_t)(xmax - xmin)), yb = bits_for((uint64_t)(ymax - ymin));
+    const int zb = bits_for((uint64_t)(zmax - zmin));
+    const uint64_t ymask = yb >= 64 ? ~0ull : ((1ull << yb) - 1), zmask = (1ull << zb) - 1;
+
+    // ---- R: distinct tuples, x-major ----------------------------------------
+    DBuf<uint64_t> r1;
+    {
+        DBuf<uint64_t> ka = c.buf<uint64_t>(nr), kb = c.buf<uint64_t>(nr);
+        uint64_t *k = ka.get();
+        for_each(c, nr, [=] __device__(int64_t i) {
+            k[i] = ((uint64_t)((int64_t)rx[i] - xmin) << yb) | (uint64_t)((int64_t)ry[i] - ymin);
+        });
+        const uint64_t *s = radix_sort(c, ka.get(), kb.get(), nr, xb + yb);
+        r1 = c.buf<uint64_t>(nr);
+        uint64_t *d = r1.get();
+        compact(
+            c, nr, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 0);
+    }
+    // ---- S: distinct tuples, y-major ----------------------------------------
+    DBuf<uint64_t> s1;
+    {
+        DBuf<uint64_t> ka = c.buf<uint64_t>(ns), kb = c.buf<uint64_t>(ns);
+        uint64_t *k = ka.get();
+        for_each(c, ns, [=] __device__(int64_t i) {
+            k[i] = ((uint64_t)((int64_t)sy[i] - ymin) << zb) | (uint64_t)((int64_t)sz[i] - zmin);
+        });
+        const uint64_t *s = radix_sort(c, ka.get(), kb.get(), ns, yb + zb);
+        s1 = c.buf<uint64_t>(ns);
+        uint64_t *d = s1.get();
+        compact(
+            c, ns, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 1);
+    }
+    // ---- distinct y of R (sorted) --------------------------------------------
+    DBuf<uint32_t> YR = c.buf<uint32_t>(nr);
+    {
+        DBuf<uint32_t> ya = c.buf<uint32_t>(nr), yb2 = c.buf<uint32_t>(nr);
+        uint32_t *k = ya.get();
+        for_each(c, nr, [=] __device__(int64_t i) { k[i] = (uint32_t)((int64_t)ry[i] - ymin); });
+        const uint32_t *s = radix_sort(c, ya.get(), yb2.get(), nr, yb);
+        uint32_t *d = YR.get();
+        compact(
+            c, nr, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 2);
+    }
+    // ---- distinct y of S (from the y-major S) --------------------------------
+    int64_t h4[4];
+    c.load_n(h4, S, 4);
+    const int64_t n_r1 = h4[0], n_s1 = h4[1], ny_r = h4[2];
+    DBuf<uint32_t> YS = c.buf<uint32_t>(n_s1);
+    {
+        const uint64_t *s = s1.get();
+        uint32_t *d = YS.get();
+        const int zbs = zb;
+        compact(
+            c, n_s1, [=] __device__(int64_t i) { return i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs); },
+            [=] __device__(int64_t i, int64_t p) { d[p] = (uint32_t)(s[i] >> zbs); }, S + 3);
+    }
+    const int64_t ny_s = c.load(S + 3);
+
+    // ---- semijoin: keep y present in both; dense y ranks ---------------------
+    DBuf<int32_t> yrank_js = c.buf<int32_t>(ny_s);
+    {
+        int32_t *yr = yrank_js.get();
+        const uint32_t *ys = YS.get(), *yrr = YR.get();
+        const int64_t nyr = ny_r;
+        for_each(c, ny_s, [=] __device__(int64_t j) { yr[j] = -1; });
+        compact(
+            c, ny_s,
+            [=] __device__(int64_t j) {
+                int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
+                return p < nyr && yrr[p] == ys[j];
+            },
+            [=] __device__(int64_t j, int64_t p) { yr[j] = (int32_t)p; }, S + 4);
+    }
+    // S tuples kept, y-major: y rank + z offset
+    DBuf<int32_t> s2_y = c.buf<int32_t>(n_s1);
+    DBuf<uint32_t> s2_z = c.buf<uint32_t>(n_s1);
+    {
+        DBuf<int32_t> seg = c.buf<int32_t>(n_s1);
+        const uint64_t *s = s1.get();
+        int32_t *sg = seg.get();
+        const int zbs = zb;
+        auto newy = [=] __device__(int64_t i) -> int64_t {
+            return (i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs)) ? 1 : 0;
+        };
+        scan_exclusive(c, n_s1, newy, [=] __device__(int64_t i, int64_t p) { sg[i] = (int32_t)(p + newy(i) - 1); });
+        const int32_t *yr = yrank_js.get();
+        int32_t *oy = s2_y.get();
+        uint32_t *oz = s2_z.get();
+        const uint64_t zm = zmask;
+        compact(
+            c, n_s1, [=] __device__(int64_t i) { return yr[sg[i]] >= 0; },
+            [=] __device__(int64_t i, int64_t p) {
+                oy[p] = yr[sg[i]];
+                oz[p] = (uint32_t)(s[i] & zm);
+            },
+            S + 5);
+    }
+    // R tuples kept, x-major: x offset + y rank
+    DBuf<uint32_t> r2_x = c.buf<uint32_t>(n_r1);
+    DBuf<int32_t> adj_r = c.buf<int32_t>(n_r1);
+    {
+        const uint64_t *s = r1.get();
+        const uint32_t *ys = YS.get();
+        const int32_t *yr = yrank_js.get();
+        const int64_t nys = ny_s;
+        const int ybs = yb;
+        const uint64_t ym = ymask;
+        uint32_t *ox = r2_x.get();
+        int32_t *oy = adj_r.get();
+        auto find = [=] __device__(int64_t i) -> int32_t {
+            uint32_t y = (uint32_t)(s[i] & ym);
+            int64_t p = lower_bound_dev(ys, (int64_t)0, nys, y);
+            return (p < nys && ys[p] == y) ? yr[p] : -1;
+        };
+        compact(
+            c, n_r1, [=] __device__(int64_t i) { return find(i) >= 0; },
+            [=] __device__(int64_t i, int64_t p) {
+                ox[p] = (uint32_t)(s[i] >> ybs);
+                oy[p] = find(i);
+            },
+            S + 6);
+    }
+    int64_t h7[3];
+    c.load_n(h7, S + 4, 3);
+    const int64_t dom_y = h7[0], n_s2 = h7[1], n_r2 = h7[2];
+    r1.reset();
+    s1.reset();
+    YR.reset();
+    if (n_r2 == 0 || n_s2 == 0) return finish_empty();
+
+    // ---- z ranks ---------------------------------------------------------------
+    DBuf<uint32_t> ZS = c.buf<uint32_t>(n_s2);
+    {
+        DBuf<uint32_t> za = c.buf<uint32_t>(n_s2), zb2 = c.buf<uint32_t>(n_s2);
+        JP_HIP(hipMemcpyAsync(za.get(), s2_z.get(), n_s2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
+        const uint32_t *s = radix_sort(c, za.get(), zb2.get(), n_s2, zb);
+        uint32_t *d = ZS.get();
+        compact(
+            c, n_s2, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 7);
+    }
+    // ---- x ranks and the x-major CSR of R -----------------------------------------
+    DBuf<int32_t> xorig = c.buf<int32_t>(n_r2);
+    DBuf<int64_t> off_x = c.buf<int64_t>(n_r2 + 1);
+    {
+        const uint32_t *xs = r2_x.get();
+        int32_t *xo = xorig.get();
+        int64_t *ox = off_x.get();
+        const int64_t xm = xmin;
+        compact(
+            c, n_r2, [=] __device__(int64_t i) { return i == 0 || xs[i] != xs[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) {
+                xo[p] = (int32_t)((int64_t)xs[i] + xm);
+                ox[p] = i;
+            },
+            S + 8);
+    }
+    int64_t h9[2];
+    c.load_n(h9, S + 7, 2);
+    const int64_t dom_z = h9[0], dom_x = h9[1];
+    DBuf<int32_t> r_xr = c.buf<int32_t>(n_r2);
+    {
+        const uint32_t *xs = r2_x.get();
+        int32_t *xr = r_xr.get();
+        int64_t *ox = off_x.get();
+        const int64_t nx = dom_x, nr2 = n_r2;
+        auto newx = [=] __device__(int64_t i) -> int64_t { return (i == 0 || xs[i] != xs[i - 1]) ? 1 : 0; };
+        scan_exclusive(c, n_r2, newx, [=] __device__(int64_t i, int64_t p) { xr[i] = (int32_t)(p + newx(i) - 1); });
+        for_each(c, 1, [=] __device__(int64_t) { ox[nx] = nr2; });
+    }
+    r2_x.reset();
+    // ---- S y-major CSR with z ranks --------------------------------------------
+    DBuf<int32_t> zorig = c.buf<int32_t>(dom_z);
+    DBuf<int32_t> adj_s = c.buf<int32_t>(n_s2);
+    DBuf<int64_t> off_y = c.buf<int64_t>(dom_y + 1);
+    {
+        const uint32_t *zs = ZS.get();
+        int32_t *zo = zorig.get();
+        const int64_t zm = zmin, nz = dom_z;
+        for_each(c, dom_z, [=] __device__(int64_t r) { zo[r] = (int32_t)((int64_t)zs[r] + zm); });
+        const uint32_t *sz2 = s2_z.get();
+        int32_t *as = adj_s.get();
+        for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zs, (int64_t)0, nz, sz2[e]); });
+        const int32_t *syr = s2_y.get();
+        int64_t *oy = off_y.get();
+        const int64_t ny = dom_y, ns2 = n_s2;
+        compact(
+            c, n_s2, [=] __device__(int64_t e) { return e == 0 || syr[e] != syr[e - 1]; },
+            [=] __device__(int64_t e, int64_t p) { oy[p] = e; }, S + 9);
+        for_each(c, 1, [=] __device__(int64_t) { oy[ny] = ns2; });
+    }
+    ZS.reset();
+    s2_z.reset();
+    // ---- degrees and the full join size J -----------------------------------------
+    DBuf<int32_t> dRy = c.buf<int32_t>(dom_y), dSz = c.buf<int32_t>(dom_z);
+    c.zero(dRy.get(), dom_y);
+    c.zero(dSz.get(), dom_z);
+    {
+        int32_t *d1 = dRy.get(), *d2 = dSz.get();
+        const int32_t *ar = adj_r.get(), *as = adj_s.get();
+        for_each(c, n_r2, [=] __device__(int64_t e) { atomicAdd(&d1[ar[e]], 1); });
+        for_each(c, n_s2, [=] __device__(int64_t e) { atomicAdd(&d2[as[e]], 1); });
+        const int64_t *oy = off_y.get();
+        reduce_sum(
+            c, dom_y, [=] __device__(int64_t y) -> int64_t { return (int64_t)d1[y] * (oy[y + 1] - oy[y]); },
+            (unsigned long long *)(S + 10));
+    }
+    const int64_t J = c.load(S + 10);
+    const int ev_ingest = tl.mark();
+
+    st.n_r = n_r2;
+    st.n_s = n_s2;
+    st.dom_x = dom_x;
+    st.dom_y = dom_y;
+    st.dom_z = dom_z;
+    st.J = J;
+
+    // ---- thresholds ---------------------------------------------------------------
+    TwoPathSummary sum;
+    sum.n_r = n_r2;
+    sum.n_s = n_s2;
+    sum.dom_x = dom_x;
+    sum.dom_y = dom_y;
+    sum.dom_z = dom_z;
+    sum.J = J;
+    sum.self_join = (rx == sz && ry == sy && nr == ns);
+    sum.out_est = estimate_out(dom_x, dom_z, J, std::max(n_r2, n_s2));
+    Thresholds th = choose_thresholds(sum, o);
+    st.delta1 = th.d1;
+    st.delta2 = th.d2;
+    st.strategy = th.strategy;
+
+    // ---- partition ------------------------------------------------------------------
+    const int64_t d1 = th.d1, d2 = th.d2;
+    const bool rule_r_only = o.y_rule == JP_Y_RULE_R_ONLY;
+    int64_t u = 0, v = 0, w = 0;
+    DBuf<int32_t> hx_of_x, x_of_hx, hz_of_z, z_of_hz, hy_of_y;
+    if (!th.light_only()) {
+        hx_of_x = c.buf<int32_t>(dom_x);
+        x_of_hx = c.buf<int32_t>(dom_x);
+        hz_of_z = c.buf<int32_t>(dom_z);
+        z_of_hz = c.buf<int32_t>(dom_z);
+        hy_of_y = c.buf<int32_t>(dom_y);
+        int32_t *hx = hx_of_x.get(), *xh = x_of_hx.get(), *hz = hz_of_z.get(), *zh = z_of_hz.get();
+        int32_t *hy = hy_of_y.get();
+        const int64_t *ox = off_x.get(), *oy = off_y.get();
+        const int32_t *dry = dRy.get(), *dsz = dSz.get();
+        for_each(c, dom_x, [=] __device__(int64_t i) { hx[i] = -1; });
+        for_each(c, dom_z, [=] __device__(int64_t i) { hz[i] = -1; });
+        for_each(c, dom_y, [=] __device__(int64_t i) { hy[i] = -1; });
+        compact(
+            c, dom_x, [=] __device__(int64_t x) { return ox[x + 1] - ox[x] > d2; },
+            [=] __device__(int64_t x, int64_t p) {
+                hx[x] = (int32_t)p;
+                xh[p] = (int32_t)x;
+            },
+            S + 11);
+        compact(
+            c, dom_z, [=] __device__(int64_t z) { return (int64_t)dsz[z] > d2; },
+            [=] __device__(int64_t z, int64_t p) {
+                hz[z] = (int32_t)p;
+                zh[p] = (int32_t)z;
+            },
+            S + 12);
+        compact(
+            c, dom_y,
+            [=] __device__(int64_t y) {
+                int64_t dr = dry[y], ds = oy[y + 1] - oy[y];
+                int64_t key = rule_r_only ? dr : (dr > ds ? dr : ds);
+                return key > d1;
+            },
+            [=] __device__(int64_t y, int64_t p) { hy[y] = (int32_t)p; }, S + 13);
+        int64_t h3[3];
+        c.load_n(h3, S + 11, 3);
+        u = h3[0];
+        w = h3[1];
+        v = h3[2];
+    }
+    const bool has_heavy = u > 0 && v > 0 && w > 0;
+    st.u = u;
+    st.v = v;
+    st.w = w;
+
+    // light-z lists of heavy y (the part of N_S(y) a heavy R tuple still meets)
+    DBuf<int64_t> lz_off;
+    DBuf<int32_t> lz_adj;
+    if (has_heavy) {
+        DBuf<int64_t> lz_cnt = c.buf<int64_t>(v);
+        lz_off = c.buf<int64_t>(v + 1);
+        c.zero(lz_cnt.get(), v);
+        int64_t *lc = lz_cnt.get(), *lo = lz_off.get();
+        const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
+        auto is_lz = [=] __device__(int64_t e) -> bool { return hy[syr[e]] >= 0 && hz[as[e]] < 0; };
+        for_each(c, n_s2, [=] __device__(int64_t e) {
+            if (is_lz(e)) atomicAdd((unsigned long long *)&lc[hy[syr[e]]], 1ull);
+        });
+        scan_exclusive(c, v, ArrayGet{lc}, ArrayPut{lo}, lo + v);
+        lz_adj = c.buf<int32_t>(std::max<int64_t>(n_s2, 1));
+        int32_t *la = lz_adj.get();
+        compact(c, n_s2, is_lz, [=] __device__(int64_t e, int64_t p) { la[p] = as[e]; }, S + 14);
+    }
+
+    // per R tuple witness count and offsets
+    DBuf<int64_t> eoff = c.buf<int64_t>(n_r2 + 1);
+    {
+        const int32_t *xr = r_xr.get(), *ar = adj_r.get();
+        const int64_t *oy = off_y.get();
+        const int32_t *hx = has_heavy ? hx_of_x.get() : nullptr, *hy = has_heavy ? hy_of_y.get() : nullptr;
+        const int64_t *lo = has_heavy ? lz_off.get() : nullptr;
+        auto len = [=] __device__(int64_t e) -> int64_t {
+            const int32_t y = ar[e];
+            if (hx) {
+                const int32_t h = hy[y];
+                if (h >= 0 && hx[xr[e]] >= 0) return lo[h + 1] - lo[h];
+            }
+            return oy[y + 1] - oy[y];
+        };
+        scan_exclusive(c, n_r2, len, ArrayPut{eoff.get()}, S + 15);
+    }
+    // heavy witness count J_H and the heavy matrices
+    DBuf<int8_t> M1, M2t;
+    int64_t ld = 0;
+    if (has_heavy) {
+        DBuf<int64_t> hxc = c.buf<int64_t>(v), hzc = c.buf<int64_t>(v);
+        c.zero(hxc.get(), v);
+        c.zero(hzc.get(), v);
+        ld = ceil_div(v, kBmmPadK) * kBmmPadK;
+        M1 = c.buf<int8_t>((size_t)(u * ld));
+        M2t = c.buf<int8_t>((size_t)(w * ld));
+        c.zero(M1.get(), (size_t)(u * ld));
+        c.zero(M2t.get(), (size_t)(w * ld));
+        int64_t *cx = hxc.get(), *cz = hzc.get();
+        int8_t *m1 = M1.get(), *m2 = M2t.get();
+        const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = adj_s.get();
+        const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
+        const int64_t ldl = ld;
+        for_each(c, n_r2, [=] __device__(int64_t e) {
+            const int32_t a = hx[xr[e]], b = hy[ar[e]];
+            if (a >= 0 && b >= 0) {
+                m1[(int64_t)a * ldl + b] = 1;
+                atomicAdd((unsigned long long *)&cx[b], 1ull);
+            }
+        });
+        for_each(c, n_s2, [=] __device__(int64_t e) {
+            const int32_t cc = hz[as[e]], b = hy[syr[e]];
+            if (cc >= 0 && b >= 0) {
+                m2[(int64_t)cc * ldl + b] = 1;
+                atomicAdd((unsigned long long *)&cz[b], 1ull);
+            }
+        });
+        reduce_sum(
+            c, v, [=] __device__(int64_t b) -> int64_t { return cx[b] * cz[b]; }, (unsigned long long *)(S + 16));
+    } else {
+        c.zero(S + 16, 1);
+    }
+    int64_t h15[2];
+    c.load_n(h15, S + 15, 2);
+    const int64_t J_L = h15[0], J_H = h15[1];
+    st.J_L = J_L;
+    st.J_H = J_H;
+    JP_CHECK(J_L + J_H == J, JP_EINTERNAL, "light and heavy witnesses do not add up to the join size");
+    const int ev_plan = tl.mark();
+
+    // ---- candidates: light witnesses + heavy nonzeros ---------------------------------
+    const int bz = bits_for((uint64_t)(dom_z - 1)), bx = bits_for((uint64_t)(dom_x - 1));
+    const double uw = (double)u * (double)w;
+    const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, uw) : 0;
+    const int64_t cap = J_L + cap_h;
+    DBuf<uint64_t> cand = c.buf<uint64_t>(std::max<int64_t>(cap, 1));
+    if (J_L > 0) {
+        ExpandArgs a;
+        a.eoff = eoff.get();
+        a.n_e = n_r2;
+        a.J_L = J_L;
+        a.r_xr = r_xr.get();
+        a.adj_r = adj_r.get();
+        a.off_y = off_y.get();
+        a.adj_s = adj_s.get();
+        a.hx_of_x = has_heavy ? hx_of_x.get() : nullptr;
+        a.hy_of_y = has_heavy ? hy_of_y.get() : nullptr;
+        a.lz_off = has_heavy ? lz_off.get() : nullptr;
+        a.lz_adj = has_heavy ? lz_adj.get() : nullptr;
+        a.bz = bz;
+        a.out = cand.get();
+        a.err = S + 19;
+        c.zero(S + 19, 1);
+        const int64_t blocks = ceil_div(J_L, kExpTile);
+        JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "light witness count too large");
+        hipLaunchKernelGGL(k_light_expand, dim3((unsigned)blocks), dim3(kExpBlock), 0, c.stream, a);
+        JP_HIP(hipGetLastError());
+    }
+    const int ev_light = tl.mark();
+    if (J_L > 0) JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside its list");
+    int64_t nnz = 0;
+    int ev_bmm0 = ev_light, ev_bmm1 = ev_light;
+    if (has_heavy) {
+        ev_bmm0 = tl.mark();
+        bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
+                         cand.get() + J_L, cap_h, (unsigned long long *)(S + 17));
+        ev_bmm1 = tl.mark();
+        nnz = c.load(S + 17);
+        JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
+        st.bmm = JP_BMM_I8_MFMA;
+        st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+    }
+    st.nnz_heavy = nnz;
+    M1.reset();
+    M2t.reset();
+    const int ev_heavy = tl.mark();
+
+    // ---- union + duplicate removal + unrank -----------------------------------------
+    const int64_t total = J_L + nnz;
+    DBuf<uint64_t> tmp = c.buf<uint64_t>(std::max<int64_t>(total, 1));
+    const uint64_t *sorted = radix_sort(c, cand.get(), tmp.get(), total, bx + bz);
+    res->cols[0] = c.buf<int32_t>(std::max<int64_t>(total, 1));
+    res->cols[1] = c.buf<int32_t>(std::max<int64_t>(total, 1));
+    {
+        int32_t *ox = res->cols[0].get(), *oz = res->cols[1].get();
+        const int32_t *xo = xorig.get(), *zo = zorig.get();
+        const uint64_t zm = (1ull << bz) - 1;
+        const int bzs = bz;
+        compact(
+            c, total, [=] __device__(int64_t i) { return i == 0 || sorted[i] != sorted[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) {
+                const uint64_t k = sorted[i];
+                ox[p] = xo[k >> bzs];
+                oz[p] = zo[k & zm];
+            },
+            S + 18);
+    }
+    res->n = c.load(S + 18);
+    st.n_out = res->n;
+    const int ev_end = tl.mark();
+    if (timing) {
+        st.ms_ingest = tl.ms(ev_start, ev_ingest);
+        st.ms_plan = tl.ms(ev_ingest, ev_plan);
+        st.ms_light = tl.ms(ev_plan, ev_light);
+        st.ms_heavy = tl.ms(ev_light, ev_heavy);
+        st.ms_bmm = tl.ms(ev_bmm0, ev_bmm1);
+        st.ms_dedup = tl.ms(ev_heavy, ev_end);
+        st.ms_total = tl.ms(ev_start, ev_end);
+    }
+    return res.release();
+}
+
+}  // namespace jp

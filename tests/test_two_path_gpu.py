@@ -1,0 +1,165 @@
+"""Two-path parity: the HIP path through the C ABI against the CPU oracle.
+
+Outputs must match bit for bit as sorted distinct pair sets; the reported
+partition statistics must match the numpy restatement of Algorithm 1.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import reference as ref
+from tests.conftest import load_golden
+
+pytestmark = pytest.mark.gpu
+
+INF = None
+
+
+@pytest.fixture(scope="module")
+def jp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_12459_amd as jp
+    return jp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.int32))).cuda()
+
+
+def run(jp, rx, ry, sz, sy, **kw):
+    x, z, st = jp.default_handle(0).two_path(dev(rx), dev(ry), dev(sz), dev(sy), **kw)
+    return x.cpu().numpy(), z.cpu().numpy(), st
+
+
+def check_equal(jp, rx, ry, sz, sy, **kw):
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    x, z, st = run(jp, rx, ry, sz, sy, **kw)
+    assert x.size == ex.size, (x.size, ex.size, kw)
+    np.testing.assert_array_equal(x, ex)
+    np.testing.assert_array_equal(z, ez)
+    return st
+
+
+def test_worked_example(jp):
+    rows = load_golden("two_path_example.txt")
+    R = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "R"])
+    S = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "S"])
+    st = check_equal(jp, R[:, 0], R[:, 1], S[:, 0], S[:, 1], delta1=2, delta2=2)
+    assert (st["u"], st["v"], st["w"]) == (3, 3, 3)
+    assert st["J"] == 35 and st["J_L"] == 19 and st["J_H"] == 16 and st["nnz_heavy"] == 9
+    assert st["n_out"] == 26
+
+
+def test_selfjoin_2000_fixed_sqrt(jp):
+    x, y = datagen.selfjoin_c1()
+    d = int(np.sqrt(len(x)))  # 44
+    st = check_equal(jp, x, y, x, y, delta1=d, delta2=d)
+    assert st["delta1"] == 44 and st["delta2"] == 44
+
+
+DELTAS = [1, 2, 3, 4, 6, 8, 12, 16, 44, None]
+
+
+def test_selfjoin_2000_threshold_invariance(jp):
+    """The output does not depend on the thresholds (Section 3.1 correctness
+    argument); the partition statistics follow Algorithm 1."""
+    x, y = datagen.selfjoin_c1()
+    ex, ez = oracle.two_path(x, y, x, y)
+    for d1, d2 in itertools.product(DELTAS, DELTAS):
+        gx, gz, st = run(jp, x, y, x, y, delta1=d1, delta2=d2, strategy="fixed")
+        np.testing.assert_array_equal(gx, ex, err_msg=f"{d1},{d2}")
+        np.testing.assert_array_equal(gz, ez, err_msg=f"{d1},{d2}")
+        if d1 in (1, 4, 12) and d2 in (2, 6, 44):
+            r = ref.two_path_stats(x, y, x, y, d1, d2)
+            for k in ("u", "v", "w", "J", "J_L", "J_H", "nnz_heavy", "dom_x", "dom_y", "dom_z"):
+                assert st[k] == r[k], (k, d1, d2, st[k], r[k])
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_small(jp, seed):
+    rng = np.random.default_rng(seed)
+    signed = seed % 2 == 0
+    nx, ny = int(rng.integers(1, 40)), int(rng.integers(1, 30))
+    rx, ry = datagen.random_small(int(rng.integers(1, 400)), nx, ny, seed, dup=True, signed=signed)
+    sz, sy = datagen.random_small(int(rng.integers(1, 400)), nx, ny, seed + 99, dup=True, signed=signed)
+    if signed:
+        sy = ry[rng.integers(0, ry.size, sy.size)]
+    for d1, d2 in [(1, 1), (2, 3), (5, 1), (None, None)]:
+        for rule in ("max", "r_only"):
+            check_equal(jp, rx, ry, sz, sy, delta1=d1, delta2=d2, strategy="fixed", y_rule=rule)
+
+
+def test_empty_and_degenerate(jp):
+    e = np.zeros(0, np.int32)
+    x, z, st = run(jp, e, e, e, e)
+    assert x.size == 0 and st["n_out"] == 0
+    x, z, st = run(jp, [1, 2], [3, 4], e, e)
+    assert x.size == 0
+    # no common y
+    x, z, st = run(jp, [1, 2], [3, 4], [5], [6])
+    assert x.size == 0
+    # a single tuple each
+    check_equal(jp, [7], [9], [-3], [9])
+    # all ids identical
+    check_equal(jp, [5] * 10, [5] * 10, [5] * 3, [5] * 3)
+    # extreme ids
+    lo, hi = -(2**31), 2**31 - 1
+    check_equal(jp, [lo, hi, 0, lo], [hi, lo, hi, lo], [hi, lo, 0], [lo, lo, hi])
+
+
+def test_auto_and_theory(jp):
+    x, y = datagen.uniform_edges(20000, 3000, 400, 11)
+    for strat in ("auto", "theory", "light"):
+        check_equal(jp, x, y, x, y, strategy=strat)
+
+
+@pytest.mark.parametrize("scale", [0.002, 0.01])
+def test_zipf_scaled(jp, scale):
+    """Skewed two-path input (Zipf y, uniform x) at a reduced scale, several
+    threshold settings, R != S."""
+    (rx, ry), (sz, sy) = datagen.twopath_c2(scale)
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    for kw in (dict(strategy="light"), dict(delta1=50, delta2=8), dict(delta1=3, delta2=3), dict(strategy="auto")):
+        x, z, st = run(jp, rx, ry, sz, sy, **kw)
+        np.testing.assert_array_equal(x, ex, err_msg=str(kw))
+        np.testing.assert_array_equal(z, ez, err_msg=str(kw))
+
+
+def test_communities_dense_heavy(jp):
+    """Dense communities: the heavy product carries most of the output."""
+    x, y = datagen.communities(4, 300, 150, 0.2, seed=5)
+    st = check_equal(jp, x, y, x, y, delta1=10, delta2=10)
+    assert st["nnz_heavy"] > 0 and st["n_out"] == 4 * 300 * 300
+
+
+@pytest.mark.parametrize("u,w,k", [(1, 1, 1), (37, 130, 200), (128, 128, 128), (257, 129, 1000), (600, 515, 77)])
+def test_bool_matmul_kernel(jp, u, w, k):
+    import torch
+    rng = np.random.default_rng(u * 7 + w)
+    ld = -(-k // 128) * 128
+    A = np.zeros((u, ld), np.int8)
+    B = np.zeros((w, ld), np.int8)
+    A[:, :k] = rng.random((u, k)) < 0.02
+    B[:, :k] = rng.random((w, k)) < 0.02
+    C = A.astype(np.int64) @ B.astype(np.int64).T
+    ei, ej = np.nonzero(C)
+    rows, cols, ms = jp.default_handle(0).bool_matmul(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), k=k)
+    got = sorted(zip(rows.cpu().numpy().tolist(), cols.cpu().numpy().tolist()))
+    assert got == sorted(zip(ei.tolist(), ej.tolist()))
+
+
+def test_bool_matmul_counts_do_not_overflow(jp):
+    """All-ones rows: counts equal K (here 4096 > int8 range); still exact."""
+    import torch
+    u, w, k = 64, 64, 4096
+    A = torch.ones((u, k), dtype=torch.int8).cuda()
+    B = torch.zeros((w, k), dtype=torch.int8)
+    B[::2] = 1
+    rows, cols, _ = jp.default_handle(0).bool_matmul(A, B.cuda())
+    assert rows.numel() == u * (w // 2)
+    assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
