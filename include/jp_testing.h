@@ -1,0 +1,31 @@
+/*
+ * jp_testing.h: test hooks of libjoinproject.  The device-wide primitives
+ * that the join-project pipelines are built from, exposed one by one so each
+ * can be checked against a plain host computation.  Not part of the stable
+ * ABI.  All pointers are device pointers on the handle's device; work is
+ * ordered on the handle's stream and the call waits for it.  Status codes as
+ * in jp.h.
+ */
+#ifndef JP_TESTING_H
+#define JP_TESTING_H
+
+#include "jp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Stable LSD radix sort of n keys on their low `bits` bits, in place. */
+jp_status jp_test_radix_sort_u64(jp_handle *h, uint64_t *keys, int64_t n, int32_t bits);
+jp_status jp_test_radix_sort_u32(jp_handle *h, uint32_t *keys, int64_t n, int32_t bits);
+
+/* out[i] = in[0] + ... + in[i-1]; *total (host) = sum of all n values. */
+jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, int64_t n, int64_t *total);
+
+/* Keeps the first of every run of equal adjacent keys, in order; *n_out (host). */
+jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JP_TESTING_H */

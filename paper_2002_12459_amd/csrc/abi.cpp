@@ -81,6 +81,12 @@ jp_status validate_options(jp_handle *h, const jp_options &o) {
 
 }  // namespace
 
+// Used by the test hooks (testing.hip).
+jp::Ctx jp_handle_ctx(jp_handle *h) { return make_ctx(h); }
+jp_status jp_handle_guard(jp_handle *h, void (*fn)(void *), void *arg) {
+    return guarded(h, [&] { fn(arg); });
+}
+
 extern "C" {
 
 void jp_default_options(jp_options *opt) {

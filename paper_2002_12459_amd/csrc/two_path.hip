@@ -20,6 +20,7 @@
 //             then unique + unrank into the sorted distinct output.
 #include <climits>
 
+#include "debug.hpp"
 #include "pipeline.hpp"
 #include "prims.hpp"
 
@@ -54,27 +55,25 @@ void minmax(const Ctx &c, const int32_t *a, int64_t n, int *out) {
 
 // Light witness expansion.  Block b produces outputs [b*4096, b*4096+4096);
 // each output index finds its R tuple by binary search in the tuple offsets
-// and reads z from that tuple's list (all of N_S(y), or the light-z part of
-// N_S(y) for a heavy tuple).  Consecutive lanes read consecutive list entries
-// and write consecutive keys.
+// and reads z from that tuple's list.  All lists live in one array: N_S(y)
+// for every y (the y-major S), followed by the light-z part of N_S(y) for
+// every heavy y; `lbase` holds each tuple's list start, so the kernel has no
+// data-dependent choice of array.  Consecutive lanes read consecutive list
+// entries and write consecutive keys.
 constexpr int kExpBlock = 256;
 constexpr int kExpItems = 16;
 constexpr int64_t kExpTile = kExpBlock * kExpItems;
 
 struct ExpandArgs {
-    const int64_t *eoff;    // exclusive offsets of the per-tuple witness counts (n_e)
+    const int64_t *eoff;   // exclusive offsets of the per-tuple witness counts (n_e + 1)
     int64_t n_e, J_L;
-    const int32_t *r_xr;    // x rank of each R tuple
-    const int32_t *adj_r;   // y rank of each R tuple
-    const int64_t *off_y;   // S y-major offsets
-    const int32_t *adj_s;   // S z ranks
-    const int32_t *hx_of_x; // heavy id of x or -1 (nullptr: no heavy part)
-    const int32_t *hy_of_y; // heavy id of y or -1
-    const int64_t *lz_off;  // light-z list offsets per heavy y
-    const int32_t *lz_adj;  // light-z lists
+    const int32_t *r_xr;   // x rank of each R tuple
+    const int64_t *lbase;  // start of each tuple's list in zlist
+    const int32_t *zlist;  // concatenated z-rank lists
+    int64_t zlist_n;
     int bz;
     uint64_t *out;
-    int64_t *err;           // set when an index falls outside its list
+    int64_t *err;          // set when an index falls outside zlist
 };
 
 __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
@@ -82,38 +81,16 @@ __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
     const int64_t olast = std::min<int64_t>(o0 + kExpTile, a.J_L) - 1;
     const int64_t lo = upper_bound_dev(a.eoff, (int64_t)0, a.n_e, o0) - 1;
     const int64_t hi = upper_bound_dev(a.eoff, lo, a.n_e, olast);
-#pragma unroll 4
     for (int j = 0; j < kExpItems; ++j) {
         const int64_t o = o0 + (int64_t)j * kExpBlock + threadIdx.x;
-        if (o > olast) break;
-        const int64_t e = upper_bound_dev(a.eoff, lo, hi, o) - 1;
-        const int64_t t = o - a.eoff[e];
-        const int32_t x = a.r_xr[e], y = a.adj_r[e];
-        int32_t z;
-        bool heavy_tuple = false;
-        int32_t hy = -1;
-        if (a.hx_of_x) {
-            hy = a.hy_of_y[y];
-            heavy_tuple = hy >= 0 && a.hx_of_x[x] >= 0;
+        if (o <= olast) {
+            const int64_t e = upper_bound_dev(a.eoff, lo, hi, o) - 1;
+            const int64_t idx = a.lbase[e] + (o - a.eoff[e]);
+            const bool ok = idx >= 0 && idx < a.zlist_n;
+            const int32_t z = a.zlist[ok ? idx : 0];
+            if (!ok) *a.err = 1;
+            a.out[o] = ((uint64_t)(uint32_t)a.r_xr[e] << a.bz) | (uint64_t)(uint32_t)z;
         }
-        int64_t b0, b1;
-        const int32_t *list;
-        if (heavy_tuple) {
-            b0 = a.lz_off[hy];
-            b1 = a.lz_off[hy + 1];
-            list = a.lz_adj;
-        } else {
-            b0 = a.off_y[y];
-            b1 = a.off_y[y + 1];
-            list = a.adj_s;
-        }
-        if (t < 0 || b0 + t >= b1) {
-            *a.err = 1;
-            a.out[o] = 0;
-            continue;
-        }
-        z = list[b0 + t];
-        a.out[o] = ((uint64_t)(uint32_t)x << a.bz) | (uint64_t)(uint32_t)z;
     }
 }
 
@@ -231,8 +208,9 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         compact(
             c, ny_s,
             [=] __device__(int64_t j) {
-                int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
-                return p < nyr && yrr[p] == ys[j];
+                const int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
+                const int64_t q = p < nyr ? p : nyr - 1;
+                return (p < nyr) & (yrr[q] == ys[j]);
             },
             [=] __device__(int64_t j, int64_t p) { yr[j] = (int32_t)p; }, S + 4);
     }
@@ -274,8 +252,10 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         int32_t *oy = adj_r.get();
         auto find = [=] __device__(int64_t i) -> int32_t {
             uint32_t y = (uint32_t)(s[i] & ym);
-            int64_t p = lower_bound_dev(ys, (int64_t)0, nys, y);
-            return (p < nys && ys[p] == y) ? yr[p] : -1;
+            const int64_t p = lower_bound_dev(ys, (int64_t)0, nys, y);
+            const int64_t q = p < nys ? p : nys - 1;
+            const int32_t r = yr[q];
+            return ((p < nys) & (ys[q] == y)) ? r : -1;
         };
         compact(
             c, n_r1, [=] __device__(int64_t i) { return find(i) >= 0; },
@@ -372,6 +352,25 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     }
     const int64_t J = c.load(S + 10);
     const int ev_ingest = tl.mark();
+    auto check_index = [&](const char *when) {
+        std::string w(when);
+        check_range(c, (w + ": r_xr").c_str(), r_xr.get(), n_r2, 0, dom_x);
+        check_monotone(c, (w + ": r_xr order").c_str(), r_xr.get(), n_r2, 0, -1);
+        check_range(c, (w + ": adj_r").c_str(), adj_r.get(), n_r2, 0, dom_y);
+        check_range(c, (w + ": adj_s").c_str(), adj_s.get(), n_s2, 0, dom_z);
+        check_monotone(c, (w + ": off_x").c_str(), off_x.get(), dom_x + 1, 0, n_r2);
+        check_monotone(c, (w + ": off_y").c_str(), off_y.get(), dom_y + 1, 0, n_s2);
+        check_range(c, (w + ": s2_y").c_str(), s2_y.get(), n_s2, 0, dom_y);
+    };
+    check_index("ingest");
+    dump(c, "r_xr", r_xr.get(), n_r2);
+    dump(c, "adj_r", adj_r.get(), n_r2);
+    dump(c, "off_x", off_x.get(), dom_x + 1);
+    dump(c, "off_y", off_y.get(), dom_y + 1);
+    dump(c, "adj_s", adj_s.get(), n_s2);
+    dump(c, "s2_y", s2_y.get(), n_s2);
+    dump(c, "dRy", dRy.get(), dom_y);
+    dump(c, "dSz", dSz.get(), dom_z);
 
     st.n_r = n_r2;
     st.n_s = n_s2;
@@ -442,45 +441,85 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         v = h3[2];
     }
     const bool has_heavy = u > 0 && v > 0 && w > 0;
+    if (!th.light_only()) {
+        check_range(c, "hx_of_x", hx_of_x.get(), dom_x, -1, u);
+        check_range(c, "hz_of_z", hz_of_z.get(), dom_z, -1, w);
+        check_range(c, "hy_of_y", hy_of_y.get(), dom_y, -1, v);
+        check_range(c, "x_of_hx", x_of_hx.get(), u, 0, dom_x);
+        check_range(c, "z_of_hz", z_of_hz.get(), w, 0, dom_z);
+        dump(c, "hx_of_x", hx_of_x.get(), dom_x);
+        dump(c, "hy_of_y", hy_of_y.get(), dom_y);
+        dump(c, "hz_of_z", hz_of_z.get(), dom_z);
+    }
     st.u = u;
     st.v = v;
     st.w = w;
 
-    // light-z lists of heavy y (the part of N_S(y) a heavy R tuple still meets)
+    // Witness lists.  zlist = N_S(y) for all y (adj_s), then for heavy y the
+    // light-z part of N_S(y) (what a heavy R tuple still meets).
     DBuf<int64_t> lz_off;
-    DBuf<int32_t> lz_adj;
+    DBuf<int32_t> zlist_own;
+    const int32_t *zlist = adj_s.get();
+    int64_t zlist_n = n_s2;
     if (has_heavy) {
         DBuf<int64_t> lz_cnt = c.buf<int64_t>(v);
         lz_off = c.buf<int64_t>(v + 1);
         c.zero(lz_cnt.get(), v);
         int64_t *lc = lz_cnt.get(), *lo = lz_off.get();
         const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
-        auto is_lz = [=] __device__(int64_t e) -> bool { return hy[syr[e]] >= 0 && hz[as[e]] < 0; };
+        auto is_lz = [=] __device__(int64_t e) -> bool { return (hy[syr[e]] >= 0) & (hz[as[e]] < 0); };
         for_each(c, n_s2, [=] __device__(int64_t e) {
-            if (is_lz(e)) atomicAdd((unsigned long long *)&lc[hy[syr[e]]], 1ull);
+            const int32_t h = hy[syr[e]];
+            if ((h >= 0) & (hz[as[e]] < 0)) atomicAdd((unsigned long long *)&lc[h], 1ull);
         });
         scan_exclusive(c, v, ArrayGet{lc}, ArrayPut{lo}, lo + v);
-        lz_adj = c.buf<int32_t>(std::max<int64_t>(n_s2, 1));
-        int32_t *la = lz_adj.get();
+        zlist_own = c.buf<int32_t>(2 * n_s2);
+        int32_t *zl = zlist_own.get();
+        JP_HIP(hipMemcpyAsync(zl, as, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
+        int32_t *la = zl + n_s2;
         compact(c, n_s2, is_lz, [=] __device__(int64_t e, int64_t p) { la[p] = as[e]; }, S + 14);
+        const int64_t n_lz = c.load(S + 14);
+        check_monotone(c, "lz_off", lz_off.get(), v + 1, 0, n_lz);
+        check_range(c, "lz lists", la, n_lz, 0, dom_z);
+        dump(c, "lz_off", lz_off.get(), v + 1);
+        dump(c, "lz lists", la, n_lz);
+        zlist = zl;
+        zlist_n = n_s2 + n_lz;
     }
 
-    // per R tuple witness count and offsets
+    // Per R tuple: list start and witness count (all loads unconditional,
+    // choices by select), then offsets by scan.
+    DBuf<int64_t> lbase = c.buf<int64_t>(n_r2);
     DBuf<int64_t> eoff = c.buf<int64_t>(n_r2 + 1);
     {
+        DBuf<int64_t> elen = c.buf<int64_t>(n_r2);
         const int32_t *xr = r_xr.get(), *ar = adj_r.get();
         const int64_t *oy = off_y.get();
-        const int32_t *hx = has_heavy ? hx_of_x.get() : nullptr, *hy = has_heavy ? hy_of_y.get() : nullptr;
-        const int64_t *lo = has_heavy ? lz_off.get() : nullptr;
-        auto len = [=] __device__(int64_t e) -> int64_t {
-            const int32_t y = ar[e];
-            if (hx) {
-                const int32_t h = hy[y];
-                if (h >= 0 && hx[xr[e]] >= 0) return lo[h + 1] - lo[h];
-            }
-            return oy[y + 1] - oy[y];
-        };
-        scan_exclusive(c, n_r2, len, ArrayPut{eoff.get()}, S + 15);
+        int64_t *lb = lbase.get(), *ln = elen.get();
+        if (has_heavy) {
+            const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get();
+            const int64_t *lo = lz_off.get();
+            const int64_t ns2 = n_s2;
+            for_each(c, n_r2, [=] __device__(int64_t e) {
+                const int32_t y = ar[e];
+                const int32_t hyv = hy[y], hxv = hx[xr[e]];
+                const bool heavy = (hyv | hxv) >= 0;  // both non-negative
+                const int32_t hi2 = heavy ? hyv : 0;
+                const int64_t l0 = lo[hi2], l1 = lo[hi2 + 1];
+                const int64_t s0 = oy[y], s1v = oy[y + 1];
+                lb[e] = heavy ? ns2 + l0 : s0;
+                ln[e] = heavy ? l1 - l0 : s1v - s0;
+            });
+        } else {
+            for_each(c, n_r2, [=] __device__(int64_t e) {
+                const int32_t y = ar[e];
+                lb[e] = oy[y];
+                ln[e] = oy[y + 1] - oy[y];
+            });
+        }
+        int64_t *eo = eoff.get();
+        scan_exclusive(c, n_r2, ArrayGet{ln}, ArrayPut{eo}, eo + n_r2);
+        JP_HIP(hipMemcpyAsync(S + 15, eo + n_r2, sizeof(int64_t), hipMemcpyDeviceToDevice, c.stream));
     }
     // heavy witness count J_H and the heavy matrices
     DBuf<int8_t> M1, M2t;
@@ -524,6 +563,10 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     st.J_L = J_L;
     st.J_H = J_H;
     JP_CHECK(J_L + J_H == J, JP_EINTERNAL, "light and heavy witnesses do not add up to the join size");
+    check_monotone(c, "eoff", eoff.get(), n_r2 + 1, 0, J_L);
+    dump(c, "eoff", eoff.get(), n_r2 + 1);
+    dump(c, "lbase", lbase.get(), n_r2);
+    check_index("before expansion");
     const int ev_plan = tl.mark();
 
     // ---- candidates: light witnesses + heavy nonzeros ---------------------------------
@@ -538,13 +581,9 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         a.n_e = n_r2;
         a.J_L = J_L;
         a.r_xr = r_xr.get();
-        a.adj_r = adj_r.get();
-        a.off_y = off_y.get();
-        a.adj_s = adj_s.get();
-        a.hx_of_x = has_heavy ? hx_of_x.get() : nullptr;
-        a.hy_of_y = has_heavy ? hy_of_y.get() : nullptr;
-        a.lz_off = has_heavy ? lz_off.get() : nullptr;
-        a.lz_adj = has_heavy ? lz_adj.get() : nullptr;
+        a.lbase = lbase.get();
+        a.zlist = zlist;
+        a.zlist_n = zlist_n;
         a.bz = bz;
         a.out = cand.get();
         a.err = S + 19;
@@ -555,7 +594,9 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         JP_HIP(hipGetLastError());
     }
     const int ev_light = tl.mark();
-    if (J_L > 0) JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside its list");
+    if (J_L > 0) JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside the witness lists");
+    dump(c, "light keys", cand.get(), J_L);
+    check_range(c, "light keys", cand.get(), J_L, 0, (int64_t)1 << std::min(62, bx + bz));
     int64_t nnz = 0;
     int ev_bmm0 = ev_light, ev_bmm1 = ev_light;
     if (has_heavy) {
@@ -565,6 +606,8 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         ev_bmm1 = tl.mark();
         nnz = c.load(S + 17);
         JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
+        dump(c, "heavy keys", cand.get() + J_L, nnz);
+        dump(c, "light keys after product", cand.get(), J_L);
         st.bmm = JP_BMM_I8_MFMA;
         st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
     }
@@ -584,15 +627,22 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         const int32_t *xo = xorig.get(), *zo = zorig.get();
         const uint64_t zm = (1ull << bz) - 1;
         const int bzs = bz;
+        const uint64_t nx = (uint64_t)dom_x, nz = (uint64_t)dom_z;
+        int64_t *err = S + 20;
+        c.zero(err, 1);
         compact(
             c, total, [=] __device__(int64_t i) { return i == 0 || sorted[i] != sorted[i - 1]; },
             [=] __device__(int64_t i, int64_t p) {
                 const uint64_t k = sorted[i];
-                ox[p] = xo[k >> bzs];
-                oz[p] = zo[k & zm];
+                const uint64_t xi = k >> bzs, zi = k & zm;
+                const bool ok = (xi < nx) & (zi < nz);
+                if (!ok) *err = 1;
+                ox[p] = xo[ok ? xi : 0];
+                oz[p] = zo[ok ? zi : 0];
             },
             S + 18);
     }
+    JP_CHECK(c.load(S + 20) == 0, JP_EINTERNAL, "output key outside the rank tables");
     res->n = c.load(S + 18);
     st.n_out = res->n;
     const int ev_end = tl.mark();

@@ -4,6 +4,9 @@ import sys
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# Parity tests run the library with its stage-by-stage index validation on:
+# an inconsistent intermediate array becomes an error, not a bad access.
+os.environ.setdefault("JP_CHECKS", "1")
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 

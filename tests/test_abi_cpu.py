@@ -10,12 +10,12 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "jp.h")
+HEADERS = [os.path.join(ROOT, "include", "jp.h"), os.path.join(ROOT, "include", "jp_testing.h")]
 LIB = os.path.join(ROOT, "paper_2002_12459_amd", "libjoinproject.so")
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "\n".join(open(p).read() for p in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(jp_[a-z_0-9]+)\s*\(", text, flags=re.M)
     return sorted(set(names))
