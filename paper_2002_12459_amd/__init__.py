@@ -180,7 +180,7 @@ class Handle:
     def _options(self, delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed):
         o = Options()
         _load().jp_default_options(ctypes.byref(o))
-        if delta1 is not None or delta2 is not None:
+        if delta1 is not None or delta2 is not None or strategy == "fixed":
             if strategy in (None, "auto"):
                 strategy = "fixed"
             o.delta1 = DELTA_INF if delta1 is None else int(delta1)

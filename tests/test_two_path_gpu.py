@@ -132,7 +132,9 @@ def test_zipf_scaled(jp, scale):
 
 def test_communities_dense_heavy(jp):
     """Dense communities: the heavy product carries most of the output."""
-    x, y = datagen.communities(4, 300, 150, 0.2, seed=5)
+    # p = 0.5 over 150 y per community: two x of a community miss a common y
+    # with probability 0.75^150 (about 1e-19), so every in-community pair is out.
+    x, y = datagen.communities(4, 300, 150, 0.5, seed=5)
     st = check_equal(jp, x, y, x, y, delta1=10, delta2=10)
     assert st["nnz_heavy"] > 0 and st["n_out"] == 4 * 300 * 300
 
