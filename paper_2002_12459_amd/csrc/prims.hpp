@@ -209,33 +209,45 @@ constexpr int kRsBlock = 256;
 constexpr int kRsItems = 16;
 constexpr int64_t kRsTile = kRsBlock * kRsItems;
 
-// Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Each thread
-// walks 16 consecutive keys and flushes runs of equal digits, which keeps the
-// LDS atomics cheap when digits repeat.
+// Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Keys are
+// read coalesced (each wave takes 64 consecutive keys per step); lanes of a
+// wave holding the same digit are matched by ballots and their leader adds
+// the group size to the wave's private histogram, so skewed digits cost no
+// atomic contention.
 template <class K>
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, int shift, uint32_t *counts,
                                                       int64_t ntiles) {
-    __shared__ uint32_t h[256];
-    for (int d = threadIdx.x; d < 256; d += kRsBlock) h[d] = 0;
+    constexpr int W = kRsBlock / kWave;
+    __shared__ uint32_t h[W][256];
+    for (int d = threadIdx.x; d < 256; d += kRsBlock)
+#pragma unroll
+        for (int q = 0; q < W; ++q) h[q][d] = 0;
     __syncthreads();
     const int64_t tile = blockIdx.x;
-    const int64_t base = tile * kRsTile + (int64_t)threadIdx.x * kRsItems;
-    uint32_t cur = 0, run = 0;
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t wbase = tile * kRsTile + (int64_t)w * kWave * kRsItems;
+    K k[kRsItems];
+#pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
-        int64_t i = base + j;
-        if (i < n) {
-            uint32_t d = (uint32_t)(keys[i] >> shift) & 255u;
-            if (run && d != cur) {
-                atomicAdd(&h[cur], run);
-                run = 0;
-            }
-            cur = d;
-            ++run;
-        }
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        k[j] = i < n ? keys[i] : K(0);
     }
-    if (run) atomicAdd(&h[cur], run);
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        const bool valid = i < n;
+        const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
+        const uint64_t peers = match_digit<8>(d, ballot(valid));
+        const int leader = peers ? (int)(__ffsll((unsigned long long)peers) - 1) : 0;
+        if (valid && lane == leader) h[w][d] += (uint32_t)__popcll(peers);
+    }
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kRsBlock) counts[(int64_t)d * ntiles + tile] = h[d];
+    for (int d = threadIdx.x; d < 256; d += kRsBlock) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int q = 0; q < W; ++q) t += h[q][d];
+        counts[(int64_t)d * ntiles + tile] = t;
+    }
 }
 
 template <class K>

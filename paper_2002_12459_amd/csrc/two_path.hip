@@ -172,22 +172,36 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             c, ns, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
             [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 1);
     }
-    // ---- distinct y of R (sorted) --------------------------------------------
-    DBuf<uint32_t> YR = c.buf<uint32_t>(nr);
+    // ---- distinct y of R with their R degrees (sorted y of the distinct R) -----
+    int64_t h2[2];
+    c.load_n(h2, S, 2);
+    const int64_t n_r1 = h2[0], n_s1 = h2[1];
+    DBuf<uint32_t> YR = c.buf<uint32_t>(n_r1);
+    DBuf<int64_t> rstart = c.buf<int64_t>(n_r1 + 1);
     {
-        DBuf<uint32_t> ya = c.buf<uint32_t>(nr), yb2 = c.buf<uint32_t>(nr);
+        DBuf<uint32_t> ya = c.buf<uint32_t>(n_r1), yb2 = c.buf<uint32_t>(n_r1);
         uint32_t *k = ya.get();
-        for_each(c, nr, [=] __device__(int64_t i) { k[i] = (uint32_t)((int64_t)ry[i] - ymin); });
-        const uint32_t *s = radix_sort(c, ya.get(), yb2.get(), nr, yb);
+        const uint64_t *r = r1.get();
+        const uint64_t ym = ymask;
+        for_each(c, n_r1, [=] __device__(int64_t i) { k[i] = (uint32_t)(r[i] & ym); });
+        const uint32_t *s = radix_sort(c, ya.get(), yb2.get(), n_r1, yb);
         uint32_t *d = YR.get();
+        int64_t *rs = rstart.get();
         compact(
-            c, nr, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 2);
+            c, n_r1, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
+            [=] __device__(int64_t i, int64_t p) {
+                d[p] = s[i];
+                rs[p] = i;
+            },
+            S + 2);
+    }
+    const int64_t ny_r = c.load(S + 2);
+    {
+        int64_t *rs = rstart.get();
+        const int64_t nyr = ny_r, nr1 = n_r1;
+        for_each(c, 1, [=] __device__(int64_t) { rs[nyr] = nr1; });
     }
     // ---- distinct y of S (from the y-major S) --------------------------------
-    int64_t h4[4];
-    c.load_n(h4, S, 4);
-    const int64_t n_r1 = h4[0], n_s1 = h4[1], ny_r = h4[2];
     DBuf<uint32_t> YS = c.buf<uint32_t>(n_s1);
     {
         const uint64_t *s = s1.get();
@@ -199,22 +213,30 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     }
     const int64_t ny_s = c.load(S + 3);
 
-    // ---- semijoin: keep y present in both; dense y ranks ---------------------
+    // ---- semijoin: keep y present in both; dense y ranks; R degree of y -------
     DBuf<int32_t> yrank_js = c.buf<int32_t>(ny_s);
+    DBuf<int32_t> dRy = c.buf<int32_t>(ny_s);
     {
-        int32_t *yr = yrank_js.get();
+        int32_t *yr = yrank_js.get(), *dr = dRy.get();
         const uint32_t *ys = YS.get(), *yrr = YR.get();
+        const int64_t *rs = rstart.get();
         const int64_t nyr = ny_r;
         for_each(c, ny_s, [=] __device__(int64_t j) { yr[j] = -1; });
+        auto pos = [=] __device__(int64_t j) -> int64_t {
+            const int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
+            const int64_t q = p < nyr ? p : nyr - 1;
+            return ((p < nyr) & (yrr[q] == ys[j])) ? q : -1;
+        };
         compact(
-            c, ny_s,
-            [=] __device__(int64_t j) {
-                const int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
-                const int64_t q = p < nyr ? p : nyr - 1;
-                return (p < nyr) & (yrr[q] == ys[j]);
+            c, ny_s, [=] __device__(int64_t j) { return pos(j) >= 0; },
+            [=] __device__(int64_t j, int64_t p) {
+                const int64_t q = pos(j);
+                yr[j] = (int32_t)p;
+                dr[p] = (int32_t)(rs[q + 1] - rs[q]);
             },
-            [=] __device__(int64_t j, int64_t p) { yr[j] = (int32_t)p; }, S + 4);
+            S + 4);
     }
+    rstart.reset();
     // S tuples kept, y-major: y rank + z offset
     DBuf<int32_t> s2_y = c.buf<int32_t>(n_s1);
     DBuf<uint32_t> s2_z = c.buf<uint32_t>(n_s1);
@@ -276,14 +298,20 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
 
     // ---- z ranks ---------------------------------------------------------------
     DBuf<uint32_t> ZS = c.buf<uint32_t>(n_s2);
+    DBuf<int64_t> zstart = c.buf<int64_t>(n_s2 + 1);
     {
         DBuf<uint32_t> za = c.buf<uint32_t>(n_s2), zb2 = c.buf<uint32_t>(n_s2);
         JP_HIP(hipMemcpyAsync(za.get(), s2_z.get(), n_s2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
         const uint32_t *s = radix_sort(c, za.get(), zb2.get(), n_s2, zb);
         uint32_t *d = ZS.get();
+        int64_t *zs0 = zstart.get();
         compact(
             c, n_s2, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 7);
+            [=] __device__(int64_t i, int64_t p) {
+                d[p] = s[i];
+                zs0[p] = i;
+            },
+            S + 7);
     }
     // ---- x ranks and the x-major CSR of R -----------------------------------------
     DBuf<int32_t> xorig = c.buf<int32_t>(n_r2);
@@ -337,20 +365,20 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     }
     ZS.reset();
     s2_z.reset();
-    // ---- degrees and the full join size J -----------------------------------------
-    DBuf<int32_t> dRy = c.buf<int32_t>(dom_y), dSz = c.buf<int32_t>(dom_z);
-    c.zero(dRy.get(), dom_y);
-    c.zero(dSz.get(), dom_z);
+    // ---- degrees (run lengths of the sorts above) and the full join size J ------
+    DBuf<int32_t> dSz = c.buf<int32_t>(dom_z);
     {
-        int32_t *d1 = dRy.get(), *d2 = dSz.get();
-        const int32_t *ar = adj_r.get(), *as = adj_s.get();
-        for_each(c, n_r2, [=] __device__(int64_t e) { atomicAdd(&d1[ar[e]], 1); });
-        for_each(c, n_s2, [=] __device__(int64_t e) { atomicAdd(&d2[as[e]], 1); });
+        int32_t *d2 = dSz.get();
+        const int64_t *zs0 = zstart.get();
+        const int64_t nz = dom_z, ns2 = n_s2;
+        for_each(c, dom_z, [=] __device__(int64_t r) { d2[r] = (int32_t)((r + 1 < nz ? zs0[r + 1] : ns2) - zs0[r]); });
+        const int32_t *d1 = dRy.get();
         const int64_t *oy = off_y.get();
         reduce_sum(
             c, dom_y, [=] __device__(int64_t y) -> int64_t { return (int64_t)d1[y] * (oy[y + 1] - oy[y]); },
             (unsigned long long *)(S + 10));
     }
+    zstart.reset();
     const int64_t J = c.load(S + 10);
     const int ev_ingest = tl.mark();
     auto check_index = [&](const char *when) {
