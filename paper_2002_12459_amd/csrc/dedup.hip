@@ -17,12 +17,10 @@
 //    window's part of every sorted list, marks it in an LDS bitmap and reads
 //    the set bits back in z order.
 //
-// One kernel handles all units.  Workgroups take units in order from a ticket
-// counter; a unit publishes its distinct count, finds its output offset by
-// looking back over its predecessors' published counts (every predecessor
-// already holds a ticket and never waits on a later unit, so the wait ends;
-// it is also bounded), and writes its (x, z) pairs, unranked, straight into
-// the output columns.
+// One kernel handles all units.  A unit writes its distinct (x, z) pairs,
+// unranked, to a staging array at its candidate offset (an upper bound of its
+// output offset, so units never wait on each other); a scan of the per-unit
+// counts gives output offsets and a load-balanced copy packs the output.
 #include "debug.hpp"
 #include "pipeline.hpp"
 #include "prims.hpp"
@@ -70,74 +68,52 @@ struct DedupArgs {
     uint32_t zmask;
     int64_t dom_x, dom_z;
     const int32_t *xorig, *zorig;
-    int32_t *out_x, *out_z;
-    int64_t cap;                     // capacity of the output columns
-    unsigned long long *status;      // look-back slots, one per unit, zeroed
-    unsigned int *ticket;            // unit ticket counter, zeroed
-    int64_t *total;                  // distinct pairs overall
+    int2 *stage;             // distinct (x, z) of every unit, at ubase[u]
+    int64_t *ucount;         // distinct pairs of every unit
+    int64_t *ubase;          // where the unit's pairs start in stage
     int64_t *err;
+    unsigned long long *clk; // optional per-phase cycle totals (JP_PHASE_CLOCKS)
 };
 
-constexpr unsigned long long kAgg = 1ull << 62, kPre = 2ull << 62, kValMask = (1ull << 62) - 1;
-
-__device__ __forceinline__ unsigned long long ld_status(const unsigned long long *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_status(unsigned long long *p, unsigned long long v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Executed by the first wave.  Returns the number of outputs of all earlier
-// units and publishes this unit's inclusive count.
-__device__ int64_t look_back(const DedupArgs &a, int64_t u, int64_t agg) {
-    const int lane = lane_id();
-    if (u == 0) {
-        if (lane == 0) st_status(&a.status[0], kPre | (unsigned long long)agg);
-        return 0;
-    }
-    if (lane == 0) st_status(&a.status[u], kAgg | (unsigned long long)agg);
-    int64_t excl = 0;
-    int64_t top = u - 1;
-    int spins = 0;
-    while (top >= 0) {
-        const int64_t idx = top - lane;
-        const unsigned long long s = idx >= 0 ? ld_status(&a.status[idx]) : kPre;
-        const unsigned long long flag = s & ~kValMask;
-        const uint64_t pre = ballot(flag == kPre);
-        const uint64_t notready = ballot(flag == 0);
-        const int first = pre ? (int)(__ffsll((unsigned long long)pre) - 1) : kWave;
-        const uint64_t need = first < kWave ? ((first == 63) ? ~0ull : ((2ull << first) - 1)) : ~0ull;
-        if (notready & need) {
-            if (++spins > (1 << 22)) {  // bounded: report and continue with what is known
-                if (lane == 0) *a.err = 2;
-                break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-            continue;
+// Phase clock: thread 0 adds the cycles since the last mark to clk[phase].
+struct PhaseClock {
+    unsigned long long *clk;
+    long long t;
+    __device__ explicit PhaseClock(unsigned long long *c) : clk(c), t(clock64()) {}
+    __device__ void mark(int phase) {
+        if (clk && threadIdx.x == 0) {
+            const long long now = clock64();
+            atomicAdd(&clk[phase], (unsigned long long)(now - t));
+            t = now;
         }
-        const int64_t v = (lane <= first) ? (int64_t)(s & kValMask) : 0;
-        excl += wave_sum(v);
-        if (first < kWave) break;
-        top -= kWave;
     }
-    if (lane == 0) st_status(&a.status[u], kPre | (unsigned long long)(excl + agg));
-    return excl;
+};
+enum { kPhGather, kPhSort, kPhUnique, kPhWritePacked, kPhLists, kPhWriteWin, kPhUnitsPacked, kPhUnitsWin,
+       kPhCount };
+
+// LDS layouts padded against bank conflicts: key slot i and counter word w.
+__device__ __forceinline__ int kpad(int i) { return i + (i >> 5); }
+__device__ __forceinline__ int cpad(int w) { return w + (w >> 4); }
+constexpr int kSkWords = kDCap + kDCap / 32;
+constexpr int kCntWords = kRD * kDT / 2;
+constexpr int kCntPadded = kCntWords + kCntWords / 16;
+constexpr int kMaxStagedEdges = 1024;  // R tuples of a packed unit staged in LDS for the gather
+static_assert(4 * (kMaxStagedEdges + 2) + 12 * kMaxStagedEdges <= 4 * kCntPadded, "staging fits the counters");
+
+__device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
+    const int ci = d * kDT + t;
+    return reinterpret_cast<uint16_t *>(cnt)[2 * cpad(ci >> 1) + (ci & 1)];
 }
 
 __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
-    __shared__ uint32_t sk[kDCap];           // keys, then distinct keys; or the window bitmap
-    __shared__ uint32_t cnt[kRD * kDT / 2];  // packed 16-bit digit counters [digit][thread]
+    __shared__ uint32_t sk[kSkWords];     // keys, then distinct keys; or the window bitmap
+    __shared__ __attribute__((aligned(8))) uint32_t cnt[kCntPadded];  // digit counters; before that, staged tuples
     __shared__ uint32_t lds_scan[kDT / kWave + 1];
     __shared__ int64_t lds_scan64[kDT / kWave + 1];
-    __shared__ int64_t sh[4];
-    __shared__ int64_t lpre[kListChunk + 1];  // window units: list prefix counts
-    __shared__ int64_t lbeg[kListChunk];      // window units: list sub-range starts
 
     const int tid = threadIdx.x;
-    if (tid == 0) sh[0] = (int64_t)atomicAdd(a.ticket, 1u);
-    __syncthreads();
-    const int64_t u = sh[0];
-    if (u >= a.n_units) return;
+    PhaseClock pc(a.clk);
+    const int64_t u = blockIdx.x;
     const int32_t xa = a.ustart[u];
     const int32_t win = a.uwin[u];
 
@@ -152,32 +128,54 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         const bool over = n > kDCap;
         if (over && tid == 0) *a.err = 1;
         const int nn = over ? 0 : (int)n;
-        const int64_t nLc = over ? 0 : nL;
+        const int nLc = over ? 0 : (int)nL;
+
+        // stage the unit's R tuples (offsets relative to the unit, list
+        // starts, local x) in LDS when they fit
+        const int64_t ne = e1 - e0;
+        const bool staged = ne <= kMaxStagedEdges;
+        int64_t *slb = reinterpret_cast<int64_t *>(cnt);               // ne
+        int32_t *seo = reinterpret_cast<int32_t *>(slb + kMaxStagedEdges);  // ne + 1
+        int32_t *sxl = seo + kMaxStagedEdges + 2;                          // ne
+        if (staged) {
+            for (int i = tid; i <= ne; i += kDT) seo[i] = (int32_t)(a.eoff[e0 + i] - c0);
+            for (int i = tid; i < ne; i += kDT) {
+                slb[i] = a.lbase[e0 + i];
+                sxl[i] = a.r_xr[e0 + i] - xa;
+            }
+        }
+        __syncthreads();
 
         // gather candidates [tid*kDI, tid*kDI + kDI): one search, then a walk
         uint32_t k[kDI];
         {
             const int p0 = tid * kDI;
-            int64_t e = e0;
-            if (p0 < nLc) e = upper_bound_dev(a.eoff, e0, e1, c0 + p0) - 1;
-            int64_t eo = a.eoff[e];
-            int64_t enext = a.eoff[e + 1];
-            int64_t lb = p0 < nLc ? a.lbase[e] : 0;
-            uint32_t xl = p0 < nLc ? (uint32_t)(a.r_xr[e] - xa) << a.bz : 0u;
+            int64_t e = 0;  // relative to e0
+            if (p0 < nLc)
+                e = staged ? upper_bound_dev(seo, (int64_t)0, ne, (int32_t)p0) - 1
+                           : upper_bound_dev(a.eoff, e0, e1, c0 + p0) - 1 - e0;
+            int32_t eo = 0, enext = 0;
+            int64_t lb = 0;
+            uint32_t xl = 0;
+            if (p0 < nLc) {
+                eo = staged ? seo[e] : (int32_t)(a.eoff[e0 + e] - c0);
+                enext = staged ? seo[e + 1] : (int32_t)(a.eoff[e0 + e + 1] - c0);
+                lb = staged ? slb[e] : a.lbase[e0 + e];
+                xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
+            }
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = p0 + j;
                 uint32_t key = 0xffffffffu;
                 if (p < nLc) {
-                    const int64_t q = c0 + p;
-                    while (q >= enext) {  // next R tuple with a nonempty list
+                    while (p >= enext) {  // next R tuple with a nonempty list
                         ++e;
                         eo = enext;
-                        enext = a.eoff[e + 1];
-                        lb = a.lbase[e];
-                        xl = (uint32_t)(a.r_xr[e] - xa) << a.bz;
+                        enext = staged ? seo[e + 1] : (int32_t)(a.eoff[e0 + e + 1] - c0);
+                        lb = staged ? slb[e] : a.lbase[e0 + e];
+                        xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
                     }
-                    key = xl | (uint32_t)a.zlist[lb + (q - eo)];
+                    key = xl | (uint32_t)a.zlist[lb + (p - eo)];
                 } else if (p < nn) {
                     const uint64_t hk = a.hkeys[h0 + (p - nL)];
                     key = ((uint32_t)((int64_t)(hk >> a.bz) - xa) << a.bz) | ((uint32_t)hk & a.zmask);
@@ -185,67 +183,70 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
                 k[j] = key;
             }
         }
+        __syncthreads();  // staged tuple data is overwritten by the counters below
+        pc.mark(kPhGather);
 
         // LSD radix sort: 5-bit digits over the significant bits
         const int xbits = (xb - xa - 1) > 0 ? 32 - __clz((uint32_t)(xb - xa - 1)) : 0;
         const int B = xbits + a.bz > 0 ? xbits + a.bz : 1;
         const int passes = (B + kRB - 1) / kRB;
-        uint16_t *c16 = reinterpret_cast<uint16_t *>(cnt);
         for (int pass = 0; pass < passes; ++pass) {
             const int shift = pass * kRB;
-            for (int i = tid; i < kRD * kDT / 2; i += kDT) cnt[i] = 0;
+            for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
             __syncthreads();
             uint16_t loc[kDI];
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = tid * kDI + j;
-                const uint32_t d = (k[j] >> shift) & (kRD - 1);
-                const int ci = (int)d * kDT + tid;
-                const uint16_t c = c16[ci];
-                loc[j] = c;
-                if (p < nn) c16[ci] = (uint16_t)(c + 1);
+                const int d = (int)((k[j] >> shift) & (kRD - 1));
+                uint16_t &c = ctr(cnt, d, tid);
+                const uint16_t v = c;
+                loc[j] = v;
+                if (p < nn) c = (uint16_t)(v + 1);
             }
             __syncthreads();
             // raking exclusive scan over [digit][thread]: thread t owns `per`
-            // consecutive words (two 16-bit counters each)
-            constexpr int per = kRD * kDT / 2 / kDT;
+            // consecutive counter words (two 16-bit counters each)
+            constexpr int per = kCntWords / kDT;
             uint32_t s = 0;
 #pragma unroll
             for (int i = 0; i < per; ++i) {
-                const uint32_t wv = cnt[tid * per + i];
+                const uint32_t wv = cnt[cpad(tid * per + i)];
                 s += (wv & 0xffffu) + (wv >> 16);
             }
             uint32_t all;
             uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
 #pragma unroll
             for (int i = 0; i < per; ++i) {
-                const uint32_t wv = cnt[tid * per + i];
+                const int wi = cpad(tid * per + i);
+                const uint32_t wv = cnt[wi];
                 const uint32_t lo = wv & 0xffffu, hi = wv >> 16;
-                const uint32_t p0 = run, p1 = run + lo;
+                const uint32_t q0 = run, q1 = run + lo;
                 run += lo + hi;
-                cnt[tid * per + i] = (p0 & 0xffffu) | (p1 << 16);
+                cnt[wi] = (q0 & 0xffffu) | (q1 << 16);
             }
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = tid * kDI + j;
                 if (p < nn) {
-                    const uint32_t d = (k[j] >> shift) & (kRD - 1);
-                    const uint32_t dst = (uint32_t)c16[(int)d * kDT + tid] + loc[j];
-                    sk[dst < (uint32_t)kDCap ? dst : 0] = k[j];
+                    const int d = (int)((k[j] >> shift) & (kRD - 1));
+                    const uint32_t dst = (uint32_t)ctr(cnt, d, tid) + loc[j];
+                    sk[kpad(dst < (uint32_t)kDCap ? (int)dst : 0)] = k[j];
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = tid * kDI + j;
-                k[j] = p < nn ? sk[p] : 0xffffffffu;
+                k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
             }
             __syncthreads();
         }
+        pc.mark(kPhSort);
         // first of every run of equal keys, compacted into sk in order
         uint32_t flags = 0, mine = 0;
-        uint32_t prev = (tid > 0 && tid * kDI - 1 < nn) ? sk[tid * kDI - 1] : 0u;
+        uint32_t prev = (tid > 0 && tid * kDI - 1 < nn) ? sk[kpad(tid * kDI - 1)] : 0u;
 #pragma unroll
         for (int j = 0; j < kDI; ++j) {
             const int p = tid * kDI + j;
@@ -258,25 +259,23 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         uint32_t pos = block_excl_scan<kDT>(mine, lds_scan, &d_all);
 #pragma unroll
         for (int j = 0; j < kDI; ++j)
-            if ((flags >> j) & 1u) sk[pos++] = k[j];
-        if (tid < kWave) {
-            const int64_t ex = look_back(a, u, (int64_t)d_all);
-            if (tid == 0) sh[1] = ex;
-        }
+            if ((flags >> j) & 1u) sk[kpad((int)pos++)] = k[j];
         __syncthreads();
-        const int64_t base = sh[1];
-        if (u == a.n_units - 1 && tid == 0) *a.total = base + d_all;
+        pc.mark(kPhUnique);
+        const int64_t base = a.toff[xa];
         for (uint32_t i = tid; i < d_all; i += kDT) {
-            const uint32_t key = sk[i];
-            const int64_t o = base + i;
+            const uint32_t key = sk[kpad((int)i)];
             const int64_t xi = (int64_t)xa + (key >> a.bz), zi = key & a.zmask;
-            const bool ok = (o < a.cap) & (xi < a.dom_x) & (zi < a.dom_z);
+            const bool ok = (xi < a.dom_x) & (zi < a.dom_z);
             if (!ok) *a.err = 3;
-            if (o < a.cap) {
-                a.out_x[o] = a.xorig[ok ? xi : 0];
-                a.out_z[o] = a.zorig[ok ? zi : 0];
-            }
+            a.stage[base + i] = make_int2(a.xorig[ok ? xi : 0], a.zorig[ok ? zi : 0]);
         }
+        if (tid == 0) {
+            a.ucount[u] = d_all;
+            a.ubase[u] = base;
+        }
+        pc.mark(kPhWritePacked);
+        if (a.clk && tid == 0) atomicAdd(&a.clk[kPhUnitsPacked], 1ull);
         return;
     }
 
@@ -290,12 +289,16 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
     const int64_t wbits = zhi > zlo ? zhi - zlo : 0;  // <= kWinBits
     const int nwords = (int)cdiv(wbits, 32);
     for (int i = tid; i < nwords; i += kDT) sk[i] = 0;
+    int64_t *lpre = reinterpret_cast<int64_t *>(cnt);  // kListChunk + 1
+    int64_t *lbeg = lpre + kListChunk + 1;             // kListChunk
     __syncthreads();
     const int64_t e0 = a.off_x[x], e1 = a.off_x[x + 1];
-    // lists of x in chunks of kListChunk; the heavy nonzeros of x are one more list
+    // lists of x in chunks of kListChunk; the heavy nonzeros of x are one more
+    // list.  `before` counts the candidates of x below zlo (stage offset).
     const int64_t nlists = (e1 - e0) + 1;
+    int64_t before = 0;
     for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
-        int64_t b = 0, len = 0;
+        int64_t b = 0, len = 0, skipped = 0;
         const int64_t l = l0 + tid;
         if (l < nlists) {
             if (l < e1 - e0) {
@@ -307,6 +310,7 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
                 const int64_t s1 = lower_bound_dev(L, s0, ln, (int32_t)zhi);
                 b = lb + s0;
                 len = s1 - s0;
+                skipped = s0;
             } else {
                 const int64_t h0 = a.hoff[x], h1 = a.hoff[x + 1];
                 const uint64_t kx = (uint64_t)x << a.bz;
@@ -314,9 +318,12 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
                 const int64_t s1 = lower_bound_dev(a.hkeys, s0, h1, kx | (uint64_t)zhi);
                 b = -1 - s0;  // negative: heavy keys starting at s0
                 len = s1 - s0;
+                skipped = s0 - h0;
             }
         }
-        int64_t tot;
+        int64_t tot, sk_tot;
+        (void)block_excl_scan<kDT>(skipped, lds_scan64, &sk_tot);
+        before += sk_tot;
         const int64_t pre = block_excl_scan<kDT>(len, lds_scan64, &tot);
         lpre[tid] = pre;
         lbeg[tid] = b;
@@ -334,37 +341,58 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         }
         __syncthreads();
     }
-    // distinct count, offset, then set bits in z order: rounds of kDT words
+    pc.mark(kPhLists);
+    // set bits in z order: thread t owns a contiguous run of words
+    const int per = (nwords + kDT - 1) / kDT;
+    const int w0 = tid * per;
+    const int w1 = w0 + per < nwords ? w0 + per : nwords;
     uint32_t c = 0;
-    for (int i = tid; i < nwords; i += kDT) c += __popc(sk[i]);
+    for (int i = w0; i < w1; ++i) c += __popc(sk[i]);
     uint32_t d_all;
-    (void)block_excl_scan<kDT>(c, lds_scan, &d_all);
-    if (tid < kWave) {
-        const int64_t ex = look_back(a, u, (int64_t)d_all);
-        if (tid == 0) sh[1] = ex;
-    }
-    __syncthreads();
-    int64_t base = sh[1];
-    if (u == a.n_units - 1 && tid == 0) *a.total = base + d_all;
+    uint32_t pos = block_excl_scan<kDT>(c, lds_scan, &d_all);
+    const int64_t base = a.toff[x] + before;
     const int32_t xo = a.xorig[x < a.dom_x ? x : 0];
-    for (int r0 = 0; r0 < nwords; r0 += kDT) {
-        const int i = r0 + tid;
-        uint32_t word = i < nwords ? sk[i] : 0u;
-        uint32_t rt;
-        int64_t o = base + block_excl_scan<kDT>((uint32_t)__popc(word), lds_scan, &rt);
+    for (int i = w0; i < w1; ++i) {
+        uint32_t word = sk[i];
         while (word) {
             const int bit = __ffs(word) - 1;
             word &= word - 1;
             const int64_t zi = zlo + (int64_t)i * 32 + bit;
-            if (o < a.cap) {
-                a.out_x[o] = xo;
-                a.out_z[o] = a.zorig[zi < a.dom_z ? zi : 0];
-            } else {
-                *a.err = 3;
-            }
-            ++o;
+            a.stage[base + pos] = make_int2(xo, a.zorig[zi < a.dom_z ? zi : 0]);
+            ++pos;
         }
-        base += rt;
+    }
+    if (tid == 0) {
+        a.ucount[u] = d_all;
+        a.ubase[u] = base;
+    }
+    pc.mark(kPhWriteWin);
+    if (a.clk && tid == 0) atomicAdd(&a.clk[kPhUnitsWin], 1ull);
+}
+
+// Copies every unit's pairs from the stage to its output offset.
+struct CopyArgs {
+    const int64_t *uoff;  // output offset of every unit (n_units + 1)
+    const int64_t *ubase;
+    int64_t n_units, n_out;
+    const int2 *stage;
+    int32_t *out_x, *out_z;
+};
+constexpr int kCopyBlock = 256, kCopyItems = 16;
+__global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
+    const int64_t o0 = (int64_t)blockIdx.x * kCopyBlock * kCopyItems;
+    const int64_t olast = std::min<int64_t>(o0 + kCopyBlock * kCopyItems, a.n_out) - 1;
+    const int64_t lo = upper_bound_dev(a.uoff, (int64_t)0, a.n_units, o0) - 1;
+    const int64_t hi = upper_bound_dev(a.uoff, lo, a.n_units, olast);
+#pragma unroll 4
+    for (int j = 0; j < kCopyItems; ++j) {
+        const int64_t o = o0 + (int64_t)j * kCopyBlock + threadIdx.x;
+        if (o <= olast) {
+            const int64_t uu = upper_bound_dev(a.uoff, lo, hi, o) - 1;
+            const int2 v = a.stage[a.ubase[uu] + (o - a.uoff[uu])];
+            a.out_x[o] = v.x;
+            a.out_z[o] = v.y;
+        }
     }
 }
 
@@ -454,12 +482,8 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
     dump(c, "ustart", ustart.get(), n_units + 1);
     dump(c, "uwin", uwin.get(), n_units + 1);
 
-    *out_x = c.buf<int32_t>(std::max<int64_t>(n_cand, 1));
-    *out_z = c.buf<int32_t>(std::max<int64_t>(n_cand, 1));
-    DBuf<unsigned long long> status = c.buf<unsigned long long>(std::max<int64_t>(n_units, 1));
-    DBuf<unsigned int> ticket = c.buf<unsigned int>(1);
-    c.zero(status.get(), std::max<int64_t>(n_units, 1));
-    c.zero(ticket.get(), 1);
+    DBuf<int2> stage = c.buf<int2>(std::max<int64_t>(n_cand, 1));
+    DBuf<int64_t> ucount = c.buf<int64_t>(n_units + 1), ubase = c.buf<int64_t>(n_units + 1);
     if (n_units > 0) {
         JP_CHECK(n_units < (1ll << 31), JP_EINVAL, "too many dedup units for one launch");
         DedupArgs a;
@@ -480,22 +504,52 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         a.dom_z = dom_z;
         a.xorig = in.xorig;
         a.zorig = in.zorig;
-        a.out_x = out_x->get();
-        a.out_z = out_z->get();
-        a.cap = n_cand;
-        a.status = status.get();
-        a.ticket = ticket.get();
-        a.total = S + 0;
+        a.stage = stage.get();
+        a.ucount = ucount.get();
+        a.ubase = ubase.get();
         a.err = S + 1;
+        DBuf<unsigned long long> clk;
+        a.clk = nullptr;
+        if (std::getenv("JP_PHASE_CLOCKS")) {
+            clk = c.buf<unsigned long long>(kPhCount);
+            c.zero(clk.get(), kPhCount);
+            a.clk = clk.get();
+        }
         hipLaunchKernelGGL(k_dedup, dim3((unsigned)n_units), dim3(kDT), 0, c.stream, a);
         JP_HIP(hipGetLastError());
+        if (a.clk) {
+            unsigned long long hc[kPhCount];
+            c.load_n(hc, clk.get(), kPhCount);
+            static const char *nm[kPhCount] = {"gather", "sort", "unique", "write", "win.lists", "win.write",
+                                               "units.packed", "units.window"};
+            std::fprintf(stderr, "[jp] dedup phase cycles (thread 0, summed over units):");
+            for (int i = 0; i < kPhCount; ++i) std::fprintf(stderr, " %s=%llu", nm[i], hc[i]);
+            std::fprintf(stderr, "\n");
+        }
     }
+    DBuf<int64_t> uoff = c.buf<int64_t>(n_units + 1);
+    scan_exclusive(c, n_units, ArrayGet{ucount.get()}, ArrayPut{uoff.get()}, uoff.get() + n_units);
     int64_t h2[2];
     c.load_n(h2, S, 2);
     JP_CHECK(h2[1] != 1, JP_EINTERNAL, "a dedup unit exceeded its on-chip capacity");
-    JP_CHECK(h2[1] != 2, JP_EINTERNAL, "dedup look-back did not complete");
     JP_CHECK(h2[1] == 0, JP_EINTERNAL, "dedup produced a key outside the rank tables");
-    *n_out = h2[0];
+    const int64_t total = n_units > 0 ? c.load(uoff.get() + n_units) : 0;
+    *out_x = c.buf<int32_t>(std::max<int64_t>(total, 1));
+    *out_z = c.buf<int32_t>(std::max<int64_t>(total, 1));
+    if (total > 0) {
+        CopyArgs ca;
+        ca.uoff = uoff.get();
+        ca.ubase = ubase.get();
+        ca.n_units = n_units;
+        ca.n_out = total;
+        ca.stage = stage.get();
+        ca.out_x = out_x->get();
+        ca.out_z = out_z->get();
+        const int64_t blocks = ceil_div(total, (int64_t)kCopyBlock * kCopyItems);
+        hipLaunchKernelGGL(k_stage_copy, dim3((unsigned)blocks), dim3(kCopyBlock), 0, c.stream, ca);
+        JP_HIP(hipGetLastError());
+    }
+    *n_out = total;
     if (stats) {
         stats->n_units = n_units;
         stats->n_cand = n_cand;

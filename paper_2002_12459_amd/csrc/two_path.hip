@@ -29,6 +29,7 @@ namespace jp {
 namespace {
 
 __global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int *out) {
+    __shared__ int smn[256 / kWave], smx[256 / kWave];
     int mn = INT_MAX, mx = INT_MIN;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         int v = a[i];
@@ -41,7 +42,17 @@ __global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int
         mn = a2 < mn ? a2 : mn;
         mx = b2 > mx ? b2 : mx;
     }
+    const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
+        smn[w] = mn;
+        smx[w] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < 256 / kWave; ++i) {
+            mn = smn[i] < mn ? smn[i] : mn;
+            mx = smx[i] > mx ? smx[i] : mx;
+        }
         atomicMin(&out[0], mn);
         atomicMax(&out[1], mx);
     }
@@ -49,7 +60,7 @@ __global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int
 
 void minmax(const Ctx &c, const int32_t *a, int64_t n, int *out) {
     if (n <= 0) return;
-    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 4);
+    int64_t blocks = std::min<int64_t>(ceil_div(n, 256 * 16), (int64_t)c.num_cus);
     hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, c.stream, a, n, out);
     JP_HIP(hipGetLastError());
 }
