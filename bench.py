@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--scale", type=float, default=1.0, help="shrink the workload (testing only)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-bmm", action="store_true")
-    p.add_argument("--cpu-sample", type=float, default=0.1, help="fraction of x ids in the oracle sample")
+    p.add_argument("--cpu-sample", type=float, default=0.3, help="fraction of x ids in the oracle sample")
     return p.parse_args()
 
 
@@ -82,10 +82,45 @@ def main():
     dt = (time.perf_counter() - t0) / a.steps
     log(f"timed {a.steps} steps: {dt * 1e3:.2f} ms/step, |OUT|={n_out}")
 
-    # one more evaluation with per-phase device timing
+    # one more evaluation with per-phase / dominant-kernel device timing
     _, ph = step(timing=True)
     log("phases ms: " + ", ".join(f"{k[3:]}={ph[k]:.3f}" for k in ph if k.startswith("ms_")))
-    log(f"J={ph['J']} J_L={ph['J_L']} J_H={ph['J_H']} u={ph['u']} v={ph['v']} w={ph['w']}")
+    log(f"J={ph['J']} J_L={ph['J_L']} J_H={ph['J_H']} u={ph['u']} v={ph['v']} w={ph['w']} units={ph['dedup_units']}")
+    dom_ms = ph["ms_kernel_dedup"]
+    dom_bytes = ph["dedup_alg_bytes"]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
+    roofline = {"kernel": "k_dedup (per-x witness gather + on-chip sort/bitmap dedup)", "bound": "hbm",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "alg_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms}
+
+    # heavy product at forced thresholds (the cost model keeps this workload light)
+    bmm = None
+    if not a.no_bmm:
+        d1, d2 = 1000, 12
+        step(delta1=d1, delta2=d2)  # warm-up of the product kernel
+        nb, pb = step(delta1=d1, delta2=d2, timing=True)
+        if pb["ms_bmm"] > 0:
+            tops = pb["bmm_ops"] / (pb["ms_bmm"] * 1e-3) / 1e12
+            bmm = {"delta1": d1, "delta2": d2, "u": pb["u"], "v": pb["v"], "w": pb["w"],
+                   "nnz": pb["nnz_heavy"], "ms": pb["ms_bmm"], "tops": tops, "peak_tops": INT8_PEAK_TOPS,
+                   "frac": tops / INT8_PEAK_TOPS, "n_out": nb, "ms_total": pb["ms_total"]}
+            log(f"heavy product u={pb['u']} v={pb['v']} w={pb['w']}: {pb['ms_bmm']:.2f} ms, {tops:.1f} TOP/s")
+
+    # CPU oracle on a bounded sample of the same workload: R restricted to an
+    # x-id range (its outputs are exactly the outputs with x in that range)
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        lim = int(a.cpu_sample * max(int(1_000_000 * a.scale), 1))
+        m = rx < lim
+        t0 = time.perf_counter()
+        ox, oz = oracle.two_path(rx[m], ry[m], sz, sy)
+        tc = time.perf_counter() - t0
+        cpu = {"value": ox.size / tc, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "sample": f"R restricted to x < {lim} ({int(m.sum())} edges), all of S; "
+                         f"{ox.size} distinct pairs in {tc:.1f} s (full join, qsort, unique; one thread)"}
+        log(f"cpu oracle: {cpu['sample']}")
 
     out = {
         "metric": "distinct (x,z) output pairs/sec for two-path join-project, + heavy-BMM int8 TOPS",
@@ -103,6 +138,9 @@ def main():
         "config": {"workload": "two-path R(x,y),S(z,y): |R|=|S|=10M, 1M x/z ids, 200K y ids, Zipf(1.1) y, "
                                "cost-model thresholds" if a.scale == 1.0 else f"two-path scaled x{a.scale}",
                    "n_out": n_out, "J": ph["J"], "delta1": ph["delta1"], "delta2": ph["delta2"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "heavy_bmm": bmm,
         "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
     }
     print(json.dumps(out), flush=True)

@@ -121,6 +121,9 @@ typedef struct jp_stats {
     double ms_bmm;               /* the product kernel alone */
     double ms_dedup;             /* duplicate removal, union, output */
     double ms_total;             /* whole call, device time */
+    double ms_kernel_dedup;      /* per-x duplicate-removal kernel alone (segmented strategy) */
+    double dedup_alg_bytes;      /* its algorithmic HBM bytes: 4 per witness read + 8 per distinct pair written */
+    int64_t dedup_units;         /* on-chip units it processed */
 } jp_stats;
 
 typedef struct jp_handle jp_handle;

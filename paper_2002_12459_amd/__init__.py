@@ -50,7 +50,9 @@ class Stats(ctypes.Structure):
                [(n, ctypes.c_int32) for n in ("strategy", "bmm", "dedup", "arity")] + \
                [(n, ctypes.c_int64) for n in ("u", "v", "w", "J", "J_L", "J_H", "nnz_heavy", "n_out")] + \
                [(n, ctypes.c_double) for n in ("bmm_ops", "ms_ingest", "ms_plan", "ms_light", "ms_heavy",
-                                               "ms_bmm", "ms_dedup", "ms_total")]
+                                               "ms_bmm", "ms_dedup", "ms_total", "ms_kernel_dedup",
+                                               "dedup_alg_bytes")] + \
+               [("dedup_units", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
 bool segmented_dedup_fits(int bz) { return bz <= 26; }
 
 void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, DBuf<int32_t> *out_z,
-                     int64_t *n_out, SegDedupStats *stats) {
+                     int64_t *n_out, SegDedupStats *stats, bool timing) {
     JP_CHECK(segmented_dedup_fits(in.bz), JP_EINTERNAL, "segmented dedup needs bz <= 26");
     const int64_t dom_x = in.dom_x, dom_z = in.dom_z;
     DBuf<int64_t> scal = c.buf<int64_t>(8);
@@ -515,8 +515,12 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             c.zero(clk.get(), kPhCount);
             a.clk = clk.get();
         }
+        Timeline tk(c, timing);
+        const int k0 = tk.mark();
         hipLaunchKernelGGL(k_dedup, dim3((unsigned)n_units), dim3(kDT), 0, c.stream, a);
         JP_HIP(hipGetLastError());
+        const int k1 = tk.mark();
+        if (stats && timing) stats->ms_kernel = tk.ms(k0, k1);
         if (a.clk) {
             unsigned long long hc[kPhCount];
             c.load_n(hc, clk.get(), kPhCount);

@@ -20,6 +20,7 @@ struct SegDedupIn {
 
 struct SegDedupStats {
     int64_t n_units = 0, n_small = 0, n_big = 0, n_cand = 0;
+    double ms_kernel = 0;  // the dedup kernel alone (when timed)
 };
 
 // Whether z ranks of `bz` bits leave room for the local x index in 32 bits.
@@ -27,6 +28,6 @@ bool segmented_dedup_fits(int bz);
 
 // Sorted distinct (x, z) output (original ids) into out_x / out_z.
 void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, DBuf<int32_t> *out_z,
-                     int64_t *n_out, SegDedupStats *stats);
+                     int64_t *n_out, SegDedupStats *stats, bool timing = false);
 
 }  // namespace jp

@@ -653,8 +653,11 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         in.xorig = xorig.get();
         in.zorig = zorig.get();
         SegDedupStats sst;
-        segmented_dedup(c, in, &res->cols[0], &res->cols[1], &res->n, &sst);
+        segmented_dedup(c, in, &res->cols[0], &res->cols[1], &res->n, &sst, timing);
         st.n_out = res->n;
+        st.ms_kernel_dedup = sst.ms_kernel;
+        st.dedup_alg_bytes = 4.0 * (double)(J_L + nnz) + 8.0 * (double)res->n;
+        st.dedup_units = sst.n_units;
     } else {
         // ---- candidates: light witnesses + heavy nonzeros, one device-wide sort ------
         st.dedup = JP_DEDUP_GLOBAL;
