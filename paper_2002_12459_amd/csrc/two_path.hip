@@ -561,52 +561,35 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         scan_exclusive(c, n_r2, ArrayGet{ln}, ArrayPut{eo}, eo + n_r2);
         JP_HIP(hipMemcpyAsync(S + 15, eo + n_r2, sizeof(int64_t), hipMemcpyDeviceToDevice, c.stream));
     }
-    // heavy witness count J_H and the heavy matrices
+    // heavy matrices: M1 = heavy x by heavy y (R), M2^T = heavy z by heavy y (S)
     DBuf<int8_t> M1, M2t;
     int64_t ld = 0;
     if (has_heavy) {
-        DBuf<int64_t> hxc = c.buf<int64_t>(v), hzc = c.buf<int64_t>(v);
-        c.zero(hxc.get(), v);
-        c.zero(hzc.get(), v);
         ld = ceil_div(v, kBmmPadK) * kBmmPadK;
         M1 = c.buf<int8_t>((size_t)(u * ld));
         M2t = c.buf<int8_t>((size_t)(w * ld));
         c.zero(M1.get(), (size_t)(u * ld));
         c.zero(M2t.get(), (size_t)(w * ld));
-        int64_t *cx = hxc.get(), *cz = hzc.get();
         int8_t *m1 = M1.get(), *m2 = M2t.get();
         const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = adj_s.get();
         const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
         const int64_t ldl = ld;
         for_each(c, n_r2, [=] __device__(int64_t e) {
             const int32_t a = hx[xr[e]], b = hy[ar[e]];
-            if (a >= 0 && b >= 0) {
-                m1[(int64_t)a * ldl + b] = 1;
-                atomicAdd((unsigned long long *)&cx[b], 1ull);
-            }
+            if ((a >= 0) & (b >= 0)) m1[(int64_t)(a >= 0 ? a : 0) * ldl + (b >= 0 ? b : 0)] = 1;
         });
         for_each(c, n_s2, [=] __device__(int64_t e) {
             const int32_t cc = hz[as[e]], b = hy[syr[e]];
-            if (cc >= 0 && b >= 0) {
-                m2[(int64_t)cc * ldl + b] = 1;
-                atomicAdd((unsigned long long *)&cz[b], 1ull);
-            }
+            if ((cc >= 0) & (b >= 0)) m2[(int64_t)(cc >= 0 ? cc : 0) * ldl + (b >= 0 ? b : 0)] = 1;
         });
-        reduce_sum(
-            c, v, [=] __device__(int64_t b) -> int64_t { return cx[b] * cz[b]; }, (unsigned long long *)(S + 16));
-    } else {
-        c.zero(S + 16, 1);
     }
-    int64_t h15[2];
-    c.load_n(h15, S + 15, 2);
-    const int64_t J_L = h15[0], J_H = h15[1];
+    // Light and heavy witnesses partition the full join: J_H = J - J_L.
+    const int64_t J_L = c.load(S + 15);
+    JP_CHECK(J_L >= 0 && J_L <= J, JP_EINTERNAL, "light witness count exceeds the join size");
+    const int64_t J_H = J - J_L;
+    JP_CHECK(has_heavy || J_H == 0, JP_EINTERNAL, "heavy witnesses without a heavy part");
     st.J_L = J_L;
     st.J_H = J_H;
-    JP_CHECK(J_L + J_H == J, JP_EINTERNAL, "light and heavy witnesses do not add up to the join size");
-    check_monotone(c, "eoff", eoff.get(), n_r2 + 1, 0, J_L);
-    dump(c, "eoff", eoff.get(), n_r2 + 1);
-    dump(c, "lbase", lbase.get(), n_r2);
-    check_index("before expansion");
     const int ev_plan = tl.mark();
 
     const int bz = bits_for((uint64_t)(dom_z - 1)), bx = bits_for((uint64_t)(dom_x - 1));
