@@ -40,6 +40,33 @@ struct PairEmit {  // nonzero (i, j) -> rows[pos] = i, cols[pos] = j
     }
 };
 
+// Row sources of the A operand: 16 bytes of row r starting at byte k.
+struct PlainRows {  // A stored row-major
+    const int8_t *A;
+    int64_t ld;
+    __device__ v4i load(int64_t r, int64_t k) const { return *(const v4i *)(A + r * ld + k); }
+};
+struct PairRows {  // row (a1, a2) = M1[a1,:] AND M2[a2,:] (0/1 bytes), a1 = r / u2, a2 = r % u2
+    const int8_t *M1, *M2;
+    int64_t ld, u2;
+    __device__ v4i load(int64_t r, int64_t k) const {
+        const int64_t a1 = r / u2, a2 = r - a1 * u2;
+        const v4i p = *(const v4i *)(M1 + a1 * ld + k), q = *(const v4i *)(M2 + a2 * ld + k);
+        return p & q;
+    }
+};
+template <class K>
+struct TripleEmit {  // nonzero ((a1,a2), a3) -> x1 << s1 | x2 << s2 | x3
+    const int32_t *x1_of, *x2_of, *x3_of;
+    int64_t u2;
+    int s1, s2;
+    K *keys;
+    __device__ void operator()(int64_t pos, int64_t i, int64_t j) const {
+        const int64_t a1 = i / u2, a2 = i - a1 * u2;
+        keys[pos] = ((K)(uint32_t)x1_of[a1] << s1) | ((K)(uint32_t)x2_of[a2] << s2) | (K)(uint32_t)x3_of[j];
+    }
+};
+
 // Block index -> tile, grouping consecutive blocks of one XCD (blocks are
 // dealt round-robin to the 8 XCDs) onto a compact 2-D patch of tiles so that
 // tiles sharing A rows / B rows share that XCD's L2.
@@ -61,10 +88,10 @@ __device__ __forceinline__ void tile_of_block(int64_t bid, int64_t tiles_m, int6
     *tn = in / gm;
 }
 
-template <class Emit>
-__global__ __launch_bounds__(256) void k_bmm_i8(const int8_t *__restrict__ A, const int8_t *__restrict__ Bt,
-                                                int64_t u, int64_t w, int64_t ld, int64_t tiles_m, int64_t tiles_n,
-                                                Emit emit, int64_t cap, unsigned long long *count) {
+template <class ARows, class Emit>
+__global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__restrict__ Bt, int64_t u, int64_t w,
+                                                int64_t ld, int64_t tiles_m, int64_t tiles_n, Emit emit, int64_t cap,
+                                                unsigned long long *count) {
     __shared__ __attribute__((aligned(16))) int8_t sA[BM * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[BN * LDS_STRIDE];
     int64_t tm, tn;
@@ -81,7 +108,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(const int8_t *__restrict__ A, co
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             int64_t r = row0 + lr + 32 * q;
-            ra[q] = r < u ? *(const v4i *)(A + r * ld + k0 + lc) : v4i{0, 0, 0, 0};
+            ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
             int64_t c = col0 + lr + 32 * q;
             rb[q] = c < w ? *(const v4i *)(Bt + c * ld + k0 + lc) : v4i{0, 0, 0, 0};
         }
@@ -157,9 +184,9 @@ __global__ __launch_bounds__(256) void k_bmm_i8(const int8_t *__restrict__ A, co
             }
 }
 
-template <class Emit>
-void launch_bmm(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
-                Emit emit, int64_t cap, unsigned long long *count_dev) {
+template <class ARows, class Emit>
+void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind, Emit emit,
+                int64_t cap, unsigned long long *count_dev) {
     JP_CHECK(ld % kBmmPadK == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 128");
     c.zero(count_dev, 1);
     if (u <= 0 || w <= 0 || ld <= 0) return;
@@ -167,8 +194,8 @@ void launch_bmm(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int6
     const int64_t tm = ceil_div(u, BM), tn = ceil_div(w, BN);
     const int64_t blocks = tm * tn;
     JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "heavy product too large for one launch");
-    hipLaunchKernelGGL((k_bmm_i8<Emit>), dim3((unsigned)blocks), dim3(256), 0, c.stream, A, Bt, u, w, ld, tm, tn,
-                       emit, cap, count_dev);
+    hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3((unsigned)blocks), dim3(256), 0, c.stream, arows, Bt, u, w, ld,
+                       tm, tn, emit, cap, count_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -176,13 +203,26 @@ void launch_bmm(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int6
 
 void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                        int32_t *out_i, int32_t *out_j, int64_t cap, unsigned long long *count_dev) {
-    launch_bmm(c, A, Bt, u, w, ld, kind, PairEmit{out_i, out_j}, cap, count_dev);
+    launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, kind, PairEmit{out_i, out_j}, cap, count_dev);
 }
 
 void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,
                       unsigned long long *count_dev) {
-    launch_bmm(c, A, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
+    launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
+}
+
+void star_bmm_keys(const Ctx &c, const int8_t *M1, const int8_t *M2, const int8_t *M3, int64_t u1, int64_t u2,
+                   int64_t u3, int64_t ld, const int32_t *x1_of, const int32_t *x2_of, const int32_t *x3_of, int s1,
+                   int s2, void *keys, bool wide, int64_t cap, unsigned long long *count_dev) {
+    const PairRows rows{M1, M2, ld, u2};
+    if (wide)
+        launch_bmm(c, rows, M3, u1 * u2, u3, ld, JP_BMM_I8_MFMA,
+                   TripleEmit<unsigned __int128>{x1_of, x2_of, x3_of, u2, s1, s2, (unsigned __int128 *)keys}, cap,
+                   count_dev);
+    else
+        launch_bmm(c, rows, M3, u1 * u2, u3, ld, JP_BMM_I8_MFMA,
+                   TripleEmit<uint64_t>{x1_of, x2_of, x3_of, u2, s1, s2, (uint64_t *)keys}, cap, count_dev);
 }
 
 }  // namespace jp

@@ -1,0 +1,125 @@
+"""Star query Q*_3 parity: the HIP path through the C ABI against the CPU
+oracle (bit-exact sorted tuples) and the numpy restatement of the Section 3.2
+partition (J, light / heavy witness counts)."""
+import itertools
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from oracle import reference as ref
+from tests.conftest import load_golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def jp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_12459_amd as jp
+    return jp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.int32))).cuda()
+
+
+def run(jp, rels, **kw):
+    cols, st = jp.default_handle(0).star([(dev(a), dev(b)) for a, b in rels], **kw)
+    return np.stack([c.cpu().numpy() for c in cols], 1) if cols[0].numel() else np.zeros((0, len(rels)), np.int32), st
+
+
+def check(jp, rels, **kw):
+    exp = oracle.star(rels)
+    got, st = run(jp, rels, **kw)
+    assert got.shape == exp.shape, (got.shape, exp.shape, kw)
+    np.testing.assert_array_equal(got, exp)
+    return st
+
+
+def example_rels():
+    rows = load_golden("two_path_example.txt")
+    R = [(int(r[1]), int(r[2])) for r in rows if r[0] == "R"]
+    S = [(int(r[1]), int(r[2])) for r in rows if r[0] == "S"]
+    rows = load_golden("star_example.txt")
+    T = [(int(r[1]), int(r[2])) for r in rows if r[0] == "T"]
+    rel = lambda E: (np.array([e[0] for e in E]), np.array([e[1] for e in E]))
+    return [rel(R), rel(S), rel(T)]
+
+
+def test_worked_example_star(jp):
+    rels = example_rels()
+    for d1, d2 in itertools.product([1, 2, 3, None], [1, 2, 3, None]):
+        st = check(jp, rels, delta1=d1, delta2=d2, strategy="fixed")
+        assert st["n_out"] == 80
+        if d1 is not None and d2 is not None:
+            r = ref.star_stats(rels, d1, d2)
+            assert (st["J"], st["J_L"], st["J_H"]) == (r["J"], r["J_L"], r["J_H"]), (d1, d2)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_small_star(jp, seed):
+    rng = np.random.default_rng(seed)
+    signed = seed % 2 == 1
+    rels = [datagen.random_small(int(rng.integers(1, 300)), 30, 12, seed * 7 + i, dup=True, signed=signed)
+            for i in range(3)]
+    if signed:  # share y ids so the signed case still joins
+        for i in (1, 2):
+            rels[i] = (rels[i][0], rels[0][1][rng.integers(0, rels[0][1].size, rels[i][1].size)])
+    for d1, d2 in [(1, 1), (2, 3), (4, 1), (None, None)]:
+        st = check(jp, rels, delta1=d1, delta2=d2, strategy="fixed")
+        if d1 is not None and seed < 4:
+            r = ref.star_stats(rels, d1, d2)
+            assert (st["J"], st["J_L"], st["J_H"]) == (r["J"], r["J_L"], r["J_H"])
+
+
+def test_star_k2_is_two_path(jp):
+    (rx, ry), (sz, sy) = datagen.twopath_c2(0.001)
+    got, st = run(jp, [(rx, ry), (sz, sy)])
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    np.testing.assert_array_equal(got[:, 0], ex)
+    np.testing.assert_array_equal(got[:, 1], ez)
+
+
+def test_star_degenerate(jp):
+    e = np.zeros(0, np.int32)
+    got, st = run(jp, [(e, e), ([1], [2]), ([3], [2])])
+    assert got.shape[0] == 0
+    got, st = run(jp, [([1], [1]), ([1], [2]), ([3], [2])])  # no common y
+    assert got.shape[0] == 0
+    check(jp, [([5], [9]), ([-7], [9]), ([2**31 - 1], [9])])
+
+
+@pytest.mark.parametrize("scale", [0.005, 0.02])
+def test_star_zipf_scaled(jp, scale):
+    """The star workload's shape (Zipf(1.3) y, uniform x) at reduced scale,
+    with light-only, theory and forced thresholds that create a heavy part."""
+    rels = datagen.star_c3(scale)
+    exp = oracle.star(rels)
+    for kw in (dict(strategy="light"), dict(strategy="auto"), dict(delta1=8, delta2=3),
+               dict(delta1=3, delta2=2)):
+        got, st = run(jp, rels, **kw)
+        np.testing.assert_array_equal(got, exp, err_msg=str(kw))
+
+
+def test_star_communities_heavy(jp):
+    """Dense communities: every in-community triple is an output; with low
+    thresholds the heavy product carries them."""
+    x, y = datagen.communities(3, 20, 12, 1.0, seed=2)
+    st = check(jp, [(x, y)] * 3, delta1=3, delta2=3)
+    assert st["nnz_heavy"] > 0 and st["n_out"] == 3 * 20 ** 3
+
+
+def test_star_wide_keys(jp):
+    """Rank widths summing to more than 64 bits use 128-bit sort keys."""
+    n = 2_200_000
+    rng = np.random.default_rng(3)
+    rels = []
+    for i in range(3):
+        x = rng.permutation(n).astype(np.int32)
+        y = (np.arange(n) // 2).astype(np.int32)
+        rels.append((x, y))
+    check(jp, rels, strategy="light")
