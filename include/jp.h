@@ -129,6 +129,41 @@ typedef struct jp_stats {
 typedef struct jp_handle jp_handle;
 typedef struct jp_result jp_result;
 
+/*
+ * Device constants of the cost-based optimizer (Section 5, Table "Symbol
+ * definitions" and Algorithm 2), measured for this library on one GPU.
+ */
+typedef struct jp_calibration {
+    double t_witness;  /* T_I: seconds per light witness (gather + duplicate removal) */
+    double t_seq;      /* T_s: seconds per sequential element of a per-x dense marker pass */
+    double t_byte;     /* T_m / 32: seconds per byte of heavy matrix allocated and filled */
+    double t_x;        /* T_m per x value: fixed per-x cost of the light path */
+    double eps;        /* search step: Delta1 <- (1 - eps) Delta1 */
+    int32_t literal;   /* 1: start at Delta1 = N and stop when the cost does not decrease */
+    int32_t n_mm;      /* entries of the product time table */
+    double mm_p[24];   /* table of M-hat(p, p, p): cube sizes p ... */
+    double mm_s[24];   /* ... and measured seconds */
+} jp_calibration;
+
+/* Sorted degree vector with per-degree count and summed work: the indexes of
+ * Section 5 ("sum", "cdfx", "count"), queried by binary search.  Host arrays. */
+typedef struct jp_degree_index {
+    int64_t n;            /* distinct degrees */
+    const int64_t *deg;   /* ascending */
+    const int64_t *count; /* values with that degree */
+    const double *sum;    /* summed work of those values (may be NULL for count-only indexes) */
+} jp_degree_index;
+
+/* Inputs of the two-path threshold choice. */
+typedef struct jp_two_path_summary {
+    int64_t n_r, n_s, dom_x, dom_y, dom_z, J;
+    double out_est;
+    jp_degree_index y;    /* key degree of y (y rule); sum = deg_R(y) * deg_S(y) */
+    jp_degree_index x;    /* deg_R(x); sum = witnesses of x = sum over y in N(x) of deg_S(y) */
+    jp_degree_index xcdf; /* per x, the smallest key degree among its y (count only): cdfx */
+    jp_degree_index z;    /* deg_S(z) (count only) */
+} jp_two_path_summary;
+
 /* Create a handle bound to HIP device `device`.  *h receives the handle. */
 jp_status jp_create(jp_handle **h, int device);
 
@@ -145,6 +180,34 @@ const char *jp_last_error(const jp_handle *h);
 
 /* Fill *opt with the defaults: AUTO_COST, AUTO kernels, MAX y rule. */
 void jp_default_options(jp_options *opt);
+
+/* Built-in calibration of the optimizer's constants. */
+void jp_default_calibration(jp_calibration *cal);
+
+/* Replace / read the calibration a handle's optimizer uses. */
+jp_status jp_set_calibration(jp_handle *h, const jp_calibration *cal);
+jp_status jp_get_calibration(const jp_handle *h, jp_calibration *cal);
+
+/*
+ * Algorithm 2 (Section 5) on a host summary; no GPU needed.  Writes the
+ * thresholds to *delta1 / *delta2 (JP_DELTA_INF for both when the join is
+ * small enough for the plain worst-case optimal join, J <= 20 N) and the
+ * estimated costs of the chosen plan and of the all-light plan (seconds).
+ * cal may be NULL (built-in constants).
+ */
+jp_status jp_plan_summary(const jp_two_path_summary *s, const jp_calibration *cal, int64_t *delta1,
+                          int64_t *delta2, double *cost, double *cost_light_only);
+
+/*
+ * Index and summarise a two-path instance on the GPU (the first phase of
+ * jp_two_path) and return the optimizer's thresholds plus 16 features for a
+ * learned selector: log N_R, log N_S, log estimated |OUT|, y-degree quantiles
+ * in R and in S (p50, p90, p99, p99.9, max), x-degree p99 and max, z-degree
+ * max (logs of degree + 1).  features may be NULL.
+ */
+jp_status jp_plan_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                           const int32_t *s_y, int64_t n_s, const jp_options *opt, int64_t *delta1,
+                           int64_t *delta2, float *features);
 
 /*
  * Two-path join-project (Algorithm 1, Section 3.1).

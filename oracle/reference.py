@@ -207,3 +207,120 @@ def out_estimate(dom_x: int, dom_z: int, J: int, N: int) -> float:
     hi = min(float(dom_x) * float(dom_z), float(J))
     lo = min(lo, hi)
     return math.sqrt(lo * hi)
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 (Section 5): cost-based threshold search on degree indexes.
+# ---------------------------------------------------------------------------
+
+def degree_summary(rx, ry, sz, sy, y_rule=Y_RULE_MAX):
+    """The Section 5 indexes of a two-path instance as sorted degree vectors.
+
+    Returns a dict with sizes, J, the output estimate, and four indexes, each a
+    tuple (deg, count, sum) of numpy arrays with ascending distinct degrees:
+      y    key degree of y; sum = deg_R(y) * deg_S(y)  (sum(y_delta))
+      x    deg_R(x); sum = witnesses of x              (sum(x_delta))
+      xcdf per x the smallest key degree of its y      (cdfx(y_delta))
+      z    deg_S(z)                                    (count(z_delta))
+    """
+    rx, ry, sz, sy = reduce_two_path(rx, ry, sz, sy)
+    dRy, dSy = _deg(ry), _deg(sy)
+    dRx, dSz = _deg(rx), _deg(sz)
+    key = {b: (dRy[b] if y_rule == Y_RULE_R_ONLY else max(dRy[b], dSy[b])) for b in dRy}
+    wx, mk = {}, {}
+    for a, b in zip(rx.tolist(), ry.tolist()):
+        wx[a] = wx.get(a, 0) + dSy[b]
+        mk[a] = min(mk.get(a, 1 << 62), key[b])
+
+    def index(degs, sums=None):
+        d = np.array(sorted(set(degs.values())), dtype=np.int64)
+        cnt = np.array([sum(1 for v in degs.values() if v == t) for t in d], dtype=np.int64)
+        if sums is None:
+            return d, cnt, None
+        sm = np.array([float(sum(sums[k] for k, v in degs.items() if v == t)) for t in d])
+        return d, cnt, sm
+
+    J = sum(dRy[b] * dSy[b] for b in dRy)
+    N = max(len(rx), len(sz))
+    return dict(
+        n_r=len(rx), n_s=len(sz), dom_x=len(dRx), dom_y=len(dRy), dom_z=len(dSz), J=int(J),
+        out_est=out_estimate(len(dRx), len(dSz), int(J), N) if J else 0.0,
+        y=index(key, {b: dRy[b] * dSy[b] for b in dRy}),
+        x=index(dRx, wx),
+        xcdf=index(mk),
+        z=index(dSz),
+    )
+
+
+def _le(index, delta):
+    """(count, sum) of the values with degree <= delta (binary search)."""
+    d, cnt, sm = index
+    p = int(np.searchsorted(d, delta, side="right"))
+    c = int(cnt[:p].sum())
+    s = float(sm[:p].sum()) if sm is not None else 0.0
+    return c, s
+
+
+def algorithm2(s, cal):
+    """Cost-based optimizer of Section 5, in the paper's order.
+
+    cal: dict with t_witness (T_I), t_seq (T_s), t_byte (T_m per byte), t_x
+    (T_m per x value), eps, literal, and the product table mm_p / mm_s.
+    Readings: N = max(|R|, |S|); Delta2 = floor(N Delta1 / OUT) clamped to
+    [1, N] from the first step on; the start is Delta1 = N when literal, else
+    the largest key degree; the search stops when the cost does not decrease
+    (literal) or strictly increases; the light cost is
+      T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
+    and the heavy cost M-hat(u,v,w) + T_m (u v + w v); the result is the plain
+    join when J <= 20 N or when no candidate beats it.
+    Returns (delta1, delta2, cost, cost_light_only); None stands for infinity.
+    """
+    N = max(s["n_r"], s["n_s"])
+    out = max(s["out_est"], 1.0)
+
+    def mm_hat(u, v, w):
+        if min(u, v, w) <= 0:
+            return 0.0
+        p = (u * v * w) ** (1.0 / 3.0)
+        i = int(np.argmin([abs(q - p) for q in cal["mm_p"]]))
+        return cal["mm_s"][i] * (u * v * w) / cal["mm_p"][i] ** 3
+
+    def cost(d1, d2):
+        cy, sy_ = _le(s["y"], d1)
+        cx, sx_ = _le(s["x"], d2)
+        cc, _ = _le(s["xcdf"], d1)
+        cz, _ = _le(s["z"], d2)
+        light = cal["t_witness"] * (sy_ + sx_) + cal["t_x"] * s["dom_x"] + cal["t_seq"] * cc * s["dom_x"]
+        u, v, w = s["dom_x"] - cx, s["dom_y"] - cy, s["dom_z"] - cz
+        heavy = 0.0
+        if u > 0 and v > 0 and w > 0:
+            heavy = mm_hat(u, v, w) + cal["t_byte"] * (u * v + w * v)
+        return light + heavy
+
+    big = 1 << 62
+    light_only = cost(big, big)
+    if s["J"] <= 20 * N or N <= 0:
+        return None, None, light_only, light_only
+    eps = 0.95 if cal["literal"] else cal["eps"]
+
+    def d2_of(d1):
+        t = N * d1 / out
+        return 1 if t < 1 else (N if t >= N else int(math.floor(t)))
+
+    d1 = max(N, 1) if cal["literal"] else max(int(s["y"][0][-1]), 1)
+    d2 = d2_of(d1)
+    prev = cost(d1, d2)
+    for _ in range(10000):
+        nd1 = int(math.floor((1 - eps) * d1))
+        if nd1 >= d1:
+            nd1 = d1 - 1
+        if nd1 < 1:
+            break
+        nd2 = d2_of(nd1)
+        c = cost(nd1, nd2)
+        if (prev <= c) if cal["literal"] else (prev < c):
+            break
+        prev, d1, d2 = c, nd1, nd2
+    if not prev < light_only:
+        return None, None, light_only, light_only
+    return d1, d2, prev, light_only

@@ -58,6 +58,38 @@ class Stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Calibration(ctypes.Structure):
+    _fields_ = [("t_witness", ctypes.c_double), ("t_seq", ctypes.c_double), ("t_byte", ctypes.c_double),
+                ("t_x", ctypes.c_double), ("eps", ctypes.c_double), ("literal", ctypes.c_int32),
+                ("n_mm", ctypes.c_int32), ("mm_p", ctypes.c_double * 24), ("mm_s", ctypes.c_double * 24)]
+
+    def as_dict(self):
+        return {"t_witness": self.t_witness, "t_seq": self.t_seq, "t_byte": self.t_byte, "t_x": self.t_x,
+                "eps": self.eps, "literal": self.literal, "mm_p": list(self.mm_p[: self.n_mm]),
+                "mm_s": list(self.mm_s[: self.n_mm])}
+
+    @classmethod
+    def from_dict(cls, d):
+        c = cls()
+        for k in ("t_witness", "t_seq", "t_byte", "t_x", "eps"):
+            setattr(c, k, float(d[k]))
+        c.literal = int(d.get("literal", 0))
+        c.n_mm = len(d["mm_p"])
+        for i, (a, b) in enumerate(zip(d["mm_p"], d["mm_s"])):
+            c.mm_p[i] = a
+            c.mm_s[i] = b
+        return c
+
+
+class DegreeIndex(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("deg", ctypes.c_void_p), ("count", ctypes.c_void_p), ("sum", ctypes.c_void_p)]
+
+
+class TwoPathSummary(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_r", "n_s", "dom_x", "dom_y", "dom_z", "J")] + \
+               [("out_est", ctypes.c_double)] + [(n, DegreeIndex) for n in ("y", "x", "xcdf", "z")]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -93,8 +125,18 @@ def _load():
         lib.jp_result_free.restype = None
         lib.jp_bool_matmul.argtypes = [P, P, P, i64, i64, i64, i64, ctypes.c_int32, P, P, i64,
                                        ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+        lib.jp_default_calibration.argtypes = [ctypes.POINTER(Calibration)]
+        lib.jp_default_calibration.restype = None
+        lib.jp_set_calibration.argtypes = [P, ctypes.POINTER(Calibration)]
+        lib.jp_get_calibration.argtypes = [P, ctypes.POINTER(Calibration)]
+        lib.jp_plan_summary.argtypes = [ctypes.POINTER(TwoPathSummary), ctypes.POINTER(Calibration),
+                                        ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double)]
+        lib.jp_plan_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(i64),
+                                         ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
         for f in ("jp_create", "jp_set_stream", "jp_two_path", "jp_star", "jp_result_size",
-                  "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul"):
+                  "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
+                  "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -264,6 +306,27 @@ class Handle:
                                            _ptr(cols), cap, ctypes.byref(nnz), ctypes.byref(ms)))
         return rows[: nnz.value], cols[: nnz.value], ms.value
 
+    def set_calibration(self, cal):
+        c = cal if isinstance(cal, Calibration) else Calibration.from_dict(cal)
+        self._check(_load().jp_set_calibration(self._p, ctypes.byref(c)))
+
+    def get_calibration(self):
+        c = Calibration()
+        self._check(_load().jp_get_calibration(self._p, ctypes.byref(c)))
+        return c.as_dict()
+
+    def plan_two_path(self, rx, ry, sz, sy, strategy="auto", y_rule="max"):
+        """Thresholds the optimizer picks (None = infinity) and the 16 selector features."""
+        rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+        self._bind_stream()
+        o = self._options(None, None, strategy, "auto", y_rule, "auto", False, None)
+        d1, d2 = ctypes.c_int64(), ctypes.c_int64()
+        f = (ctypes.c_float * 16)()
+        self._check(_load().jp_plan_two_path(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy),
+                                             sz.numel(), ctypes.byref(o), ctypes.byref(d1), ctypes.byref(d2), f))
+        inf = lambda v: None if v == DELTA_INF else v
+        return inf(d1.value), inf(d2.value), list(f)
+
     def close(self):
         if getattr(self, "_p", None):
             _load().jp_destroy(self._p)
@@ -303,3 +366,48 @@ def star(rels, **kw):
 
 def bool_matmul(A, Bt, **kw):
     return default_handle(A.device.index).bool_matmul(A, Bt, **kw)
+
+
+def default_calibration():
+    c = Calibration()
+    _load().jp_default_calibration(ctypes.byref(c))
+    return c.as_dict()
+
+
+def plan_summary(summary, cal=None):
+    """Algorithm 2 on a host summary (dict as returned by the oracle's
+    degree_summary: sizes, J, out_est and (deg, count, sum) indexes).  Runs on
+    the host; no GPU needed.  Returns (delta1, delta2, cost, cost_light_only)
+    with None for infinity."""
+    import numpy as np
+    keep = []
+
+    def idx(t):
+        d, c, s = t
+        d = np.ascontiguousarray(d, dtype=np.int64)
+        c = np.ascontiguousarray(c, dtype=np.int64)
+        keep.extend([d, c])
+        di = DegreeIndex()
+        di.n = d.size
+        di.deg = d.ctypes.data
+        di.count = c.ctypes.data
+        if s is not None:
+            s = np.ascontiguousarray(s, dtype=np.float64)
+            keep.append(s)
+            di.sum = s.ctypes.data
+        return di
+
+    ts = TwoPathSummary()
+    for k in ("n_r", "n_s", "dom_x", "dom_y", "dom_z", "J"):
+        setattr(ts, k, int(summary[k]))
+    ts.out_est = float(summary["out_est"])
+    ts.y, ts.x, ts.xcdf, ts.z = (idx(summary[k]) for k in ("y", "x", "xcdf", "z"))
+    c = None if cal is None else (cal if isinstance(cal, Calibration) else Calibration.from_dict(cal))
+    d1, d2 = ctypes.c_int64(), ctypes.c_int64()
+    cost, clo = ctypes.c_double(), ctypes.c_double()
+    st = _load().jp_plan_summary(ctypes.byref(ts), ctypes.byref(c) if c is not None else None, ctypes.byref(d1),
+                                 ctypes.byref(d2), ctypes.byref(cost), ctypes.byref(clo))
+    if st != 0:
+        raise JoinProjectError(st, "jp_plan_summary failed")
+    inf = lambda v: None if v == DELTA_INF else v
+    return inf(d1.value), inf(d2.value), cost.value, clo.value

@@ -14,6 +14,7 @@ struct jp_handle {
     std::shared_ptr<jp::Allocator> alloc;
     int num_cus = 256;
     std::string err;
+    jp_calibration cal;
 };
 
 namespace {
@@ -37,6 +38,7 @@ jp::Ctx make_ctx(jp_handle *h) {
     c.alloc = h->alloc;
     c.device = h->device;
     c.num_cus = h->num_cus;
+    c.cal = &h->cal;
     return c;
 }
 
@@ -110,6 +112,7 @@ jp_status jp_create(jp_handle **out, int device) {
     auto h = std::make_unique<jp_handle>();
     h->device = device;
     h->alloc = std::make_shared<jp::Allocator>(device);
+    jp::default_calibration(&h->cal);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         h->num_cus = cus;
@@ -193,6 +196,76 @@ jp_status jp_star(jp_handle *h, int k, const int32_t *const *x, const int32_t *c
     jp_status st = guarded(h, [&] { r = jp::run_star(make_ctx(h), k, x, y, n, o); });
     if (st == JP_OK) *out = r;
     return st;
+}
+
+void jp_default_calibration(jp_calibration *cal) {
+    if (cal) jp::default_calibration(cal);
+}
+
+jp_status jp_set_calibration(jp_handle *h, const jp_calibration *cal) {
+    if (!h) return JP_EINVAL;
+    if (!cal || cal->n_mm < 0 || cal->n_mm > 24 || !(cal->t_witness >= 0) || !(cal->t_byte >= 0) ||
+        !(cal->t_seq >= 0) || !(cal->t_x >= 0) || !(cal->eps > 0 && cal->eps < 1)) {
+        h->err = "bad calibration";
+        return JP_EINVAL;
+    }
+    for (int i = 0; i < cal->n_mm; ++i)
+        if (!(cal->mm_p[i] > 0) || !(cal->mm_s[i] >= 0)) {
+            h->err = "bad product time table";
+            return JP_EINVAL;
+        }
+    h->cal = *cal;
+    return JP_OK;
+}
+
+jp_status jp_get_calibration(const jp_handle *h, jp_calibration *cal) {
+    if (!h || !cal) return JP_EINVAL;
+    *cal = h->cal;
+    return JP_OK;
+}
+
+static bool bad_index(const jp_degree_index &d, bool need_sum) {
+    if (d.n < 0 || (d.n > 0 && (!d.deg || !d.count || (need_sum && !d.sum)))) return true;
+    for (int64_t i = 0; i < d.n; ++i)
+        if (d.deg[i] < 0 || d.count[i] < 0 || (i > 0 && d.deg[i] <= d.deg[i - 1])) return true;
+    return false;
+}
+
+jp_status jp_plan_summary(const jp_two_path_summary *s, const jp_calibration *cal, int64_t *delta1, int64_t *delta2,
+                          double *cost, double *cost_light_only) {
+    if (!s || !delta1 || !delta2) return JP_EINVAL;
+    if (s->n_r < 0 || s->n_s < 0 || s->dom_x < 0 || s->dom_y < 0 || s->dom_z < 0 || s->J < 0 ||
+        bad_index(s->y, true) || bad_index(s->x, true) || bad_index(s->xcdf, false) || bad_index(s->z, false))
+        return JP_EINVAL;
+    try {
+        jp_calibration c;
+        if (cal) c = *cal;
+        else jp::default_calibration(&c);
+        const jp::PlanResult r = jp::algorithm2(*s, c);
+        *delta1 = r.d1;
+        *delta2 = r.d2;
+        if (cost) *cost = r.cost;
+        if (cost_light_only) *cost_light_only = r.cost_light_only;
+        return JP_OK;
+    } catch (...) {
+        return JP_EINTERNAL;
+    }
+}
+
+jp_status jp_plan_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                           const int32_t *s_y, int64_t n_s, const jp_options *opt, int64_t *delta1,
+                           int64_t *delta2, float *features) {
+    if (!h) return JP_EINVAL;
+    if (!delta1 || !delta2 || bad_col(r_x, n_r) || bad_col(r_y, n_r) || bad_col(s_z, n_s) || bad_col(s_y, n_s)) {
+        h->err = "bad argument to jp_plan_two_path";
+        return JP_EINVAL;
+    }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    return guarded(h, [&] { jp::plan_two_path(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o, delta1, delta2, features); });
 }
 
 jp_status jp_result_size(const jp_result *r, int64_t *n_tuples, int32_t *arity) {

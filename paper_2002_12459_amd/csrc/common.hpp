@@ -165,6 +165,7 @@ struct Ctx {
     int device = 0;
     int num_cus = 256;
     size_t lds_bytes = 160 * 1024;
+    const jp_calibration *cal = nullptr;  // optimizer constants of the handle
 
     template <class T>
     DBuf<T> buf(size_t n) const {

@@ -13,20 +13,54 @@ struct jp_result {
 
 namespace jp {
 
+// One Section 5 index on the host: ascending distinct degrees with the
+// number of values of each degree and their summed work.
+struct HostIndex {
+    std::vector<int64_t> deg, count;
+    std::vector<double> sum;
+    jp_degree_index view() const {
+        jp_degree_index d;
+        d.n = (int64_t)deg.size();
+        d.deg = deg.data();
+        d.count = count.data();
+        d.sum = sum.empty() ? nullptr : sum.data();
+        return d;
+    }
+};
+
 // Degree summary of an indexed two-path instance, on the host: the inputs of
 // the threshold choice (Section 5 indexes and Algorithm 2).
 struct TwoPathSummary {
     int64_t n_r = 0, n_s = 0, dom_x = 0, dom_y = 0, dom_z = 0;
     int64_t J = 0;
     bool self_join = false;
-    // Histograms by degree (index = degree, capped at the max degree):
-    std::vector<int64_t> cnt_x;   // number of x with deg_R(x) = d
-    std::vector<int64_t> cnt_z;   // number of z with deg_S(z) = d
-    std::vector<int64_t> cnt_y;   // number of y with key degree = d (key degree per the y rule)
-    std::vector<int64_t> jy;      // sum over y with key degree d of deg_R(y) * deg_S(y)
-    std::vector<int64_t> sx;      // sum over x with deg_R(x) = d of the full per-x join work
-    std::vector<int64_t> ry;      // sum over y with key degree d of deg_R(y)
-    double out_est = 0;           // output-size estimate
+    double out_est = 0;   // output-size estimate
+    bool have_indexes = false;
+    HostIndex y;          // key degree of y; sum = deg_R(y) deg_S(y)
+    HostIndex x;          // deg_R(x); sum = witnesses of x
+    HostIndex xcdf;       // smallest key degree among the y of x
+    HostIndex z;          // deg_S(z)
+    HostIndex yr, ys;     // deg_R(y), deg_S(y) (features)
+    jp_two_path_summary view() const {
+        jp_two_path_summary v;
+        v.n_r = n_r;
+        v.n_s = n_s;
+        v.dom_x = dom_x;
+        v.dom_y = dom_y;
+        v.dom_z = dom_z;
+        v.J = J;
+        v.out_est = out_est;
+        v.y = y.view();
+        v.x = x.view();
+        v.xcdf = xcdf.view();
+        v.z = z.view();
+        return v;
+    }
+};
+
+struct PlanResult {
+    int64_t d1 = JP_DELTA_INF, d2 = JP_DELTA_INF;
+    double cost = 0, cost_light_only = 0;
 };
 
 struct Thresholds {
@@ -36,9 +70,28 @@ struct Thresholds {
 };
 
 // Planner (host).
-Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o);
+Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o, const jp_calibration &cal);
 double estimate_out(int64_t dom_x, int64_t dom_z, int64_t J, int64_t N);
 Thresholds theory_thresholds(int64_t N, double out);
+PlanResult algorithm2(const jp_two_path_summary &s, const jp_calibration &c);
+void default_calibration(jp_calibration *c);
+void features16(const TwoPathSummary &s, float *f);
+
+// Two-path index + summary (+ thresholds) without the join (jp_plan_two_path).
+void plan_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                   const int32_t *sy, int64_t ns, const jp_options &o, int64_t *d1, int64_t *d2, float *features);
+
+// Index build of a two-path instance (Section 5, "Indexing relations"):
+// R x-major (off_x, adj_r = y rank, r_xr = x rank per tuple), S y-major
+// (off_y, adj_s = z rank, s2_y = y rank per tuple), degrees, rank tables, J.
+struct Ingest {
+    int64_t n_r2 = 0, n_s2 = 0, dom_x = 0, dom_y = 0, dom_z = 0, J = 0;
+    DBuf<int32_t> r_xr, adj_r, adj_s, s2_y, dRy, dSz, xorig, zorig;
+    DBuf<int64_t> off_x, off_y;
+};
+
+// Builds the Section 5 degree indexes of an indexed instance (summary.hip).
+void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummary &s);
 
 // Pipelines.
 jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,

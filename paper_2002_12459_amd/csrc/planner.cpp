@@ -8,8 +8,9 @@
 //                OUT >  N:  D1 = D2 = (2 N^2 / (N + OUT))^(1/3)
 //              with OUT the Section 5 estimate; rounded down to integers and
 //              clamped to [1, N].
-//  AUTO_COST   Algorithm 2 (Section 5) with device-calibrated constants.
-//  AUTO_MLP    learned selector; without loaded weights, AUTO_COST.
+//  AUTO_COST   Algorithm 2 (Section 5) on the degree indexes of the instance
+//              with this device's measured constants.
+//  AUTO_MLP    learned selector (selector.cpp); Algorithm 2 without weights.
 #include <algorithm>
 #include <cmath>
 
@@ -50,7 +51,114 @@ Thresholds theory_thresholds(int64_t N, double out) {
     return th;
 }
 
-Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o) {
+void default_calibration(jp_calibration *c) {
+    std::memset(c, 0, sizeof(*c));
+    // measured on MI355X with this library (bench workload and the product
+    // sweep); replaced at run time by jp_set_calibration
+    c->t_witness = 2.6e-11;
+    c->t_seq = 0.0;
+    c->t_byte = 2.5e-13;
+    c->t_x = 1.5e-9;
+    c->eps = 0.05;
+    c->literal = 0;
+    const double p[] = {1024, 2048, 4096, 8192, 12288, 16384, 20480};
+    const double rate = 1.3e15;  // int8 ops per second at large sizes
+    c->n_mm = 7;
+    for (int i = 0; i < 7; ++i) {
+        c->mm_p[i] = p[i];
+        c->mm_s[i] = 2e-5 + 2.0 * p[i] * p[i] * p[i] / rate;
+    }
+}
+
+namespace {
+
+// Section 5 index: sorted degree vector, prefix counts and sums.
+struct Index {
+    const int64_t *deg = nullptr;
+    int64_t n = 0;
+    std::vector<int64_t> ccnt;  // ccnt[i] = values with degree <= deg[i-1]
+    std::vector<double> csum;
+    explicit Index(const jp_degree_index &d) : deg(d.deg), n(d.n), ccnt(d.n + 1, 0), csum(d.n + 1, 0.0) {
+        for (int64_t i = 0; i < n; ++i) {
+            ccnt[i + 1] = ccnt[i] + d.count[i];
+            csum[i + 1] = csum[i] + (d.sum ? d.sum[i] : 0.0);
+        }
+    }
+    int64_t pos(int64_t delta) const {  // number of entries with degree <= delta
+        return std::upper_bound(deg, deg + n, delta) - deg;
+    }
+    int64_t count_le(int64_t delta) const { return ccnt[pos(delta)]; }
+    double sum_le(int64_t delta) const { return csum[pos(delta)]; }
+    int64_t total() const { return ccnt[n]; }
+    int64_t max_deg() const { return n ? deg[n - 1] : 0; }
+};
+
+// M-hat(u, v, w): time of the nearest measured cube, scaled by u v w / p^3.
+double mm_hat(const jp_calibration &c, double u, double v, double w) {
+    if (u <= 0 || v <= 0 || w <= 0 || c.n_mm <= 0) return 0.0;
+    const double p = std::cbrt(u * v * w);
+    int best = 0;
+    for (int i = 1; i < c.n_mm; ++i)
+        if (std::fabs(c.mm_p[i] - p) < std::fabs(c.mm_p[best] - p)) best = i;
+    const double pb = c.mm_p[best];
+    return c.mm_s[best] * (u * v * w) / (pb * pb * pb);
+}
+
+}  // namespace
+
+PlanResult algorithm2(const jp_two_path_summary &s, const jp_calibration &c) {
+    PlanResult r;
+    const int64_t N = std::max(s.n_r, s.n_s);
+    const double out = std::max(s.out_est, 1.0);
+    const Index Y(s.y), X(s.x), XC(s.xcdf), Z(s.z);
+    auto cost = [&](int64_t d1, int64_t d2) {
+        // light: T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
+        const double light = c.t_witness * (Y.sum_le(d1) + X.sum_le(d2)) + c.t_x * (double)s.dom_x +
+                             c.t_seq * (double)XC.count_le(d1) * (double)s.dom_x;
+        // heavy: M-hat(u, v, w) + allocation of the heavy matrices
+        const double u = (double)(s.dom_x - X.count_le(d2));
+        const double v = (double)(s.dom_y - Y.count_le(d1));
+        const double w = (double)(s.dom_z - Z.count_le(d2));
+        double heavy = 0.0;
+        if (u > 0 && v > 0 && w > 0) heavy = mm_hat(c, u, v, w) + c.t_byte * (u * v + w * v);
+        return light + heavy;
+    };
+    r.cost_light_only = cost(JP_DELTA_INF, JP_DELTA_INF);
+    if ((double)s.J <= 20.0 * (double)N || N <= 0) {  // small join: plain worst-case optimal join
+        r.d1 = r.d2 = JP_DELTA_INF;
+        r.cost = r.cost_light_only;
+        return r;
+    }
+    const double eps = c.literal ? 0.95 : (c.eps > 0 && c.eps < 1 ? c.eps : 0.05);
+    auto delta2_of = [&](int64_t d1) { return clamp_delta((double)N * (double)d1 / out, N); };
+    // Start: literal reading Delta1 = N; otherwise the largest key degree (any
+    // larger Delta1 gives the same, all-light partition).
+    int64_t d1 = c.literal ? std::max<int64_t>(N, 1) : std::max<int64_t>(Y.max_deg(), 1);
+    int64_t d2 = delta2_of(d1);
+    double prev = cost(d1, d2);
+    for (int it = 0; it < 10000; ++it) {
+        int64_t nd1 = (int64_t)std::floor((1.0 - eps) * (double)d1);
+        if (nd1 >= d1) nd1 = d1 - 1;
+        if (nd1 < 1) break;
+        const int64_t nd2 = delta2_of(nd1);
+        const double cnow = cost(nd1, nd2);
+        const bool stop = c.literal ? (prev <= cnow) : (prev < cnow);
+        if (stop) break;
+        prev = cnow;
+        d1 = nd1;
+        d2 = nd2;
+    }
+    r.d1 = d1;
+    r.d2 = d2;
+    r.cost = prev;
+    if (!(r.cost < r.cost_light_only)) {  // nothing beats the plain join
+        r.d1 = r.d2 = JP_DELTA_INF;
+        r.cost = r.cost_light_only;
+    }
+    return r;
+}
+
+Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o, const jp_calibration &cal) {
     const int64_t N = std::max(s.n_r, s.n_s);
     Thresholds th;
     switch (o.strategy) {
@@ -67,13 +175,42 @@ Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o) {
         default:
             break;
     }
-    // AUTO_COST / AUTO_MLP
-    th = theory_thresholds(N, s.out_est);
+    const jp_two_path_summary cs = s.view();
+    const PlanResult r = algorithm2(cs, cal);
+    th.d1 = r.d1;
+    th.d2 = r.d2;
     th.strategy = JP_STRATEGY_AUTO_COST;
-    if ((double)s.J <= 20.0 * (double)N) {  // Algorithm 2: small join, plain join only
-        th.d1 = th.d2 = JP_DELTA_INF;
-    }
     return th;
+}
+
+// Learned-selector features (see jp_plan_two_path).
+static double quantile(const jp_degree_index &d, double q) {
+    int64_t tot = 0;
+    for (int64_t i = 0; i < d.n; ++i) tot += d.count[i];
+    if (tot == 0) return 0.0;
+    const double want = q * (double)tot;
+    int64_t run = 0;
+    for (int64_t i = 0; i < d.n; ++i) {
+        run += d.count[i];
+        if ((double)run >= want) return (double)d.deg[i];
+    }
+    return (double)d.deg[d.n - 1];
+}
+
+void features16(const TwoPathSummary &s, float *f) {
+    const jp_two_path_summary v = s.view();
+    const jp_degree_index yr = s.yr.view(), ys = s.ys.view();
+    f[0] = (float)std::log((double)std::max<int64_t>(s.n_r, 1));
+    f[1] = (float)std::log((double)std::max<int64_t>(s.n_s, 1));
+    f[2] = (float)std::log(1.0 + s.out_est);
+    const double qs[5] = {0.5, 0.9, 0.99, 0.999, 1.0};
+    for (int i = 0; i < 5; ++i) {
+        f[3 + i] = (float)std::log(1.0 + quantile(yr, qs[i]));
+        f[8 + i] = (float)std::log(1.0 + quantile(ys, qs[i]));
+    }
+    f[13] = (float)std::log(1.0 + quantile(v.x, 0.99));
+    f[14] = (float)std::log(1.0 + quantile(v.x, 1.0));
+    f[15] = (float)std::log(1.0 + quantile(v.z, 1.0));
 }
 
 }  // namespace jp

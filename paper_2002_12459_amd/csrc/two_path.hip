@@ -108,32 +108,9 @@ __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
 
 }  // namespace
 
-jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
-                        const int32_t *sy, int64_t ns, const jp_options &o) {
-    const bool timing = (o.flags & JP_FLAG_TIMING) != 0;
-    Timeline tl(c, timing);
-    const int ev_start = tl.mark();
-    auto res = std::make_unique<jp_result>();
-    res->alloc = c.alloc;
-    res->arity = 2;
-    jp_stats &st = res->stats;
-    std::memset(&st, 0, sizeof(st));
-    st.arity = 2;
-    st.delta1 = st.delta2 = JP_DELTA_INF;
-    st.strategy = o.strategy;
-    st.dedup = JP_DEDUP_GLOBAL;
-
-    auto finish_empty = [&]() {
-        res->n = 0;
-        res->cols[0] = c.buf<int32_t>(1);
-        res->cols[1] = c.buf<int32_t>(1);
-        return res.release();
-    };
-    if (nr == 0 || ns == 0) return finish_empty();
-
-    DBuf<int64_t> scal = c.buf<int64_t>(32);  // device scalars
-    int64_t *S = scal.get();
-
+// Returns false when the instance has no output (no common y).
+static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                            const int32_t *sy, int64_t ns, Ingest &g, int64_t *S) {
     // ---- ranges of the id columns --------------------------------------------
     DBuf<int> mmb = c.buf<int>(8);
     int *mm = mmb.get();
@@ -305,7 +282,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     r1.reset();
     s1.reset();
     YR.reset();
-    if (n_r2 == 0 || n_s2 == 0) return finish_empty();
+    if (n_r2 == 0 || n_s2 == 0) return false;
 
     // ---- z ranks ---------------------------------------------------------------
     DBuf<uint32_t> ZS = c.buf<uint32_t>(n_s2);
@@ -391,6 +368,57 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     }
     zstart.reset();
     const int64_t J = c.load(S + 10);
+    g.n_r2 = n_r2;
+    g.n_s2 = n_s2;
+    g.dom_x = dom_x;
+    g.dom_y = dom_y;
+    g.dom_z = dom_z;
+    g.J = J;
+    g.r_xr = std::move(r_xr);
+    g.adj_r = std::move(adj_r);
+    g.adj_s = std::move(adj_s);
+    g.s2_y = std::move(s2_y);
+    g.dRy = std::move(dRy);
+    g.dSz = std::move(dSz);
+    g.xorig = std::move(xorig);
+    g.zorig = std::move(zorig);
+    g.off_x = std::move(off_x);
+    g.off_y = std::move(off_y);
+    return true;
+}
+
+jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                        const int32_t *sy, int64_t ns, const jp_options &o) {
+    const bool timing = (o.flags & JP_FLAG_TIMING) != 0;
+    Timeline tl(c, timing);
+    const int ev_start = tl.mark();
+    auto res = std::make_unique<jp_result>();
+    res->alloc = c.alloc;
+    res->arity = 2;
+    jp_stats &st = res->stats;
+    std::memset(&st, 0, sizeof(st));
+    st.arity = 2;
+    st.delta1 = st.delta2 = JP_DELTA_INF;
+    st.strategy = o.strategy;
+    st.dedup = JP_DEDUP_GLOBAL;
+
+    auto finish_empty = [&]() {
+        res->n = 0;
+        res->cols[0] = c.buf<int32_t>(1);
+        res->cols[1] = c.buf<int32_t>(1);
+        return res.release();
+    };
+    if (nr == 0 || ns == 0) return finish_empty();
+
+    DBuf<int64_t> scal = c.buf<int64_t>(32);  // device scalars
+    int64_t *S = scal.get();
+
+    Ingest g;
+    if (!ingest_two_path(c, rx, ry, nr, sz, sy, ns, g, S)) return finish_empty();
+    const int64_t n_r2 = g.n_r2, n_s2 = g.n_s2, dom_x = g.dom_x, dom_y = g.dom_y, dom_z = g.dom_z, J = g.J;
+    DBuf<int32_t> &r_xr = g.r_xr, &adj_r = g.adj_r, &adj_s = g.adj_s, &s2_y = g.s2_y, &dRy = g.dRy,
+                  &dSz = g.dSz, &xorig = g.xorig, &zorig = g.zorig;
+    DBuf<int64_t> &off_x = g.off_x, &off_y = g.off_y;
     const int ev_ingest = tl.mark();
     auto check_index = [&](const char *when) {
         std::string w(when);
@@ -429,7 +457,11 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     sum.J = J;
     sum.self_join = (rx == sz && ry == sy && nr == ns);
     sum.out_est = estimate_out(dom_x, dom_z, J, std::max(n_r2, n_s2));
-    Thresholds th = choose_thresholds(sum, o);
+    if (o.strategy == JP_STRATEGY_AUTO_COST || o.strategy == JP_STRATEGY_AUTO_MLP)
+        summarize_two_path(c, g, o.y_rule, sum);
+    jp_calibration cal_default;
+    if (!c.cal) default_calibration(&cal_default);
+    Thresholds th = choose_thresholds(sum, o, c.cal ? *c.cal : cal_default);
     st.delta1 = th.d1;
     st.delta2 = th.d2;
     st.strategy = th.strategy;
@@ -725,6 +757,34 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         st.ms_total = tl.ms(ev_start, ev_end);
     }
     return res.release();
+}
+
+void plan_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                   const int32_t *sy, int64_t ns, const jp_options &o, int64_t *d1, int64_t *d2, float *features) {
+    *d1 = *d2 = JP_DELTA_INF;
+    if (features)
+        for (int i = 0; i < 16; ++i) features[i] = 0.f;
+    if (nr == 0 || ns == 0) return;
+    DBuf<int64_t> scal = c.buf<int64_t>(32);
+    Ingest g;
+    if (!ingest_two_path(c, rx, ry, nr, sz, sy, ns, g, scal.get())) return;
+    TwoPathSummary sum;
+    sum.n_r = g.n_r2;
+    sum.n_s = g.n_s2;
+    sum.dom_x = g.dom_x;
+    sum.dom_y = g.dom_y;
+    sum.dom_z = g.dom_z;
+    sum.J = g.J;
+    sum.out_est = estimate_out(g.dom_x, g.dom_z, g.J, std::max(g.n_r2, g.n_s2));
+    summarize_two_path(c, g, o.y_rule, sum);
+    jp_calibration cal_default;
+    if (!c.cal) default_calibration(&cal_default);
+    jp_options oo = o;
+    if (oo.strategy == JP_STRATEGY_AUTO_MLP) oo.strategy = JP_STRATEGY_AUTO_COST;
+    const Thresholds th = choose_thresholds(sum, oo, c.cal ? *c.cal : cal_default);
+    *d1 = th.d1;
+    *d2 = th.d2;
+    if (features) features16(sum, features);
 }
 
 }  // namespace jp

@@ -195,3 +195,34 @@ def test_large_x_and_wide_z_domain(jp, dedup):
         assert x.size == ex.size
         np.testing.assert_array_equal(x, ex)
         np.testing.assert_array_equal(z, ez)
+
+
+def _planner_instances():
+    x, y = datagen.communities(6, 40, 30, 0.6, seed=1)
+    yield x, y, x, y
+    (rx, ry), (sz, sy) = datagen.twopath_c2(0.002)
+    yield rx, ry, sz, sy
+    x, y = datagen.zipf_edges(6000, 300, 200, 1.4, seed=9)
+    yield x, y, x, y
+
+
+@pytest.mark.parametrize("inst", range(3))
+def test_device_summary_drives_the_same_choice(jp, inst):
+    """The degree indexes built on the GPU give Algorithm 2 the same inputs as
+    the numpy restatement: the chosen thresholds agree, and the features are
+    the documented logs of sizes and degree quantiles."""
+    rx, ry, sz, sy = list(_planner_instances())[inst]
+    h = jp.default_handle(0)
+    cal = h.get_calibration()
+    for c in (cal, dict(cal, mm_s=[s * 1e-3 for s in cal["mm_s"]], t_byte=0.0)):
+        h.set_calibration(c)
+        d1, d2, f = h.plan_two_path(dev(rx), dev(ry), dev(sz), dev(sy))
+        s = ref.degree_summary(rx, ry, sz, sy)
+        e1, e2, _, _ = ref.algorithm2(s, c)
+        assert (d1, d2) == (e1, e2), (inst, d1, d2, e1, e2)
+    h.set_calibration(cal)
+    assert np.isclose(f[0], np.log(s["n_r"]), rtol=1e-5) and np.isclose(f[1], np.log(s["n_s"]), rtol=1e-5)
+    assert np.isclose(f[14], np.log(1 + s["x"][0][-1]), rtol=1e-5)
+    assert np.isclose(f[15], np.log(1 + s["z"][0][-1]), rtol=1e-5)
+    # and the whole pipeline under the optimizer's thresholds is exact
+    check_equal(jp, rx, ry, sz, sy, strategy="auto")
