@@ -53,20 +53,21 @@ Thresholds theory_thresholds(int64_t N, double out) {
 
 void default_calibration(jp_calibration *c) {
     std::memset(c, 0, sizeof(*c));
-    // measured on MI355X with this library (bench workload and the product
-    // sweep); replaced at run time by jp_set_calibration
-    c->t_witness = 2.6e-11;
+    // measured on MI355X with this library (paper_2002_12459_amd.calibrate):
+    // light witness cost, per-x index cost, heavy-matrix bytes, and the int8
+    // product on p x p x p operands; replaced at run time by jp_set_calibration
+    c->t_witness = 2.5188e-11;
     c->t_seq = 0.0;
-    c->t_byte = 2.5e-13;
-    c->t_x = 1.5e-9;
+    c->t_byte = 2.5000e-13;
+    c->t_x = 4.1686e-09;
     c->eps = 0.05;
     c->literal = 0;
     const double p[] = {1024, 2048, 4096, 8192, 12288, 16384, 20480};
-    const double rate = 1.3e15;  // int8 ops per second at large sizes
-    c->n_mm = 7;
-    for (int i = 0; i < 7; ++i) {
+    const double s[] = {2.4956e-05, 4.1555e-05, 1.3162e-04, 7.0919e-04, 2.2700e-03, 4.9962e-03, 9.9194e-03};
+    c->n_mm = (int32_t)(sizeof(p) / sizeof(p[0]));
+    for (int i = 0; i < c->n_mm; ++i) {
         c->mm_p[i] = p[i];
-        c->mm_s[i] = 2e-5 + 2.0 * p[i] * p[i] * p[i] / rate;
+        c->mm_s[i] = s[i];
     }
 }
 
