@@ -210,6 +210,70 @@ jp_status jp_plan_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y,
                            int64_t *delta2, float *features);
 
 /*
+ * Cost-model view of given thresholds on one instance (for threshold sweeps):
+ * indexes and summarises the instance like jp_plan_two_path, then writes for
+ * each i < n_cells Algorithm 2's estimated seconds of (delta1[i], delta2[i])
+ * (Section 5 cost terms with the handle's calibration) to est_seconds[i], and
+ * the heavy dimensions u, v, w the pair would give to heavy_dims[3i .. 3i+2].
+ * delta1 / delta2 are host arrays of values >= 1 (JP_DELTA_INF allowed);
+ * est_seconds and heavy_dims are host arrays and may be NULL.  An instance
+ * whose join is empty gives 0 everywhere.
+ */
+jp_status jp_plan_cells(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                        const int32_t *s_y, int64_t n_s, const jp_options *opt, int32_t n_cells,
+                        const int64_t *delta1, const int64_t *delta2, double *est_seconds, int64_t *heavy_dims);
+
+/*
+ * Learned threshold selector (strategy AUTO_MLP).  It replaces Algorithm 2's
+ * search (Section 5) by a fixed-size multilayer perceptron; any thresholds
+ * keep the result exact (Section 3.1), so only the run time depends on it.
+ *
+ * Network: the 16 features of jp_plan_two_path, normalised as
+ * (f - mean) / scale, then 16 -> 64 (ReLU) -> 64 (ReLU) -> n_out, fp32.
+ * Output k is the predicted log run-time ratio of threshold cell k; the cell
+ * with the smallest output is used.  Parameters are one flat fp32 array:
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[n_out][64], b3[n_out]
+ * (jp_mlp_param_count(n_out) floats).
+ */
+
+/* Threshold cells scored by the selector, fixed by the features: cell
+ * 8 i + j (i, j < 8) has Delta1 = round(2 (Ymax / 2)^(i/7)) and
+ * Delta2 = round(Xmax^(j/7)), with Ymax = max(2, largest y degree in R or S)
+ * and Xmax = max(1, largest x degree) read back from features 7, 12 and 14;
+ * cell 64 is light only (both JP_DELTA_INF).  Writes 65 entries to each
+ * host array and returns 65 (0 if an argument is NULL). */
+int32_t jp_selector_cells(const float *features, int64_t *delta1, int64_t *delta2);
+
+/* Number of parameters of the selector network with n_out outputs. */
+int64_t jp_mlp_param_count(int32_t n_out);
+
+/* Install selector weights in the handle (host arrays, copied; n_out must be
+ * 65; feat_mean / feat_scale hold 16 values, scale > 0).  params == NULL
+ * removes the selector, after which AUTO_MLP behaves as AUTO_COST. */
+jp_status jp_set_selector(jp_handle *h, const float *params, int32_t n_out, const float *feat_mean,
+                          const float *feat_scale);
+
+/* Forward pass for a batch: x is batch x 16 and y is batch x n_out, row-major
+ * device fp32 arrays; params is the device parameter array.  1 <= n_out <= 256. */
+jp_status jp_mlp_forward(jp_handle *h, const float *params, int32_t n_out, const float *x, int64_t batch, float *y);
+
+/* Gradient of the weighted squared error
+ *   L = (1/batch) sum_s [sum_k m[s,k] (y[s,k] - t[s,k])^2] / max(1, sum_k m[s,k])
+ * with respect to params, for targets t (batch x n_out) and weights
+ * m >= 0 (batch x n_out; 0 marks a missing label).  Device arrays; grad
+ * (jp_mlp_param_count floats) and *loss (1 float) are overwritten.  The
+ * per-sample terms are summed with atomics, so the last bits vary between
+ * runs. */
+jp_status jp_mlp_grad(jp_handle *h, const float *params, int32_t n_out, const float *x, const float *target,
+                      const float *weight, int64_t batch, float *grad, float *loss);
+
+/* One Adam step (bias-corrected, step counted from 1) on n device fp32
+ * values: m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ * p <- p - lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+jp_status jp_mlp_adam(jp_handle *h, float *params, float *m, float *v, const float *grad, int64_t n, int32_t step,
+                      float lr, float beta1, float beta2, float eps);
+
+/*
  * Two-path join-project (Algorithm 1, Section 3.1).
  * R = (r_x[i], r_y[i]) for i < n_r and S = (s_z[i], s_y[i]) for i < n_s.
  * opt may be NULL (defaults).  With strategy FIXED, delta1 and delta2 must be

@@ -17,11 +17,16 @@ import threading
 
 __all__ = [
     "LIB_PATH", "JoinProjectError", "Handle", "Result", "two_path", "star", "bool_matmul",
-    "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF",
+    "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF", "selector_cells", "mlp_param_count",
+    "SELECTOR_PATH", "load_selector_file",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjoinproject.so")
+# Trained threshold-selector weights for MI355X (written by selector.py).
+SELECTOR_PATH = os.path.join(_HERE, "selector_mi355x.json")
+N_FEATURES = 16
+N_CELLS = 65
 
 DELTA_INF = 2**63 - 1
 STRATEGY = {"auto": 0, "cost": 0, "theory": 1, "fixed": 2, "light": 3, "mlp": 4}
@@ -134,9 +139,23 @@ def _load():
                                         ctypes.POINTER(ctypes.c_double)]
         lib.jp_plan_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(i64),
                                          ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
+        lib.jp_plan_cells.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.c_int32,
+                                      ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
+                                      ctypes.POINTER(i64)]
+        lib.jp_selector_cells.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.jp_selector_cells.restype = ctypes.c_int32
+        lib.jp_mlp_param_count.argtypes = [ctypes.c_int32]
+        lib.jp_mlp_param_count.restype = i64
+        lib.jp_set_selector.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]
+        lib.jp_mlp_forward.argtypes = [P, P, ctypes.c_int32, P, i64, P]
+        lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
+        f32 = ctypes.c_float
+        lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
         for f in ("jp_create", "jp_set_stream", "jp_two_path", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
-                  "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path"):
+                  "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
+                  "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -200,10 +219,31 @@ class Result:
             pass
 
 
-class Handle:
-    """One library handle per device; work goes to torch's current stream."""
+def _f32(t, name, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must hold {n} values")
+    return t
 
-    def __init__(self, device: int = 0):
+
+def load_selector_file(path=SELECTOR_PATH):
+    """(params, mean, scale) lists of a selector weight file (JSON)."""
+    import json
+    with open(path) as fh:
+        d = json.load(fh)
+    return d["params"], d["mean"], d["scale"]
+
+
+class Handle:
+    """One library handle per device; work goes to torch's current stream.
+
+    ``selector="default"`` installs the packaged MI355X selector weights when
+    the file exists (used by strategy "mlp"); None leaves the handle without
+    a selector, so "mlp" behaves as "auto"."""
+
+    def __init__(self, device: int = 0, selector="default"):
         lib = _load()
         self.device = device
         p = ctypes.c_void_p()
@@ -211,6 +251,11 @@ class Handle:
         if st != 0:
             raise JoinProjectError(st, f"jp_create({device}) failed")
         self._p = p
+        if selector == "default":
+            if os.path.exists(SELECTOR_PATH):
+                self.set_selector(*load_selector_file(SELECTOR_PATH))
+        elif selector is not None:
+            self.set_selector(*selector)
 
     def _check(self, st):
         if st != 0:
@@ -327,6 +372,79 @@ class Handle:
         inf = lambda v: None if v == DELTA_INF else v
         return inf(d1.value), inf(d2.value), list(f)
 
+    def plan_cells(self, rx, ry, sz, sy, delta1, delta2, y_rule="max"):
+        """Cost-model seconds and heavy (u, v, w) of each threshold pair
+        (None = infinity) on one instance."""
+        rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+        n = len(delta1)
+        if len(delta2) != n:
+            raise ValueError("delta1 and delta2 differ in length")
+        self._bind_stream()
+        o = self._options(None, None, "auto", "auto", y_rule, "auto", False, None)
+        conv = lambda v: DELTA_INF if v is None else int(v)
+        a = (ctypes.c_int64 * max(n, 1))(*[conv(v) for v in delta1])
+        b = (ctypes.c_int64 * max(n, 1))(*[conv(v) for v in delta2])
+        est = (ctypes.c_double * max(n, 1))()
+        dims = (ctypes.c_int64 * max(3 * n, 1))()
+        self._check(_load().jp_plan_cells(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(),
+                                          ctypes.byref(o), n, a, b, est, dims))
+        return list(est[:n]), [tuple(dims[3 * i: 3 * i + 3]) for i in range(n)]
+
+    def set_selector(self, params, mean, scale):
+        """Install selector weights (sequences of floats: parameters, 16 feature
+        means, 16 feature scales)."""
+        npar = mlp_param_count(N_CELLS)
+        if len(params) != npar or len(mean) != N_FEATURES or len(scale) != N_FEATURES:
+            raise ValueError(f"selector needs {npar} parameters and 16 means / scales")
+        P = (ctypes.c_float * npar)(*[float(v) for v in params])
+        M = (ctypes.c_float * N_FEATURES)(*[float(v) for v in mean])
+        S = (ctypes.c_float * N_FEATURES)(*[float(v) for v in scale])
+        self._check(_load().jp_set_selector(self._p, P, N_CELLS, M, S))
+
+    def clear_selector(self):
+        self._check(_load().jp_set_selector(self._p, None, 0, None, None))
+
+    def mlp_forward(self, params, x, n_out=N_CELLS):
+        """Forward pass of the selector network on a (batch, 16) float32 CUDA tensor."""
+        torch = _torch()
+        _f32(params, "params", mlp_param_count(n_out))
+        _f32(x, "x")
+        b = x.numel() // N_FEATURES
+        if x.numel() != b * N_FEATURES:
+            raise ValueError("x must have 16 columns")
+        y = torch.empty((b, n_out), dtype=torch.float32, device=x.device)
+        self._bind_stream()
+        self._check(_load().jp_mlp_forward(self._p, _ptr(params), n_out, _ptr(x), b, _ptr(y)))
+        return y
+
+    def mlp_grad(self, params, x, target, weight, grad=None, loss=None):
+        """Loss gradient (written into / returned as a new tensor) and loss."""
+        torch = _torch()
+        b, n_out = target.shape
+        _f32(params, "params", mlp_param_count(n_out))
+        _f32(x, "x", b * N_FEATURES)
+        _f32(target, "target")
+        _f32(weight, "weight", b * n_out)
+        if grad is None:
+            grad = torch.empty_like(params)
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=params.device)
+        _f32(grad, "grad", params.numel())
+        _f32(loss, "loss", 1)
+        self._bind_stream()
+        self._check(_load().jp_mlp_grad(self._p, _ptr(params), n_out, _ptr(x), _ptr(target), _ptr(weight), b,
+                                         _ptr(grad), _ptr(loss)))
+        return grad, loss
+
+    def mlp_adam(self, params, m, v, grad, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        """One Adam step in place on params, m, v."""
+        n = params.numel()
+        for t, nm in ((params, "params"), (m, "m"), (v, "v"), (grad, "grad")):
+            _f32(t, nm, n)
+        self._bind_stream()
+        self._check(_load().jp_mlp_adam(self._p, _ptr(params), _ptr(m), _ptr(v), _ptr(grad), n, int(step),
+                                         float(lr), float(beta1), float(beta2), float(eps)))
+
     def close(self):
         if getattr(self, "_p", None):
             _load().jp_destroy(self._p)
@@ -366,6 +484,21 @@ def star(rels, **kw):
 
 def bool_matmul(A, Bt, **kw):
     return default_handle(A.device.index).bool_matmul(A, Bt, **kw)
+
+
+def selector_cells(features):
+    """The 65 (delta1, delta2) cells the selector scores for these 16
+    features (None = infinity)."""
+    f = (ctypes.c_float * N_FEATURES)(*[float(v) for v in features])
+    a = (ctypes.c_int64 * N_CELLS)()
+    b = (ctypes.c_int64 * N_CELLS)()
+    n = _load().jp_selector_cells(f, a, b)
+    inf = lambda v: None if v == DELTA_INF else v
+    return [inf(v) for v in a[:n]], [inf(v) for v in b[:n]]
+
+
+def mlp_param_count(n_out=N_CELLS):
+    return int(_load().jp_mlp_param_count(n_out))
 
 
 def default_calibration():

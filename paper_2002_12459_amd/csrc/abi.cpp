@@ -2,6 +2,7 @@
 // exception-to-status translation and result ownership.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <memory>
 #include <string>
@@ -15,6 +16,7 @@ struct jp_handle {
     int num_cus = 256;
     std::string err;
     jp_calibration cal;
+    jp::Selector sel;  // after alloc: its buffer returns to the allocator first
 };
 
 namespace {
@@ -39,6 +41,7 @@ jp::Ctx make_ctx(jp_handle *h) {
     c.device = h->device;
     c.num_cus = h->num_cus;
     c.cal = &h->cal;
+    c.sel = &h->sel;
     return c;
 }
 
@@ -266,6 +269,106 @@ jp_status jp_plan_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y,
     jp_status v = validate_options(h, o);
     if (v != JP_OK) return v;
     return guarded(h, [&] { jp::plan_two_path(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o, delta1, delta2, features); });
+}
+
+jp_status jp_plan_cells(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                        const int32_t *s_y, int64_t n_s, const jp_options *opt, int32_t n_cells,
+                        const int64_t *delta1, const int64_t *delta2, double *est_seconds, int64_t *heavy_dims) {
+    if (!h) return JP_EINVAL;
+    if (n_cells < 0 || (n_cells > 0 && (!delta1 || !delta2)) || bad_col(r_x, n_r) || bad_col(r_y, n_r) ||
+        bad_col(s_z, n_s) || bad_col(s_y, n_s)) {
+        h->err = "bad argument to jp_plan_cells";
+        return JP_EINVAL;
+    }
+    for (int32_t i = 0; i < n_cells; ++i)
+        if (delta1[i] < 1 || delta2[i] < 1) {
+            h->err = "thresholds must be >= 1";
+            return JP_EINVAL;
+        }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    return guarded(h, [&] {
+        jp::plan_cells(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o, n_cells, delta1, delta2, est_seconds,
+                       heavy_dims);
+    });
+}
+
+int32_t jp_selector_cells(const float *features, int64_t *delta1, int64_t *delta2) {
+    if (!features || !delta1 || !delta2) return 0;
+    jp::selector_cells(features, delta1, delta2);
+    return jp::kSelectorCells;
+}
+
+int64_t jp_mlp_param_count(int32_t n_out) { return n_out < 1 ? 0 : jp::mlp_param_count(n_out); }
+
+jp_status jp_set_selector(jp_handle *h, const float *params, int32_t n_out, const float *feat_mean,
+                          const float *feat_scale) {
+    if (!h) return JP_EINVAL;
+    if (!params) {
+        h->sel.params.reset();
+        h->sel.n_out = 0;
+        return JP_OK;
+    }
+    if (n_out != jp::kSelectorCells || !feat_mean || !feat_scale) {
+        h->err = "selector needs 65 outputs and the feature mean and scale";
+        return JP_EINVAL;
+    }
+    for (int i = 0; i < jp::kFeatures; ++i)
+        if (!(feat_scale[i] > 0) || !std::isfinite(feat_mean[i])) {
+            h->err = "feature scale must be positive and the mean finite";
+            return JP_EINVAL;
+        }
+    const int64_t np = jp::mlp_param_count(n_out);
+    for (int64_t i = 0; i < np; ++i)
+        if (!std::isfinite(params[i])) {
+            h->err = "selector weights must be finite";
+            return JP_EINVAL;
+        }
+    return guarded(h, [&] {
+        jp::Ctx c = make_ctx(h);
+        jp::DBuf<float> p = c.buf<float>((size_t)np);
+        JP_HIP(hipMemcpyAsync(p.get(), params, (size_t)np * sizeof(float), hipMemcpyHostToDevice, c.stream));
+        c.sync();
+        h->sel.params = std::move(p);
+        h->sel.n_out = n_out;
+        std::memcpy(h->sel.mean, feat_mean, sizeof(h->sel.mean));
+        std::memcpy(h->sel.scale, feat_scale, sizeof(h->sel.scale));
+    });
+}
+
+jp_status jp_mlp_forward(jp_handle *h, const float *params, int32_t n_out, const float *x, int64_t batch,
+                         float *y) {
+    if (!h) return JP_EINVAL;
+    if (n_out < 1 || n_out > 256 || batch < 0 || !params || bad_col(x, batch) || bad_col(y, batch)) {
+        h->err = "bad argument to jp_mlp_forward";
+        return JP_EINVAL;
+    }
+    return guarded(h, [&] { jp::mlp_forward(make_ctx(h), params, n_out, x, batch, y); });
+}
+
+jp_status jp_mlp_grad(jp_handle *h, const float *params, int32_t n_out, const float *x, const float *target,
+                      const float *weight, int64_t batch, float *grad, float *loss) {
+    if (!h) return JP_EINVAL;
+    if (n_out < 1 || n_out > 256 || batch < 0 || !params || !grad || !loss || bad_col(x, batch) ||
+        bad_col(target, batch) || bad_col(weight, batch)) {
+        h->err = "bad argument to jp_mlp_grad";
+        return JP_EINVAL;
+    }
+    return guarded(h, [&] { jp::mlp_grad(make_ctx(h), params, n_out, x, target, weight, batch, grad, loss); });
+}
+
+jp_status jp_mlp_adam(jp_handle *h, float *params, float *m, float *v, const float *grad, int64_t n, int32_t step,
+                      float lr, float beta1, float beta2, float eps) {
+    if (!h) return JP_EINVAL;
+    if (n < 0 || step < 1 || bad_col(params, n) || bad_col(m, n) || bad_col(v, n) || bad_col(grad, n) ||
+        !(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0)) {
+        h->err = "bad argument to jp_mlp_adam";
+        return JP_EINVAL;
+    }
+    return guarded(h, [&] { jp::mlp_adam(make_ctx(h), params, m, v, grad, n, step, lr, beta1, beta2, eps); });
 }
 
 jp_status jp_result_size(const jp_result *r, int64_t *n_tuples, int32_t *arity) {

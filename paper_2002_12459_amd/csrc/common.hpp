@@ -158,6 +158,8 @@ class DBuf {
     size_t n_ = 0;
 };
 
+struct Selector;
+
 // Execution context of one call: device, stream, allocator, chip size.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -166,6 +168,7 @@ struct Ctx {
     int num_cus = 256;
     size_t lds_bytes = 160 * 1024;
     const jp_calibration *cal = nullptr;  // optimizer constants of the handle
+    const Selector *sel = nullptr;        // learned threshold selector of the handle (may be empty)
 
     template <class T>
     DBuf<T> buf(size_t n) const {

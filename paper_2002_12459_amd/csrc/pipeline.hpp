@@ -69,6 +69,24 @@ struct Thresholds {
     bool light_only() const { return d1 == JP_DELTA_INF && d2 == JP_DELTA_INF; }
 };
 
+// Learned threshold selector: weights on the device, input normalisation on
+// the host (mlp.hip).
+constexpr int kFeatures = 16;
+constexpr int kSelectorCells = 65;  // 8 x 8 geometric (Delta1, Delta2) grid + light only
+struct Selector {
+    int32_t n_out = 0;
+    DBuf<float> params;
+    float mean[kFeatures] = {}, scale[kFeatures] = {};
+    bool ready() const { return n_out > 0 && params.get() != nullptr; }
+};
+int64_t mlp_param_count(int n_out);
+void mlp_forward(const Ctx &c, const float *params, int K, const float *x, int64_t batch, float *y);
+void mlp_grad(const Ctx &c, const float *params, int K, const float *x, const float *target, const float *mask,
+              int64_t batch, float *grad, float *loss);
+void mlp_adam(const Ctx &c, float *params, float *m, float *v, const float *grad, int64_t n, int step, float lr,
+              float b1, float b2, float eps);
+void selector_cells(const float *features, int64_t *d1, int64_t *d2);
+
 // Planner (host).
 Thresholds choose_thresholds(const TwoPathSummary &s, const jp_options &o, const jp_calibration &cal);
 double estimate_out(int64_t dom_x, int64_t dom_z, int64_t J, int64_t N);
@@ -76,10 +94,19 @@ Thresholds theory_thresholds(int64_t N, double out);
 PlanResult algorithm2(const jp_two_path_summary &s, const jp_calibration &c);
 void default_calibration(jp_calibration *c);
 void features16(const TwoPathSummary &s, float *f);
+// Algorithm 2's cost of one threshold pair and the heavy dimensions u, v, w.
+double plan_cost(const jp_two_path_summary &s, const jp_calibration &c, int64_t d1, int64_t d2, int64_t *uvw);
+// Threshold choice for any strategy, running the selector for AUTO_MLP when
+// the context holds one (otherwise Algorithm 2).
+Thresholds select_thresholds(const Ctx &c, const TwoPathSummary &s, const jp_options &o);
 
 // Two-path index + summary (+ thresholds) without the join (jp_plan_two_path).
 void plan_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
                    const int32_t *sy, int64_t ns, const jp_options &o, int64_t *d1, int64_t *d2, float *features);
+// Cost-model estimates of given threshold pairs on one instance (jp_plan_cells).
+void plan_cells(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz, const int32_t *sy,
+                int64_t ns, const jp_options &o, int32_t n_cells, const int64_t *d1, const int64_t *d2,
+                double *est_seconds, int64_t *heavy_dims);
 
 // Index build of a two-path instance (Section 5, "Indexing relations"):
 // R x-major (off_x, adj_r = y rank, r_xr = x rank per tuple), S y-major

@@ -10,7 +10,7 @@
 //              clamped to [1, N].
 //  AUTO_COST   Algorithm 2 (Section 5) on the degree indexes of the instance
 //              with this device's measured constants.
-//  AUTO_MLP    learned selector (selector.cpp); Algorithm 2 without weights.
+//  AUTO_MLP    learned selector (mlp.hip); Algorithm 2 when the handle has none.
 #include <algorithm>
 #include <cmath>
 
@@ -105,25 +105,44 @@ double mm_hat(const jp_calibration &c, double u, double v, double w) {
     return c.mm_s[best] * (u * v * w) / (pb * pb * pb);
 }
 
+// Algorithm 2's cost of a threshold pair on one instance's indexes.
+struct CostModel {
+    const jp_two_path_summary &s;
+    const jp_calibration &c;
+    Index Y, X, XC, Z;
+    CostModel(const jp_two_path_summary &s_, const jp_calibration &c_)
+        : s(s_), c(c_), Y(s_.y), X(s_.x), XC(s_.xcdf), Z(s_.z) {}
+    double operator()(int64_t d1, int64_t d2, int64_t *uvw = nullptr) const {
+        // light: T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
+        const double light = c.t_witness * (Y.sum_le(d1) + X.sum_le(d2)) + c.t_x * (double)s.dom_x +
+                             c.t_seq * (double)XC.count_le(d1) * (double)s.dom_x;
+        // heavy: M-hat(u, v, w) + allocation of the heavy matrices
+        const int64_t u = s.dom_x - X.count_le(d2), v = s.dom_y - Y.count_le(d1), w = s.dom_z - Z.count_le(d2);
+        if (uvw) {
+            uvw[0] = u;
+            uvw[1] = v;
+            uvw[2] = w;
+        }
+        double heavy = 0.0;
+        if (u > 0 && v > 0 && w > 0)
+            heavy = mm_hat(c, (double)u, (double)v, (double)w) + c.t_byte * ((double)u * v + (double)w * v);
+        return light + heavy;
+    }
+};
+
 }  // namespace
+
+double plan_cost(const jp_two_path_summary &s, const jp_calibration &c, int64_t d1, int64_t d2, int64_t *uvw) {
+    return CostModel(s, c)(d1, d2, uvw);
+}
 
 PlanResult algorithm2(const jp_two_path_summary &s, const jp_calibration &c) {
     PlanResult r;
     const int64_t N = std::max(s.n_r, s.n_s);
     const double out = std::max(s.out_est, 1.0);
-    const Index Y(s.y), X(s.x), XC(s.xcdf), Z(s.z);
-    auto cost = [&](int64_t d1, int64_t d2) {
-        // light: T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
-        const double light = c.t_witness * (Y.sum_le(d1) + X.sum_le(d2)) + c.t_x * (double)s.dom_x +
-                             c.t_seq * (double)XC.count_le(d1) * (double)s.dom_x;
-        // heavy: M-hat(u, v, w) + allocation of the heavy matrices
-        const double u = (double)(s.dom_x - X.count_le(d2));
-        const double v = (double)(s.dom_y - Y.count_le(d1));
-        const double w = (double)(s.dom_z - Z.count_le(d2));
-        double heavy = 0.0;
-        if (u > 0 && v > 0 && w > 0) heavy = mm_hat(c, u, v, w) + c.t_byte * (u * v + w * v);
-        return light + heavy;
-    };
+    const CostModel cm(s, c);
+    const Index &Y = cm.Y;
+    auto cost = [&](int64_t d1, int64_t d2) { return cm(d1, d2); };
     r.cost_light_only = cost(JP_DELTA_INF, JP_DELTA_INF);
     if ((double)s.J <= 20.0 * (double)N || N <= 0) {  // small join: plain worst-case optimal join
         r.d1 = r.d2 = JP_DELTA_INF;

@@ -377,7 +377,7 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
             return (p < n) & (a[q] == v);
         };
         compact(
-            c, raw[0].ny, [=] __device__(int64_t j) { return in(y1, n1, y0[j]) & in(y2, n2, y0[j]); },
+            c, raw[0].ny, [=] __device__(int64_t j) { return (int)in(y1, n1, y0[j]) & (int)in(y2, n2, y0[j]); },
             [=] __device__(int64_t j, int64_t p) { d[p] = y0[j]; }, S + 1);
     }
     const int64_t dom_y = c.load(S + 1);

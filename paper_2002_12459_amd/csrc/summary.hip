@@ -1,9 +1,14 @@
 // Degree indexes of a two-path instance for the threshold choice (Section 5,
 // "Indexing relations": for a threshold delta the indexes give sum(y_delta),
 // sum(x_delta), cdfx(y_delta) and count(w_delta) by binary search over a
-// sorted degree vector).  Built on the device as degree histograms (LDS bins
-// for small degrees, global bins up to kHist, a compacted list beyond), then
-// compacted to the nonzero degrees and copied to the host.
+// sorted degree vector).
+//
+// All six indexes (y key degree with witness sums, deg_R(y), deg_S(y),
+// deg_R(x) with witness sums, cdfx, deg_S(z)) are built by one histogram
+// launch (grid.y = index): degrees below kLdsBins go to per-workgroup LDS
+// bins, degrees below kHist to global bins, larger ones to an append list.
+// One compaction keeps the nonzero bins; the host then waits twice (sizes,
+// then data) and merges the append list.
 #include <algorithm>
 
 #include "pipeline.hpp"
@@ -12,148 +17,187 @@
 namespace jp {
 namespace {
 
-constexpr int64_t kHist = 1 << 16;
-constexpr int kLdsBins = 1024;
+constexpr int kIdx = 6;              // y, yr, ys, x, xcdf, z
+constexpr int64_t kHist = 1 << 16;   // global bins per index
+constexpr int kLdsBins = 1024;       // LDS bins per workgroup
+constexpr int kHistBlock = 256;
 
-template <class DegF, class SumF>
-__global__ __launch_bounds__(256) void k_deg_hist(int64_t n, DegF degf, SumF sumf, unsigned long long *cnt,
-                                                  unsigned long long *sums) {
+struct IndexArgs {
+    const int32_t *dry, *dsz, *ar;
+    const int64_t *oy, *ox;
+    int64_t dom_y, dom_x, dom_z;
+    bool ronly;
+    unsigned long long *cnt;   // [kIdx][kHist]
+    unsigned long long *sums;  // [kIdx][kHist]
+    int64_t *big;              // append list: idx << 56 | degree, then sum (pairs)
+    unsigned long long *nbig;
+    int64_t big_cap;
+};
+
+__device__ __forceinline__ int64_t key_deg(const IndexArgs &a, int64_t y) {
+    const int64_t dr = a.dry[y], ds = a.oy[y + 1] - a.oy[y];
+    return a.ronly ? dr : (dr > ds ? dr : ds);
+}
+
+// Degree and summed work of element i of index k.
+__device__ __forceinline__ void index_value(const IndexArgs &a, int k, int64_t i, int64_t &d, unsigned long long &s) {
+    s = 0;
+    switch (k) {
+        case 0: {  // y: key degree, witnesses deg_R(y) deg_S(y)
+            const int64_t ds = a.oy[i + 1] - a.oy[i];
+            d = key_deg(a, i);
+            s = (unsigned long long)a.dry[i] * (unsigned long long)ds;
+            break;
+        }
+        case 1: d = a.dry[i]; break;
+        case 2: d = a.oy[i + 1] - a.oy[i]; break;
+        case 3: {  // x: deg_R(x), witnesses sum over y of deg_S(y)
+            const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
+            unsigned long long w = 0;
+            for (int64_t e = e0; e < e1; ++e) {
+                const int32_t y = a.ar[e];
+                w += (unsigned long long)(a.oy[y + 1] - a.oy[y]);
+            }
+            d = e1 - e0;
+            s = w;
+            break;
+        }
+        case 4: {  // cdfx: smallest key degree among the y of x
+            int64_t m = INT64_MAX;
+            for (int64_t e = a.ox[i]; e < a.ox[i + 1]; ++e) {
+                const int64_t kd = key_deg(a, a.ar[e]);
+                m = kd < m ? kd : m;
+            }
+            d = m;
+            break;
+        }
+        default: d = a.dsz[i]; break;
+    }
+}
+
+__global__ __launch_bounds__(kHistBlock) void k_index_hist(IndexArgs a) {
     __shared__ unsigned int lc[kLdsBins];
     __shared__ unsigned long long ls[kLdsBins];
-    for (int b = threadIdx.x; b < kLdsBins; b += 256) {
+    const int k = blockIdx.y;
+    const int64_t n = k < 3 ? a.dom_y : (k < 5 ? a.dom_x : a.dom_z);
+    if ((int64_t)blockIdx.x * kHistBlock >= n) return;  // whole workgroup idle for this index
+    for (int b = threadIdx.x; b < kLdsBins; b += kHistBlock) {
         lc[b] = 0;
         ls[b] = 0;
     }
     __syncthreads();
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int64_t d = degf(i);
-        const unsigned long long s = sumf(i);
+    unsigned long long *cnt = a.cnt + (int64_t)k * kHist, *sums = a.sums + (int64_t)k * kHist;
+    for (int64_t i = (int64_t)blockIdx.x * kHistBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kHistBlock) {
+        int64_t d;
+        unsigned long long s;
+        index_value(a, k, i, d, s);
         if (d < kLdsBins) {
             atomicAdd(&lc[d], 1u);
             if (s) atomicAdd(&ls[d], s);
         } else if (d < kHist) {
             atomicAdd(&cnt[d], 1ull);
             if (s) atomicAdd(&sums[d], s);
+        } else {
+            const unsigned long long p = atomicAdd(a.nbig, 1ull);
+            if ((int64_t)p < a.big_cap) {
+                a.big[2 * p] = ((int64_t)k << 56) | (d < (1ll << 56) ? d : (1ll << 56) - 1);
+                a.big[2 * p + 1] = (int64_t)s;
+            }
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < kLdsBins; b += 256) {
+    for (int b = threadIdx.x; b < kLdsBins; b += kHistBlock) {
         if (lc[b]) atomicAdd(&cnt[b], (unsigned long long)lc[b]);
         if (ls[b]) atomicAdd(&sums[b], ls[b]);
     }
 }
 
-template <class DegF, class SumF>
-HostIndex build_index(const Ctx &c, int64_t n, DegF degf, SumF sumf, bool with_sum) {
-    HostIndex h;
-    if (n <= 0) return h;
-    DBuf<unsigned long long> cnt = c.buf<unsigned long long>(kHist), sums = c.buf<unsigned long long>(kHist);
-    c.zero(cnt.get(), kHist);
-    c.zero(sums.get(), kHist);
-    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 4);
-    hipLaunchKernelGGL((k_deg_hist<DegF, SumF>), dim3((unsigned)blocks), dim3(256), 0, c.stream, n, degf, sumf,
-                       cnt.get(), sums.get());
-    JP_HIP(hipGetLastError());
-    DBuf<int64_t> S = c.buf<int64_t>(2);
-    // nonzero bins
-    DBuf<int64_t> bd = c.buf<int64_t>(kHist), bc = c.buf<int64_t>(kHist), bs = c.buf<int64_t>(kHist);
-    {
-        const unsigned long long *cp = cnt.get(), *sp = sums.get();
-        int64_t *d = bd.get(), *cc = bc.get(), *ss = bs.get();
-        compact(
-            c, kHist, [=] __device__(int64_t b) { return cp[b] != 0; },
-            [=] __device__(int64_t b, int64_t p) {
-                d[p] = b;
-                cc[p] = (int64_t)cp[b];
-                ss[p] = (int64_t)sp[b];
-            },
-            S.get());
-    }
-    // values with degree >= kHist, listed one by one
-    DBuf<int64_t> od = c.buf<int64_t>(n), os = c.buf<int64_t>(n);
-    {
-        int64_t *d = od.get(), *ss = os.get();
-        compact(
-            c, n, [=] __device__(int64_t i) { return degf(i) >= kHist; },
-            [=] __device__(int64_t i, int64_t p) {
-                d[p] = degf(i);
-                ss[p] = (int64_t)sumf(i);
-            },
-            S.get() + 1);
-    }
-    int64_t hn[2];
-    c.load_n(hn, S.get(), 2);
-    std::vector<int64_t> d(hn[0]), cc(hn[0]), ss(hn[0]), e(hn[1]), es(hn[1]);
-    c.load_n(d.data(), bd.get(), hn[0]);
-    c.load_n(cc.data(), bc.get(), hn[0]);
-    c.load_n(ss.data(), bs.get(), hn[0]);
-    c.load_n(e.data(), od.get(), hn[1]);
-    c.load_n(es.data(), os.get(), hn[1]);
-    h.deg = d;
-    h.count = cc;
-    if (with_sum) h.sum.assign(ss.begin(), ss.end());
-    if (hn[1]) {
-        std::vector<std::pair<int64_t, int64_t>> big(hn[1]);
-        for (int64_t i = 0; i < hn[1]; ++i) big[i] = {e[i], es[i]};
-        std::sort(big.begin(), big.end());
-        for (size_t i = 0; i < big.size();) {
-            size_t j = i;
-            int64_t cn = 0;
-            double sm = 0;
-            while (j < big.size() && big[j].first == big[i].first) {
-                ++cn;
-                sm += (double)big[j].second;
-                ++j;
-            }
-            h.deg.push_back(big[i].first);
-            h.count.push_back(cn);
-            if (with_sum) h.sum.push_back(sm);
-            i = j;
-        }
-    }
-    return h;
-}
-
 }  // namespace
 
 void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummary &s) {
-    const int32_t *dry = g.dRy.get(), *dsz = g.dSz.get(), *ar = g.adj_r.get();
-    const int64_t *oy = g.off_y.get(), *ox = g.off_x.get();
-    const bool ronly = y_rule == JP_Y_RULE_R_ONLY;
-    auto kd = [=] __device__(int64_t y) -> int64_t {
-        const int64_t dr = dry[y], ds = oy[y + 1] - oy[y];
-        return ronly ? dr : (dr > ds ? dr : ds);
-    };
-    auto zero = [=] __device__(int64_t) -> unsigned long long { return 0ull; };
-    s.y = build_index(
-        c, g.dom_y, kd,
-        [=] __device__(int64_t y) -> unsigned long long {
-            return (unsigned long long)dry[y] * (unsigned long long)(oy[y + 1] - oy[y]);
-        },
-        true);
-    s.yr = build_index(c, g.dom_y, [=] __device__(int64_t y) -> int64_t { return dry[y]; }, zero, false);
-    s.ys = build_index(c, g.dom_y, [=] __device__(int64_t y) -> int64_t { return oy[y + 1] - oy[y]; }, zero, false);
-    s.x = build_index(
-        c, g.dom_x, [=] __device__(int64_t x) -> int64_t { return ox[x + 1] - ox[x]; },
-        [=] __device__(int64_t x) -> unsigned long long {
-            unsigned long long w = 0;
-            for (int64_t e = ox[x]; e < ox[x + 1]; ++e) w += (unsigned long long)(oy[ar[e] + 1] - oy[ar[e]]);
-            return w;
-        },
-        true);
-    s.xcdf = build_index(
-        c, g.dom_x,
-        [=] __device__(int64_t x) -> int64_t {
-            int64_t m = INT64_MAX;
-            for (int64_t e = ox[x]; e < ox[x + 1]; ++e) {
-                const int64_t k = kd(ar[e]);
-                m = k < m ? k : m;
-            }
-            return m;
-        },
-        zero, false);
-    s.z = build_index(c, g.dom_z, [=] __device__(int64_t z) -> int64_t { return dsz[z]; }, zero, false);
+    HostIndex *out[kIdx] = {&s.y, &s.yr, &s.ys, &s.x, &s.xcdf, &s.z};
+    const bool with_sum[kIdx] = {true, false, false, true, false, false};
+    for (HostIndex *h : out) *h = HostIndex();
     s.have_indexes = true;
+    const int64_t nmax = std::max(g.dom_y, std::max(g.dom_x, g.dom_z));
+    if (nmax <= 0) return;
+
+    IndexArgs a;
+    a.dry = g.dRy.get();
+    a.dsz = g.dSz.get();
+    a.ar = g.adj_r.get();
+    a.oy = g.off_y.get();
+    a.ox = g.off_x.get();
+    a.dom_y = g.dom_y;
+    a.dom_x = g.dom_x;
+    a.dom_z = g.dom_z;
+    a.ronly = y_rule == JP_Y_RULE_R_ONLY;
+    // one block for counts and sums, cleared together
+    DBuf<unsigned long long> bins = c.buf<unsigned long long>(2 * kIdx * kHist);
+    c.zero(bins.get(), 2 * kIdx * kHist);
+    a.cnt = bins.get();
+    a.sums = bins.get() + kIdx * kHist;
+    // Values of degree >= kHist: at most 3 dom_y + 2 dom_x + dom_z in all.
+    a.big_cap = 3 * g.dom_y + 2 * g.dom_x + g.dom_z;
+    DBuf<int64_t> big = c.buf<int64_t>((size_t)(2 * a.big_cap));
+    DBuf<int64_t> S = c.buf<int64_t>(2);
+    c.zero(S.get(), 2);
+    a.big = big.get();
+    a.nbig = (unsigned long long *)(S.get() + 1);
+    const int64_t bx = std::min<int64_t>(ceil_div(nmax, kHistBlock), (int64_t)c.num_cus * 2);
+    hipLaunchKernelGGL(k_index_hist, dim3((unsigned)bx, kIdx), dim3(kHistBlock), 0, c.stream, a);
+    JP_HIP(hipGetLastError());
+
+    // nonzero bins of all indexes, in (index, degree) order
+    const int64_t nb = kIdx * kHist;
+    DBuf<int64_t> rec = c.buf<int64_t>((size_t)(3 * nb));
+    {
+        const unsigned long long *cp = a.cnt, *sp = a.sums;
+        int64_t *r = rec.get();
+        compact(
+            c, nb, [=] __device__(int64_t b) { return cp[b] != 0; },
+            [=] __device__(int64_t b, int64_t p) {
+                r[3 * p] = b;
+                r[3 * p + 1] = (int64_t)cp[b];
+                r[3 * p + 2] = (int64_t)sp[b];
+            },
+            S.get());
+    }
+    int64_t hn[2];
+    c.load_n(hn, S.get(), 2);
+    JP_CHECK(hn[1] <= a.big_cap, JP_EINTERNAL, "degree index overflow list exceeds its bound");
+    std::vector<int64_t> r(3 * hn[0]), e(2 * hn[1]);
+    if (hn[0]) JP_HIP(hipMemcpyAsync(r.data(), rec.get(), r.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    if (hn[1]) JP_HIP(hipMemcpyAsync(e.data(), big.get(), e.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+    c.sync();
+
+    for (int64_t i = 0; i < hn[0]; ++i) {
+        const int64_t b = r[3 * i];
+        HostIndex &h = *out[b / kHist];
+        h.deg.push_back(b % kHist);
+        h.count.push_back(r[3 * i + 1]);
+        if (with_sum[b / kHist]) h.sum.push_back((double)r[3 * i + 2]);
+    }
+    // append list: sort by (index, degree), merge equal degrees
+    std::vector<std::pair<int64_t, int64_t>> bigv(hn[1]);
+    for (int64_t i = 0; i < hn[1]; ++i) bigv[i] = {e[2 * i], e[2 * i + 1]};
+    std::sort(bigv.begin(), bigv.end());
+    for (size_t i = 0; i < bigv.size();) {
+        size_t j = i;
+        int64_t cn = 0;
+        double sm = 0;
+        while (j < bigv.size() && bigv[j].first == bigv[i].first) {
+            ++cn;
+            sm += (double)bigv[j].second;
+            ++j;
+        }
+        const int k = (int)(bigv[i].first >> 56);
+        HostIndex &h = *out[k];
+        h.deg.push_back(bigv[i].first & ((1ll << 56) - 1));
+        h.count.push_back(cn);
+        if (with_sum[k]) h.sum.push_back(sm);
+        i = j;
+    }
 }
 
 }  // namespace jp

@@ -459,9 +459,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     sum.out_est = estimate_out(dom_x, dom_z, J, std::max(n_r2, n_s2));
     if (o.strategy == JP_STRATEGY_AUTO_COST || o.strategy == JP_STRATEGY_AUTO_MLP)
         summarize_two_path(c, g, o.y_rule, sum);
-    jp_calibration cal_default;
-    if (!c.cal) default_calibration(&cal_default);
-    Thresholds th = choose_thresholds(sum, o, c.cal ? *c.cal : cal_default);
+    Thresholds th = select_thresholds(c, sum, o);
     st.delta1 = th.d1;
     st.delta2 = th.d2;
     st.strategy = th.strategy;
@@ -759,32 +757,55 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     return res.release();
 }
 
-void plan_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
-                   const int32_t *sy, int64_t ns, const jp_options &o, int64_t *d1, int64_t *d2, float *features) {
-    *d1 = *d2 = JP_DELTA_INF;
-    if (features)
-        for (int i = 0; i < 16; ++i) features[i] = 0.f;
-    if (nr == 0 || ns == 0) return;
+// Index and summarise an instance for the planner entry points; false when
+// the join is empty (no summary).
+static bool summary_of(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                       const int32_t *sy, int64_t ns, const jp_options &o, TwoPathSummary &sum) {
+    if (nr == 0 || ns == 0) return false;
     DBuf<int64_t> scal = c.buf<int64_t>(32);
     Ingest g;
-    if (!ingest_two_path(c, rx, ry, nr, sz, sy, ns, g, scal.get())) return;
-    TwoPathSummary sum;
+    if (!ingest_two_path(c, rx, ry, nr, sz, sy, ns, g, scal.get())) return false;
     sum.n_r = g.n_r2;
     sum.n_s = g.n_s2;
     sum.dom_x = g.dom_x;
     sum.dom_y = g.dom_y;
     sum.dom_z = g.dom_z;
     sum.J = g.J;
+    sum.self_join = (rx == sz && ry == sy && nr == ns);
     sum.out_est = estimate_out(g.dom_x, g.dom_z, g.J, std::max(g.n_r2, g.n_s2));
     summarize_two_path(c, g, o.y_rule, sum);
-    jp_calibration cal_default;
-    if (!c.cal) default_calibration(&cal_default);
-    jp_options oo = o;
-    if (oo.strategy == JP_STRATEGY_AUTO_MLP) oo.strategy = JP_STRATEGY_AUTO_COST;
-    const Thresholds th = choose_thresholds(sum, oo, c.cal ? *c.cal : cal_default);
+    return true;
+}
+
+void plan_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
+                   const int32_t *sy, int64_t ns, const jp_options &o, int64_t *d1, int64_t *d2, float *features) {
+    *d1 = *d2 = JP_DELTA_INF;
+    if (features)
+        for (int i = 0; i < kFeatures; ++i) features[i] = 0.f;
+    TwoPathSummary sum;
+    if (!summary_of(c, rx, ry, nr, sz, sy, ns, o, sum)) return;
+    const Thresholds th = select_thresholds(c, sum, o);
     *d1 = th.d1;
     *d2 = th.d2;
     if (features) features16(sum, features);
+}
+
+void plan_cells(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz, const int32_t *sy,
+                int64_t ns, const jp_options &o, int32_t n_cells, const int64_t *d1, const int64_t *d2,
+                double *est_seconds, int64_t *heavy_dims) {
+    TwoPathSummary sum;
+    const bool any = summary_of(c, rx, ry, nr, sz, sy, ns, o, sum);
+    jp_calibration cal_default;
+    if (!c.cal) default_calibration(&cal_default);
+    const jp_calibration &cal = c.cal ? *c.cal : cal_default;
+    const jp_two_path_summary v = sum.view();
+    for (int32_t i = 0; i < n_cells; ++i) {
+        int64_t uvw[3] = {0, 0, 0};
+        const double t = any ? plan_cost(v, cal, d1[i], d2[i], uvw) : 0.0;
+        if (est_seconds) est_seconds[i] = t;
+        if (heavy_dims)
+            for (int j = 0; j < 3; ++j) heavy_dims[3 * i + j] = uvw[j];
+    }
 }
 
 }  // namespace jp
