@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -160,6 +161,14 @@ class DBuf {
 
 struct Selector;
 
+// Clearing kernel (used instead of hipMemsetAsync so that a captured stream
+// holds only kernel nodes).
+template <class W>
+__global__ __launch_bounds__(256) void k_zero_words(W *p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = W{};
+}
+
 // Execution context of one call: device, stream, allocator, chip size.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -190,7 +199,19 @@ struct Ctx {
     }
     template <class T>
     void zero(T *dev, size_t n) const {
-        if (n) JP_HIP(hipMemsetAsync(dev, 0, n * sizeof(T), stream));
+        const size_t bytes = n * sizeof(T);
+        const uintptr_t a = (uintptr_t)dev;
+        if (bytes == 0) return;
+        if (a % 16 == 0 && bytes % 16 == 0) zero_words((uint4 *)dev, bytes / 16);
+        else if (a % 8 == 0 && bytes % 8 == 0) zero_words((uint64_t *)dev, bytes / 8);
+        else if (a % 4 == 0 && bytes % 4 == 0) zero_words((uint32_t *)dev, bytes / 4);
+        else zero_words((uint8_t *)dev, bytes);
+    }
+    template <class W>
+    void zero_words(W *p, size_t n) const {
+        const int64_t blocks = std::min<int64_t>(((int64_t)n + 255) / 256, (int64_t)num_cus * 8);
+        hipLaunchKernelGGL(k_zero_words<W>, dim3((unsigned)blocks), dim3(256), 0, stream, p, (int64_t)n);
+        JP_HIP(hipGetLastError());
     }
 };
 

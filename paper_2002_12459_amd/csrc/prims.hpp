@@ -1,7 +1,7 @@
 // Device-wide primitives written for this library: grid loops, exclusive
-// scan (reduce-then-scan, no inter-block waiting), stable LSD radix sort of
-// 32/64-bit keys (per-tile digit counts, scan, wave-ballot ranked scatter
-// staged through LDS) and stable stream compaction by wave ballots.
+// scan and stable stream compaction (one pass each, decoupled look-back
+// between tiles), and stable LSD radix sort of 32/64-bit keys (per-tile digit
+// counts, scan, wave-ballot ranked scatter staged through LDS).
 #pragma once
 
 #include <algorithm>
@@ -31,32 +31,83 @@ void for_each(const Ctx &c, int64_t n, F f) {
 
 // ---------------------------------------------------------------------------
 // Exclusive scan of int64 values produced by get(i); put(i, prefix) receives
-// the exclusive prefix of element i.  Tiles of 4096 elements: each wave scans
-// 1024 consecutive elements in 16 coalesced rounds of 64.
+// the exclusive prefix of element i.  One pass with decoupled look-back:
+// tiles of 4096 elements (each wave scans 1024 consecutive elements in 16
+// coalesced rounds of 64) take ordered tickets, publish their sum, and the
+// first wave of each tile sums its predecessors' published values, 64 at a
+// time, back to the nearest tile whose inclusive prefix is already known.
+// Every predecessor holds an earlier ticket, so it is resident or finished
+// and every wait ends.
 // ---------------------------------------------------------------------------
 constexpr int kTileItems = 16;
 constexpr int kTileBlock = 256;
 constexpr int64_t kTile = kTileItems * kTileBlock;
 
-template <class G>
-__global__ __launch_bounds__(kTileBlock) void k_scan_reduce(int64_t n, G get, int64_t *partial) {
-    __shared__ int64_t lds[kTileBlock / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    int64_t s = 0;
-#pragma unroll 4
-    for (int j = 0; j < kTileItems; ++j) {
-        int64_t i = base + (int64_t)j * kTileBlock + threadIdx.x;
-        if (i < n) s += get(i);
+// status word of a tile: (value << 2) | flag, flag 1 = tile sum, 2 = inclusive prefix
+__device__ __forceinline__ void lb_publish(uint64_t *status, int64_t t, int64_t v, uint64_t flag) {
+    __hip_atomic_store(status + t, ((uint64_t)v << 2) | flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Exclusive prefix of tile t >= 1, computed by one whole wave (all lanes get it).
+__device__ __forceinline__ int64_t lb_lookback(uint64_t *status, int64_t t) {
+    const int lane = lane_id();
+    int64_t excl = 0;
+    for (int64_t top = t - 1;; top -= kWave) {
+        const int64_t idx = top - lane;
+        uint64_t s = 2;  // before tile 0: inclusive prefix 0
+        if (idx >= 0) {
+            s = __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            while ((s & 3u) == 0) {
+                __builtin_amdgcn_s_sleep(1);
+                s = __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        const uint64_t inc = ballot((s & 3u) == 2);
+        const int stop = inc ? (int)(__ffsll((unsigned long long)inc) - 1) : kWave;
+        excl += wave_sum(lane <= stop ? ((int64_t)s >> 2) : (int64_t)0);
+        if (inc) break;
     }
-    int64_t tot = block_sum<kTileBlock>(s, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+    return excl;
+}
+
+// Tile index of this workgroup: an ordered ticket, or blockIdx.x for one tile.
+__device__ __forceinline__ int64_t lb_tile(unsigned *ticket, int64_t *sh) {
+    if (threadIdx.x == 0) *sh = ticket ? (int64_t)atomicAdd(ticket, 1u) : (int64_t)blockIdx.x;
+    __syncthreads();
+    return *sh;
+}
+
+// Wave 0 resolves the tile's exclusive prefix from its sum A; returns it to all threads.
+__device__ __forceinline__ int64_t lb_resolve(uint64_t *status, int64_t t, int64_t A, int64_t *sh, int64_t *total,
+                                              int64_t ntiles) {
+    if (threadIdx.x < kWave) {
+        int64_t excl = 0;
+        if (status) {
+            if (t == 0) {
+                if (threadIdx.x == 0) lb_publish(status, 0, A, 2);
+            } else {
+                if (threadIdx.x == 0) lb_publish(status, t, A, 1);
+                excl = lb_lookback(status, t);
+                if (threadIdx.x == 0) lb_publish(status, t, excl + A, 2);
+            }
+        }
+        if (threadIdx.x == 0) {
+            *sh = excl;
+            if (total && t == ntiles - 1) *total = excl + A;
+        }
+    }
+    __syncthreads();
+    return *sh;
 }
 
 template <class G, class P>
-__global__ __launch_bounds__(kTileBlock) void k_scan_down(int64_t n, G get, const int64_t *partial_scan, P put) {
+__global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put, uint64_t *status, unsigned *ticket,
+                                                        int64_t *total) {
     __shared__ int64_t lds[kTileBlock / kWave + 1];
+    __shared__ int64_t sh_tile, sh_excl;
+    const int64_t t = lb_tile(ticket, &sh_tile);
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t wbase = (int64_t)blockIdx.x * kTile + (int64_t)w * kWave * kTileItems;
+    const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
     int64_t v[kTileItems];
     int64_t wtot = 0;
 #pragma unroll
@@ -66,12 +117,10 @@ __global__ __launch_bounds__(kTileBlock) void k_scan_down(int64_t n, G get, cons
         wtot += v[j];
     }
     wtot = wave_sum(wtot);
-    // prefix of the wave totals inside the block
-    int64_t dummy;
-    int64_t contrib = (lane == 0) ? wtot : 0;
-    int64_t wpre = block_excl_scan<kTileBlock>(contrib, lds, &dummy);
+    int64_t A;
+    int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wtot : (int64_t)0, lds, &A);
     wpre = __shfl(wpre, 0);
-    int64_t carry = partial_scan[blockIdx.x] + wpre;
+    int64_t carry = lb_resolve(status, t, A, &sh_excl, total, gridDim.x) + wpre;
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
@@ -90,6 +139,22 @@ struct ArrayPut {
     __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
 };
 
+// Cleared tile status words and ticket for a look-back pass over nt tiles
+// (none needed for a single tile).
+struct LookbackState {
+    DBuf<uint64_t> buf;
+    uint64_t *status = nullptr;
+    unsigned *ticket = nullptr;
+    LookbackState(const Ctx &c, int64_t nt) {
+        JP_CHECK(nt < (1ll << 31), JP_EINVAL, "input too large for one pass");
+        if (nt <= 1) return;
+        buf = c.buf<uint64_t>((size_t)nt + 1);
+        c.zero(buf.get(), (size_t)nt + 1);
+        status = buf.get();
+        ticket = (unsigned *)(buf.get() + nt);
+    }
+};
+
 // Exclusive scan; if total_dev is given, the overall sum is stored there.
 template <class G, class P>
 void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = nullptr) {
@@ -98,25 +163,10 @@ void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = 
         return;
     }
     const int64_t nt = ceil_div(n, kTile);
-    DBuf<int64_t> part = c.buf<int64_t>((size_t)nt + 1);
-    hipLaunchKernelGGL((k_scan_reduce<G>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, get, part.get());
+    LookbackState lb(c, nt);
+    hipLaunchKernelGGL((k_scan_lb<G, P>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, get, put, lb.status,
+                       lb.ticket, total_dev);
     JP_HIP(hipGetLastError());
-    // scan the partials in place (recursively), sum into part[nt]
-    DBuf<int64_t> part_scan = c.buf<int64_t>((size_t)nt + 1);
-    if (nt == 1) {
-        int64_t *ps = part_scan.get(), *p = part.get();
-        for_each(c, 1, [=] __device__(int64_t) {
-            ps[0] = 0;
-            ps[1] = p[0];
-        });
-    } else {
-        scan_exclusive(c, nt, ArrayGet{part.get()}, ArrayPut{part_scan.get()}, part_scan.get() + nt);
-    }
-    hipLaunchKernelGGL((k_scan_down<G, P>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, get,
-                       (const int64_t *)part_scan.get(), put);
-    JP_HIP(hipGetLastError());
-    if (total_dev) JP_HIP(hipMemcpyAsync(total_dev, part_scan.get() + nt, sizeof(int64_t),
-                                         hipMemcpyDeviceToDevice, c.stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -142,27 +192,17 @@ void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
 
 // ---------------------------------------------------------------------------
 // Stable compaction: for i in [0,n) with pred(i), emit(i, pos) with pos the
-// rank of i among selected elements.  Ballot + mbcnt inside each wave, block
-// prefix of wave counts, tile prefix from a scan of per-tile counts.
+// rank of i among selected elements.  One pass: ballot + mbcnt inside each
+// wave, block prefix of wave counts, tile prefix by decoupled look-back.
 // ---------------------------------------------------------------------------
-template <class Pr>
-__global__ __launch_bounds__(kTileBlock) void k_compact_count(int64_t n, Pr pred, int64_t *partial) {
-    __shared__ int64_t lds[kTileBlock / kWave + 1];
-    const int64_t base = (int64_t)blockIdx.x * kTile;
-    int64_t s = 0;
-    for (int j = 0; j < kTileItems; ++j) {
-        int64_t i = base + (int64_t)j * kTileBlock + threadIdx.x;
-        if (i < n && pred(i)) ++s;
-    }
-    int64_t tot = block_sum<kTileBlock>(s, lds);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
 template <class Pr, class Em>
-__global__ __launch_bounds__(kTileBlock) void k_compact_write(int64_t n, Pr pred, Em emit, const int64_t *partial_scan) {
+__global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Pr pred, Em emit, uint64_t *status,
+                                                           unsigned *ticket, int64_t *count) {
     __shared__ int64_t lds[kTileBlock / kWave + 1];
+    __shared__ int64_t sh_tile, sh_excl;
+    const int64_t t = lb_tile(ticket, &sh_tile);
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t wbase = (int64_t)blockIdx.x * kTile + (int64_t)w * kWave * kTileItems;
+    const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
     uint32_t flags = 0;
     int64_t wcnt = 0;
     for (int j = 0; j < kTileItems; ++j) {
@@ -171,10 +211,10 @@ __global__ __launch_bounds__(kTileBlock) void k_compact_write(int64_t n, Pr pred
         flags |= (uint32_t)f << j;
         wcnt += __popcll(ballot(f));
     }
-    int64_t dummy;
-    int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wcnt : (int64_t)0, lds, &dummy);
+    int64_t A;
+    int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wcnt : (int64_t)0, lds, &A);
     wpre = __shfl(wpre, 0);
-    int64_t pos = partial_scan[blockIdx.x] + wpre;
+    int64_t pos = lb_resolve(status, t, A, &sh_excl, count, gridDim.x) + wpre;
     for (int j = 0; j < kTileItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         bool f = (flags >> j) & 1u;
@@ -192,13 +232,9 @@ void compact(const Ctx &c, int64_t n, Pr pred, Em emit, int64_t *count_dev) {
         return;
     }
     const int64_t nt = ceil_div(n, kTile);
-    DBuf<int64_t> part = c.buf<int64_t>((size_t)nt);
-    DBuf<int64_t> part_scan = c.buf<int64_t>((size_t)nt);
-    hipLaunchKernelGGL((k_compact_count<Pr>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, pred, part.get());
-    JP_HIP(hipGetLastError());
-    scan_exclusive(c, nt, ArrayGet{part.get()}, ArrayPut{part_scan.get()}, count_dev);
-    hipLaunchKernelGGL((k_compact_write<Pr, Em>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, pred, emit,
-                       (const int64_t *)part_scan.get());
+    LookbackState lb(c, nt);
+    hipLaunchKernelGGL((k_compact_lb<Pr, Em>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, pred, emit,
+                       lb.status, lb.ticket, count_dev);
     JP_HIP(hipGetLastError());
 }
 

@@ -532,23 +532,27 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     const int32_t *zlist = adj_s.get();
     int64_t zlist_n = n_s2;
     if (has_heavy) {
-        DBuf<int64_t> lz_cnt = c.buf<int64_t>(v);
+        // One scan over S (y-major) of the "light z at heavy y" flags gives
+        // both the compacted lists and, at the first entry of each heavy y,
+        // that y's list start.
         lz_off = c.buf<int64_t>(v + 1);
-        c.zero(lz_cnt.get(), v);
-        int64_t *lc = lz_cnt.get(), *lo = lz_off.get();
+        int64_t *lo = lz_off.get();
         const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
-        auto is_lz = [=] __device__(int64_t e) -> bool { return (hy[syr[e]] >= 0) & (hz[as[e]] < 0); };
-        for_each(c, n_s2, [=] __device__(int64_t e) {
-            const int32_t h = hy[syr[e]];
-            if ((h >= 0) & (hz[as[e]] < 0)) atomicAdd((unsigned long long *)&lc[h], 1ull);
-        });
-        scan_exclusive(c, v, ArrayGet{lc}, ArrayPut{lo}, lo + v);
         zlist_own = c.buf<int32_t>(2 * n_s2);
         int32_t *zl = zlist_own.get();
         JP_HIP(hipMemcpyAsync(zl, as, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
         int32_t *la = zl + n_s2;
-        compact(c, n_s2, is_lz, [=] __device__(int64_t e, int64_t p) { la[p] = as[e]; }, S + 14);
-        const int64_t n_lz = c.load(S + 14);
+        scan_exclusive(
+            c, n_s2,
+            [=] __device__(int64_t e) -> int64_t { return (int64_t)((hy[syr[e]] >= 0) & (hz[as[e]] < 0)); },
+            [=] __device__(int64_t e, int64_t p) {
+                const int32_t y = syr[e];
+                const int32_t h = hy[y];
+                if ((h >= 0) & (hz[as[e]] < 0)) la[p] = as[e];
+                if (h >= 0 && (e == 0 || syr[e - 1] != y)) lo[h] = p;
+            },
+            lo + v);
+        const int64_t n_lz = c.load(lo + v);
         check_monotone(c, "lz_off", lz_off.get(), v + 1, 0, n_lz);
         check_range(c, "lz lists", la, n_lz, 0, dom_z);
         dump(c, "lz_off", lz_off.get(), v + 1);
