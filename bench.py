@@ -9,6 +9,11 @@ timed region.  One step = one full evaluation (index build, thresholds,
 partition, light expansion, heavy product, union, duplicate removal, sorted
 output in HBM).
 
+A second leg measures the batched mode on the serving-style set: 512
+independent two-path instances, edge counts log-uniform in [1K, 1M], Zipf
+exponent U[0.6, 1.6], evaluated in one call; it is reported under "batched"
+next to the time of the same instances evaluated one call each.
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 Prints one JSON line.
 """
@@ -40,7 +45,52 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-bmm", action="store_true")
     p.add_argument("--cpu-sample", type=float, default=0.3, help="fraction of x ids in the oracle sample")
+    p.add_argument("--no-batch", action="store_true")
+    p.add_argument("--batch-instances", type=int, default=512)
     return p.parse_args()
+
+
+def _batch_instance(i):
+    import datagen
+    return datagen.batch_instance(i)
+
+
+def batched_leg(h, insts, steps, warmup):
+    """Batched evaluation of all instances vs one call per instance."""
+    import torch
+    dev = torch.device("cuda:0")
+    T = lambda v: torch.from_numpy(v).to(dev)
+    tin = [(T(r[0]), T(r[1]), T(s[0]), T(s[1])) for r, s in insts]
+    for _ in range(warmup):
+        h.two_path_batch_result(tin).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = h.two_path_batch_result(tin)
+        n, st = r.n, r.stats
+        r.free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    # the same instances one call each (after one warm-up pass)
+    for q in tin:
+        h.two_path_result(*q).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_single = 0
+    for q in tin:
+        r = h.two_path_result(*q)
+        n_single += r.n
+        r.free()
+    torch.cuda.synchronize()
+    ds = time.perf_counter() - t0
+    if n_single != n:
+        raise RuntimeError(f"batched output size {n} differs from per-instance total {n_single}")
+    return {"workload": f"{len(insts)} two-path instances, |R|=|S| log-uniform [1K,1M], Zipf U[0.6,1.6], "
+                        f"x/z ids E/10, y ids E/50; one batched call, cost-model thresholds",
+            "edges_r": int(sum(q[0].numel() for q in tin)), "n_out": n, "J": st["J"],
+            "ms_per_step": dt * 1e3, "pairs_per_s": n / dt, "instances_per_s": len(insts) / dt,
+            "delta1": st["delta1"], "delta2": st["delta2"],
+            "per_instance_calls_ms": ds * 1e3, "speedup_vs_per_instance_calls": ds / dt}
 
 
 def main():
@@ -50,6 +100,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
+
+    # batched-set generation in worker processes, forked before this process
+    # touches the GPU
+    pool = batch_async = None
+    if not a.no_batch:
+        import multiprocessing as mp
+        pool = mp.get_context("fork").Pool(min(12, os.cpu_count() or 1))
+        batch_async = pool.map_async(_batch_instance, range(a.batch_instances))
+
     import torch
 
     import datagen
@@ -69,6 +128,8 @@ def main():
         r.free()
         return n, st
 
+    if batch_async is not None:
+        batch_async.wait()  # no host work competes with the timed region
     for i in range(a.warmup):
         n, st = step()
         log(f"warmup {i}: |OUT|={n} strategy={st['strategy']} d1={st['delta1']} d2={st['delta2']}")
@@ -107,6 +168,17 @@ def main():
                    "frac": tops / INT8_PEAK_TOPS, "n_out": nb, "ms_total": pb["ms_total"]}
             log(f"heavy product u={pb['u']} v={pb['v']} w={pb['w']}: {pb['ms_bmm']:.2f} ms, {tops:.1f} TOP/s")
 
+    batched = None
+    if batch_async is not None:
+        t0 = time.time()
+        insts = batch_async.get()
+        pool.close()
+        log(f"batched set ready ({time.time() - t0:.1f}s wait)")
+        batched = batched_leg(h, insts, max(1, min(a.steps, 3)), 1)
+        log(f"batched: {batched['ms_per_step']:.1f} ms per call for {len(insts)} instances, "
+            f"{batched['pairs_per_s']:.3g} pairs/s; one call per instance: {batched['per_instance_calls_ms']:.1f} ms")
+        del insts
+
     # CPU oracle on a bounded sample of the same workload: R restricted to an
     # x-id range (its outputs are exactly the outputs with x in that range)
     cpu = None
@@ -141,6 +213,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "heavy_bmm": bmm,
+        "batched": batched,
         "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
     }
     print(json.dumps(out), flush=True)

@@ -31,31 +31,48 @@ __all__ = [
     "twopath_c2",
     "star_c3",
     "batch_c4",
+    "batch_instance",
     "selector_instance",
+    "selector_instance_clustered",
 ]
 
 
 def _first_distinct(draw, n: int, n_y: int, rng, max_rounds: int = 64):
     """Draw (x, y) batches with ``draw(rng, m)`` until ``n`` distinct pairs exist.
 
-    Keeps the first ``n`` distinct pairs in draw order.
+    Keeps the first ``n`` distinct pairs in draw order.  Each round draws
+    ``max(1024, 1.15 (n - have) + 16)`` pairs, where ``have`` is the number of
+    distinct pairs drawn so far.  The pairs seen so far are kept as sorted
+    per-round chunks, so a round costs time in its own size only.
     """
-    xs = np.empty(0, dtype=np.int64)
-    ys = np.empty(0, dtype=np.int64)
+    chunks = []      # sorted distinct keys first seen in each round
+    firsts = []      # their global draw positions
+    bxs, bys = [], []
+    have = 0
+    drawn = 0
     for _ in range(max_rounds):
-        have = 0
-        if xs.size:
-            key = xs * n_y + ys
-            _, first = np.unique(key, return_index=True)
-            have = first.size
-            if have >= n:
-                first.sort()
-                first = first[:n]
-                return xs[first].astype(np.int32), ys[first].astype(np.int32)
+        if have >= n:
+            pos = np.sort(np.concatenate(firsts))[:n]
+            xs = np.concatenate(bxs)
+            ys = np.concatenate(bys)
+            return xs[pos].astype(np.int32), ys[pos].astype(np.int32)
         m = max(1024, int((n - have) * 1.15) + 16)
         bx, by = draw(rng, m)
-        xs = np.concatenate([xs, bx.astype(np.int64)])
-        ys = np.concatenate([ys, by.astype(np.int64)])
+        bx = bx.astype(np.int64)
+        by = by.astype(np.int64)
+        key = bx * n_y + by
+        uk, first = np.unique(key, return_index=True)
+        new = np.ones(uk.size, dtype=bool)
+        for ch in chunks:
+            j = np.searchsorted(ch, uk)
+            j = np.minimum(j, ch.size - 1)
+            new &= ch[j] != uk
+        chunks.append(uk[new])
+        firsts.append(first[new] + drawn)
+        bxs.append(bx)
+        bys.append(by)
+        have += int(new.sum())
+        drawn += m
     raise RuntimeError("could not draw enough distinct pairs; domain too small")
 
 
@@ -169,6 +186,20 @@ def star_c3(scale: float = 1.0):
     return [zipf_edges(n, nx, ny, 1.3, seed=4 + i) for i in range(3)]
 
 
+def batch_instance(i: int, lo: float = 1e3, hi: float = 1e6, seed0: int = 1000):
+    """Instance i of the batched set: ((rx, ry), (sz, sy)), see ``batch_c4``."""
+    rng = np.random.default_rng(seed0 + i)
+    e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+    s = float(rng.uniform(0.6, 1.6))
+    nx = max(2, -(-e // 10))
+    ny = max(2, -(-e // 50))
+    e = min(e, nx * ny // 2)
+    sub = int(rng.integers(0, 2**31 - 1))
+    r = zipf_edges(e, nx, ny, s, seed=sub)
+    t = zipf_edges(e, nx, ny, s, seed=sub + 1)
+    return r, t
+
+
 def batch_c4(n_inst: int = 512, lo: float = 1e3, hi: float = 1e6, seed0: int = 1000):
     """Batched set: instance i has E_i ~ log-uniform[lo,hi] edges per relation.
 
@@ -176,19 +207,7 @@ def batch_c4(n_inst: int = 512, lo: float = 1e3, hi: float = 1e6, seed0: int = 1
     |dom y| = ceil(E/50) (the same ratios as the single two-path input).
     Returns a list of ((rx, ry), (sz, sy)) tuples.
     """
-    out = []
-    for i in range(n_inst):
-        rng = np.random.default_rng(seed0 + i)
-        e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
-        s = float(rng.uniform(0.6, 1.6))
-        nx = max(2, -(-e // 10))
-        ny = max(2, -(-e // 50))
-        e = min(e, nx * ny // 2)
-        sub = int(rng.integers(0, 2**31 - 1))
-        r = zipf_edges(e, nx, ny, s, seed=sub)
-        t = zipf_edges(e, nx, ny, s, seed=sub + 1)
-        out.append((r, t))
-    return out
+    return [batch_instance(i, lo, hi, seed0) for i in range(n_inst)]
 
 
 def selector_instance(i: int, lo: float = 1e5, hi: float = 2e7, seed0: int = 10_000,
@@ -205,3 +224,42 @@ def selector_instance(i: int, lo: float = 1e5, hi: float = 2e7, seed0: int = 10_
     e = min(e, nx * ny // 2)
     sub = int(rng.integers(0, 2**31 - 1))
     return zipf_edges(e, nx, ny, s, seed=sub), zipf_edges(e, nx, ny, s, seed=sub + 1), s
+
+
+def selector_instance_clustered(i: int, lo: float = 1e5, hi: float = 1e7, seed0: int = 30_000):
+    """Instance i of the clustered selector set: dense communities plus a sparse part.
+
+    |R| = |S| ~ E log-uniform in [lo, hi].  A fraction f ~ U[0.3, 0.9] of the
+    edges forms c ~ U{1..200} communities (the structure of the paper's
+    Example 1): each has m x-ids and g y-ids with edge probability
+    p ~ U[0.05, 0.5], where d = m p ~ log-uniform [4, 400] (capped so that
+    f E d <= 5e8) and g = f E / (c d).  S uses the same y blocks with its own
+    z blocks and draws.  The rest is a Zipf part as in ``selector_instance``
+    (exponent U[0.5, 1.8], domains E/10 and E/50) on ids above the
+    communities'.  Returns ((rx, ry), (sz, sy), params).
+    """
+    rng = np.random.default_rng(seed0 + i)
+    e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+    f = float(rng.uniform(0.3, 0.9))
+    c = int(rng.integers(1, 201))
+    p = float(rng.uniform(0.05, 0.5))
+    d = float(np.exp(rng.uniform(np.log(4.0), np.log(400.0))))
+    d = min(d, 5e8 / max(f * e, 1.0))
+    m = max(2, int(round(d / p)))
+    g = max(2, int(round(f * e / (c * max(d, 1.0)))))
+    s = float(rng.uniform(0.5, 1.8))
+    sub = int(rng.integers(0, 2**31 - 1))
+    cx, cy = communities(c, m, g, p, seed=sub)
+    dz, dy = communities(c, m, g, p, seed=sub + 1)
+    es = max(1, e - cx.size)
+    nx = max(2, -(-es // 10))
+    ny = max(2, -(-es // 50))
+    es = min(es, nx * ny // 2)
+    (zx, zy) = zipf_edges(es, nx, ny, s, seed=sub + 2)
+    (wz, wy) = zipf_edges(es, nx, ny, s, seed=sub + 3)
+    ox, oy = c * m, c * g
+    rx = np.concatenate([cx, zx + ox]).astype(np.int32)
+    ry = np.concatenate([cy, zy + oy]).astype(np.int32)
+    sz = np.concatenate([dz, wz + ox]).astype(np.int32)
+    sy = np.concatenate([dy, wy + oy]).astype(np.int32)
+    return (rx, ry), (sz, sy), {"e": e, "f": f, "c": c, "m": m, "g": g, "p": p, "s": s}

@@ -284,6 +284,35 @@ jp_status jp_two_path(jp_handle *h,
                       const int32_t *s_z, const int32_t *s_y, int64_t n_s,
                       const jp_options *opt, jp_result **out);
 
+/* One two-path instance of a batch: device columns as for jp_two_path. */
+typedef struct jp_instance {
+    const int32_t *r_x, *r_y;
+    int64_t n_r;
+    const int32_t *s_z, *s_y;
+    int64_t n_s;
+} jp_instance;
+
+/*
+ * Many independent two-path instances in one evaluation (Algorithm 1 run
+ * once over all of them).  inst is a host array of n_inst descriptors
+ * (0 <= n_inst <= 65535).  The instances are laid side by side in disjoint id ranges,
+ * which keeps each instance's output exact (no y is shared between
+ * instances), and share one threshold pair chosen by opt for the combined
+ * input.  The sum over instances of (max id - min id + 1) must stay below
+ * 2^31 for each of x, y and z (JP_EINVAL otherwise).  On JP_OK, *out holds
+ * one arity-2 result with all instances' tuples, instance by instance, each
+ * instance's tuples distinct and sorted as in jp_two_path; the slice of
+ * instance i is given by jp_result_batch_offsets.
+ */
+jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
+                            jp_result **out);
+
+/* Slices of a batched result: *n_inst receives the instance count; when
+ * offsets is not NULL it receives n_inst + 1 host values, instance i owning
+ * tuples [offsets[i], offsets[i+1]).  A result that is not batched reports
+ * n_inst = 0. */
+jp_status jp_result_batch_offsets(const jp_result *r, int32_t *n_inst, int64_t *offsets);
+
 /*
  * Star join-project Q*_k (Section 3.2), 2 <= k <= 3.  Relation i has columns
  * x[i], y[i] of n[i] rows (host arrays of device pointers).  On JP_OK, *out

@@ -95,6 +95,11 @@ class TwoPathSummary(ctypes.Structure):
                [("out_est", ctypes.c_double)] + [(n, DegreeIndex) for n in ("y", "x", "xcdf", "z")]
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("r_x", ctypes.c_void_p), ("r_y", ctypes.c_void_p), ("n_r", ctypes.c_int64),
+                ("s_z", ctypes.c_void_p), ("s_y", ctypes.c_void_p), ("n_s", ctypes.c_int64)]
+
+
 _lib = None
 _lock = threading.Lock()
 
@@ -139,6 +144,9 @@ def _load():
                                         ctypes.POINTER(ctypes.c_double)]
         lib.jp_plan_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(i64),
                                          ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
+        lib.jp_two_path_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Instance), ctypes.POINTER(Options),
+                                          ctypes.POINTER(P)]
+        lib.jp_result_batch_offsets.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
         lib.jp_plan_cells.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.c_int32,
                                       ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(i64)]
@@ -155,7 +163,8 @@ def _load():
         for f in ("jp_create", "jp_set_stream", "jp_two_path", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
-                  "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam"):
+                  "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
+                  "jp_two_path_batch", "jp_result_batch_offsets"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -196,6 +205,17 @@ class Result:
         s = Stats()
         lib.jp_result_stats(ptr, ctypes.byref(s))
         self.stats = s.as_dict()
+
+    def batch_offsets(self):
+        """Instance slices of a batched result (list of n_inst + 1 ints), or None."""
+        lib = _load()
+        n = ctypes.c_int32()
+        lib.jp_result_batch_offsets(self._p, ctypes.byref(n), None)
+        if n.value == 0:
+            return None
+        offs = (ctypes.c_int64 * (n.value + 1))()
+        lib.jp_result_batch_offsets(self._p, ctypes.byref(n), offs)
+        return list(offs)
 
     def to_torch(self):
         """Copy the columns into new int32 torch tensors (stream-ordered)."""
@@ -304,6 +324,33 @@ class Handle:
         finally:
             r.free()
 
+    def two_path_batch_result(self, instances, delta1=None, delta2=None, strategy=None, bmm="auto", y_rule="max",
+                              dedup="auto", timing=False, seed=None) -> Result:
+        """All instances [(r_x, r_y, s_z, s_y), ...] in one evaluation."""
+        descs = (Instance * max(len(instances), 1))()
+        keep = []
+        for i, (rx, ry, sz, sy) in enumerate(instances):
+            rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+            if rx.numel() != ry.numel() or sz.numel() != sy.numel():
+                raise ValueError(f"instance {i}: column lengths differ")
+            keep.extend([rx, ry, sz, sy])
+            descs[i] = Instance(_ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel())
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed)
+        out = ctypes.c_void_p()
+        self._check(_load().jp_two_path_batch(self._p, len(instances), descs, ctypes.byref(o), ctypes.byref(out)))
+        return Result(self, out)
+
+    def two_path_batch(self, instances, **kw):
+        """Per-instance outputs [(x, z), ...] (views of two shared tensors) and the stats."""
+        r = self.two_path_batch_result(instances, **kw)
+        try:
+            x, z = r.to_torch()
+            offs = r.batch_offsets() or [0] * (len(instances) + 1)
+            return [(x[offs[i]:offs[i + 1]], z[offs[i]:offs[i + 1]]) for i in range(len(instances))], r.stats
+        finally:
+            r.free()
+
     def star_result(self, rels, delta1=None, delta2=None, strategy=None, bmm="auto", dedup="auto",
                     timing=False, seed=None) -> Result:
         k = len(rels)
@@ -350,6 +397,26 @@ class Handle:
         self._check(_load().jp_bool_matmul(self._p, _ptr(A), _ptr(Bt), u, w, k, ld, BMM[kind], _ptr(rows),
                                            _ptr(cols), cap, ctypes.byref(nnz), ctypes.byref(ms)))
         return rows[: nnz.value], cols[: nnz.value], ms.value
+
+    def bool_matmul_count(self, A, Bt, k=None, kind="i8"):
+        """Number of nonzero entries of A @ Bt.T (nothing is stored) and the
+        kernel's device time in ms."""
+        torch = _torch()
+        if A.dtype != torch.int8 or Bt.dtype != torch.int8 or not (A.is_cuda and Bt.is_cuda):
+            raise TypeError("A and Bt must be int8 CUDA tensors")
+        A = A.contiguous()
+        Bt = Bt.contiguous()
+        u, ld = A.shape
+        w = Bt.shape[0]
+        k = ld if k is None else k
+        self._bind_stream()
+        nnz = ctypes.c_int64()
+        ms = ctypes.c_double()
+        st = _load().jp_bool_matmul(self._p, _ptr(A), _ptr(Bt), u, w, k, ld, BMM[kind], None, None, 0,
+                                    ctypes.byref(nnz), ctypes.byref(ms))
+        if st not in (0, 4):  # JP_ECAPACITY reports the count
+            self._check(st)
+        return nnz.value, ms.value
 
     def set_calibration(self, cal):
         c = cal if isinstance(cal, Calibration) else Calibration.from_dict(cal)

@@ -173,6 +173,43 @@ jp_status jp_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int6
     return st;
 }
 
+jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
+                            jp_result **out) {
+    if (!h) return JP_EINVAL;
+    if (!out) {
+        h->err = "out is NULL";
+        return JP_EINVAL;
+    }
+    *out = nullptr;
+    if (n_inst < 0 || (n_inst > 0 && !inst)) {
+        h->err = "n_inst must be >= 0 and inst non-NULL";
+        return JP_EINVAL;
+    }
+    for (int32_t i = 0; i < n_inst; ++i)
+        if (bad_col(inst[i].r_x, inst[i].n_r) || bad_col(inst[i].r_y, inst[i].n_r) ||
+            bad_col(inst[i].s_z, inst[i].n_s) || bad_col(inst[i].s_y, inst[i].n_s)) {
+            h->err = "instance " + std::to_string(i) + ": relation column is NULL or its length is negative";
+            return JP_EINVAL;
+        }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    jp_result *r = nullptr;
+    jp_status st = guarded(h, [&] { r = jp::run_two_path_batch(make_ctx(h), n_inst, inst, o); });
+    if (st == JP_OK) *out = r;
+    return st;
+}
+
+jp_status jp_result_batch_offsets(const jp_result *r, int32_t *n_inst, int64_t *offsets) {
+    if (!r || !n_inst) return JP_EINVAL;
+    *n_inst = r->batch_off.empty() ? 0 : (int32_t)(r->batch_off.size() - 1);
+    if (offsets)
+        for (size_t i = 0; i < r->batch_off.size(); ++i) offsets[i] = r->batch_off[i];
+    return JP_OK;
+}
+
 jp_status jp_star(jp_handle *h, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
                   const jp_options *opt, jp_result **out) {
     if (!h) return JP_EINVAL;

@@ -94,94 +94,100 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                                                 unsigned long long *count) {
     __shared__ __attribute__((aligned(16))) int8_t sA[BM * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[BN * LDS_STRIDE];
-    int64_t tm, tn;
-    tile_of_block(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
-    const int64_t row0 = tm * BM, col0 = tn * BN;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     const int wm = wv >> 1, wn = wv & 1;
-
     // global -> register staging: each thread moves 4 x 16 B of A and of B
     // per stage: row = (tid / 8) + 32 * q, byte offset = (tid % 8) * 16
     const int lr = tid / 8, lc = (tid % 8) * 16;
-    v4i ra[4], rb[4];
-    auto load_stage = [&](int64_t k0) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int64_t r = row0 + lr + 32 * q;
-            ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
-            int64_t c = col0 + lr + 32 * q;
-            rb[q] = c < w ? *(const v4i *)(Bt + c * ld + k0 + lc) : v4i{0, 0, 0, 0};
-        }
-    };
-    auto store_stage = [&]() {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            *(v4i *)(sA + (lr + 32 * q) * LDS_STRIDE + lc) = ra[q];
-            *(v4i *)(sB + (lr + 32 * q) * LDS_STRIDE + lc) = rb[q];
-        }
-    };
-
-    v4i acc[4][4];
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int g = 0; g < 4; ++g) acc[f][g] = v4i{0, 0, 0, 0};
-
     const int fr = lane % 16, fk = (lane / 16) * 16;
-    load_stage(0);
-    for (int64_t k0 = 0; k0 < ld; k0 += BK) {
-        __syncthreads();
-        store_stage();
-        __syncthreads();
-        if (k0 + BK < ld) load_stage(k0 + BK);
+    // Workgroups loop over tiles when the tile count exceeds the grid (the
+    // grid is a multiple of 8, so a workgroup stays on its XCD's tile patch).
+    const int64_t total = tiles_m * tiles_n;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        int64_t tm, tn;
+        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        const int64_t row0 = tm * BM, col0 = tn * BN;
+        v4i ra[4], rb[4];
+        auto load_stage = [&](int64_t k0) {
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 64) {
-            v4i a[4], b[4];
+            for (int q = 0; q < 4; ++q) {
+                int64_t r = row0 + lr + 32 * q;
+                ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
+                int64_t c = col0 + lr + 32 * q;
+                rb[q] = c < w ? *(const v4i *)(Bt + c * ld + k0 + lc) : v4i{0, 0, 0, 0};
+            }
+        };
+        auto store_stage = [&]() {
 #pragma unroll
-            for (int f = 0; f < 4; ++f) a[f] = *(const v4i *)(sA + (wm * 64 + f * 16 + fr) * LDS_STRIDE + kk + fk);
+            for (int q = 0; q < 4; ++q) {
+                *(v4i *)(sA + (lr + 32 * q) * LDS_STRIDE + lc) = ra[q];
+                *(v4i *)(sB + (lr + 32 * q) * LDS_STRIDE + lc) = rb[q];
+            }
+        };
+
+        v4i acc[4][4];
 #pragma unroll
-            for (int g = 0; g < 4; ++g) b[g] = *(const v4i *)(sB + (wn * 64 + g * 16 + fr) * LDS_STRIDE + kk + fk);
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
-            for (int f = 0; f < 4; ++f)
+            for (int g = 0; g < 4; ++g) acc[f][g] = v4i{0, 0, 0, 0};
+
+        load_stage(0);
+        for (int64_t k0 = 0; k0 < ld; k0 += BK) {
+            __syncthreads();
+            store_stage();
+            __syncthreads();
+            if (k0 + BK < ld) load_stage(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 64) {
+                v4i a[4], b[4];
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    a[f] = *(const v4i *)(sA + (wm * 64 + f * 16 + fr) * LDS_STRIDE + kk + fk);
 #pragma unroll
                 for (int g = 0; g < 4; ++g)
-                    acc[f][g] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[f], b[g], acc[f][g], 0, 0, 0);
+                    b[g] = *(const v4i *)(sB + (wn * 64 + g * 16 + fr) * LDS_STRIDE + kk + fk);
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[f], b[g], acc[f][g], 0, 0, 0);
+            }
         }
-    }
 
-    // Epilogue: C[row][col] with row = 4*(lane/16) + r inside the 16x16 block,
-    // col = lane % 16.  Count this lane's nonzeros, one atomic per wave.
-    uint32_t mine = 0;
+        // Epilogue: C[row][col] with row = 4*(lane/16) + r inside the 16x16
+        // block, col = lane % 16.  Count this lane's nonzeros, one atomic per wave.
+        uint32_t mine = 0;
 #pragma unroll
-    for (int f = 0; f < 4; ++f)
+        for (int f = 0; f < 4; ++f)
 #pragma unroll
-        for (int g = 0; g < 4; ++g)
+            for (int g = 0; g < 4; ++g)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
-                int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
-                mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
-            }
-    uint32_t incl = wave_incl_scan(mine);
-    uint32_t wtot = __shfl(incl, kWave - 1);
-    if (wtot == 0) return;
-    unsigned long long base = 0;
-    if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
-    base = __shfl(base, 0);
-    int64_t pos = (int64_t)base + (incl - mine);
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
-                int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
-                if (acc[f][g][r] > 0 && i < u && j < w) {
-                    if (pos < cap) emit(pos, i, j);
-                    ++pos;
+                for (int r = 0; r < 4; ++r) {
+                    int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
+                    int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
+                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
                 }
-            }
+        uint32_t incl = wave_incl_scan(mine);
+        uint32_t wtot = __shfl(incl, kWave - 1);
+        if (wtot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
+        base = __shfl(base, 0);
+        int64_t pos = (int64_t)base + (incl - mine);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
+                    int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
+                    if (acc[f][g][r] > 0 && i < u && j < w) {
+                        if (pos < cap) emit(pos, i, j);
+                        ++pos;
+                    }
+                }
+    }
 }
 
 template <class ARows, class Emit>
@@ -192,9 +198,10 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
     if (u <= 0 || w <= 0 || ld <= 0) return;
     (void)kind;
     const int64_t tm = ceil_div(u, BM), tn = ceil_div(w, BN);
-    const int64_t blocks = tm * tn;
-    JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "heavy product too large for one launch");
-    hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3((unsigned)blocks), dim3(256), 0, c.stream, arows, Bt, u, w, ld,
+    const int64_t total = tm * tn;
+    constexpr int64_t kMaxGrid = 1ll << 22;  // tiles beyond this are looped over (multiple of 8)
+    const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
+    hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, Bt, u, w, ld,
                        tm, tn, emit, cap, count_dev);
     JP_HIP(hipGetLastError());
 }

@@ -161,6 +161,14 @@ class DBuf {
 
 struct Selector;
 
+// x dimension of a launch grid.  A dispatch counts its work-items in 32 bits,
+// so a grid of 2^32 or more work-items would be cut short: refuse it.
+inline unsigned grid_x(int64_t blocks, int threads) {
+    if (blocks < 1 || blocks * (int64_t)threads > (int64_t)UINT32_MAX)
+        fail(JP_EINVAL, "launch grid of " + std::to_string(blocks) + " workgroups out of range");
+    return (unsigned)blocks;
+}
+
 // Clearing kernel (used instead of hipMemsetAsync so that a captured stream
 // holds only kernel nodes).
 template <class W>
@@ -210,7 +218,7 @@ struct Ctx {
     template <class W>
     void zero_words(W *p, size_t n) const {
         const int64_t blocks = std::min<int64_t>(((int64_t)n + 255) / 256, (int64_t)num_cus * 8);
-        hipLaunchKernelGGL(k_zero_words<W>, dim3((unsigned)blocks), dim3(256), 0, stream, p, (int64_t)n);
+        hipLaunchKernelGGL(k_zero_words<W>, dim3(grid_x(blocks, 256)), dim3(256), 0, stream, p, (int64_t)n);
         JP_HIP(hipGetLastError());
     }
 };
@@ -251,5 +259,6 @@ inline int bits_for(uint64_t max_value) {  // bits needed to hold values 0..max_
 }
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 
 }  // namespace jp

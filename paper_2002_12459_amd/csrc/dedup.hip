@@ -517,7 +517,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         }
         Timeline tk(c, timing);
         const int k0 = tk.mark();
-        hipLaunchKernelGGL(k_dedup, dim3((unsigned)n_units), dim3(kDT), 0, c.stream, a);
+        hipLaunchKernelGGL(k_dedup, dim3(grid_x(n_units, kDT)), dim3(kDT), 0, c.stream, a);
         JP_HIP(hipGetLastError());
         const int k1 = tk.mark();
         if (stats && timing) stats->ms_kernel = tk.ms(k0, k1);
@@ -550,7 +550,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         ca.out_x = out_x->get();
         ca.out_z = out_z->get();
         const int64_t blocks = ceil_div(total, (int64_t)kCopyBlock * kCopyItems);
-        hipLaunchKernelGGL(k_stage_copy, dim3((unsigned)blocks), dim3(kCopyBlock), 0, c.stream, ca);
+        hipLaunchKernelGGL(k_stage_copy, dim3(grid_x(blocks, kCopyBlock)), dim3(kCopyBlock), 0, c.stream, ca);
         JP_HIP(hipGetLastError());
     }
     *n_out = total;

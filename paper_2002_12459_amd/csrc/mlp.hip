@@ -149,8 +149,7 @@ __global__ __launch_bounds__(256) void k_adam(float *params, float *m, float *v,
 void mlp_forward(const Ctx &c, const float *params, int K, const float *x, int64_t batch, float *y) {
     JP_CHECK(K >= 1 && K <= 256, JP_EINVAL, "selector outputs must be in [1, 256]");
     if (batch <= 0) return;
-    JP_CHECK(batch < (1ll << 31), JP_EINVAL, "batch too large");
-    hipLaunchKernelGGL(k_mlp_fwd, dim3((unsigned)batch), dim3(kH), 0, c.stream, params, K, x, batch, y);
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(grid_x(batch, kH)), dim3(kH), 0, c.stream, params, K, x, batch, y);
     JP_HIP(hipGetLastError());
 }
 
@@ -160,8 +159,7 @@ void mlp_grad(const Ctx &c, const float *params, int K, const float *x, const fl
     c.zero(grad, (size_t)mlp_param_count(K));
     c.zero(loss, 1);
     if (batch <= 0) return;
-    JP_CHECK(batch < (1ll << 31), JP_EINVAL, "batch too large");
-    hipLaunchKernelGGL(k_mlp_grad, dim3((unsigned)batch), dim3(kH), 0, c.stream, params, K, x, target, mask, batch,
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid_x(batch, kH)), dim3(kH), 0, c.stream, params, K, x, target, mask, batch,
                        grad, loss);
     JP_HIP(hipGetLastError());
 }
@@ -171,7 +169,7 @@ void mlp_adam(const Ctx &c, float *params, float *m, float *v, const float *grad
     if (n <= 0) return;
     JP_CHECK(step >= 1, JP_EINVAL, "Adam step counts from 1");
     const float c1 = 1.f - std::pow(b1, (float)step), c2 = 1.f - std::pow(b2, (float)step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, c.stream, params, m, v, grad, n, lr,
+    hipLaunchKernelGGL(k_adam, dim3(grid_x(ceil_div(n, 256), 256)), dim3(256), 0, c.stream, params, m, v, grad, n, lr,
                        b1, b2, eps, c1, c2);
     JP_HIP(hipGetLastError());
 }

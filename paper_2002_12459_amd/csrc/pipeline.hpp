@@ -9,6 +9,7 @@ struct jp_result {
     int64_t n = 0;
     jp::DBuf<int32_t> cols[8];
     jp_stats stats{};
+    std::vector<int64_t> batch_off;  // batched results: instance i owns tuples [off[i], off[i+1])
 };
 
 namespace jp {
@@ -123,6 +124,7 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
 // Pipelines.
 jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
                         const int32_t *sy, int64_t ns, const jp_options &o);
+jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst, const jp_options &o);
 jp_result *run_star(const Ctx &c, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
                     const jp_options &o);
 

@@ -25,7 +25,7 @@ template <class F>
 void for_each(const Ctx &c, int64_t n, F f) {
     if (n <= 0) return;
     int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 32);
-    hipLaunchKernelGGL(k_for_each<F>, dim3((unsigned)blocks), dim3(256), 0, c.stream, n, f);
+    hipLaunchKernelGGL(k_for_each<F>, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, f);
     JP_HIP(hipGetLastError());
 }
 
@@ -146,7 +146,7 @@ struct LookbackState {
     uint64_t *status = nullptr;
     unsigned *ticket = nullptr;
     LookbackState(const Ctx &c, int64_t nt) {
-        JP_CHECK(nt < (1ll << 31), JP_EINVAL, "input too large for one pass");
+        (void)grid_x(nt, kTileBlock);
         if (nt <= 1) return;
         buf = c.buf<uint64_t>((size_t)nt + 1);
         c.zero(buf.get(), (size_t)nt + 1);
@@ -164,7 +164,7 @@ void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = 
     }
     const int64_t nt = ceil_div(n, kTile);
     LookbackState lb(c, nt);
-    hipLaunchKernelGGL((k_scan_lb<G, P>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, get, put, lb.status,
+    hipLaunchKernelGGL((k_scan_lb<G, P>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, get, put, lb.status,
                        lb.ticket, total_dev);
     JP_HIP(hipGetLastError());
 }
@@ -186,7 +186,7 @@ void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
     c.zero(out_dev, 1);
     if (n <= 0) return;
     int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 8);
-    hipLaunchKernelGGL((k_reduce_sum<G>), dim3((unsigned)blocks), dim3(256), 0, c.stream, n, get, out_dev);
+    hipLaunchKernelGGL((k_reduce_sum<G>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, get, out_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -233,7 +233,7 @@ void compact(const Ctx &c, int64_t n, Pr pred, Em emit, int64_t *count_dev) {
     }
     const int64_t nt = ceil_div(n, kTile);
     LookbackState lb(c, nt);
-    hipLaunchKernelGGL((k_compact_lb<Pr, Em>), dim3((unsigned)nt), dim3(kTileBlock), 0, c.stream, n, pred, emit,
+    hipLaunchKernelGGL((k_compact_lb<Pr, Em>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, pred, emit,
                        lb.status, lb.ticket, count_dev);
     JP_HIP(hipGetLastError());
 }
@@ -372,13 +372,13 @@ K *radix_sort(const Ctx &c, K *keys, K *tmp, int64_t n, int bits) {
     K *src = keys, *dst = tmp;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        hipLaunchKernelGGL((k_rs_hist<K>), dim3((unsigned)nt), dim3(kRsBlock), 0, c.stream, (const K *)src, n, shift,
+        hipLaunchKernelGGL((k_rs_hist<K>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, (const K *)src, n, shift,
                            counts.get(), nt);
         JP_HIP(hipGetLastError());
         const uint32_t *cp = counts.get();
         scan_exclusive(
             c, 256 * nt, [=] __device__(int64_t i) -> int64_t { return (int64_t)cp[i]; }, ArrayPut{offs.get()});
-        hipLaunchKernelGGL((k_rs_scatter<K>), dim3((unsigned)nt), dim3(kRsBlock), 0, c.stream, (const K *)src, dst, n,
+        hipLaunchKernelGGL((k_rs_scatter<K>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, (const K *)src, dst, n,
                            shift, (const int64_t *)offs.get(), nt);
         JP_HIP(hipGetLastError());
         std::swap(src, dst);

@@ -529,11 +529,10 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
         ba.err = S + 9;
         c.zero(S + 9, 1);
         const int64_t blocks = ceil_div(J_L, 4096);
-        JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "light witness count too large");
         if (wide)
-            hipLaunchKernelGGL(k_star_expand<u128>, dim3((unsigned)blocks), dim3(256), 0, c.stream, ba);
+            hipLaunchKernelGGL(k_star_expand<u128>, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, ba);
         else
-            hipLaunchKernelGGL(k_star_expand<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, c.stream, ba);
+            hipLaunchKernelGGL(k_star_expand<uint64_t>, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, ba);
         JP_HIP(hipGetLastError());
         JP_CHECK(c.load(S + 9) == 0, JP_EINTERNAL, "star expansion index outside its box");
     }

@@ -145,7 +145,7 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     a.big = big.get();
     a.nbig = (unsigned long long *)(S.get() + 1);
     const int64_t bx = std::min<int64_t>(ceil_div(nmax, kHistBlock), (int64_t)c.num_cus * 2);
-    hipLaunchKernelGGL(k_index_hist, dim3((unsigned)bx, kIdx), dim3(kHistBlock), 0, c.stream, a);
+    hipLaunchKernelGGL(k_index_hist, dim3(grid_x(bx, kHistBlock), kIdx), dim3(kHistBlock), 0, c.stream, a);
     JP_HIP(hipGetLastError());
 
     // nonzero bins of all indexes, in (index, degree) order

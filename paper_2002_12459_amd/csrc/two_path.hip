@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int
 void minmax(const Ctx &c, const int32_t *a, int64_t n, int *out) {
     if (n <= 0) return;
     int64_t blocks = std::min<int64_t>(ceil_div(n, 256 * 16), (int64_t)c.num_cus);
-    hipLaunchKernelGGL(k_minmax, dim3((unsigned)blocks), dim3(256), 0, c.stream, a, n, out);
+    hipLaunchKernelGGL(k_minmax, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, a, n, out);
     JP_HIP(hipGetLastError());
 }
 
@@ -694,8 +694,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             a.err = S + 19;
             c.zero(S + 19, 1);
             const int64_t blocks = ceil_div(J_L, kExpTile);
-            JP_CHECK(blocks < (1ll << 31), JP_EINVAL, "light witness count too large");
-            hipLaunchKernelGGL(k_light_expand, dim3((unsigned)blocks), dim3(kExpBlock), 0, c.stream, a);
+            hipLaunchKernelGGL(k_light_expand, dim3(grid_x(blocks, kExpBlock)), dim3(kExpBlock), 0, c.stream, a);
             JP_HIP(hipGetLastError());
         }
         ev_light = tl.mark();

@@ -14,8 +14,12 @@ Algorithm 2 (Section 5), which stays the fallback.
     python -m paper_2002_12459_amd.selector train --data sweep*.jsonl --holdout-from 1000 \\
         --out selector_mi355x.json --report report.json
 
-Instances: ``datagen.selector_instance`` (|R| = |S| log-uniform, Zipf y
-degrees with exponent U[0.5, 1.8], x / y domains |R|/10 and |R|/50).
+Instances: two families, each indexed from 0.  "zipf":
+``datagen.selector_instance`` (|R| = |S| log-uniform, Zipf y degrees with
+exponent U[0.5, 1.8], x / y domains |R|/10 and |R|/50; the output is close to
+the join size, few duplicates).  "clustered":
+``datagen.selector_instance_clustered`` (dense communities, as in the
+paper's Example 1, plus a Zipf part; many duplicate witnesses).
 Instances whose full join J = sum_y deg_R(y) deg_S(y) exceeds ``--jmax`` are
 recorded as rejected and not timed: their run time is dominated by writing an
 output close to |dom x| |dom z| pairs whatever the thresholds.
@@ -44,11 +48,15 @@ N_FEATURES = 16
 
 # ---------------------------------------------------------------------------- sweep
 
-def _generate(i, lo, hi, jmax):
+def _generate(i, family, lo, hi, jmax):
     import numpy as np
 
     import datagen
-    (rx, ry), (sz, sy), s = datagen.selector_instance(i, lo=lo, hi=hi)
+    if family == "clustered":
+        (rx, ry), (sz, sy), prm = datagen.selector_instance_clustered(i, lo=lo, hi=hi)
+        s = prm["s"]
+    else:
+        (rx, ry), (sz, sy), s = datagen.selector_instance(i, lo=lo, hi=hi)
     ny = int(max(ry.max(), sy.max())) + 1
     J = int((np.bincount(ry, minlength=ny).astype(np.int64) * np.bincount(sy, minlength=ny)).sum())
     if J > jmax:
@@ -56,7 +64,13 @@ def _generate(i, lo, hi, jmax):
     return i, (rx, ry, sz, sy), s, J
 
 
+def _key(rec):
+    return rec.get("family", "zipf"), rec["i"]
+
+
 def _done_indices(paths):
+    """Instances already swept cleanly (records whose cells disagreed on the
+    output size are swept again)."""
     done = set()
     for p in paths:
         if not os.path.exists(p):
@@ -65,7 +79,9 @@ def _done_indices(paths):
             for line in fh:
                 line = line.strip()
                 if line:
-                    done.add(json.loads(line)["i"])
+                    r = json.loads(line)
+                    if not r.get("mismatch"):
+                        done.add(_key(r))
     return done
 
 
@@ -73,10 +89,10 @@ def sweep(args):
     import multiprocessing as mp
 
     done = _done_indices(args.resume + [args.out])
-    todo = [i for i in range(args.first, args.first + args.count) if i not in done]
+    todo = [i for i in range(args.first, args.first + args.count) if (args.family, i) not in done]
     # workers only run numpy; they are forked before this process touches the GPU
     pool = mp.get_context("fork").Pool(args.workers)
-    gen = pool.imap(functools.partial(_generate, lo=args.lo, hi=args.hi, jmax=args.jmax), todo)
+    gen = pool.imap(functools.partial(_generate, family=args.family, lo=args.lo, hi=args.hi, jmax=args.jmax), todo)
 
     import numpy as np
     import torch
@@ -90,7 +106,7 @@ def sweep(args):
     out = open(args.out, "a")
     n_done = 0
     for i, data, s, J in gen:
-        rec = {"i": i, "s": s, "J": J}
+        rec = {"family": args.family, "i": i, "s": s, "J": J}
         if data is None:
             rec["rejected"] = True
             out.write(json.dumps(rec) + "\n")
@@ -172,6 +188,8 @@ def sweep(args):
 # ---------------------------------------------------------------------------- train
 
 def load_records(paths):
+    """Clean records (every cell gave the same output size), one per
+    (family, instance), the last one read winning."""
     recs = {}
     for p in paths:
         with open(p) as fh:
@@ -179,8 +197,9 @@ def load_records(paths):
                 line = line.strip()
                 if line:
                     r = json.loads(line)
-                    recs[r["i"]] = r
-    return [recs[i] for i in sorted(recs)]
+                    if not r.get("mismatch"):
+                        recs[_key(r)] = r
+    return [recs[k] for k in sorted(recs)]
 
 
 def targets(rec, skip_ratio):
@@ -221,10 +240,12 @@ def train(args):
     import paper_2002_12459_amd as jp
 
     recs = [r for r in load_records(args.data) if not r.get("rejected")]
-    tr = [r for r in recs if r["i"] < args.holdout_from]
-    te = [r for r in recs if r["i"] >= args.holdout_from]
-    nval = max(1, int(len(tr) * args.val_frac))
-    fit, val = tr[:-nval], tr[-nval:]
+    hold = {"zipf": args.holdout_from, "clustered": args.holdout_from_clustered}
+    tr = [r for r in recs if r["i"] < hold[_key(r)[0]]]
+    te = [r for r in recs if r["i"] >= hold[_key(r)[0]]]
+    every = max(2, int(round(1.0 / args.val_frac)))  # every k-th training instance validates
+    fit = [r for k, r in enumerate(tr) if k % every != every - 1]
+    val = [r for k, r in enumerate(tr) if k % every == every - 1]
     X = lambda rs: np.asarray([r["features"] for r in rs], dtype=np.float32)
     Y = lambda rs: np.asarray([targets(r, args.skip_ratio) for r in rs], dtype=np.float32)
     mean = X(fit).mean(axis=0)
@@ -275,16 +296,24 @@ def train(args):
     if te:
         xt = norm(te)
         ks = picks(best_p, xt)
+        best = lambda r: min(x for x in r["t"] if x is not None)
         rows = {"mlp": [regret(r, int(k), args.skip_ratio) for r, k in zip(te, ks)]}
         for name in ("auto", "theory", "sqrtN"):
-            best = lambda r: min(x for x in r["t"] if x is not None)
             rows[name] = [r[name]["t"] / best(r) for r in te]
         rows["light_only"] = [regret(r, 64, args.skip_ratio) for r in te]
+        fam = [_key(r)[0] for r in te]
         report["holdout"] = {k: _summary(vv) for k, vv in rows.items()}
         report["holdout_n"] = len(te)
-        for k, s in report["holdout"].items():
-            print(f"[eval] {k:10s} geomean {s['geomean']:.3f} p50 {s['p50']:.3f} p90 {s['p90']:.3f} "
-                  f"max {s['max']:.2f}", flush=True)
+        report["holdout_by_family"] = {
+            f: {k: _summary([x for x, g in zip(vv, fam) if g == f]) for k, vv in rows.items()}
+            for f in sorted(set(fam))}
+        report["mlp_picks"] = {"light_only": int(sum(int(k) == 64 for k in ks)), "grid": int(sum(int(k) != 64 for k in ks))}
+        for k, s_ in report["holdout"].items():
+            print(f"[eval] {k:10s} geomean {s_['geomean']:.3f} p50 {s_['p50']:.3f} p90 {s_['p90']:.3f} "
+                  f"max {s_['max']:.2f}", flush=True)
+        for f, d in report["holdout_by_family"].items():
+            print(f"[eval] {f}: mlp {d['mlp']['geomean']:.3f} auto {d['auto']['geomean']:.3f} "
+                  f"light {d['light_only']['geomean']:.3f} (n={d['mlp']['n']})", flush=True)
     if args.report:
         with open(args.report, "w") as fh:
             json.dump(report, fh, indent=1)
@@ -295,6 +324,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2002_12459_amd.selector")
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("sweep")
+    a.add_argument("--family", choices=["zipf", "clustered"], default="zipf")
     a.add_argument("--first", type=int, default=0)
     a.add_argument("--count", type=int, default=100)
     a.add_argument("--out", required=True)
@@ -310,7 +340,8 @@ def main(argv=None):
     a.add_argument("--time-budget", type=float, default=900.0)
     b = sub.add_parser("train")
     b.add_argument("--data", nargs="+", required=True)
-    b.add_argument("--holdout-from", type=int, default=1000)
+    b.add_argument("--holdout-from", type=int, default=1000, help="first held-out zipf instance")
+    b.add_argument("--holdout-from-clustered", type=int, default=450, help="first held-out clustered instance")
     b.add_argument("--val-frac", type=float, default=0.1)
     b.add_argument("--steps", type=int, default=4000)
     b.add_argument("--lr", type=float, default=3e-3)

@@ -167,6 +167,20 @@ def test_bool_matmul_counts_do_not_overflow(jp):
     assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
 
 
+def test_bool_matmul_more_tiles_than_one_grid(jp):
+    """600000 x 600000 output (22M tiles of 128 x 128, more work-items than one
+    dispatch can count): one-hot rows at column i % 128, so C[i][j] > 0 iff
+    i and j agree mod 128; the count has a closed form."""
+    import torch
+    u = w = 600_000
+    A = torch.zeros((u, 128), dtype=torch.int8, device="cuda")
+    idx = torch.arange(u, device="cuda")
+    A[idx, idx % 128] = 1
+    nnz, _ = jp.default_handle(0).bool_matmul_count(A, A)
+    per = np.bincount(np.arange(u) % 128, minlength=128).astype(np.int64)
+    assert nnz == int((per * per).sum())
+
+
 @pytest.mark.parametrize("dedup", ["global", "segmented"])
 def test_dedup_strategies(jp, dedup):
     """Both duplicate-removal strategies (one device-wide sort; per-x on-chip
