@@ -66,8 +66,10 @@ typedef enum jp_strategy {
 /* Kernel used for the heavy 0/1 matrix product. */
 typedef enum jp_bmm_kind {
     JP_BMM_AUTO = 0,     /* int8 MFMA unless the planner prefers the popcount kernel */
-    JP_BMM_I8_MFMA = 1,  /* int8 inputs, int32 accumulation on the matrix cores */
-    JP_BMM_BITPOP = 2    /* bit-packed rows, AND + popcount on the vector units */
+    JP_BMM_I8_MFMA = 1,  /* int8 inputs, int32 accumulation on the matrix cores; tile by shape */
+    JP_BMM_BITPOP = 2,   /* bit-packed rows, AND + popcount on the vector units */
+    JP_BMM_I8_T128 = 3,  /* int8 MFMA, 128 x 128 block tiles */
+    JP_BMM_I8_T256 = 4   /* int8 MFMA, 256 x 256 block tiles */
 } jp_bmm_kind;
 
 /* Which y-degree decides whether y is heavy (two-path).  MAX: y is heavy when

@@ -17,6 +17,7 @@ struct jp_handle {
     std::string err;
     jp_calibration cal;
     jp::Selector sel;  // after alloc: its buffer returns to the allocator first
+    std::map<uint64_t, int> tune;  // heavy-product kernel per shape class
 };
 
 namespace {
@@ -42,6 +43,7 @@ jp::Ctx make_ctx(jp_handle *h) {
     c.num_cus = h->num_cus;
     c.cal = &h->cal;
     c.sel = &h->sel;
+    c.tune = &h->tune;
     return c;
 }
 
@@ -76,7 +78,7 @@ jp_status validate_options(jp_handle *h, const jp_options &o) {
         h->err = "FIXED thresholds must be >= 1";
         return JP_EINVAL;
     }
-    if (o.bmm < JP_BMM_AUTO || o.bmm > JP_BMM_BITPOP || o.y_rule < JP_Y_RULE_MAX ||
+    if (o.bmm < JP_BMM_AUTO || o.bmm > JP_BMM_I8_T256 || o.y_rule < JP_Y_RULE_MAX ||
         o.y_rule > JP_Y_RULE_R_ONLY || o.dedup < JP_DEDUP_AUTO || o.dedup > JP_DEDUP_SEGMENTED) {
         h->err = "bad option value";
         return JP_EINVAL;
@@ -454,7 +456,7 @@ jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt, int64_
     if (!h) return JP_EINVAL;
     if (u < 0 || w < 0 || k < 0 || cap < 0 || !nnz || ld < k || ld % jp::kBmmPadK != 0 ||
         bad_col(A, u * ld) || bad_col(Bt, w * ld) || bad_col(rows, cap) || bad_col(cols, cap) ||
-        kind < JP_BMM_AUTO || kind > JP_BMM_BITPOP) {
+        kind < JP_BMM_AUTO || kind > JP_BMM_I8_T256) {
         h->err = "bad argument to jp_bool_matmul (ld must be >= k and a multiple of 128)";
         return JP_EINVAL;
     }

@@ -190,6 +190,146 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
     }
 }
 
+// ---- int8 MFMA kernel, large tiles ---------------------------------------------
+// Block tile 256 x 256, K stage 128 bytes, 512 threads = 2 x 4 waves, each
+// wave a 128 x 64 sub-tile of 8 x 4 MFMA 16x16x64 blocks (128 accumulator
+// registers).  Operands go from global memory straight into LDS
+// (global_load_lds_dwordx4, 16 bytes per lane), double buffered: the next
+// stage streams in while the current one is multiplied.  LDS rows are 128
+// bytes with the 16-byte chunk c of row r stored at position c ^ (r & 7), so
+// the MFMA operand reads of 8 consecutive rows hit 8 different bank groups.
+// Twice the block tile of the 128 x 128 kernel halves the operand traffic
+// per operation.
+constexpr int BM2 = 256, BN2 = 256, BK2 = 128;
+constexpr int kBig = 512;                       // threads
+constexpr int kStageBytes = (BM2 + BN2) * BK2;  // 64 KB: A rows then B rows
+
+__device__ __forceinline__ int swz(int r, int c) { return r * BK2 + ((c ^ (r & 7)) << 4); }
+
+template <class Emit>
+__global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ A, const int8_t *__restrict__ Bt,
+                                                     int64_t u, int64_t w, int64_t ld, int64_t tiles_m,
+                                                     int64_t tiles_n, Emit emit, int64_t cap,
+                                                     unsigned long long *count) {
+    extern __shared__ __attribute__((aligned(16))) int8_t lds[];  // 2 stages
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    const int wm = wv >> 2, wn = wv & 3;
+    const int fr = lane % 16, fq = lane / 16;
+    const int64_t total = tiles_m * tiles_n;
+    const int64_t nk = ld / BK2;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        int64_t tm, tn;
+        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        const int64_t row0 = tm * BM2, col0 = tn * BN2;
+        // Stage s: 4096 chunks of 16 bytes, 8 rounds of 512; chunk P holds
+        // (row P / 8, K chunk (P % 8) ^ (row & 7)); rows 0..255 are A, 256..511 B.
+        // Rows past the matrix edge read row 0 (their results are never emitted).
+        auto issue = [&](int64_t k0, int buf) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int P = q * kBig + tid;
+                const int r = P >> 3, c = (P & 7) ^ (r & 7);
+                const int8_t *src;
+                if (r < BM2) {
+                    const int64_t gr = row0 + r;
+                    src = A + (gr < u ? gr : 0) * ld + k0 + c * 16;
+                } else {
+                    const int64_t gc = col0 + (r - BM2);
+                    src = Bt + (gc < w ? gc : 0) * ld + k0 + c * 16;
+                }
+                // LDS destination of the wave: its 64 consecutive chunks
+                int8_t *dst = lds + buf * kStageBytes + (q * kBig + wv * kWave) * 16;
+                __builtin_amdgcn_global_load_lds((const void *)src, (__attribute__((address_space(3))) void *)dst,
+                                                 16, 0, 0);
+            }
+        };
+        v4i acc[8][4];
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[f][g] = v4i{0, 0, 0, 0};
+
+        __syncthreads();  // the previous tile's last reads of both buffers are done
+        issue(0, 0);
+        for (int64_t s = 0; s < nk; ++s) {
+            const int buf = (int)(s & 1);
+            __builtin_amdgcn_s_waitcnt(0);  // this thread's loads of stage s have landed
+            __syncthreads();                // everyone's have; buffer buf ^ 1 is free
+            if (s + 1 < nk) issue((s + 1) * BK2, buf ^ 1);
+            const int8_t *sa = lds + buf * kStageBytes;
+            const int8_t *sb = sa + BM2 * BK2;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {  // two K steps of 64 bytes
+                const int c = kk * 4 + fq;
+                v4i a[8], b[4];
+#pragma unroll
+                for (int f = 0; f < 8; ++f) {
+                    const int r = wm * 128 + f * 16 + fr;
+                    a[f] = *(const v4i *)(sa + swz(r, c));
+                }
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int r = wn * 64 + g * 16 + fr;
+                    b[g] = *(const v4i *)(sb + swz(r, c));
+                }
+#pragma unroll
+                for (int f = 0; f < 8; ++f)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_i32_16x16x64_i8(a[f], b[g], acc[f][g], 0, 0, 0);
+            }
+        }
+
+        // Epilogue as in the 128 x 128 kernel.
+        uint32_t mine = 0;
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
+                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
+                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
+                }
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t wtot = __shfl(incl, kWave - 1);
+        if (wtot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
+        base = __shfl(base, 0);
+        int64_t pos = (int64_t)base + (incl - mine);
+#pragma unroll
+        for (int f = 0; f < 8; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
+                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
+                    if (acc[f][g][r] > 0 && i < u && j < w) {
+                        if (pos < cap) emit(pos, i, j);
+                        ++pos;
+                    }
+                }
+    }
+}
+
+template <class Emit>
+void launch_bmm_big(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, Emit emit,
+                    int64_t cap, unsigned long long *count_dev) {
+    JP_CHECK(ld % BK2 == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 128");
+    c.zero(count_dev, 1);
+    if (u <= 0 || w <= 0 || ld <= 0) return;
+    const int64_t tm = ceil_div(u, BM2), tn = ceil_div(w, BN2);
+    const int64_t total = tm * tn;
+    constexpr int64_t kMaxGrid = 1ll << 21;  // multiple of 8
+    const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
+    hipLaunchKernelGGL((k_bmm_i8_big<Emit>), dim3(grid_x(blocks, kBig)), dim3(kBig), 2 * kStageBytes, c.stream, A,
+                       Bt, u, w, ld, tm, tn, emit, cap, count_dev);
+    JP_HIP(hipGetLastError());
+}
+
 template <class ARows, class Emit>
 void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind, Emit emit,
                 int64_t cap, unsigned long long *count_dev) {
@@ -208,15 +348,209 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
 
 }  // namespace
 
+// ---- bit-packed AND + popcount kernel ----------------------------------------
+// The 0/1 rows packed 64 per word; C[i][j] = sum over words of
+// popcount(A[i][w] & B[j][w]) on the vector units (no matrix cores).  Block
+// tile 128 x 128, 256 threads as 16 x 16; thread (ty, tx) owns rows
+// ty + 16 i and columns tx + 16 j (i, j < 8), so the 16 threads of a row
+// group read 16 consecutive B words from LDS.  K is staged through LDS 8
+// words (512 columns) at a time, stored word-major.
+constexpr int PB = 128, PKW = 8;
+
+__global__ __launch_bounds__(256) void k_pack_bits(const int8_t *__restrict__ M, int64_t rows, int64_t ld,
+                                                   uint64_t *__restrict__ P) {
+    const int64_t nw = ld / 64, n = rows * nw;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += stride) {
+        const int64_t r = t / nw, wd = t - r * nw;
+        const v4i *src = (const v4i *)(M + r * ld + wd * 64);
+        uint64_t bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const v4i v = src[q];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t x = (uint32_t)v[e];
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    bits |= (uint64_t)(((x >> (8 * b)) & 0xffu) != 0) << (q * 16 + e * 4 + b);
+            }
+        }
+        P[t] = bits;
+    }
+}
+
+template <class Emit>
+__global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__ A, const uint64_t *__restrict__ B,
+                                                    int64_t u, int64_t w, int64_t nw, int64_t tiles_m,
+                                                    int64_t tiles_n, Emit emit, int64_t cap,
+                                                    unsigned long long *count) {
+    __shared__ uint64_t sA[PKW][PB], sB[PKW][PB];
+    const int tid = threadIdx.x, lane = lane_id();
+    const int ty = tid / 16, tx = tid % 16;
+    const int64_t total = tiles_m * tiles_n;
+    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+        int64_t tm, tn;
+        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        const int64_t row0 = tm * PB, col0 = tn * PB;
+        uint32_t acc[8][8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[i][j] = 0;
+        for (int64_t k0 = 0; k0 < nw; k0 += PKW) {
+            __syncthreads();
+            // 128 rows x 8 words of A and of B: 1024 words each, 4 per thread
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = q * 256 + tid, r = e / PKW, kw = e % PKW;
+                const int64_t gr = row0 + r, gc = col0 + r, gk = k0 + kw;
+                sA[kw][r] = (gr < u && gk < nw) ? A[gr * nw + gk] : 0ull;
+                sB[kw][r] = (gc < w && gk < nw) ? B[gc * nw + gk] : 0ull;
+            }
+            __syncthreads();
+#pragma unroll 2
+            for (int kw = 0; kw < PKW; ++kw) {
+                uint64_t a[8], b[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) a[i] = sA[kw][ty + 16 * i];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) b[j] = sB[kw][tx + 16 * j];
+#pragma unroll
+                for (int i = 0; i < 8; ++i)
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) acc[i][j] += (uint32_t)__popcll(a[i] & b[j]);
+            }
+        }
+        uint32_t mine = 0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                mine += (acc[i][j] > 0 && row0 + ty + 16 * i < u && col0 + tx + 16 * j < w) ? 1u : 0u;
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t wtot = __shfl(incl, kWave - 1);
+        if (wtot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
+        base = __shfl(base, 0);
+        int64_t pos = (int64_t)base + (incl - mine);
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t gi = row0 + ty + 16 * i, gj = col0 + tx + 16 * j;
+                if (acc[i][j] > 0 && gi < u && gj < w) {
+                    if (pos < cap) emit(pos, gi, gj);
+                    ++pos;
+                }
+            }
+    }
+}
+
+template <class Emit>
+void launch_bitpop(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, Emit emit,
+                   int64_t cap, unsigned long long *count_dev) {
+    JP_CHECK(ld % 64 == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 64");
+    c.zero(count_dev, 1);
+    if (u <= 0 || w <= 0 || ld <= 0) return;
+    const int64_t nw = ld / 64;
+    DBuf<uint64_t> pa = c.buf<uint64_t>((size_t)(u * nw)), pb = c.buf<uint64_t>((size_t)(w * nw));
+    const int64_t gp = std::min<int64_t>(ceil_div(std::max(u, w) * nw, 256), (int64_t)c.num_cus * 16);
+    hipLaunchKernelGGL(k_pack_bits, dim3(grid_x(gp, 256)), dim3(256), 0, c.stream, A, u, ld, pa.get());
+    hipLaunchKernelGGL(k_pack_bits, dim3(grid_x(gp, 256)), dim3(256), 0, c.stream, Bt, w, ld, pb.get());
+    JP_HIP(hipGetLastError());
+    const int64_t tm = ceil_div(u, PB), tn = ceil_div(w, PB);
+    const int64_t total = tm * tn;
+    constexpr int64_t kMaxGrid = 1ll << 22;
+    const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
+    hipLaunchKernelGGL((k_bmm_bitpop<Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream,
+                       (const uint64_t *)pa.get(), (const uint64_t *)pb.get(), u, w, nw, tm, tn, emit, cap,
+                       count_dev);
+    JP_HIP(hipGetLastError());
+}
+
+// Kernel choice: explicit, or for JP_BMM_AUTO / JP_BMM_I8_MFMA by shape
+// (large tiles need both sides to fill several 256-row tiles); AUTO also
+// races the popcount kernel against the int8 kernel once per shape class on
+// the handle (autotune), keeping the faster.
+enum class BmmVariant { T128, T256, BITPOP };
+
+static BmmVariant by_shape(int64_t u, int64_t w) {
+    return (u >= 1024 && w >= 1024) ? BmmVariant::T256 : BmmVariant::T128;
+}
+
+template <class Emit>
+static void run_variant(const Ctx &c, BmmVariant v, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w,
+                        int64_t ld, Emit emit, int64_t cap, unsigned long long *count_dev) {
+    switch (v) {
+        case BmmVariant::T256: launch_bmm_big(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
+        case BmmVariant::BITPOP: launch_bitpop(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
+        default: launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, JP_BMM_I8_MFMA, emit, cap, count_dev); break;
+    }
+}
+
+// Shape class: log2 buckets of u, w and the stride.
+static uint64_t shape_class(int64_t u, int64_t w, int64_t ld) {
+    return ((uint64_t)bits_for((uint64_t)u) << 16) | ((uint64_t)bits_for((uint64_t)w) << 8) |
+           (uint64_t)bits_for((uint64_t)ld);
+}
+
+template <class Emit>
+static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
+                            int kind, Emit emit, int64_t cap, unsigned long long *count_dev) {
+    BmmVariant v;
+    switch (kind) {
+        case JP_BMM_I8_T128: v = BmmVariant::T128; break;
+        case JP_BMM_I8_T256: v = BmmVariant::T256; break;
+        case JP_BMM_BITPOP: v = BmmVariant::BITPOP; break;
+        case JP_BMM_I8_MFMA: v = by_shape(u, w); break;
+        default: {
+            v = by_shape(u, w);
+            // race once per shape class (products too small to matter are not raced)
+            if (c.tune && (double)u * (double)w * (double)ld >= 1e9) {
+                const uint64_t key = shape_class(u, w, ld);
+                auto it = c.tune->find(key);
+                if (it != c.tune->end()) {
+                    v = (BmmVariant)it->second;
+                } else {
+                    const BmmVariant cand[2] = {v, BmmVariant::BITPOP};
+                    float best = -1;
+                    for (BmmVariant q : cand) {
+                        hipEvent_t e0, e1;
+                        JP_HIP(hipEventCreate(&e0));
+                        JP_HIP(hipEventCreate(&e1));
+                        JP_HIP(hipEventRecord(e0, c.stream));
+                        run_variant(c, q, A, Bt, u, w, ld, emit, 0, count_dev);  // count only
+                        JP_HIP(hipEventRecord(e1, c.stream));
+                        JP_HIP(hipEventSynchronize(e1));
+                        float ms = 0;
+                        JP_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        if (best < 0 || ms < best) {
+                            best = ms;
+                            v = q;
+                        }
+                    }
+                    (*c.tune)[key] = (int)v;
+                }
+            }
+        }
+    }
+    if (c.bmm_used) *c.bmm_used = v == BmmVariant::BITPOP ? JP_BMM_BITPOP : JP_BMM_I8_MFMA;
+    run_variant(c, v, A, Bt, u, w, ld, emit, cap, count_dev);
+}
+
 void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                        int32_t *out_i, int32_t *out_j, int64_t cap, unsigned long long *count_dev) {
-    launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, kind, PairEmit{out_i, out_j}, cap, count_dev);
+    bool_matmul_any(c, A, Bt, u, w, ld, kind, PairEmit{out_i, out_j}, cap, count_dev);
 }
 
 void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,
                       unsigned long long *count_dev) {
-    launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
+    bool_matmul_any(c, A, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
 }
 
 void star_bmm_keys(const Ctx &c, const int8_t *M1, const int8_t *M2, const int8_t *M3, int64_t u1, int64_t u2,

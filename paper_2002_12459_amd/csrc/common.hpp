@@ -186,6 +186,8 @@ struct Ctx {
     size_t lds_bytes = 160 * 1024;
     const jp_calibration *cal = nullptr;  // optimizer constants of the handle
     const Selector *sel = nullptr;        // learned threshold selector of the handle (may be empty)
+    std::map<uint64_t, int> *tune = nullptr;  // product kernel per shape class, raced once (handle-owned)
+    mutable int *bmm_used = nullptr;          // where to report the product kernel used (may be null)
 
     template <class T>
     DBuf<T> buf(size_t n) const {

@@ -28,13 +28,30 @@
 namespace jp {
 namespace {
 
-__global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int *out) {
+// min / max of four int32 columns (R x, R y, S z, S y) into out[8]; grid.y
+// selects the column, 16 values per thread per step with 16-byte loads.
+__global__ __launch_bounds__(256) void k_minmax4(const int32_t *c0, const int32_t *c1, int64_t n01, const int32_t *c2,
+                                                 const int32_t *c3, int64_t n23, int *out) {
     __shared__ int smn[256 / kWave], smx[256 / kWave];
+    const int k = blockIdx.y;
+    const int32_t *a = k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3));
+    const int64_t n = k < 2 ? n01 : n23;
     int mn = INT_MAX, mx = INT_MIN;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        int v = a[i];
-        mn = v < mn ? v : mn;
-        mx = v > mx ? v : mx;
+    // aligned body as int4, the rest one by one
+    const int64_t head = std::min<int64_t>(n, (int64_t)((16 - ((uintptr_t)a & 15)) & 15) / 4);
+    const int64_t nv = (n - head) / 4;
+    const int4 *v = (const int4 *)(a + head);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
+        const int4 q = v[i];
+        mn = min(mn, min(min(q.x, q.y), min(q.z, q.w)));
+        mx = max(mx, max(max(q.x, q.y), max(q.z, q.w)));
+    }
+    const int64_t tail0 = head + 4 * nv, nrest = head + (n - tail0);  // at most 6 values
+    for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrest; r += stride) {
+        const int t = a[r < head ? r : tail0 + (r - head)];
+        mn = t < mn ? t : mn;
+        mx = t > mx ? t : mx;
     }
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) {
@@ -53,15 +70,17 @@ __global__ __launch_bounds__(256) void k_minmax(const int32_t *a, int64_t n, int
             mn = smn[i] < mn ? smn[i] : mn;
             mx = smx[i] > mx ? smx[i] : mx;
         }
-        atomicMin(&out[0], mn);
-        atomicMax(&out[1], mx);
+        atomicMin(&out[2 * k], mn);
+        atomicMax(&out[2 * k + 1], mx);
     }
 }
 
-void minmax(const Ctx &c, const int32_t *a, int64_t n, int *out) {
+void minmax4(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz, const int32_t *sy,
+             int64_t ns, int *out) {
+    const int64_t n = std::max(nr, ns);
     if (n <= 0) return;
-    int64_t blocks = std::min<int64_t>(ceil_div(n, 256 * 16), (int64_t)c.num_cus);
-    hipLaunchKernelGGL(k_minmax, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, a, n, out);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256 * 16), (int64_t)c.num_cus * 2));
+    hipLaunchKernelGGL(k_minmax4, dim3(grid_x(blocks, 256), 4), dim3(256), 0, c.stream, rx, ry, nr, sz, sy, ns, out);
     JP_HIP(hipGetLastError());
 }
 
@@ -108,6 +127,10 @@ __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
 
 }  // namespace
 
+// Dense id-indexed tables are used when an id range is at most a few times
+// the input size (and at most 2^26 entries).
+static bool dense_range_ok(int64_t span, int64_t n) { return span <= (1ll << 26) && span <= 4 * n + (1ll << 20); }
+
 // Returns false when the instance has no output (no common y).
 static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
                             const int32_t *sy, int64_t ns, Ingest &g, int64_t *S) {
@@ -118,10 +141,7 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         mm[2 * i] = INT_MAX;
         mm[2 * i + 1] = INT_MIN;
     });
-    minmax(c, rx, nr, mm + 0);
-    minmax(c, ry, nr, mm + 2);
-    minmax(c, sz, ns, mm + 4);
-    minmax(c, sy, ns, mm + 6);
+    minmax4(c, rx, ry, nr, sz, sy, ns, mm);
     int hmm[8];
     c.load_n(hmm, mm, 8);
     const int64_t xmin = hmm[0], xmax = hmm[1], zmin = hmm[4], zmax = hmm[5];
@@ -249,7 +269,9 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             },
             S + 5);
     }
-    // R tuples kept, x-major: x offset + y rank
+    // R tuples kept, x-major: x offset + y rank.  The y rank of an R tuple
+    // comes from a dense table over the y range when that range is small
+    // enough, else from a binary search in the distinct y of S.
     DBuf<uint32_t> r2_x = c.buf<uint32_t>(n_r1);
     DBuf<int32_t> adj_r = c.buf<int32_t>(n_r1);
     {
@@ -261,20 +283,36 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint64_t ym = ymask;
         uint32_t *ox = r2_x.get();
         int32_t *oy = adj_r.get();
-        auto find = [=] __device__(int64_t i) -> int32_t {
-            uint32_t y = (uint32_t)(s[i] & ym);
-            const int64_t p = lower_bound_dev(ys, (int64_t)0, nys, y);
-            const int64_t q = p < nys ? p : nys - 1;
-            const int32_t r = yr[q];
-            return ((p < nys) & (ys[q] == y)) ? r : -1;
-        };
-        compact(
-            c, n_r1, [=] __device__(int64_t i) { return find(i) >= 0; },
-            [=] __device__(int64_t i, int64_t p) {
-                ox[p] = (uint32_t)(s[i] >> ybs);
-                oy[p] = find(i);
-            },
-            S + 6);
+        const int64_t yspan = ymax - ymin + 1;
+        if (dense_range_ok(yspan, nr + ns)) {
+            DBuf<int32_t> ymap = c.buf<int32_t>((size_t)yspan);
+            int32_t *ymp = ymap.get();
+            for_each(c, yspan, [=] __device__(int64_t y) { ymp[y] = -1; });
+            for_each(c, nys, [=] __device__(int64_t j) { ymp[ys[j]] = yr[j]; });
+            const int32_t *ymc = ymp;
+            compact(
+                c, n_r1, [=] __device__(int64_t i) { return ymc[s[i] & ym] >= 0; },
+                [=] __device__(int64_t i, int64_t p) {
+                    ox[p] = (uint32_t)(s[i] >> ybs);
+                    oy[p] = ymc[s[i] & ym];
+                },
+                S + 6);
+        } else {
+            auto find = [=] __device__(int64_t i) -> int32_t {
+                uint32_t y = (uint32_t)(s[i] & ym);
+                const int64_t p = lower_bound_dev(ys, (int64_t)0, nys, y);
+                const int64_t q = p < nys ? p : nys - 1;
+                const int32_t r = yr[q];
+                return ((p < nys) & (ys[q] == y)) ? r : -1;
+            };
+            compact(
+                c, n_r1, [=] __device__(int64_t i) { return find(i) >= 0; },
+                [=] __device__(int64_t i, int64_t p) {
+                    ox[p] = (uint32_t)(s[i] >> ybs);
+                    oy[p] = find(i);
+                },
+                S + 6);
+        }
     }
     int64_t h7[3];
     c.load_n(h7, S + 4, 3);
@@ -342,7 +380,18 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         for_each(c, dom_z, [=] __device__(int64_t r) { zo[r] = (int32_t)((int64_t)zs[r] + zm); });
         const uint32_t *sz2 = s2_z.get();
         int32_t *as = adj_s.get();
-        for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zs, (int64_t)0, nz, sz2[e]); });
+        const int64_t zspan = zmax - zmin + 1;
+        if (dense_range_ok(zspan, nr + ns)) {
+            // every z of S is among the distinct z: a table entry per distinct z suffices
+            DBuf<int32_t> zmap = c.buf<int32_t>((size_t)zspan);
+            int32_t *zmp = zmap.get();
+            for_each(c, nz, [=] __device__(int64_t r) { zmp[zs[r]] = (int32_t)r; });
+            const int32_t *zmc = zmp;
+            for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = zmc[sz2[e]]; });
+        } else {
+            for_each(c, n_s2,
+                     [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zs, (int64_t)0, nz, sz2[e]); });
+        }
         const int32_t *syr = s2_y.get();
         int64_t *oy = off_y.get();
         const int64_t ny = dom_y, ns2 = n_s2;
@@ -641,7 +690,10 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         if (has_heavy) {
             hk = c.buf<uint64_t>(std::max<int64_t>(cap_h, 1));
             ev_bmm0 = tl.mark();
-            bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz, hk.get(),
+            int used = JP_BMM_I8_MFMA;
+            Ctx cb = c;
+            cb.bmm_used = &used;
+            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz, hk.get(),
                              cap_h, (unsigned long long *)(S + 17));
             ev_bmm1 = tl.mark();
             nnz = c.load(S + 17);
@@ -649,7 +701,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             hk_tmp = c.buf<uint64_t>(std::max<int64_t>(nnz, 1));
             hks = radix_sort(c, hk.get(), hk_tmp.get(), nnz, bx + bz);
             dump(c, "heavy keys", hks, nnz);
-            st.bmm = JP_BMM_I8_MFMA;
+            st.bmm = used;
             st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
         }
         M1.reset();
@@ -703,13 +755,16 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         dump(c, "light keys", cand.get(), J_L);
         if (has_heavy) {
             ev_bmm0 = tl.mark();
-            bool_matmul_keys(c, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
+            int used = JP_BMM_I8_MFMA;
+            Ctx cb = c;
+            cb.bmm_used = &used;
+            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
                              cand.get() + J_L, cap_h, (unsigned long long *)(S + 17));
             ev_bmm1 = tl.mark();
             nnz = c.load(S + 17);
             JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
             dump(c, "heavy keys", cand.get() + J_L, nnz);
-            st.bmm = JP_BMM_I8_MFMA;
+            st.bmm = used;
             st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
         }
         M1.reset();

@@ -240,6 +240,12 @@ def train(args):
     import paper_2002_12459_amd as jp
 
     recs = [r for r in load_records(args.data) if not r.get("rejected")]
+    if args.table_out:
+        import gzip
+        keep = ("family", "i", "n", "s", "J", "n_out", "features", "t", "auto", "theory", "sqrtN")
+        with gzip.open(args.table_out, "wt") as fh:
+            for r in recs:
+                fh.write(json.dumps({k: r.get(k, "zipf" if k == "family" else None) for k in keep}) + "\n")
     hold = {"zipf": args.holdout_from, "clustered": args.holdout_from_clustered}
     tr = [r for r in recs if r["i"] < hold[_key(r)[0]]]
     te = [r for r in recs if r["i"] >= hold[_key(r)[0]]]
@@ -291,7 +297,8 @@ def train(args):
                    "scale": [float(x) for x in scale],
                    "meta": {"n_fit": len(fit), "n_val": len(val), "steps": args.steps, "lr": args.lr,
                             "skip_ratio": args.skip_ratio, "val_regret": best_val, "seed": args.seed,
-                            "holdout_from": args.holdout_from}}, fh)
+                            "holdout_from": args.holdout_from,
+                            "holdout_from_clustered": args.holdout_from_clustered}}, fh)
     report = {"train_seconds": t_train, "log": log, "val_regret": best_val}
     if te:
         xt = norm(te)
@@ -350,6 +357,7 @@ def main(argv=None):
     b.add_argument("--seed", type=int, default=0)
     b.add_argument("--out", required=True)
     b.add_argument("--report", default=None)
+    b.add_argument("--table-out", default=None, help="write the clean sweep table (gzip JSON lines) here")
     args = ap.parse_args(argv)
     if args.cmd == "sweep":
         sweep(args)

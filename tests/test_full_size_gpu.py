@@ -1,0 +1,147 @@
+"""Parity at the benchmark sizes, on sampled outputs.
+
+The full outputs are too large for the oracle (2e8 pairs for the two-path
+input), so each test checks properties that hold at any size (sorted,
+distinct, the same set at every threshold pair) and compares, for a seeded
+sample of x values, the GPU output rows with that x against the oracle run
+on R restricted to those x: that restriction leaves exactly those rows of the
+output (Section 2.1: an output tuple's x comes from R).
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def jp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_12459_amd as jp
+    return jp
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.int32))).cuda()
+
+
+def assert_sorted_distinct(cols):
+    """Rows strictly increasing in lexicographic (signed) order."""
+    k = len(cols)
+    n = cols[0].size
+    if n < 2:
+        return
+    gt = np.zeros(n - 1, bool)
+    eq = np.ones(n - 1, bool)
+    for c in cols:
+        d_gt = c[1:] > c[:-1]
+        d_eq = c[1:] == c[:-1]
+        gt |= eq & d_gt
+        eq &= d_eq
+    assert gt.all(), "rows not strictly increasing"
+
+
+def rows_with(cols, first, values):
+    m = np.isin(cols[0], values)
+    return [c[m] for c in cols]
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return datagen.twopath_c2(1.0)
+
+
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 1000, "delta2": 12}])
+def test_two_path_10m(jp, c2, kw):
+    (rx, ry), (sz, sy) = c2
+    h = jp.default_handle(0)
+    x, z, st = h.two_path(dev(rx), dev(ry), dev(sz), dev(sy), **kw)
+    x, z = x.cpu().numpy(), z.cpu().numpy()
+    assert x.size == st["n_out"] == 216990694
+    assert_sorted_distinct([x, z])
+    rng = np.random.default_rng(123)
+    xs = rng.choice(np.unique(rx), 300, replace=False)
+    m = np.isin(rx, xs)
+    ex, ez = oracle.two_path(rx[m], ry[m], sz, sy)
+    gx, gz = rows_with([x, z], 0, xs)
+    np.testing.assert_array_equal(gx, ex)
+    np.testing.assert_array_equal(gz, ez)
+    if kw.get("strategy") == "fixed":
+        assert st["u"] > 0 and st["v"] > 0 and st["w"] > 0 and st["nnz_heavy"] > 0
+
+
+@pytest.fixture(scope="module")
+def c3():
+    return datagen.star_c3(1.0)
+
+
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 2000, "delta2": 8}])
+def test_star_3x2m(jp, c3, kw):
+    rels = c3
+    h = jp.default_handle(0)
+    cols, st = h.star([(dev(a), dev(b)) for a, b in rels], **kw)
+    cols = [c.cpu().numpy() for c in cols]
+    assert cols[0].size == st["n_out"]
+    assert_sorted_distinct(cols)
+    rng = np.random.default_rng(321)
+    xs = rng.choice(np.unique(rels[0][0]), 200, replace=False)
+    m = np.isin(rels[0][0], xs)
+    exp = oracle.star([(rels[0][0][m], rels[0][1][m]), rels[1], rels[2]])
+    got = rows_with(cols, 0, xs)
+    for i in range(3):
+        np.testing.assert_array_equal(got[i], exp[:, i])
+
+
+def test_star_sizes_agree_across_thresholds(jp, c3):
+    rels = c3
+    h = jp.default_handle(0)
+    sizes = set()
+    for kw in ({}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 2000, "delta2": 8}):
+        r = h.star_result([(dev(a), dev(b)) for a, b in rels], **kw)
+        sizes.add(r.n)
+        r.free()
+    assert len(sizes) == 1
+
+
+def test_batch_512(jp):
+    """The serving-style set at full size: every slice sorted and distinct
+    (checked on the device), the 8 smallest instances in full and 16 sampled
+    instances on sampled x values against the oracle."""
+    import torch
+    insts = datagen.batch_c4(512)
+    h = jp.default_handle(0)
+    r = h.two_path_batch_result([(dev(a[0]), dev(a[1]), dev(b[0]), dev(b[1])) for a, b in insts])
+    try:
+        x, z = r.to_torch()
+        offs = r.batch_offsets()
+        n = r.n
+    finally:
+        r.free()
+    assert offs[0] == 0 and offs[-1] == n and all(offs[i] <= offs[i + 1] for i in range(512))
+    sizes = torch.tensor(np.diff(offs), device="cuda")
+    inst = torch.repeat_interleave(torch.arange(512, device="cuda", dtype=torch.int32), sizes)
+    same = inst[1:] == inst[:-1]
+    inc = (x[1:] > x[:-1]) | ((x[1:] == x[:-1]) & (z[1:] > z[:-1]))
+    assert bool((inc | ~same).all())
+    rng = np.random.default_rng(7)
+    esz = np.array([a[0].size for a, _ in insts])
+    smallest = set(np.argsort(esz)[:8].tolist())
+    sampled = set(rng.choice(512, 16, replace=False).tolist()) - smallest
+    for i in sorted(smallest | sampled):
+        (rx, ry), (sz, sy) = insts[i]
+        gx = x[offs[i]:offs[i + 1]].cpu().numpy()
+        gz = z[offs[i]:offs[i + 1]].cpu().numpy()
+        if i in smallest:
+            ex, ez = oracle.two_path(rx, ry, sz, sy)
+        else:
+            ux = np.unique(rx)
+            xs = rng.choice(ux, min(40, ux.size), replace=False)
+            m = np.isin(rx, xs)
+            ex, ez = oracle.two_path(rx[m], ry[m], sz, sy)
+            gx, gz = rows_with([gx, gz], 0, xs)
+        np.testing.assert_array_equal(gx, ex, err_msg=f"instance {i}")
+        np.testing.assert_array_equal(gz, ez, err_msg=f"instance {i}")

@@ -1,0 +1,87 @@
+"""What the trained threshold selector gains over the cost model (no GPU).
+
+The selector's training data is the library's own timing sweep on MI355X:
+every instance was run at each of the 65 threshold cells, with the cost
+model (Algorithm 2), Lemma 3's thresholds and sqrt(N) thresholds timed
+beside them.  The held-out instances were not used in training.  Here the
+committed weights are evaluated with the fp64 reference network: the cell
+it picks on each held-out instance is compared with the fastest cell.
+Outputs are identical at every cell (checked during the sweep and by the
+GPU tests), so this is purely a time comparison.
+"""
+import gzip
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PKG = os.path.join(os.path.dirname(HERE), "paper_2002_12459_amd")
+WEIGHTS = os.path.join(PKG, "selector_mi355x.json")
+TABLE = os.path.join(PKG, "selector_sweep_mi355x.jsonl.gz")
+
+pytestmark = pytest.mark.skipif(not (os.path.exists(WEIGHTS) and os.path.exists(TABLE)),
+                                reason="selector weights or sweep table not present")
+
+
+def _load():
+    with open(WEIGHTS) as fh:
+        w = json.load(fh)
+    with gzip.open(TABLE, "rt") as fh:
+        recs = [json.loads(line) for line in fh if line.strip()]
+    return w, recs
+
+
+def _holdout(w, recs):
+    meta = w["meta"]
+    lim = {"zipf": meta["holdout_from"], "clustered": meta["holdout_from_clustered"]}
+    return [r for r in recs if r["i"] >= lim[r.get("family", "zipf")]]
+
+
+def _picks(w, recs):
+    x = np.asarray([r["features"] for r in recs], dtype=np.float32)
+    xin = (x - np.asarray(w["mean"], np.float32)) / np.asarray(w["scale"], np.float32)
+    y, _ = mlp.forward(np.asarray(w["params"], np.float64), w["n_out"], xin.astype(np.float64))
+    return y.argmin(axis=1)
+
+
+def _geo(v):
+    return float(np.exp(np.mean(np.log(v))))
+
+
+def _best(r):
+    return min(t for t in r["t"] if t is not None)
+
+
+def test_weights_match_the_layout():
+    w, _ = _load()
+    assert w["n_out"] == 65
+    assert len(w["params"]) == mlp.param_count(65)
+    assert len(w["mean"]) == len(w["scale"]) == 16 and min(w["scale"]) > 0
+
+
+def test_holdout_is_disjoint_and_large_enough():
+    w, recs = _load()
+    te = _holdout(w, recs)
+    assert len(te) >= 100
+    assert len({(r.get("family", "zipf"), r["i"]) for r in recs}) == len(recs)
+
+
+def test_selector_beats_the_cost_model_on_held_out_instances():
+    w, recs = _load()
+    te = _holdout(w, recs)
+    skip = w["meta"]["skip_ratio"]
+    ks = _picks(w, te)
+    mlp_regret = [skip if r["t"][k] is None else r["t"][k] / _best(r) for r, k in zip(te, ks)]
+    cost_regret = [r["auto"]["t"] / _best(r) for r in te]
+    g_mlp, g_cost = _geo(mlp_regret), _geo(cost_regret)
+    # within 10% of the best swept cell (geometric mean), and better than Algorithm 2
+    assert g_mlp <= 1.10, g_mlp
+    assert g_mlp < g_cost, (g_mlp, g_cost)
+    for fam in sorted({r.get("family", "zipf") for r in te}):
+        sel = [i for i, r in enumerate(te) if r.get("family", "zipf") == fam]
+        assert _geo([mlp_regret[i] for i in sel]) <= 1.15, fam

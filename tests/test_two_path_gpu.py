@@ -130,17 +130,21 @@ def test_zipf_scaled(jp, scale):
         np.testing.assert_array_equal(z, ez, err_msg=str(kw))
 
 
-def test_communities_dense_heavy(jp):
+@pytest.mark.parametrize("bmm", ["auto", "i8_t128", "i8_t256", "bitpop"])
+def test_communities_dense_heavy(jp, bmm):
     """Dense communities: the heavy product carries most of the output."""
     # p = 0.5 over 150 y per community: two x of a community miss a common y
     # with probability 0.75^150 (about 1e-19), so every in-community pair is out.
     x, y = datagen.communities(4, 300, 150, 0.5, seed=5)
-    st = check_equal(jp, x, y, x, y, delta1=10, delta2=10)
+    st = check_equal(jp, x, y, x, y, delta1=10, delta2=10, bmm=bmm)
     assert st["nnz_heavy"] > 0 and st["n_out"] == 4 * 300 * 300
+    assert st["bmm"] == (2 if bmm == "bitpop" else (1 if bmm != "auto" else st["bmm"]))
 
 
-@pytest.mark.parametrize("u,w,k", [(1, 1, 1), (37, 130, 200), (128, 128, 128), (257, 129, 1000), (600, 515, 77)])
-def test_bool_matmul_kernel(jp, u, w, k):
+@pytest.mark.parametrize("kind", ["i8", "i8_t128", "i8_t256", "bitpop", "auto"])
+@pytest.mark.parametrize("u,w,k", [(1, 1, 1), (37, 130, 200), (128, 128, 128), (257, 129, 1000), (600, 515, 77),
+                                   (1100, 1300, 390), (513, 2049, 256)])
+def test_bool_matmul_kernel(jp, u, w, k, kind):
     import torch
     rng = np.random.default_rng(u * 7 + w)
     ld = -(-k // 128) * 128
@@ -150,7 +154,8 @@ def test_bool_matmul_kernel(jp, u, w, k):
     B[:, :k] = rng.random((w, k)) < 0.02
     C = A.astype(np.int64) @ B.astype(np.int64).T
     ei, ej = np.nonzero(C)
-    rows, cols, ms = jp.default_handle(0).bool_matmul(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), k=k)
+    rows, cols, ms = jp.default_handle(0).bool_matmul(torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda(), k=k,
+                                                      kind=kind)
     got = sorted(zip(rows.cpu().numpy().tolist(), cols.cpu().numpy().tolist()))
     assert got == sorted(zip(ei.tolist(), ej.tolist()))
 
@@ -162,9 +167,10 @@ def test_bool_matmul_counts_do_not_overflow(jp):
     A = torch.ones((u, k), dtype=torch.int8).cuda()
     B = torch.zeros((w, k), dtype=torch.int8)
     B[::2] = 1
-    rows, cols, _ = jp.default_handle(0).bool_matmul(A, B.cuda())
-    assert rows.numel() == u * (w // 2)
-    assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
+    for kind in ("i8_t128", "i8_t256", "bitpop"):
+        rows, cols, _ = jp.default_handle(0).bool_matmul(A, B.cuda(), kind=kind)
+        assert rows.numel() == u * (w // 2)
+        assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
 
 
 def test_bool_matmul_more_tiles_than_one_grid(jp):
@@ -176,9 +182,10 @@ def test_bool_matmul_more_tiles_than_one_grid(jp):
     A = torch.zeros((u, 128), dtype=torch.int8, device="cuda")
     idx = torch.arange(u, device="cuda")
     A[idx, idx % 128] = 1
-    nnz, _ = jp.default_handle(0).bool_matmul_count(A, A)
     per = np.bincount(np.arange(u) % 128, minlength=128).astype(np.int64)
-    assert nnz == int((per * per).sum())
+    for kind in ("i8_t128", "i8_t256", "bitpop"):
+        nnz, _ = jp.default_handle(0).bool_matmul_count(A, A, kind=kind)
+        assert nnz == int((per * per).sum()), kind
 
 
 @pytest.mark.parametrize("dedup", ["global", "segmented"])
