@@ -155,6 +155,20 @@ def main():
                 "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
                 "alg_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms}
 
+    # the learned selector on the same input (when weights are installed)
+    selector = None
+    if os.path.exists(jp.SELECTOR_PATH):
+        step(strategy="mlp")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            n_m, st_m = step(strategy="mlp")
+        torch.cuda.synchronize()
+        dm = (time.perf_counter() - t0) / a.steps
+        selector = {"strategy": "learned selector (AUTO_MLP)", "ms_per_step": dm * 1e3, "value": n_m / dm,
+                    "delta1": st_m["delta1"], "delta2": st_m["delta2"], "speedup_vs_cost_model": dt / dm}
+        log(f"selector: {dm * 1e3:.2f} ms/step (d1={st_m['delta1']} d2={st_m['delta2']})")
+
     # heavy product at forced thresholds (the cost model keeps this workload light)
     bmm = None
     if not a.no_bmm:
@@ -214,6 +228,7 @@ def main():
         "cpu_baseline": cpu,
         "heavy_bmm": bmm,
         "batched": batched,
+        "selector": selector,
         "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
     }
     print(json.dumps(out), flush=True)

@@ -370,29 +370,23 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
     if (a.clk && tid == 0) atomicAdd(&a.clk[kPhUnitsWin], 1ull);
 }
 
-// Copies every unit's pairs from the stage to its output offset.
+// Copies every unit's pairs from the stage to its output offset: one
+// workgroup per unit, coalesced 8-byte reads and 4-byte writes.
 struct CopyArgs {
-    const int64_t *uoff;  // output offset of every unit (n_units + 1)
-    const int64_t *ubase;
-    int64_t n_units, n_out;
+    const int64_t *uoff;   // output offset of every unit
+    const int64_t *ubase;  // stage offset of every unit
+    const int64_t *ucount;
     const int2 *stage;
     int32_t *out_x, *out_z;
 };
-constexpr int kCopyBlock = 256, kCopyItems = 16;
+constexpr int kCopyBlock = 256;
 __global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
-    const int64_t o0 = (int64_t)blockIdx.x * kCopyBlock * kCopyItems;
-    const int64_t olast = std::min<int64_t>(o0 + kCopyBlock * kCopyItems, a.n_out) - 1;
-    const int64_t lo = upper_bound_dev(a.uoff, (int64_t)0, a.n_units, o0) - 1;
-    const int64_t hi = upper_bound_dev(a.uoff, lo, a.n_units, olast);
-#pragma unroll 4
-    for (int j = 0; j < kCopyItems; ++j) {
-        const int64_t o = o0 + (int64_t)j * kCopyBlock + threadIdx.x;
-        if (o <= olast) {
-            const int64_t uu = upper_bound_dev(a.uoff, lo, hi, o) - 1;
-            const int2 v = a.stage[a.ubase[uu] + (o - a.uoff[uu])];
-            a.out_x[o] = v.x;
-            a.out_z[o] = v.y;
-        }
+    const int64_t u = blockIdx.x;
+    const int64_t n = a.ucount[u], src = a.ubase[u], dst = a.uoff[u];
+    for (int64_t i = threadIdx.x; i < n; i += kCopyBlock) {
+        const int2 v = a.stage[src + i];
+        a.out_x[dst + i] = v.x;
+        a.out_z[dst + i] = v.y;
     }
 }
 
@@ -544,13 +538,11 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         CopyArgs ca;
         ca.uoff = uoff.get();
         ca.ubase = ubase.get();
-        ca.n_units = n_units;
-        ca.n_out = total;
+        ca.ucount = ucount.get();
         ca.stage = stage.get();
         ca.out_x = out_x->get();
         ca.out_z = out_z->get();
-        const int64_t blocks = ceil_div(total, (int64_t)kCopyBlock * kCopyItems);
-        hipLaunchKernelGGL(k_stage_copy, dim3(grid_x(blocks, kCopyBlock)), dim3(kCopyBlock), 0, c.stream, ca);
+        hipLaunchKernelGGL(k_stage_copy, dim3(grid_x(n_units, kCopyBlock)), dim3(kCopyBlock), 0, c.stream, ca);
         JP_HIP(hipGetLastError());
     }
     *n_out = total;

@@ -262,7 +262,9 @@ def train(args):
     h = jp.Handle(0, selector=None)
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     xf, tf = norm(fit), dev(Y(fit))
-    wf = torch.ones_like(tf)
+    # errors near an instance's best cells decide its pick: weight each target
+    # by exp(-target) (1 at the best cell, 1/e at a cell e times slower)
+    wf = torch.exp(-tf) if args.weighted else torch.ones_like(tf)
     xv = norm(val)
     p = dev(_init_params(args.seed))
     m = torch.zeros_like(p)
@@ -291,12 +293,28 @@ def train(args):
                 best_val, best_p = vr, p.clone()
     t_train = time.perf_counter() - t0
 
+    # Margin toward light only: a grid cell is picked only when its predicted
+    # log ratio beats light only by more than m.  m is chosen on the
+    # validation instances and folded into the output biases, so the library's
+    # argmin applies it.
+    nb3 = N_CELLS
+    yv = h.mlp_forward(best_p, xv).cpu().numpy()
+    margins = [0.0, 0.01, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0, 2.0]
+    scores = []
+    for m in margins:
+        ks = (yv + np.where(np.arange(nb3) < 64, m, 0.0)).argmin(axis=1)
+        scores.append(float(np.exp(np.mean([math.log(regret(r, int(k), args.skip_ratio)) for r, k in zip(val, ks)]))))
+    m_best = margins[int(np.argmin(scores))]
+    print(f"[train] light-only margin {m_best} (validation geo-regret {min(scores):.4f})", flush=True)
+    best_p[-nb3:-1] += m_best
     params = best_p.cpu().numpy().astype(np.float64)
     with open(args.out, "w") as fh:
         json.dump({"n_out": N_CELLS, "params": [float(x) for x in params], "mean": [float(x) for x in mean],
                    "scale": [float(x) for x in scale],
                    "meta": {"n_fit": len(fit), "n_val": len(val), "steps": args.steps, "lr": args.lr,
                             "skip_ratio": args.skip_ratio, "val_regret": best_val, "seed": args.seed,
+                            "light_margin": m_best, "val_regret_with_margin": min(scores),
+                            "weighted": bool(args.weighted),
                             "holdout_from": args.holdout_from,
                             "holdout_from_clustered": args.holdout_from_clustered}}, fh)
     report = {"train_seconds": t_train, "log": log, "val_regret": best_val}
@@ -355,6 +373,7 @@ def main(argv=None):
     b.add_argument("--eval-every", type=int, default=100)
     b.add_argument("--skip-ratio", type=float, default=30.0)
     b.add_argument("--seed", type=int, default=0)
+    b.add_argument("--weighted", type=int, default=1, help="weight targets by exp(-target)")
     b.add_argument("--out", required=True)
     b.add_argument("--report", default=None)
     b.add_argument("--table-out", default=None, help="write the clean sweep table (gzip JSON lines) here")

@@ -188,6 +188,27 @@ def test_bool_matmul_more_tiles_than_one_grid(jp):
         assert nnz == int((per * per).sum()), kind
 
 
+def test_dedup_unit_class_boundaries(jp):
+    """x values whose candidate counts sit on both sides of the per-x class
+    limits of the duplicate removal (512: wave units; 4096: block units;
+    more: z windows), interleaved, with duplicates inside every x."""
+    rng = np.random.default_rng(11)
+    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 4095, 4096, 4097,
+              9000, 3, 700, 512, 512, 2]
+    rx, ry, sz, sy = [], [], [], []
+    nz = 20000
+    for i, cnt in enumerate(counts):
+        # x = i meets two lists: y = 2i (cnt distinct z) and y = 2i + 1 (half of them again)
+        zs = rng.choice(nz, cnt, replace=False)
+        half = zs[: max(1, cnt // 2)]
+        rx += [i, i]
+        ry += [2 * i, 2 * i + 1]
+        sz += zs.tolist() + half.tolist()
+        sy += [2 * i] * cnt + [2 * i + 1] * half.size
+    check_equal(jp, rx, ry, sz, sy, strategy="light")
+    check_equal(jp, rx, ry, sz, sy, strategy="fixed", delta1=600, delta2=1)
+
+
 @pytest.mark.parametrize("dedup", ["global", "segmented"])
 def test_dedup_strategies(jp, dedup):
     """Both duplicate-removal strategies (one device-wide sort; per-x on-chip
