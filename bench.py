@@ -31,6 +31,21 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 
+# HBM bytes moved by one k_dedup launch on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each
+# scaled by what the same counter reads for a 1 GiB device copy (FETCH_SIZE
+# reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
+# profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
+# whose SHA-256 is given (None: not measured for the current source).
+DEDUP_TRAFFIC = {"sha256": None, "bytes_per_launch": None}
+
+
+def dedup_traffic():
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2002_12459_amd", "csrc", "dedup.hip"), "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    return DEDUP_TRAFFIC["bytes_per_launch"] if digest == DEDUP_TRAFFIC["sha256"] else None
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -152,7 +167,7 @@ def main():
     achieved = dom_bytes / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else None
     roofline = {"kernel": "k_dedup (per-x witness gather + on-chip sort/bitmap dedup)", "bound": "hbm",
                 "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": None,
+                "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": dedup_traffic(),
                 "alg_bytes_per_launch": dom_bytes, "ms_per_launch": dom_ms}
 
     # the learned selector on the same input (when weights are installed)

@@ -124,7 +124,7 @@ typedef struct jp_stats {
     double ms_dedup;             /* duplicate removal, union, output */
     double ms_total;             /* whole call, device time */
     double ms_kernel_dedup;      /* per-x duplicate-removal kernel alone (segmented strategy) */
-    double dedup_alg_bytes;      /* its algorithmic HBM bytes: 4 per witness read + 8 per distinct pair written */
+    double dedup_alg_bytes;      /* its algorithmic HBM bytes: 4 per witness read + 4 per distinct pair key written */
     int64_t dedup_units;         /* on-chip units it processed */
 } jp_stats;
 

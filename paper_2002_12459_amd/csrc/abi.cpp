@@ -18,6 +18,7 @@ struct jp_handle {
     jp_calibration cal;
     jp::Selector sel;  // after alloc: its buffer returns to the allocator first
     std::map<uint64_t, int> tune;  // heavy-product kernel per shape class
+    std::unique_ptr<jp::PinnedScratch> pinned;  // small read-backs
 };
 
 namespace {
@@ -44,6 +45,7 @@ jp::Ctx make_ctx(jp_handle *h) {
     c.cal = &h->cal;
     c.sel = &h->sel;
     c.tune = &h->tune;
+    c.pinned = h->pinned.get();
     return c;
 }
 
@@ -117,6 +119,13 @@ jp_status jp_create(jp_handle **out, int device) {
     auto h = std::make_unique<jp_handle>();
     h->device = device;
     h->alloc = std::make_shared<jp::Allocator>(device);
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if (prev != device) (void)hipSetDevice(device);
+        h->pinned = std::make_unique<jp::PinnedScratch>(4096);
+        if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+    }
     jp::default_calibration(&h->cal);
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)

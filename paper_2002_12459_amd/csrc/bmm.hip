@@ -88,10 +88,15 @@ __device__ __forceinline__ void tile_of_block(int64_t bid, int64_t tiles_m, int6
     *tn = in / gm;
 }
 
+// With kchunk < ld the K range is split into chunks (split-K, for products
+// with few output tiles and long rows): workgroup item = (tile, chunk), and
+// the epilogue ORs "count > 0" into a u x w bitmap instead of emitting
+// (entries are sums of non-negative chunk counts, so the OR of the chunk
+// tests is the test of the sum).
 template <class ARows, class Emit>
 __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__restrict__ Bt, int64_t u, int64_t w,
                                                 int64_t ld, int64_t tiles_m, int64_t tiles_n, Emit emit, int64_t cap,
-                                                unsigned long long *count) {
+                                                unsigned long long *count, int64_t kchunk, uint32_t *bitmap) {
     __shared__ __attribute__((aligned(16))) int8_t sA[BM * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[BN * LDS_STRIDE];
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
@@ -102,10 +107,13 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
     const int fr = lane % 16, fk = (lane / 16) * 16;
     // Workgroups loop over tiles when the tile count exceeds the grid (the
     // grid is a multiple of 8, so a workgroup stays on its XCD's tile patch).
-    const int64_t total = tiles_m * tiles_n;
+    const int64_t nchunks = (ld + kchunk - 1) / kchunk;
+    const int64_t total = tiles_m * tiles_n * nchunks;
     for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
         int64_t tm, tn;
-        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        tile_of_block(bid / nchunks, tiles_m, tiles_n, &tm, &tn);
+        const int64_t kbeg = (bid % nchunks) * kchunk;
+        const int64_t kend = kbeg + kchunk < ld ? kbeg + kchunk : ld;
         const int64_t row0 = tm * BM, col0 = tn * BN;
         v4i ra[4], rb[4];
         auto load_stage = [&](int64_t k0) {
@@ -131,12 +139,12 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
 #pragma unroll
             for (int g = 0; g < 4; ++g) acc[f][g] = v4i{0, 0, 0, 0};
 
-        load_stage(0);
-        for (int64_t k0 = 0; k0 < ld; k0 += BK) {
+        load_stage(kbeg);
+        for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
             __syncthreads();
             store_stage();
             __syncthreads();
-            if (k0 + BK < ld) load_stage(k0 + BK);
+            if (k0 + BK < kend) load_stage(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 64) {
                 v4i a[4], b[4];
@@ -156,6 +164,22 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
 
         // Epilogue: C[row][col] with row = 4*(lane/16) + r inside the 16x16
         // block, col = lane % 16.  Count this lane's nonzeros, one atomic per wave.
+        if (bitmap) {
+#pragma unroll
+            for (int f = 0; f < 4; ++f)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
+                        const int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
+                        if (acc[f][g][r] > 0 && i < u && j < w) {
+                            const int64_t b = i * w + j;
+                            atomicOr(&bitmap[b >> 5], 1u << (b & 31));
+                        }
+                    }
+            continue;
+        }
         uint32_t mine = 0;
 #pragma unroll
         for (int f = 0; f < 4; ++f)
@@ -330,6 +354,36 @@ void launch_bmm_big(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, 
     JP_HIP(hipGetLastError());
 }
 
+// Nonzeros of a u x w bitmap, emitted with one atomic per wave.
+template <class Emit>
+__global__ __launch_bounds__(256) void k_emit_bitmap(const uint32_t *bitmap, int64_t u, int64_t w, Emit emit,
+                                                     int64_t cap, unsigned long long *count) {
+    const int lane = lane_id();
+    const int64_t nwords = (u * w + 31) / 32;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    const int64_t iters = (nwords + stride - 1) / stride;  // the same for every lane: ballots stay uniform
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t q = it * stride + (int64_t)blockIdx.x * 256 + threadIdx.x;
+        const uint32_t word = q < nwords ? bitmap[q] : 0u;
+        const uint32_t mine = (uint32_t)__popc(word);
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t wtot = __shfl(incl, kWave - 1);
+        if (wtot == 0) continue;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
+        base = __shfl(base, 0);
+        int64_t pos = (int64_t)base + (incl - mine);
+        uint32_t bits = word;
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            const int64_t e = q * 32 + b;
+            if (pos < cap) emit(pos, e / w, e % w);
+            ++pos;
+        }
+    }
+}
+
 template <class ARows, class Emit>
 void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind, Emit emit,
                 int64_t cap, unsigned long long *count_dev) {
@@ -338,11 +392,34 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
     if (u <= 0 || w <= 0 || ld <= 0) return;
     (void)kind;
     const int64_t tm = ceil_div(u, BM), tn = ceil_div(w, BN);
-    const int64_t total = tm * tn;
-    constexpr int64_t kMaxGrid = 1ll << 22;  // tiles beyond this are looped over (multiple of 8)
+    const int64_t tiles = tm * tn;
+    // Split K when the tiles alone would leave most of the chip idle and the
+    // rows are long: about two workgroups per compute unit, chunks of at least
+    // 1024 bytes.
+    int64_t kchunk = ld;
+    if (tiles < c.num_cus && ld >= 4 * 1024) {
+        const int64_t want = std::max<int64_t>(1, (2 * c.num_cus) / tiles);
+        kchunk = std::max<int64_t>(1024, ceil_div(ceil_div(ld, want), BK) * BK);
+    }
+    const int64_t nchunks = ceil_div(ld, kchunk);
+    const int64_t total = tiles * nchunks;
+    constexpr int64_t kMaxGrid = 1ll << 22;  // items beyond this are looped over (multiple of 8)
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
+    if (nchunks == 1) {
+        hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, Bt, u, w,
+                           ld, tm, tn, emit, cap, count_dev, kchunk, (uint32_t *)nullptr);
+        JP_HIP(hipGetLastError());
+        return;
+    }
+    const int64_t nwords = ceil_div(u * w, 32);
+    DBuf<uint32_t> bitmap = c.buf<uint32_t>((size_t)nwords);
+    c.zero(bitmap.get(), (size_t)nwords);
     hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, Bt, u, w, ld,
-                       tm, tn, emit, cap, count_dev);
+                       tm, tn, emit, cap, count_dev, kchunk, bitmap.get());
+    JP_HIP(hipGetLastError());
+    const int64_t eb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nwords, 256), (int64_t)c.num_cus * 4));
+    hipLaunchKernelGGL((k_emit_bitmap<Emit>), dim3(grid_x(eb, 256)), dim3(256), 0, c.stream,
+                       (const uint32_t *)bitmap.get(), u, w, emit, cap, count_dev);
     JP_HIP(hipGetLastError());
 }
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -177,6 +178,50 @@ __global__ __launch_bounds__(256) void k_zero_words(W *p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = W{};
 }
 
+// Copies n bytes of device memory to mapped pinned host memory (small
+// read-backs: one tiny kernel instead of a staged runtime copy).
+template <class B>
+__global__ __launch_bounds__(256) void k_to_host(const B *src, B *dst, int64_t n) {
+    for (int64_t i = threadIdx.x; i < n; i += 256) dst[i] = src[i];
+}
+
+// Gathers up to 8 device scalars into one contiguous block (one read-back).
+struct ScalarList {
+    const int64_t *p[8];
+    int n;
+};
+template <class T>
+__global__ __launch_bounds__(64) void k_gather_scalars(ScalarList l, T *dst) {
+    if ((int)threadIdx.x < l.n) dst[threadIdx.x] = *l.p[threadIdx.x];
+}
+
+// Pinned, device-mapped host buffer for small read-backs (one per handle).
+struct PinnedScratch {
+    uint8_t *host = nullptr, *dev = nullptr;
+    size_t bytes = 0;
+    explicit PinnedScratch(size_t n) {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, n, hipHostMallocMapped) != hipSuccess) {
+            (void)hipGetLastError();
+            return;
+        }
+        void *d = nullptr;
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(h);
+            return;
+        }
+        host = (uint8_t *)h;
+        dev = (uint8_t *)d;
+        bytes = n;
+    }
+    ~PinnedScratch() {
+        if (host) (void)hipHostFree(host);
+    }
+    PinnedScratch(const PinnedScratch &) = delete;
+    PinnedScratch &operator=(const PinnedScratch &) = delete;
+};
+
 // Execution context of one call: device, stream, allocator, chip size.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -194,17 +239,49 @@ struct Ctx {
         return DBuf<T>(alloc, n);
     }
     void sync() const { JP_HIP(hipStreamSynchronize(stream)); }
+    PinnedScratch *pinned = nullptr;  // small read-backs go through it when set
     template <class T>
     T load(const T *dev) const {  // small device-to-host read, waits on the stream
         T v;
-        JP_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, stream));
-        sync();
+        load_n(&v, dev, 1);
         return v;
+    }
+    // Several device int64 scalars with one wait: out[i] = *ptrs[i].
+    void load_scalars(std::initializer_list<const int64_t *> ptrs, int64_t *out) const {
+        ScalarList l;
+        l.n = 0;
+        for (const int64_t *q : ptrs) {
+            if (l.n == 8) fail(JP_EINTERNAL, "too many scalars in one read-back");
+            l.p[l.n++] = q;
+        }
+        if (!l.n) return;
+        int64_t *tmp = static_cast<int64_t *>(alloc->alloc(8 * sizeof(int64_t)));
+        hipLaunchKernelGGL(k_gather_scalars<int64_t>, dim3(1), dim3(64), 0, stream, l, tmp);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) {
+            try {
+                load_n(out, (const int64_t *)tmp, (size_t)l.n);
+            } catch (...) {
+                alloc->release(tmp);
+                throw;
+            }
+        }
+        alloc->release(tmp);
+        if (e != hipSuccess) fail(JP_EHIP, std::string("scalar gather failed: ") + hipGetErrorString(e));
     }
     template <class T>
     void load_n(T *host, const T *dev, size_t n) const {
         if (!n) return;
-        JP_HIP(hipMemcpyAsync(host, dev, n * sizeof(T), hipMemcpyDeviceToHost, stream));
+        const size_t bytes = n * sizeof(T);
+        if (pinned && pinned->host && bytes <= pinned->bytes && bytes <= 4096) {
+            hipLaunchKernelGGL(k_to_host<uint8_t>, dim3(1), dim3(256), 0, stream, (const uint8_t *)dev, pinned->dev,
+                               (int64_t)bytes);
+            JP_HIP(hipGetLastError());
+            sync();
+            std::memcpy(host, pinned->host, bytes);
+            return;
+        }
+        JP_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, stream));
         sync();
     }
     template <class T>

@@ -17,10 +17,11 @@
 //    window's part of every sorted list, marks it in an LDS bitmap and reads
 //    the set bits back in z order.
 //
-// One kernel handles all units.  A unit writes its distinct (x, z) pairs,
-// unranked, to a staging array at its candidate offset (an upper bound of its
-// output offset, so units never wait on each other); a scan of the per-unit
-// counts gives output offsets and a load-balanced copy packs the output.
+// One kernel handles all units.  A unit writes its distinct keys to a
+// staging array at its candidate offset (an upper bound of its output
+// offset, so units never wait on each other); a scan of the per-unit counts
+// gives output offsets, and a copy (one workgroup per unit) packs the output
+// and turns keys back into ids.
 #include "debug.hpp"
 #include "pipeline.hpp"
 #include "prims.hpp"
@@ -68,7 +69,7 @@ struct DedupArgs {
     uint32_t zmask;
     int64_t dom_x, dom_z;
     const int32_t *xorig, *zorig;
-    int2 *stage;             // distinct (x, z) of every unit, at ubase[u]
+    uint32_t *stage;         // distinct keys (x - unit's first x) << bz | z of every unit, at ubase[u]
     int64_t *ucount;         // distinct pairs of every unit
     int64_t *ubase;          // where the unit's pairs start in stage
     int64_t *err;
@@ -99,6 +100,7 @@ constexpr int kCntWords = kRD * kDT / 2;
 constexpr int kCntPadded = kCntWords + kCntWords / 16;
 constexpr int kMaxStagedEdges = 1024;  // R tuples of a packed unit staged in LDS for the gather
 static_assert(4 * (kMaxStagedEdges + 2) + 12 * kMaxStagedEdges <= 4 * kCntPadded, "staging fits the counters");
+
 
 __device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
     const int ci = d * kDT + t;
@@ -263,13 +265,7 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         __syncthreads();
         pc.mark(kPhUnique);
         const int64_t base = a.toff[xa];
-        for (uint32_t i = tid; i < d_all; i += kDT) {
-            const uint32_t key = sk[kpad((int)i)];
-            const int64_t xi = (int64_t)xa + (key >> a.bz), zi = key & a.zmask;
-            const bool ok = (xi < a.dom_x) & (zi < a.dom_z);
-            if (!ok) *a.err = 3;
-            a.stage[base + i] = make_int2(a.xorig[ok ? xi : 0], a.zorig[ok ? zi : 0]);
-        }
+        for (uint32_t i = tid; i < d_all; i += kDT) a.stage[base + i] = sk[kpad((int)i)];
         if (tid == 0) {
             a.ucount[u] = d_all;
             a.ubase[u] = base;
@@ -351,14 +347,12 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
     uint32_t d_all;
     uint32_t pos = block_excl_scan<kDT>(c, lds_scan, &d_all);
     const int64_t base = a.toff[x] + before;
-    const int32_t xo = a.xorig[x < a.dom_x ? x : 0];
     for (int i = w0; i < w1; ++i) {
         uint32_t word = sk[i];
         while (word) {
             const int bit = __ffs(word) - 1;
             word &= word - 1;
-            const int64_t zi = zlo + (int64_t)i * 32 + bit;
-            a.stage[base + pos] = make_int2(xo, a.zorig[zi < a.dom_z ? zi : 0]);
+            a.stage[base + pos] = (uint32_t)(zlo + (int64_t)i * 32 + bit);  // the unit's x: local 0
             ++pos;
         }
     }
@@ -370,24 +364,38 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
     if (a.clk && tid == 0) atomicAdd(&a.clk[kPhUnitsWin], 1ull);
 }
 
-// Copies every unit's pairs from the stage to its output offset: one
-// workgroup per unit, coalesced 8-byte reads and 4-byte writes.
+// Copies every unit's pairs from the stage to its output offset, turning
+// the unit-local keys back into ids: one workgroup per unit, coalesced reads
+// and writes, id lookups in the rank tables.
 struct CopyArgs {
     const int64_t *uoff;   // output offset of every unit
     const int64_t *ubase;  // stage offset of every unit
     const int64_t *ucount;
-    const int2 *stage;
+    const int32_t *ustart; // first x of every unit
+    const uint32_t *stage;
+    int bz;
+    uint32_t zmask;
+    int64_t dom_x, dom_z;
+    const int32_t *xorig, *zorig;
+    int64_t xbase, zbase;  // dense id ranges (INT64_MIN: use the tables)
     int32_t *out_x, *out_z;
+    int64_t *err;
 };
 constexpr int kCopyBlock = 256;
 __global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
     const int64_t u = blockIdx.x;
     const int64_t n = a.ucount[u], src = a.ubase[u], dst = a.uoff[u];
+    const int64_t xa = a.ustart[u];
+    bool bad = false;
     for (int64_t i = threadIdx.x; i < n; i += kCopyBlock) {
-        const int2 v = a.stage[src + i];
-        a.out_x[dst + i] = v.x;
-        a.out_z[dst + i] = v.y;
+        const uint32_t key = a.stage[src + i];
+        const int64_t xi = xa + (key >> a.bz), zi = key & a.zmask;
+        const bool ok = (xi < a.dom_x) & (zi < a.dom_z);
+        bad |= !ok;
+        a.out_x[dst + i] = a.xbase != INT64_MIN ? (int32_t)(a.xbase + xi) : a.xorig[ok ? xi : 0];
+        a.out_z[dst + i] = a.zbase != INT64_MIN ? (int32_t)(a.zbase + zi) : a.zorig[ok ? zi : 0];
     }
+    if (bad) *a.err = 3;
 }
 
 }  // namespace
@@ -451,10 +459,9 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             },
             ArrayPut{nu}, nu + dom_x);
     }
-    int64_t hn[1];
-    c.load_n(hn, nunits_x.get() + dom_x, 1);
-    const int64_t n_units = hn[0];
-    const int64_t n_cand = c.load(toff.get() + dom_x);
+    int64_t hn[2];
+    c.load_scalars({nunits_x.get() + dom_x, toff.get() + dom_x}, hn);
+    const int64_t n_units = hn[0], n_cand = hn[1];
     DBuf<int32_t> ustart = c.buf<int32_t>(n_units + 1), uwin = c.buf<int32_t>(n_units + 1);
     {
         const int64_t *to = toff.get(), *nu = nunits_x.get();
@@ -476,7 +483,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
     dump(c, "ustart", ustart.get(), n_units + 1);
     dump(c, "uwin", uwin.get(), n_units + 1);
 
-    DBuf<int2> stage = c.buf<int2>(std::max<int64_t>(n_cand, 1));
+    DBuf<uint32_t> stage = c.buf<uint32_t>(std::max<int64_t>(n_cand, 1));
     DBuf<int64_t> ucount = c.buf<int64_t>(n_units + 1), ubase = c.buf<int64_t>(n_units + 1);
     if (n_units > 0) {
         JP_CHECK(n_units < (1ll << 31), JP_EINVAL, "too many dedup units for one launch");
@@ -528,10 +535,10 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
     DBuf<int64_t> uoff = c.buf<int64_t>(n_units + 1);
     scan_exclusive(c, n_units, ArrayGet{ucount.get()}, ArrayPut{uoff.get()}, uoff.get() + n_units);
     int64_t h2[2];
-    c.load_n(h2, S, 2);
-    JP_CHECK(h2[1] != 1, JP_EINTERNAL, "a dedup unit exceeded its on-chip capacity");
-    JP_CHECK(h2[1] == 0, JP_EINTERNAL, "dedup produced a key outside the rank tables");
-    const int64_t total = n_units > 0 ? c.load(uoff.get() + n_units) : 0;
+    c.load_scalars({S + 1, uoff.get() + n_units}, h2);
+    JP_CHECK(h2[0] != 1, JP_EINTERNAL, "a dedup unit exceeded its on-chip capacity");
+    JP_CHECK(h2[0] == 0, JP_EINTERNAL, "dedup produced a key outside the rank tables");
+    const int64_t total = n_units > 0 ? h2[1] : 0;
     *out_x = c.buf<int32_t>(std::max<int64_t>(total, 1));
     *out_z = c.buf<int32_t>(std::max<int64_t>(total, 1));
     if (total > 0) {
@@ -539,11 +546,23 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         ca.uoff = uoff.get();
         ca.ubase = ubase.get();
         ca.ucount = ucount.get();
+        ca.ustart = ustart.get();
         ca.stage = stage.get();
+        ca.bz = in.bz;
+        ca.zmask = (uint32_t)((1ull << in.bz) - 1);
+        ca.dom_x = dom_x;
+        ca.dom_z = dom_z;
+        ca.xorig = in.xorig;
+        ca.zorig = in.zorig;
+        ca.xbase = in.x_dense_base;
+        ca.zbase = in.z_dense_base;
         ca.out_x = out_x->get();
         ca.out_z = out_z->get();
+        ca.err = S + 4;
         hipLaunchKernelGGL(k_stage_copy, dim3(grid_x(n_units, kCopyBlock)), dim3(kCopyBlock), 0, c.stream, ca);
         JP_HIP(hipGetLastError());
+        // reads are clamped, so a bad key cannot fault; checked mode reports it
+        if (checks_on()) JP_CHECK(c.load(S + 4) == 0, JP_EINTERNAL, "dedup produced a key outside the rank tables");
     }
     *n_out = total;
     if (stats) {

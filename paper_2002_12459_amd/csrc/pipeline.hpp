@@ -1,6 +1,8 @@
 // Internal interfaces between the host planner, the pipelines and the C ABI.
 #pragma once
 
+#include <climits>
+
 #include "common.hpp"
 
 struct jp_result {
@@ -114,6 +116,8 @@ void plan_cells(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, 
 // (off_y, adj_s = z rank, s2_y = y rank per tuple), degrees, rank tables, J.
 struct Ingest {
     int64_t n_r2 = 0, n_s2 = 0, dom_x = 0, dom_y = 0, dom_z = 0, J = 0;
+    int64_t x_dense_base = INT64_MIN, z_dense_base = INT64_MIN;  // see SegDedupIn
+    int64_t zmin = 0, zspan = 0;                                  // range of the z ids kept
     DBuf<int32_t> r_xr, adj_r, adj_s, s2_y, dRy, dSz, xorig, zorig;
     DBuf<int64_t> off_x, off_y;
 };

@@ -1,6 +1,8 @@
 // Per-x duplicate removal of light witnesses + heavy nonzeros (dedup.hip).
 #pragma once
 
+#include <climits>
+
 #include "common.hpp"
 
 namespace jp {
@@ -16,6 +18,9 @@ struct SegDedupIn {
     const uint64_t *hkeys = nullptr; // sorted heavy nonzeros (x << bz | z)
     int64_t nnz = 0;
     const int32_t *xorig = nullptr, *zorig = nullptr;
+    // When every id in [min, max] occurs, rank r is id min + r: the bases
+    // replace the table lookups (INT64_MIN: use the tables).
+    int64_t x_dense_base = INT64_MIN, z_dense_base = INT64_MIN;
 };
 
 struct SegDedupStats {

@@ -203,11 +203,12 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             },
             S + 2);
     }
-    const int64_t ny_r = c.load(S + 2);
     {
+        // end of the last run, written where the device count says
         int64_t *rs = rstart.get();
-        const int64_t nyr = ny_r, nr1 = n_r1;
-        for_each(c, 1, [=] __device__(int64_t) { rs[nyr] = nr1; });
+        const int64_t *cnt = S + 2;
+        const int64_t nr1 = n_r1;
+        for_each(c, 1, [=] __device__(int64_t) { rs[*cnt] = nr1; });
     }
     // ---- distinct y of S (from the y-major S) --------------------------------
     DBuf<uint32_t> YS = c.buf<uint32_t>(n_s1);
@@ -219,7 +220,9 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             c, n_s1, [=] __device__(int64_t i) { return i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs); },
             [=] __device__(int64_t i, int64_t p) { d[p] = (uint32_t)(s[i] >> zbs); }, S + 3);
     }
-    const int64_t ny_s = c.load(S + 3);
+    int64_t hy2[2];
+    c.load_n(hy2, S + 2, 2);
+    const int64_t ny_r = hy2[0], ny_s = hy2[1];
 
     // ---- semijoin: keep y present in both; dense y ranks; R degree of y -------
     DBuf<int32_t> yrank_js = c.buf<int32_t>(ny_s);
@@ -355,9 +358,26 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             },
             S + 8);
     }
-    int64_t h9[2];
-    c.load_n(h9, S + 7, 2);
-    const int64_t dom_z = h9[0], dom_x = h9[1];
+    // ---- y-major CSR offsets of S and the full join size J (no host values needed)
+    DBuf<int64_t> off_y = c.buf<int64_t>(dom_y + 1);
+    {
+        const int32_t *syr = s2_y.get();
+        int64_t *oy = off_y.get();
+        const int64_t ny = dom_y, ns2 = n_s2;
+        compact(
+            c, n_s2, [=] __device__(int64_t e) { return e == 0 || syr[e] != syr[e - 1]; },
+            [=] __device__(int64_t e, int64_t p) { oy[p] = e; }, S + 9);
+        for_each(c, 1, [=] __device__(int64_t) { oy[ny] = ns2; });
+        const int32_t *d1 = dRy.get();
+        const int64_t *oyc = oy;
+        reduce_sum(
+            c, dom_y, [=] __device__(int64_t y) -> int64_t { return (int64_t)d1[y] * (oyc[y + 1] - oyc[y]); },
+            (unsigned long long *)(S + 10));
+    }
+    int64_t h9[4];
+    c.load_n(h9, S + 7, 4);
+    const int64_t dom_z = h9[0], dom_x = h9[1], J = h9[3];
+    JP_CHECK(h9[2] == dom_y, JP_EINTERNAL, "y offsets disagree with the number of y");
     DBuf<int32_t> r_xr = c.buf<int32_t>(n_r2);
     {
         const uint32_t *xs = r2_x.get();
@@ -372,7 +392,6 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     // ---- S y-major CSR with z ranks --------------------------------------------
     DBuf<int32_t> zorig = c.buf<int32_t>(dom_z);
     DBuf<int32_t> adj_s = c.buf<int32_t>(n_s2);
-    DBuf<int64_t> off_y = c.buf<int64_t>(dom_y + 1);
     {
         const uint32_t *zs = ZS.get();
         int32_t *zo = zorig.get();
@@ -392,13 +411,6 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             for_each(c, n_s2,
                      [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zs, (int64_t)0, nz, sz2[e]); });
         }
-        const int32_t *syr = s2_y.get();
-        int64_t *oy = off_y.get();
-        const int64_t ny = dom_y, ns2 = n_s2;
-        compact(
-            c, n_s2, [=] __device__(int64_t e) { return e == 0 || syr[e] != syr[e - 1]; },
-            [=] __device__(int64_t e, int64_t p) { oy[p] = e; }, S + 9);
-        for_each(c, 1, [=] __device__(int64_t) { oy[ny] = ns2; });
     }
     ZS.reset();
     s2_z.reset();
@@ -409,14 +421,8 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const int64_t *zs0 = zstart.get();
         const int64_t nz = dom_z, ns2 = n_s2;
         for_each(c, dom_z, [=] __device__(int64_t r) { d2[r] = (int32_t)((r + 1 < nz ? zs0[r + 1] : ns2) - zs0[r]); });
-        const int32_t *d1 = dRy.get();
-        const int64_t *oy = off_y.get();
-        reduce_sum(
-            c, dom_y, [=] __device__(int64_t y) -> int64_t { return (int64_t)d1[y] * (oy[y + 1] - oy[y]); },
-            (unsigned long long *)(S + 10));
     }
     zstart.reset();
-    const int64_t J = c.load(S + 10);
     g.n_r2 = n_r2;
     g.n_s2 = n_s2;
     g.dom_x = dom_x;
@@ -431,6 +437,10 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     g.dSz = std::move(dSz);
     g.xorig = std::move(xorig);
     g.zorig = std::move(zorig);
+    if (dom_x == xmax - xmin + 1) g.x_dense_base = xmin;
+    if (dom_z == zmax - zmin + 1) g.z_dense_base = zmin;
+    g.zmin = zmin;
+    g.zspan = zmax - zmin + 1;
     g.off_x = std::move(off_x);
     g.off_y = std::move(off_y);
     return true;
@@ -601,13 +611,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
                 if (h >= 0 && (e == 0 || syr[e - 1] != y)) lo[h] = p;
             },
             lo + v);
-        const int64_t n_lz = c.load(lo + v);
-        check_monotone(c, "lz_off", lz_off.get(), v + 1, 0, n_lz);
-        check_range(c, "lz lists", la, n_lz, 0, dom_z);
-        dump(c, "lz_off", lz_off.get(), v + 1);
-        dump(c, "lz lists", la, n_lz);
-        zlist = zl;
-        zlist_n = n_s2 + n_lz;
+        zlist = zl;  // its length n_s2 + lz_off[v] is read back with J_L below
     }
 
     // Per R tuple: list start and witness count (all loads unconditional,
@@ -667,7 +671,21 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         });
     }
     // Light and heavy witnesses partition the full join: J_H = J - J_L.
-    const int64_t J_L = c.load(S + 15);
+    int64_t J_L = 0;
+    if (has_heavy) {
+        int64_t hv[2];
+        c.load_scalars({S + 15, lz_off.get() + v}, hv);
+        J_L = hv[0];
+        const int64_t n_lz = hv[1];
+        const int32_t *la = zlist_own.get() + n_s2;
+        check_monotone(c, "lz_off", lz_off.get(), v + 1, 0, n_lz);
+        check_range(c, "lz lists", la, n_lz, 0, dom_z);
+        dump(c, "lz_off", lz_off.get(), v + 1);
+        dump(c, "lz lists", la, n_lz);
+        zlist_n = n_s2 + n_lz;
+    } else {
+        J_L = c.load(S + 15);
+    }
     JP_CHECK(J_L >= 0 && J_L <= J, JP_EINTERNAL, "light witness count exceeds the join size");
     const int64_t J_H = J - J_L;
     JP_CHECK(has_heavy || J_H == 0, JP_EINTERNAL, "heavy witnesses without a heavy part");
@@ -675,9 +693,15 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     st.J_H = J_H;
     const int ev_plan = tl.mark();
 
-    const int bz = bits_for((uint64_t)(dom_z - 1)), bx = bits_for((uint64_t)(dom_x - 1));
+    const int bx = bits_for((uint64_t)(dom_x - 1));
     const double uw = (double)u * (double)w;
     const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, uw) : 0;
+    // The per-x dedup may key z by its offset from the smallest z id instead
+    // of its rank when the id range is at most a few times the number of
+    // distinct z: the output then needs no rank-to-id lookup per pair.
+    const int bzr = bits_for((uint64_t)(dom_z - 1)), bzo = bits_for((uint64_t)(g.zspan - 1));
+    const bool z_off = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
+    const int bz = z_off ? bzo : bzr;
     const bool segmented = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bz);
     int64_t nnz = 0;
     int ev_light = ev_plan, ev_bmm0 = ev_plan, ev_bmm1 = ev_plan, ev_heavy = ev_plan;
@@ -685,6 +709,24 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     if (segmented) {
         // ---- heavy nonzeros, sorted; then per-x dedup fused with enumeration ----------
         st.dedup = JP_DEDUP_SEGMENTED;
+        // z offsets (see above): the witness lists and the heavy columns in offsets
+        DBuf<int32_t> zl_off, zo_of_hz;
+        const int32_t *zl_used = zlist, *zcol = z_of_hz.get();
+        if (z_off) {
+            const int32_t *zo = zorig.get(), *zl = zlist;
+            const int64_t zm = g.zmin;
+            zl_off = c.buf<int32_t>((size_t)std::max<int64_t>(zlist_n, 1));
+            int32_t *zlo = zl_off.get();
+            for_each(c, zlist_n, [=] __device__(int64_t i) { zlo[i] = (int32_t)((int64_t)zo[zl[i]] - zm); });
+            zl_used = zlo;
+            if (has_heavy) {
+                zo_of_hz = c.buf<int32_t>((size_t)w);
+                int32_t *zh = zo_of_hz.get();
+                const int32_t *zoh = z_of_hz.get();
+                for_each(c, w, [=] __device__(int64_t j) { zh[j] = (int32_t)((int64_t)zo[zoh[j]] - zm); });
+                zcol = zh;
+            }
+        }
         DBuf<uint64_t> hk, hk_tmp;
         const uint64_t *hks = nullptr;
         if (has_heavy) {
@@ -693,7 +735,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             int used = JP_BMM_I8_MFMA;
             Ctx cb = c;
             cb.bmm_used = &used;
-            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz, hk.get(),
+            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), zcol, bz, hk.get(),
                              cap_h, (unsigned long long *)(S + 17));
             ev_bmm1 = tl.mark();
             nnz = c.load(S + 17);
@@ -710,22 +752,24 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         ev_light = ev_heavy;
         SegDedupIn in;
         in.dom_x = dom_x;
-        in.dom_z = dom_z;
+        in.dom_z = z_off ? g.zspan : dom_z;
         in.bz = bz;
         in.off_x = off_x.get();
         in.eoff = eoff.get();
         in.lbase = lbase.get();
         in.r_xr = r_xr.get();
-        in.zlist = zlist;
+        in.zlist = zl_used;
         in.hkeys = hks;
         in.nnz = nnz;
         in.xorig = xorig.get();
         in.zorig = zorig.get();
+        in.x_dense_base = g.x_dense_base;
+        in.z_dense_base = z_off ? g.zmin : g.z_dense_base;
         SegDedupStats sst;
         segmented_dedup(c, in, &res->cols[0], &res->cols[1], &res->n, &sst, timing);
         st.n_out = res->n;
         st.ms_kernel_dedup = sst.ms_kernel;
-        st.dedup_alg_bytes = 4.0 * (double)(J_L + nnz) + 8.0 * (double)res->n;
+        st.dedup_alg_bytes = 4.0 * (double)(J_L + nnz) + 4.0 * (double)res->n;
         st.dedup_units = sst.n_units;
     } else {
         // ---- candidates: light witnesses + heavy nonzeros, one device-wide sort ------

@@ -143,7 +143,8 @@ def test_communities_dense_heavy(jp, bmm):
 
 @pytest.mark.parametrize("kind", ["i8", "i8_t128", "i8_t256", "bitpop", "auto"])
 @pytest.mark.parametrize("u,w,k", [(1, 1, 1), (37, 130, 200), (128, 128, 128), (257, 129, 1000), (600, 515, 77),
-                                   (1100, 1300, 390), (513, 2049, 256)])
+                                   (1100, 1300, 390), (513, 2049, 256), (1, 1, 5000), (100, 90, 20000),
+                                   (129, 300, 9000)])
 def test_bool_matmul_kernel(jp, u, w, k, kind):
     import torch
     rng = np.random.default_rng(u * 7 + w)
@@ -186,6 +187,18 @@ def test_bool_matmul_more_tiles_than_one_grid(jp):
     for kind in ("i8_t128", "i8_t256", "bitpop"):
         nnz, _ = jp.default_handle(0).bool_matmul_count(A, A, kind=kind)
         assert nnz == int((per * per).sum()), kind
+
+
+@pytest.mark.parametrize("spacing", [1, 3, 5])
+def test_spaced_z_ids(jp, spacing):
+    """z ids spread over a range up to 5x their count (the per-x dedup keys z
+    by id offset up to 4x, by rank beyond), with and without a heavy part."""
+    x, y = datagen.communities(3, 120, 80, 0.3, seed=9)
+    (zx, zy) = datagen.communities(3, 110, 80, 0.3, seed=10)
+    sz = (zx.astype(np.int64) * spacing - 1000).astype(np.int32)
+    check_equal(jp, x, y, sz, zy, strategy="light")
+    st = check_equal(jp, x, y, sz, zy, strategy="fixed", delta1=10, delta2=10)
+    assert st["nnz_heavy"] > 0
 
 
 def test_dedup_unit_class_boundaries(jp):
