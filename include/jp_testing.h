@@ -18,6 +18,8 @@ extern "C" {
 /* Stable LSD radix sort of n keys on their low `bits` bits, in place. */
 jp_status jp_test_radix_sort_u64(jp_handle *h, uint64_t *keys, int64_t n, int32_t bits);
 jp_status jp_test_radix_sort_u32(jp_handle *h, uint32_t *keys, int64_t n, int32_t bits);
+/* 128-bit keys as (low, high) 64-bit word pairs, 16-byte aligned; bits <= 128. */
+jp_status jp_test_radix_sort_u128(jp_handle *h, uint64_t *keys, int64_t n, int32_t bits);
 
 /* out[i] = in[0] + ... + in[i-1]; *total (host) = sum of all n values. */
 jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, int64_t n, int64_t *total);

@@ -24,7 +24,8 @@ __global__ __launch_bounds__(256) void k_for_each(int64_t n, F f) {
 template <class F>
 void for_each(const Ctx &c, int64_t n, F f) {
     if (n <= 0) return;
-    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 32);
+    // one element per thread (loads of different elements overlap), grid-stride beyond 2^26 threads
+    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 1ll << 18);
     hipLaunchKernelGGL(k_for_each<F>, dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, f);
     JP_HIP(hipGetLastError());
 }
@@ -100,22 +101,37 @@ __device__ __forceinline__ int64_t lb_resolve(uint64_t *status, int64_t t, int64
     return *sh;
 }
 
+// A scan element: the summand and a value passed through to put().
+template <class V>
+struct Sum {
+    int64_t add;
+    V v;
+};
+__device__ __forceinline__ int64_t sum_add(int64_t a) { return a; }
+template <class V>
+__device__ __forceinline__ int64_t sum_add(const Sum<V> &a) { return a.add; }
+
 template <class G, class P>
 __global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put, uint64_t *status, unsigned *ticket,
                                                         int64_t *total) {
+    using R = decltype(get((int64_t)0));
     __shared__ int64_t lds[kTileBlock / kWave + 1];
     __shared__ int64_t sh_tile, sh_excl;
     const int64_t t = lb_tile(ticket, &sh_tile);
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
     int64_t v[kTileItems];
+    R r[kTileItems];
     int64_t wtot = 0;
+    // get() on a clamped index for every item, so all loads are in flight at once
 #pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
-        int64_t i = wbase + (int64_t)j * kWave + lane;
-        v[j] = i < n ? get(i) : 0;
-        wtot += v[j];
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        r[j] = get(i < n ? i : n - 1);
+        v[j] = i < n ? sum_add(r[j]) : 0;
     }
+#pragma unroll
+    for (int j = 0; j < kTileItems; ++j) wtot += v[j];
     wtot = wave_sum(wtot);
     int64_t A;
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wtot : (int64_t)0, lds, &A);
@@ -125,7 +141,7 @@ __global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put,
     for (int j = 0; j < kTileItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         int64_t inc = wave_incl_scan(v[j]);
-        if (i < n) put(i, carry + inc - v[j]);
+        if (i < n) put(i, carry + inc - v[j], r[j]);
         carry += __shfl(inc, kWave - 1);
     }
 }
@@ -137,6 +153,14 @@ struct ArrayGet {
 struct ArrayPut {
     int64_t *a;
     __device__ void operator()(int64_t i, int64_t v) const { a[i] = v; }
+};
+
+// Adapts put(i, prefix) to the kernel's put(i, prefix, value).
+template <class P>
+struct PutNoValue {
+    P put;
+    template <class R>
+    __device__ void operator()(int64_t i, int64_t pre, const R &) const { put(i, pre); }
 };
 
 // Cleared tile status words and ticket for a look-back pass over nt tiles
@@ -155,9 +179,11 @@ struct LookbackState {
     }
 };
 
-// Exclusive scan; if total_dev is given, the overall sum is stored there.
+// Exclusive scan where put(i, prefix, value) also receives get(i) (an
+// int64 summand, or a Sum<V> whose add is summed), so it needs no loads of
+// its own; if total_dev is given, the overall sum is stored there.
 template <class G, class P>
-void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = nullptr) {
+void scan_exclusive_v(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = nullptr) {
     if (n <= 0) {
         if (total_dev) c.zero(total_dev, 1);
         return;
@@ -167,6 +193,12 @@ void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = 
     hipLaunchKernelGGL((k_scan_lb<G, P>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, get, put, lb.status,
                        lb.ticket, total_dev);
     JP_HIP(hipGetLastError());
+}
+
+// Exclusive scan, put(i, prefix).
+template <class G, class P>
+void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = nullptr) {
+    scan_exclusive_v(c, n, get, PutNoValue<P>{put}, total_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,13 +223,22 @@ void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
 }
 
 // ---------------------------------------------------------------------------
-// Stable compaction: for i in [0,n) with pred(i), emit(i, pos) with pos the
-// rank of i among selected elements.  One pass: ballot + mbcnt inside each
-// wave, block prefix of wave counts, tile prefix by decoupled look-back.
+// Stable compaction: sel(i) returns {keep, value} for i in [0,n); every kept
+// i gets emit(i, pos, value) with pos its rank among the kept elements.  One
+// pass: ballot + mbcnt inside each wave, block prefix of wave counts, tile
+// prefix by decoupled look-back.  sel() runs for all items of a thread before
+// any emit, so its loads overlap; emit() should only store.
 // ---------------------------------------------------------------------------
-template <class Pr, class Em>
-__global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Pr pred, Em emit, uint64_t *status,
+template <class V>
+struct Pick {
+    bool keep;
+    V v;
+};
+
+template <class Sel, class Em>
+__global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Sel sel, Em emit, uint64_t *status,
                                                            unsigned *ticket, int64_t *count) {
+    using V = decltype(sel((int64_t)0).v);
     __shared__ int64_t lds[kTileBlock / kWave + 1];
     __shared__ int64_t sh_tile, sh_excl;
     const int64_t t = lb_tile(ticket, &sh_tile);
@@ -205,9 +246,20 @@ __global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Pr pred, E
     const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
     uint32_t flags = 0;
     int64_t wcnt = 0;
+    // sel() on a clamped index for every item, so all loads are in flight at once
+    bool fs[kTileItems];
+    V vals[kTileItems];
+#pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
-        int64_t i = wbase + (int64_t)j * kWave + lane;
-        bool f = i < n && pred(i);
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        const Pick<V> pk = sel(i < n ? i : n - 1);
+        fs[j] = pk.keep;
+        vals[j] = pk.v;
+    }
+#pragma unroll
+    for (int j = 0; j < kTileItems; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        const bool f = (i < n) & fs[j];
         flags |= (uint32_t)f << j;
         wcnt += __popcll(ballot(f));
     }
@@ -215,27 +267,46 @@ __global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Pr pred, E
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wcnt : (int64_t)0, lds, &A);
     wpre = __shfl(wpre, 0);
     int64_t pos = lb_resolve(status, t, A, &sh_excl, count, gridDim.x) + wpre;
+#pragma unroll
     for (int j = 0; j < kTileItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         bool f = (flags >> j) & 1u;
         uint64_t m = ballot(f);
-        if (f) emit(i, pos + mbcnt(m));
+        if (f) emit(i, pos + mbcnt(m), vals[j]);
         pos += __popcll(m);
     }
 }
 
-// Returns the number of selected elements in *count_dev (device scalar).
-template <class Pr, class Em>
-void compact(const Ctx &c, int64_t n, Pr pred, Em emit, int64_t *count_dev) {
+// Compaction with values (see k_compact_lb); the number of kept elements
+// goes to *count_dev (device scalar).
+template <class Sel, class Em>
+void compact_v(const Ctx &c, int64_t n, Sel sel, Em emit, int64_t *count_dev) {
     if (n <= 0) {
         c.zero(count_dev, 1);
         return;
     }
     const int64_t nt = ceil_div(n, kTile);
     LookbackState lb(c, nt);
-    hipLaunchKernelGGL((k_compact_lb<Pr, Em>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, pred, emit,
+    hipLaunchKernelGGL((k_compact_lb<Sel, Em>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, sel, emit,
                        lb.status, lb.ticket, count_dev);
     JP_HIP(hipGetLastError());
+}
+
+template <class Pr>
+struct PredPick {
+    Pr pred;
+    __device__ Pick<char> operator()(int64_t i) const { return Pick<char>{(bool)pred(i), 0}; }
+};
+template <class Em>
+struct EmitNoValue {
+    Em emit;
+    __device__ void operator()(int64_t i, int64_t p, char) const { emit(i, p); }
+};
+
+// Compaction with a predicate: emit(i, pos) for every i with pred(i).
+template <class Pr, class Em>
+void compact(const Ctx &c, int64_t n, Pr pred, Em emit, int64_t *count_dev) {
+    compact_v(c, n, PredPick<Pr>{pred}, EmitNoValue<Em>{emit}, count_dev);
 }
 
 // ---------------------------------------------------------------------------
@@ -266,7 +337,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, 
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        k[j] = i < n ? keys[i] : K(0);
+        k[j] = keys[i < n ? i : n - 1];
     }
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -308,10 +379,14 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const K *in, K *out, in
     uint32_t rank[kRsItems];
     const int64_t wbase = tbase + (int64_t)w * kWave * kRsItems;
 #pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {  // all loads in flight before the first ballot
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        k[j] = in[i < n ? i : n - 1];
+    }
+#pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         bool valid = i < n;
-        k[j] = valid ? in[i] : K(0);
         uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
         uint64_t act = ballot(valid);
         uint64_t peers = match_digit<8>(d, act);

@@ -69,6 +69,11 @@ jp_status jp_test_radix_sort_u32(jp_handle *h, uint32_t *keys, int64_t n, int32_
     SortArgs<uint32_t> a{h, keys, n, bits};
     return jp_handle_guard(h, do_sort<uint32_t>, &a);
 }
+jp_status jp_test_radix_sort_u128(jp_handle *h, uint64_t *keys, int64_t n, int32_t bits) {
+    if (!h || n < 0 || (n && !keys) || bits < 0 || bits > 128 || ((uintptr_t)keys & 15)) return JP_EINVAL;
+    SortArgs<unsigned __int128> a{h, (unsigned __int128 *)keys, n, bits};
+    return jp_handle_guard(h, do_sort<unsigned __int128>, &a);
+}
 jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, int64_t n, int64_t *total) {
     if (!h || n < 0 || (n && (!in || !out)) || !total) return JP_EINVAL;
     ScanArgs a{h, in, out, n, 0};

@@ -29,7 +29,8 @@ namespace jp {
 namespace {
 
 // min / max of four int32 columns (R x, R y, S z, S y) into out[8]; grid.y
-// selects the column, 16 values per thread per step with 16-byte loads.
+// selects the column, kMinMaxVec 16-byte loads per thread per step.
+constexpr int kMinMaxVec = 4;
 __global__ __launch_bounds__(256) void k_minmax4(const int32_t *c0, const int32_t *c1, int64_t n01, const int32_t *c2,
                                                  const int32_t *c3, int64_t n23, int *out) {
     __shared__ int smn[256 / kWave], smx[256 / kWave];
@@ -41,11 +42,19 @@ __global__ __launch_bounds__(256) void k_minmax4(const int32_t *c0, const int32_
     const int64_t head = std::min<int64_t>(n, (int64_t)((16 - ((uintptr_t)a & 15)) & 15) / 4);
     const int64_t nv = (n - head) / 4;
     const int4 *v = (const int4 *)(a + head);
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += stride) {
-        const int4 q = v[i];
-        mn = min(mn, min(min(q.x, q.y), min(q.z, q.w)));
-        mx = max(mx, max(max(q.x, q.y), max(q.z, q.w)));
+    const int64_t stride = (int64_t)gridDim.x * 256 * kMinMaxVec;
+    for (int64_t i0 = (int64_t)blockIdx.x * 256 * kMinMaxVec + threadIdx.x; i0 < nv; i0 += stride) {
+        int4 q[kMinMaxVec];
+#pragma unroll
+        for (int r = 0; r < kMinMaxVec; ++r) {  // all loads in flight at once
+            const int64_t i = i0 + (int64_t)r * 256;
+            q[r] = v[i < nv ? i : i0];
+        }
+#pragma unroll
+        for (int r = 0; r < kMinMaxVec; ++r) {
+            mn = min(mn, min(min(q[r].x, q[r].y), min(q[r].z, q[r].w)));
+            mx = max(mx, max(max(q[r].x, q[r].y), max(q[r].z, q[r].w)));
+        }
     }
     const int64_t tail0 = head + 4 * nv, nrest = head + (n - tail0);  // at most 6 values
     for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < nrest; r += stride) {
@@ -79,7 +88,7 @@ void minmax4(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, con
              int64_t ns, int *out) {
     const int64_t n = std::max(nr, ns);
     if (n <= 0) return;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256 * 16), (int64_t)c.num_cus * 2));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256 * 4 * kMinMaxVec), (int64_t)c.num_cus * 2));
     hipLaunchKernelGGL(k_minmax4, dim3(grid_x(blocks, 256), 4), dim3(256), 0, c.stream, rx, ry, nr, sz, sy, ns, out);
     JP_HIP(hipGetLastError());
 }
@@ -161,9 +170,13 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint64_t *s = radix_sort(c, ka.get(), kb.get(), nr, xb + yb);
         r1 = c.buf<uint64_t>(nr);
         uint64_t *d = r1.get();
-        compact(
-            c, nr, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 0);
+        compact_v(
+            c, nr,
+            [=] __device__(int64_t i) {
+                const uint64_t k = s[i];
+                return Pick<uint64_t>{i == 0 || k != s[i - 1], k};
+            },
+            [=] __device__(int64_t, int64_t p, uint64_t k) { d[p] = k; }, S + 0);
     }
     // ---- S: distinct tuples, y-major ----------------------------------------
     DBuf<uint64_t> s1;
@@ -176,9 +189,13 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint64_t *s = radix_sort(c, ka.get(), kb.get(), ns, yb + zb);
         s1 = c.buf<uint64_t>(ns);
         uint64_t *d = s1.get();
-        compact(
-            c, ns, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) { d[p] = s[i]; }, S + 1);
+        compact_v(
+            c, ns,
+            [=] __device__(int64_t i) {
+                const uint64_t k = s[i];
+                return Pick<uint64_t>{i == 0 || k != s[i - 1], k};
+            },
+            [=] __device__(int64_t, int64_t p, uint64_t k) { d[p] = k; }, S + 1);
     }
     // ---- distinct y of R with their R degrees (sorted y of the distinct R) -----
     int64_t h2[2];
@@ -195,10 +212,14 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint32_t *s = radix_sort(c, ya.get(), yb2.get(), n_r1, yb);
         uint32_t *d = YR.get();
         int64_t *rs = rstart.get();
-        compact(
-            c, n_r1, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                d[p] = s[i];
+        compact_v(
+            c, n_r1,
+            [=] __device__(int64_t i) {
+                const uint32_t k = s[i];
+                return Pick<uint32_t>{i == 0 || k != s[i - 1], k};
+            },
+            [=] __device__(int64_t i, int64_t p, uint32_t k) {
+                d[p] = k;
                 rs[p] = i;
             },
             S + 2);
@@ -216,9 +237,13 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint64_t *s = s1.get();
         uint32_t *d = YS.get();
         const int zbs = zb;
-        compact(
-            c, n_s1, [=] __device__(int64_t i) { return i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs); },
-            [=] __device__(int64_t i, int64_t p) { d[p] = (uint32_t)(s[i] >> zbs); }, S + 3);
+        compact_v(
+            c, n_s1,
+            [=] __device__(int64_t i) {
+                const uint64_t y = s[i] >> zbs;
+                return Pick<uint32_t>{i == 0 || y != (s[i - 1] >> zbs), (uint32_t)y};
+            },
+            [=] __device__(int64_t, int64_t p, uint32_t y) { d[p] = y; }, S + 3);
     }
     int64_t hy2[2];
     c.load_n(hy2, S + 2, 2);
@@ -233,19 +258,37 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const int64_t *rs = rstart.get();
         const int64_t nyr = ny_r;
         for_each(c, ny_s, [=] __device__(int64_t j) { yr[j] = -1; });
-        auto pos = [=] __device__(int64_t j) -> int64_t {
-            const int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
-            const int64_t q = p < nyr ? p : nyr - 1;
-            return ((p < nyr) & (yrr[q] == ys[j])) ? q : -1;
+        auto emit = [=] __device__(int64_t j, int64_t p, int32_t deg) {
+            yr[j] = (int32_t)p;
+            dr[p] = deg;
         };
-        compact(
-            c, ny_s, [=] __device__(int64_t j) { return pos(j) >= 0; },
-            [=] __device__(int64_t j, int64_t p) {
-                const int64_t q = pos(j);
-                yr[j] = (int32_t)p;
-                dr[p] = (int32_t)(rs[q + 1] - rs[q]);
-            },
-            S + 4);
+        const int64_t yspan = ymax - ymin + 1;
+        if (dense_range_ok(yspan, nr + ns)) {
+            // position of every y in the distinct y of R, from a table over the y range
+            DBuf<int32_t> yq = c.buf<int32_t>((size_t)yspan);
+            int32_t *yqp = yq.get();
+            for_each(c, yspan, [=] __device__(int64_t y) { yqp[y] = -1; });
+            for_each(c, nyr, [=] __device__(int64_t q) { yqp[yrr[q]] = (int32_t)q; });
+            const int32_t *yqc = yqp;
+            compact_v(
+                c, ny_s,
+                [=] __device__(int64_t j) {
+                    const int32_t q = yqc[ys[j]];
+                    const int64_t qc = q >= 0 ? q : 0;
+                    return Pick<int32_t>{q >= 0, (int32_t)(rs[qc + 1] - rs[qc])};
+                },
+                emit, S + 4);
+        } else {
+            compact_v(
+                c, ny_s,
+                [=] __device__(int64_t j) {
+                    const int64_t p = lower_bound_dev(yrr, (int64_t)0, nyr, ys[j]);
+                    const int64_t q = p < nyr ? p : nyr - 1;
+                    const bool hit = (p < nyr) & (yrr[q] == ys[j]);
+                    return Pick<int32_t>{hit, (int32_t)(rs[q + 1] - rs[q])};
+                },
+                emit, S + 4);
+        }
     }
     rstart.reset();
     // S tuples kept, y-major: y rank + z offset
@@ -259,16 +302,20 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         auto newy = [=] __device__(int64_t i) -> int64_t {
             return (i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs)) ? 1 : 0;
         };
-        scan_exclusive(c, n_s1, newy, [=] __device__(int64_t i, int64_t p) { sg[i] = (int32_t)(p + newy(i) - 1); });
+        scan_exclusive_v(c, n_s1, newy, [=] __device__(int64_t i, int64_t p, int64_t v) { sg[i] = (int32_t)(p + v - 1); });
         const int32_t *yr = yrank_js.get();
         int32_t *oy = s2_y.get();
         uint32_t *oz = s2_z.get();
         const uint64_t zm = zmask;
-        compact(
-            c, n_s1, [=] __device__(int64_t i) { return yr[sg[i]] >= 0; },
-            [=] __device__(int64_t i, int64_t p) {
-                oy[p] = yr[sg[i]];
-                oz[p] = (uint32_t)(s[i] & zm);
+        compact_v(
+            c, n_s1,
+            [=] __device__(int64_t i) {
+                const int32_t r = yr[sg[i]];
+                return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(s[i] & zm)};
+            },
+            [=] __device__(int64_t, int64_t p, uint64_t v) {
+                oy[p] = (int32_t)(v >> 32);
+                oz[p] = (uint32_t)v;
             },
             S + 5);
     }
@@ -293,11 +340,16 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             for_each(c, yspan, [=] __device__(int64_t y) { ymp[y] = -1; });
             for_each(c, nys, [=] __device__(int64_t j) { ymp[ys[j]] = yr[j]; });
             const int32_t *ymc = ymp;
-            compact(
-                c, n_r1, [=] __device__(int64_t i) { return ymc[s[i] & ym] >= 0; },
-                [=] __device__(int64_t i, int64_t p) {
-                    ox[p] = (uint32_t)(s[i] >> ybs);
-                    oy[p] = ymc[s[i] & ym];
+            compact_v(
+                c, n_r1,
+                [=] __device__(int64_t i) {
+                    const uint64_t k = s[i];
+                    const int32_t r = ymc[k & ym];
+                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(k >> ybs)};
+                },
+                [=] __device__(int64_t, int64_t p, uint64_t v) {
+                    ox[p] = (uint32_t)v;
+                    oy[p] = (int32_t)(v >> 32);
                 },
                 S + 6);
         } else {
@@ -308,11 +360,15 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
                 const int32_t r = yr[q];
                 return ((p < nys) & (ys[q] == y)) ? r : -1;
             };
-            compact(
-                c, n_r1, [=] __device__(int64_t i) { return find(i) >= 0; },
-                [=] __device__(int64_t i, int64_t p) {
-                    ox[p] = (uint32_t)(s[i] >> ybs);
-                    oy[p] = find(i);
+            compact_v(
+                c, n_r1,
+                [=] __device__(int64_t i) {
+                    const int32_t r = find(i);
+                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(s[i] >> ybs)};
+                },
+                [=] __device__(int64_t, int64_t p, uint64_t v) {
+                    ox[p] = (uint32_t)v;
+                    oy[p] = (int32_t)(v >> 32);
                 },
                 S + 6);
         }
@@ -334,10 +390,14 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint32_t *s = radix_sort(c, za.get(), zb2.get(), n_s2, zb);
         uint32_t *d = ZS.get();
         int64_t *zs0 = zstart.get();
-        compact(
-            c, n_s2, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                d[p] = s[i];
+        compact_v(
+            c, n_s2,
+            [=] __device__(int64_t i) {
+                const uint32_t k = s[i];
+                return Pick<uint32_t>{i == 0 || k != s[i - 1], k};
+            },
+            [=] __device__(int64_t i, int64_t p, uint32_t k) {
+                d[p] = k;
                 zs0[p] = i;
             },
             S + 7);
@@ -350,10 +410,14 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         int32_t *xo = xorig.get();
         int64_t *ox = off_x.get();
         const int64_t xm = xmin;
-        compact(
-            c, n_r2, [=] __device__(int64_t i) { return i == 0 || xs[i] != xs[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                xo[p] = (int32_t)((int64_t)xs[i] + xm);
+        compact_v(
+            c, n_r2,
+            [=] __device__(int64_t i) {
+                const uint32_t k = xs[i];
+                return Pick<uint32_t>{i == 0 || k != xs[i - 1], k};
+            },
+            [=] __device__(int64_t i, int64_t p, uint32_t k) {
+                xo[p] = (int32_t)((int64_t)k + xm);
                 ox[p] = i;
             },
             S + 8);
@@ -385,7 +449,7 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         int64_t *ox = off_x.get();
         const int64_t nx = dom_x, nr2 = n_r2;
         auto newx = [=] __device__(int64_t i) -> int64_t { return (i == 0 || xs[i] != xs[i - 1]) ? 1 : 0; };
-        scan_exclusive(c, n_r2, newx, [=] __device__(int64_t i, int64_t p) { xr[i] = (int32_t)(p + newx(i) - 1); });
+        scan_exclusive_v(c, n_r2, newx, [=] __device__(int64_t i, int64_t p, int64_t v) { xr[i] = (int32_t)(p + v - 1); });
         for_each(c, 1, [=] __device__(int64_t) { ox[nx] = nr2; });
     }
     r2_x.reset();
@@ -601,14 +665,21 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         int32_t *zl = zlist_own.get();
         JP_HIP(hipMemcpyAsync(zl, as, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
         int32_t *la = zl + n_s2;
-        scan_exclusive(
+        struct LzItem {
+            int32_t h, z;  // heavy index of the tuple's y (-1: light), z rank
+            bool first;    // first tuple of its y
+        };
+        scan_exclusive_v(
             c, n_s2,
-            [=] __device__(int64_t e) -> int64_t { return (int64_t)((hy[syr[e]] >= 0) & (hz[as[e]] < 0)); },
-            [=] __device__(int64_t e, int64_t p) {
-                const int32_t y = syr[e];
+            [=] __device__(int64_t e) {
+                const int32_t y = syr[e], z = as[e];
                 const int32_t h = hy[y];
-                if ((h >= 0) & (hz[as[e]] < 0)) la[p] = as[e];
-                if (h >= 0 && (e == 0 || syr[e - 1] != y)) lo[h] = p;
+                const bool first = e == 0 || syr[e - 1] != y;
+                return Sum<LzItem>{(int64_t)((h >= 0) & (hz[z] < 0)), LzItem{h, z, first}};
+            },
+            [=] __device__(int64_t, int64_t p, const Sum<LzItem> &it) {
+                if (it.add) la[p] = it.v.z;
+                if ((it.v.h >= 0) & it.v.first) lo[it.v.h] = p;
             },
             lo + v);
         zlist = zl;  // its length n_s2 + lz_off[v] is read back with J_L below
