@@ -9,11 +9,11 @@
 // units that follow x order:
 //
 //  * small x (at most kUnitCap candidates) are packed into units of at most
-//    kDCap candidates.  A unit gathers its candidates as 32-bit keys
+//    kDCap candidates; a medium x (at most kDCap) is a unit of its own.  A unit gathers its candidates as 32-bit keys
 //    (x - first_x) << bz | z, sorts them by LSD radix sort in LDS over the
 //    significant bits only (5-bit digits, per-thread LDS counters, raking
 //    scan), and keeps the first of every run of equal keys.
-//  * a large x is cut into z windows; a window unit binary-searches the
+//  * a large x (more than kDCap) is cut into z windows; a window unit binary-searches the
 //    window's part of every sorted list, marks it in an LDS bitmap and reads
 //    the set bits back in z order.
 //
@@ -33,12 +33,14 @@ namespace {
 constexpr int kDT = 256;                 // threads per unit
 constexpr int kDI = 32;                  // keys per thread
 constexpr int kDCap = kDT * kDI;         // keys per unit (LDS 32 KB)
-constexpr int64_t kUnitCap = kDCap / 2;  // x with more candidates get window units
+constexpr int64_t kUnitCap = kDCap / 2;  // x with more candidates get a unit of their own
+constexpr int64_t kSoloCap = kDCap;      // x with more candidates get window units
 constexpr int kRB = 5;                   // radix digit bits
 constexpr int kRD = 1 << kRB;            // digits
 constexpr int64_t kWinBits = (int64_t)kDCap * 32;  // bitmap window capacity (reuses the key buffer)
 constexpr int64_t kWinTarget = 16384;              // candidates per window unit, aimed for
 constexpr int kListChunk = kDT;                    // lists handled per round in a window unit
+constexpr int kWinBatch = 4;                       // window candidates per thread with loads in flight
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -165,10 +167,13 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
                 lb = staged ? slb[e] : a.lbase[e0 + e];
                 xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
             }
+            // list positions first (LDS and arithmetic only), then every
+            // list load in one straight run so all of them are in flight
+            uint32_t src[kDI];
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = p0 + j;
-                uint32_t key = 0xffffffffu;
+                uint32_t key = 0xffffffffu, sj = 0;
                 if (p < nLc) {
                     while (p >= enext) {  // next R tuple with a nonempty list
                         ++e;
@@ -177,12 +182,19 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
                         lb = staged ? slb[e] : a.lbase[e0 + e];
                         xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
                     }
-                    key = xl | (uint32_t)a.zlist[lb + (p - eo)];
+                    key = xl;
+                    sj = (uint32_t)(lb + (p - eo));
                 } else if (p < nn) {
                     const uint64_t hk = a.hkeys[h0 + (p - nL)];
                     key = ((uint32_t)((int64_t)(hk >> a.bz) - xa) << a.bz) | ((uint32_t)hk & a.zmask);
                 }
                 k[j] = key;
+                src[j] = sj;
+            }
+#pragma unroll
+            for (int j = 0; j < kDI; ++j) {
+                const uint32_t z = (uint32_t)a.zlist[src[j]];
+                k[j] = p0 + j < nLc ? (k[j] | z) : k[j];
             }
         }
         __syncthreads();  // staged tuple data is overwritten by the counters below
@@ -196,15 +208,18 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
             const int shift = pass * kRB;
             for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
             __syncthreads();
+            // count with LDS atomics that return the old value: the updates of
+            // one thread issue back to back instead of as dependent
+            // read-modify-writes (a thread's counter stays below 2^16)
             uint16_t loc[kDI];
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = tid * kDI + j;
                 const int d = (int)((k[j] >> shift) & (kRD - 1));
-                uint16_t &c = ctr(cnt, d, tid);
-                const uint16_t v = c;
-                loc[j] = v;
-                if (p < nn) c = (uint16_t)(v + 1);
+                const int ci = d * kDT + tid;
+                const int sh = 16 * (ci & 1);
+                const uint32_t old = atomicAdd(&cnt[cpad(ci >> 1)], (p < nn ? 1u : 0u) << sh);
+                loc[j] = (uint16_t)(old >> sh);
             }
             __syncthreads();
             // raking exclusive scan over [digit][thread]: thread t owns `per`
@@ -326,14 +341,23 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         if (tid == 0) lpre[kListChunk] = tot;
         __syncthreads();
         const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
-        for (int64_t p = tid; p < tot; p += kDT) {
-            const int64_t li = upper_bound_dev(lpre, (int64_t)0, nl, p) - 1;
-            const int64_t bb = lbeg[li];
-            const int64_t off = p - lpre[li];
-            const int64_t z = bb >= 0 ? (int64_t)a.zlist[bb + off]
-                                      : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
-            const int64_t zr = z - zlo;
-            if ((zr >= 0) & (zr < wbits)) atomicOr(&sk[zr >> 5], 1u << (zr & 31));
+        // kWinBatch candidates per thread per round: searches, then loads, then bits
+        for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
+            int64_t z[kWinBatch];
+#pragma unroll
+            for (int r = 0; r < kWinBatch; ++r) {
+                const int64_t q = q0 + (int64_t)r * kDT;
+                const int64_t p = q < tot ? q : q0;
+                const int64_t li = upper_bound_dev(lpre, (int64_t)0, nl, p) - 1;
+                const int64_t bb = lbeg[li];
+                const int64_t off = p - lpre[li];
+                z[r] = bb >= 0 ? (int64_t)a.zlist[bb + off] : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
+            }
+#pragma unroll
+            for (int r = 0; r < kWinBatch; ++r) {
+                const int64_t zr = z[r] - zlo;
+                if ((q0 + (int64_t)r * kDT < tot) & (zr >= 0) & (zr < wbits)) atomicOr(&sk[zr >> 5], 1u << (zr & 31));
+            }
         }
         __syncthreads();
     }
@@ -382,18 +406,37 @@ struct CopyArgs {
     int64_t *err;
 };
 constexpr int kCopyBlock = 256;
+constexpr int kCopyBatch = 8;  // keys per thread whose loads are in flight together
 __global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
     const int64_t u = blockIdx.x;
     const int64_t n = a.ucount[u], src = a.ubase[u], dst = a.uoff[u];
     const int64_t xa = a.ustart[u];
+    const bool xdense = a.xbase != INT64_MIN, zdense = a.zbase != INT64_MIN;
     bool bad = false;
-    for (int64_t i = threadIdx.x; i < n; i += kCopyBlock) {
-        const uint32_t key = a.stage[src + i];
-        const int64_t xi = xa + (key >> a.bz), zi = key & a.zmask;
-        const bool ok = (xi < a.dom_x) & (zi < a.dom_z);
-        bad |= !ok;
-        a.out_x[dst + i] = a.xbase != INT64_MIN ? (int32_t)(a.xbase + xi) : a.xorig[ok ? xi : 0];
-        a.out_z[dst + i] = a.zbase != INT64_MIN ? (int32_t)(a.zbase + zi) : a.zorig[ok ? zi : 0];
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += (int64_t)kCopyBlock * kCopyBatch) {
+        uint32_t key[kCopyBatch];
+#pragma unroll
+        for (int r = 0; r < kCopyBatch; ++r) {
+            const int64_t i = i0 + (int64_t)r * kCopyBlock;
+            key[r] = a.stage[src + (i < n ? i : i0)];
+        }
+        int32_t ox[kCopyBatch], oz[kCopyBatch];
+#pragma unroll
+        for (int r = 0; r < kCopyBatch; ++r) {
+            const int64_t xi = xa + (key[r] >> a.bz), zi = key[r] & a.zmask;
+            const bool ok = (xi < a.dom_x) & (zi < a.dom_z);
+            bad |= !ok;
+            ox[r] = xdense ? (int32_t)(a.xbase + xi) : a.xorig[ok ? xi : 0];
+            oz[r] = zdense ? (int32_t)(a.zbase + zi) : a.zorig[ok ? zi : 0];
+        }
+#pragma unroll
+        for (int r = 0; r < kCopyBatch; ++r) {
+            const int64_t i = i0 + (int64_t)r * kCopyBlock;
+            if (i < n) {
+                a.out_x[dst + i] = ox[r];
+                a.out_z[dst + i] = oz[r];
+            }
+        }
     }
     if (bad) *a.err = 3;
 }
@@ -405,6 +448,7 @@ bool segmented_dedup_fits(int bz) { return bz <= 26; }
 void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, DBuf<int32_t> *out_z,
                      int64_t *n_out, SegDedupStats *stats, bool timing) {
     JP_CHECK(segmented_dedup_fits(in.bz), JP_EINTERNAL, "segmented dedup needs bz <= 26");
+    JP_CHECK(in.zlist_n >= 1 && in.zlist_n < (1ll << 32), JP_EINTERNAL, "witness lists must hold 1 to 2^32-1 entries");
     const int64_t dom_x = in.dom_x, dom_z = in.dom_z;
     DBuf<int64_t> scal = c.buf<int64_t>(8);
     int64_t *S = scal.get();
@@ -437,7 +481,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
     }
 
     // Units in x order.  A small x starts a packed unit when it is the first
-    // x, follows a large x, begins a new kUnitCap window of candidate offsets,
+    // x, follows a medium or large x, begins a new kUnitCap window of candidate offsets,
     // or begins a new block of 2^(32-bz) x values (local keys fit 32 bits).
     // A large x contributes windows_of(...) window units.
     const int kb = 32 - in.bz;
@@ -450,7 +494,8 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             c, dom_x,
             [=] __device__(int64_t x) -> int64_t {
                 const int64_t t = to[x + 1] - to[x];
-                if (t > kUnitCap) return windows_of(t, dz);
+                if (t > kSoloCap) return windows_of(t, dz);
+                if (t > kUnitCap) return 1;
                 if (x == 0) return 1;
                 const bool prev_big = to[x] - to[x - 1] > kUnitCap;
                 const bool newwin = (to[x] / kUnitCap) != (to[x - 1] / kUnitCap);
@@ -468,7 +513,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         int32_t *us = ustart.get(), *uw = uwin.get();
         for_each(c, dom_x, [=] __device__(int64_t x) {
             const int64_t b = nu[x], m = nu[x + 1] - b;
-            const bool big = to[x + 1] - to[x] > kUnitCap;
+            const bool big = to[x + 1] - to[x] > kSoloCap;
             for (int64_t i = 0; i < m; ++i) {
                 us[b + i] = (int32_t)x;
                 uw[b + i] = big ? (int32_t)i : -1;

@@ -15,6 +15,7 @@ struct SegDedupIn {
     const int64_t *lbase = nullptr;  // list start of every R tuple in zlist
     const int32_t *r_xr = nullptr;   // x rank of every R tuple
     const int32_t *zlist = nullptr;  // concatenated z-rank lists
+    int64_t zlist_n = 0;             // their total length (below 2^32)
     const uint64_t *hkeys = nullptr; // sorted heavy nonzeros (x << bz | z)
     int64_t nnz = 0;
     const int32_t *xorig = nullptr, *zorig = nullptr;

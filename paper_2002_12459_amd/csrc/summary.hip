@@ -5,10 +5,12 @@
 //
 // All six indexes (y key degree with witness sums, deg_R(y), deg_S(y),
 // deg_R(x) with witness sums, cdfx, deg_S(z)) are built by one histogram
-// launch (grid.y = index): degrees below kLdsBins go to per-workgroup LDS
-// bins, degrees below kHist to global bins, larger ones to an append list.
-// One compaction keeps the nonzero bins; the host then waits twice (sizes,
-// then data) and merges the append list.
+// launch (grid.y = index, one element per thread): degrees below kLdsBins go
+// to per-workgroup LDS bins, which are flushed into one of kCopies copies of
+// the low global bins (spreading the atomics of thousands of workgroups over
+// the copies) and folded afterwards; degrees below kHist go to global bins,
+// larger ones to an append list.  One compaction keeps the nonzero bins; the
+// host then waits twice (sizes, then data) and merges the append list.
 #include <algorithm>
 
 #include "pipeline.hpp"
@@ -21,6 +23,8 @@ constexpr int kIdx = 6;              // y, yr, ys, x, xcdf, z
 constexpr int64_t kHist = 1 << 16;   // global bins per index
 constexpr int kLdsBins = 1024;       // LDS bins per workgroup
 constexpr int kHistBlock = 256;
+constexpr int kEdgeBatch = 4;        // R tuples of an x read together
+constexpr int kCopies = 16;          // copies of the low global bins
 
 struct IndexArgs {
     const int32_t *dry, *dsz, *ar;
@@ -29,6 +33,7 @@ struct IndexArgs {
     bool ronly;
     unsigned long long *cnt;   // [kIdx][kHist]
     unsigned long long *sums;  // [kIdx][kHist]
+    unsigned long long *lo;    // [kCopies][kIdx][kLdsBins] counts, then as many sums
     int64_t *big;              // append list: idx << 56 | degree, then sum (pairs)
     unsigned long long *nbig;
     int64_t big_cap;
@@ -54,19 +59,30 @@ __device__ __forceinline__ void index_value(const IndexArgs &a, int k, int64_t i
         case 3: {  // x: deg_R(x), witnesses sum over y of deg_S(y)
             const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
             unsigned long long w = 0;
-            for (int64_t e = e0; e < e1; ++e) {
-                const int32_t y = a.ar[e];
-                w += (unsigned long long)(a.oy[y + 1] - a.oy[y]);
+            for (int64_t e = e0; e < e1; e += kEdgeBatch) {  // kEdgeBatch tuples' loads at once
+                int32_t y[kEdgeBatch];
+#pragma unroll
+                for (int r = 0; r < kEdgeBatch; ++r) y[r] = a.ar[e + r < e1 ? e + r : e0];
+#pragma unroll
+                for (int r = 0; r < kEdgeBatch; ++r)
+                    if (e + r < e1) w += (unsigned long long)(a.oy[y[r] + 1] - a.oy[y[r]]);
             }
             d = e1 - e0;
             s = w;
             break;
         }
         case 4: {  // cdfx: smallest key degree among the y of x
+            const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
             int64_t m = INT64_MAX;
-            for (int64_t e = a.ox[i]; e < a.ox[i + 1]; ++e) {
-                const int64_t kd = key_deg(a, a.ar[e]);
-                m = kd < m ? kd : m;
+            for (int64_t e = e0; e < e1; e += kEdgeBatch) {
+                int32_t y[kEdgeBatch];
+#pragma unroll
+                for (int r = 0; r < kEdgeBatch; ++r) y[r] = a.ar[e + r < e1 ? e + r : e0];
+#pragma unroll
+                for (int r = 0; r < kEdgeBatch; ++r) {
+                    const int64_t kd = key_deg(a, y[r]);
+                    m = (e + r < e1) & (kd < m) ? kd : m;
+                }
             }
             d = m;
             break;
@@ -106,10 +122,28 @@ __global__ __launch_bounds__(kHistBlock) void k_index_hist(IndexArgs a) {
         }
     }
     __syncthreads();
+    unsigned long long *lo = a.lo + ((int64_t)(blockIdx.x % kCopies) * kIdx + k) * kLdsBins;
+    unsigned long long *los = lo + (int64_t)kCopies * kIdx * kLdsBins;
     for (int b = threadIdx.x; b < kLdsBins; b += kHistBlock) {
-        if (lc[b]) atomicAdd(&cnt[b], (unsigned long long)lc[b]);
-        if (ls[b]) atomicAdd(&sums[b], ls[b]);
+        if (lc[b]) atomicAdd(&lo[b], (unsigned long long)lc[b]);
+        if (ls[b]) atomicAdd(&los[b], ls[b]);
     }
+}
+
+// Low bins: the sum of the copies (these bins receive nothing else).
+__global__ __launch_bounds__(kHistBlock) void k_index_fold(IndexArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * kHistBlock + threadIdx.x;  // k * kLdsBins + b
+    if (i >= (int64_t)kIdx * kLdsBins) return;
+    const int64_t k = i / kLdsBins, b = i % kLdsBins;
+    const int64_t stride = (int64_t)kIdx * kLdsBins, sum_off = (int64_t)kCopies * kIdx * kLdsBins;
+    unsigned long long c = 0, sm = 0;
+#pragma unroll
+    for (int q = 0; q < kCopies; ++q) {
+        c += a.lo[q * stride + i];
+        sm += a.lo[sum_off + q * stride + i];
+    }
+    a.cnt[k * kHist + b] = c;
+    a.sums[k * kHist + b] = sm;
 }
 
 }  // namespace
@@ -132,11 +166,13 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     a.dom_x = g.dom_x;
     a.dom_z = g.dom_z;
     a.ronly = y_rule == JP_Y_RULE_R_ONLY;
-    // one block for counts and sums, cleared together
-    DBuf<unsigned long long> bins = c.buf<unsigned long long>(2 * kIdx * kHist);
-    c.zero(bins.get(), 2 * kIdx * kHist);
+    // one block for counts, sums and the low-bin copies, cleared together
+    const int64_t lo_words = 2ll * kCopies * kIdx * kLdsBins;
+    DBuf<unsigned long long> bins = c.buf<unsigned long long>(2 * kIdx * kHist + lo_words);
+    c.zero(bins.get(), 2 * kIdx * kHist + lo_words);
     a.cnt = bins.get();
     a.sums = bins.get() + kIdx * kHist;
+    a.lo = bins.get() + 2 * kIdx * kHist;
     // Values of degree >= kHist: at most 3 dom_y + 2 dom_x + dom_z in all.
     a.big_cap = 3 * g.dom_y + 2 * g.dom_x + g.dom_z;
     DBuf<int64_t> big = c.buf<int64_t>((size_t)(2 * a.big_cap));
@@ -144,8 +180,12 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     c.zero(S.get(), 2);
     a.big = big.get();
     a.nbig = (unsigned long long *)(S.get() + 1);
-    const int64_t bx = std::min<int64_t>(ceil_div(nmax, kHistBlock), (int64_t)c.num_cus * 2);
+    // one element per thread (up to 2^24 threads per index, then strided)
+    const int64_t bx = std::min<int64_t>(ceil_div(nmax, kHistBlock), 1ll << 16);
     hipLaunchKernelGGL(k_index_hist, dim3(grid_x(bx, kHistBlock), kIdx), dim3(kHistBlock), 0, c.stream, a);
+    JP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_index_fold, dim3(grid_x(ceil_div((int64_t)kIdx * kLdsBins, kHistBlock), kHistBlock)),
+                       dim3(kHistBlock), 0, c.stream, a);
     JP_HIP(hipGetLastError());
 
     // nonzero bins of all indexes, in (index, degree) order

@@ -830,6 +830,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         in.lbase = lbase.get();
         in.r_xr = r_xr.get();
         in.zlist = zl_used;
+        in.zlist_n = zlist_n;
         in.hkeys = hks;
         in.nnz = nnz;
         in.xorig = xorig.get();

@@ -202,12 +202,13 @@ def test_spaced_z_ids(jp, spacing):
 
 
 def test_dedup_unit_class_boundaries(jp):
-    """x values whose candidate counts sit on both sides of the per-x class
-    limits of the duplicate removal (512: wave units; 4096: block units;
-    more: z windows), interleaved, with duplicates inside every x."""
+    """x values whose candidate counts (cnt + cnt // 2 here) sit on both sides
+    of the per-x class limits of the duplicate removal (up to 4096: packed
+    with other x; up to 8192: a unit of its own; more: z windows),
+    interleaved, with duplicates inside every x."""
     rng = np.random.default_rng(11)
-    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 4095, 4096, 4097,
-              9000, 3, 700, 512, 512, 2]
+    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2730, 2731, 2732,
+              4095, 4096, 4097, 5461, 5462, 9000, 3, 700, 512, 5461, 2731, 512, 2]
     rx, ry, sz, sy = [], [], [], []
     nz = 20000
     for i, cnt in enumerate(counts):
