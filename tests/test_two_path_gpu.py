@@ -204,13 +204,13 @@ def test_spaced_z_ids(jp, spacing):
 def test_dedup_unit_class_boundaries(jp):
     """x values whose candidate counts (cnt + cnt // 2 here) sit on both sides
     of the per-x class limits of the duplicate removal (up to 4096: packed
-    with other x; up to 8192: a unit of its own; more: z windows),
-    interleaved, with duplicates inside every x."""
+    with other x; up to 8192: a unit of its own; more: z windows marked in an
+    LDS bitmap), interleaved, with duplicates inside every x."""
     rng = np.random.default_rng(11)
-    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 2730, 2731, 2732,
-              4095, 4096, 4097, 5461, 5462, 9000, 3, 700, 512, 5461, 2731, 512, 2]
+    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 1365, 1366, 2730,
+              2731, 2732, 4095, 4096, 4097, 5461, 5462, 9000, 21845, 21846, 3, 700, 512, 5461, 2731, 1366, 512, 2]
     rx, ry, sz, sy = [], [], [], []
-    nz = 20000
+    nz = 40000
     for i, cnt in enumerate(counts):
         # x = i meets two lists: y = 2i (cnt distinct z) and y = 2i + 1 (half of them again)
         zs = rng.choice(nz, cnt, replace=False)
@@ -221,6 +221,21 @@ def test_dedup_unit_class_boundaries(jp):
         sy += [2 * i] * cnt + [2 * i + 1] * half.size
     check_equal(jp, rx, ry, sz, sy, strategy="light")
     check_equal(jp, rx, ry, sz, sy, strategy="fixed", delta1=600, delta2=1)
+
+
+def test_dedup_crowded_and_wide_windows(jp):
+    """Skewed z windows: an x whose candidates all fall in the lower half of
+    a 1.3M-wide z range, an x whose candidates crowd into one narrow range,
+    and an x with 1.3M candidates (many bitmap windows)."""
+    rng = np.random.default_rng(5)
+    Z = 1_300_000
+    z_crowd = rng.choice(600_000, 6000, replace=False)          # x = 0: 6000 z in the lower half
+    z_narrow = rng.choice(20_000, 5000, replace=False) + 700_000  # x = 2: 5000 z in a narrow range
+    rx = [0, 1, 2, 2]
+    ry = [0, 1, 2, 0]
+    sz = z_crowd.tolist() + list(range(Z)) + z_narrow.tolist()
+    sy = [0] * z_crowd.size + [1] * Z + [2] * z_narrow.size
+    check_equal(jp, rx, ry, sz, sy, strategy="light")
 
 
 @pytest.mark.parametrize("dedup", ["global", "segmented"])
