@@ -67,17 +67,22 @@ struct TripleEmit {  // nonzero ((a1,a2), a3) -> x1 << s1 | x2 << s2 | x3
     }
 };
 
-// Block index -> tile, grouping consecutive blocks of one XCD (blocks are
-// dealt round-robin to the 8 XCDs) onto a compact 2-D patch of tiles so that
-// tiles sharing A rows / B rows share that XCD's L2.
-__device__ __forceinline__ void tile_of_block(int64_t bid, int64_t tiles_m, int64_t tiles_n, int64_t *tm,
+// Work items are dealt to the 8 XCDs round-robin by block index.  Item
+// sequence index -> work item: XCD r (blocks b with b % 8 == r, grids are
+// multiples of 8) takes the r-th eighth of the items, a contiguous run, so
+// tiles next to each other in tile_of_block's order share that XCD's L2.
+// The item space is padded to a multiple of 8; padding returns -1.
+__device__ __forceinline__ int64_t xcd_item(int64_t bid, int64_t total) {
+    const int64_t per = (total + 7) / 8;
+    const int64_t t = (bid & 7) * per + (bid >> 3);
+    return t < total ? t : -1;
+}
+__host__ __device__ inline int64_t xcd_padded(int64_t total) { return 8 * ((total + 7) / 8); }
+
+// Tile index -> tile: groups of 8 tile-rows swept column-major, so a run of
+// consecutive tiles forms a compact 2-D patch (tiles sharing A rows / B rows).
+__device__ __forceinline__ void tile_of_block(int64_t t, int64_t tiles_m, int64_t tiles_n, int64_t *tm,
                                               int64_t *tn) {
-    const int64_t total = tiles_m * tiles_n;
-    int64_t t = bid;
-    if (total % 8 == 0) {
-        const int64_t per = total / 8;
-        t = (bid % 8) * per + bid / 8;
-    }
     // group of 8 tile-rows swept column-major inside the group
     const int64_t G = 8;
     const int64_t group = t / (G * tiles_n);
@@ -109,10 +114,12 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
     // grid is a multiple of 8, so a workgroup stays on its XCD's tile patch).
     const int64_t nchunks = (ld + kchunk - 1) / kchunk;
     const int64_t total = tiles_m * tiles_n * nchunks;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+    for (int64_t bid = blockIdx.x; bid < xcd_padded(total); bid += gridDim.x) {
+        const int64_t item = xcd_item(bid, total);
+        if (item < 0) continue;  // padding (uniform per workgroup)
         int64_t tm, tn;
-        tile_of_block(bid / nchunks, tiles_m, tiles_n, &tm, &tn);
-        const int64_t kbeg = (bid % nchunks) * kchunk;
+        tile_of_block(item / nchunks, tiles_m, tiles_n, &tm, &tn);
+        const int64_t kbeg = (item % nchunks) * kchunk;
         const int64_t kend = kbeg + kchunk < ld ? kbeg + kchunk : ld;
         const int64_t row0 = tm * BM, col0 = tn * BN;
         v4i ra[4], rb[4];
@@ -241,9 +248,11 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
     const int fr = lane % 16, fq = lane / 16;
     const int64_t total = tiles_m * tiles_n;
     const int64_t nk = ld / BK2;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+    for (int64_t bid = blockIdx.x; bid < xcd_padded(total); bid += gridDim.x) {
+        const int64_t item = xcd_item(bid, total);
+        if (item < 0) continue;  // padding (uniform per workgroup)
         int64_t tm, tn;
-        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
         const int64_t row0 = tm * BM2, col0 = tn * BN2;
         // Stage s: 4096 chunks of 16 bytes, 8 rounds of 512; chunk P holds
         // (row P / 8, K chunk (P % 8) ^ (row & 7)); rows 0..255 are A, 256..511 B.
@@ -346,7 +355,7 @@ void launch_bmm_big(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, 
     c.zero(count_dev, 1);
     if (u <= 0 || w <= 0 || ld <= 0) return;
     const int64_t tm = ceil_div(u, BM2), tn = ceil_div(w, BN2);
-    const int64_t total = tm * tn;
+    const int64_t total = xcd_padded(tm * tn);
     constexpr int64_t kMaxGrid = 1ll << 21;  // multiple of 8
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
     hipLaunchKernelGGL((k_bmm_i8_big<Emit>), dim3(grid_x(blocks, kBig)), dim3(kBig), 2 * kStageBytes, c.stream, A,
@@ -402,7 +411,7 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
         kchunk = std::max<int64_t>(1024, ceil_div(ceil_div(ld, want), BK) * BK);
     }
     const int64_t nchunks = ceil_div(ld, kchunk);
-    const int64_t total = tiles * nchunks;
+    const int64_t total = xcd_padded(tiles * nchunks);
     constexpr int64_t kMaxGrid = 1ll << 22;  // items beyond this are looped over (multiple of 8)
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
     if (nchunks == 1) {
@@ -466,9 +475,11 @@ __global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__
     const int tid = threadIdx.x, lane = lane_id();
     const int ty = tid / 16, tx = tid % 16;
     const int64_t total = tiles_m * tiles_n;
-    for (int64_t bid = blockIdx.x; bid < total; bid += gridDim.x) {
+    for (int64_t bid = blockIdx.x; bid < xcd_padded(total); bid += gridDim.x) {
+        const int64_t item = xcd_item(bid, total);
+        if (item < 0) continue;  // padding (uniform per workgroup)
         int64_t tm, tn;
-        tile_of_block(bid, tiles_m, tiles_n, &tm, &tn);
+        tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
         const int64_t row0 = tm * PB, col0 = tn * PB;
         uint32_t acc[8][8];
 #pragma unroll
@@ -538,8 +549,8 @@ void launch_bitpop(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, i
     hipLaunchKernelGGL(k_pack_bits, dim3(grid_x(gp, 256)), dim3(256), 0, c.stream, Bt, w, ld, pb.get());
     JP_HIP(hipGetLastError());
     const int64_t tm = ceil_div(u, PB), tn = ceil_div(w, PB);
-    const int64_t total = tm * tn;
-    constexpr int64_t kMaxGrid = 1ll << 22;
+    const int64_t total = xcd_padded(tm * tn);
+    constexpr int64_t kMaxGrid = 1ll << 22;  // multiple of 8
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
     hipLaunchKernelGGL((k_bmm_bitpop<Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream,
                        (const uint64_t *)pa.get(), (const uint64_t *)pb.get(), u, w, nw, tm, tn, emit, cap,

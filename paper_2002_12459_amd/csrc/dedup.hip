@@ -9,13 +9,20 @@
 // units that follow x order:
 //
 //  * small x (at most kUnitCap candidates) are packed into units of at most
-//    kDCap candidates; a medium x (at most kDCap) is a unit of its own.  A unit gathers its candidates as 32-bit keys
-//    (x - first_x) << bz | z, sorts them by LSD radix sort in LDS over the
-//    significant bits only (5-bit digits, per-thread LDS counters, raking
-//    scan), and keeps the first of every run of equal keys.
-//  * a large x (more than kDCap) is cut into z windows; a window unit binary-searches the
-//    window's part of every sorted list, marks it in an LDS bitmap and reads
-//    the set bits back in z order.
+//    kDCap candidates; a medium x (at most kDCap) is a unit of its own.  A
+//    unit gathers its candidates as 32-bit keys (x - first_x) << bz | z,
+//    sorts them by LSD radix sort in LDS over the significant bits only
+//    (5-bit digits, per-thread 16-bit counters updated by LDS atomics that
+//    return the old count, raking scan), and keeps the first of every run of
+//    equal keys.  Unit size is set so four workgroups fit a CU (LDS and
+//    registers): the kernel is bound by memory and LDS latency.
+//  * a large x (more than kDCap) is cut into z windows.  A window unit
+//    binary-searches the window's part of every sorted list and counts the
+//    candidates; if they fit a unit it gathers and sorts them like a packed
+//    unit, else it marks them in an LDS bitmap (kWinBits z values at a time)
+//    and reads the set bits back in z order.  Windows of an x with up to
+//    4 kDCap candidates are sized to fit a unit; larger x get fewer, wider
+//    windows (fewer list searches) that use the bitmap.
 //
 // One kernel handles all units.  A unit writes its distinct keys to a
 // staging array at its candidate offset (an upper bound of its output
@@ -31,26 +38,34 @@ namespace jp {
 namespace {
 
 constexpr int kDT = 256;                 // threads per unit
-constexpr int kDI = 32;                  // keys per thread
-constexpr int kDCap = kDT * kDI;         // keys per unit (LDS 32 KB)
+constexpr int kDI = 20;                  // keys per thread (4 workgroups per CU by LDS and registers)
+constexpr int kDCap = kDT * kDI;         // keys per unit
 constexpr int64_t kUnitCap = kDCap / 2;  // x with more candidates get a unit of their own
 constexpr int64_t kSoloCap = kDCap;      // x with more candidates get window units
 constexpr int kRB = 5;                   // radix digit bits
 constexpr int kRD = 1 << kRB;            // digits
 constexpr int64_t kWinBits = (int64_t)kDCap * 32;  // bitmap window capacity (reuses the key buffer)
-constexpr int64_t kWinTarget = 16384;              // candidates per window unit, aimed for
+constexpr int64_t kWinTarget = 16384;              // candidates per bitmap window unit, aimed for
+constexpr int64_t kWinSort = (3 * kDCap) / 4;      // candidates per sorted window unit, aimed for
 constexpr int kListChunk = kDT;                    // lists handled per round in a window unit
 constexpr int kWinBatch = 4;                       // window candidates per thread with loads in flight
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Windows of a large x: enough to fit the LDS bitmap, about kWinTarget
-// candidates each, at least 64 z values wide.
+// Windows of an x with more than kDCap candidates, at least 64 z values
+// wide.  Up to 4 kDCap candidates: about kWinSort each, so a window usually
+// fits one unit's sort.  More: about kWinTarget each and at least enough to
+// fit the LDS bitmap (fewer, wider windows mean fewer list searches).
 __host__ __device__ inline int64_t windows_of(int64_t tx, int64_t dom_z) {
-    const int64_t lo = cdiv(dom_z, kWinBits);
-    const int64_t hi = cdiv(dom_z, 64) > lo ? cdiv(dom_z, 64) : lo;
-    int64_t want = cdiv(tx, kWinTarget);
-    if (want < lo) want = lo;
+    const int64_t hi = cdiv(dom_z, 64) > 1 ? cdiv(dom_z, 64) : 1;
+    int64_t want;
+    if (tx <= 4 * kDCap) {
+        want = cdiv(tx, kWinSort);
+    } else {
+        want = cdiv(tx, kWinTarget);
+        const int64_t lo = cdiv(dom_z, kWinBits);
+        if (want < lo) want = lo;
+    }
     if (want > hi) want = hi;
     return want < 1 ? 1 : want;
 }
@@ -109,7 +124,92 @@ __device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
     return reinterpret_cast<uint16_t *>(cnt)[2 * cpad(ci >> 1) + (ci & 1)];
 }
 
-__global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
+// Sorts the nn keys in k[] (thread t's slot j holds key t*kDI + j of the
+// current order, valid below nn) on their low B bits by LSD radix sort in
+// LDS: 5-bit digits, per-thread 16-bit counters updated by LDS atomics,
+// raking scan.  Leaves the distinct keys in sk[kpad(0 .. result)), in order.
+__device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int B, uint32_t *sk, uint32_t *cnt,
+                                                uint32_t *lds_scan, PhaseClock &pc) {
+const int tid = threadIdx.x;
+const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = pass * kRB;
+        for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
+        __syncthreads();
+        // count with LDS atomics that return the old value: the updates of
+        // one thread issue back to back instead of as dependent
+        // read-modify-writes (a thread's counter stays below 2^16)
+        uint16_t loc[kDI];
+#pragma unroll
+        for (int j = 0; j < kDI; ++j) {
+            const int p = tid * kDI + j;
+            const int d = (int)((k[j] >> shift) & (kRD - 1));
+            const int ci = d * kDT + tid;
+            const int sh = 16 * (ci & 1);
+            const uint32_t old = atomicAdd(&cnt[cpad(ci >> 1)], (p < nn ? 1u : 0u) << sh);
+            loc[j] = (uint16_t)(old >> sh);
+        }
+        __syncthreads();
+        // raking exclusive scan over [digit][thread]: thread t owns `per`
+        // consecutive counter words (two 16-bit counters each)
+        constexpr int per = kCntWords / kDT;
+        uint32_t s = 0;
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const uint32_t wv = cnt[cpad(tid * per + i)];
+            s += (wv & 0xffffu) + (wv >> 16);
+        }
+        uint32_t all;
+        uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
+#pragma unroll
+        for (int i = 0; i < per; ++i) {
+            const int wi = cpad(tid * per + i);
+            const uint32_t wv = cnt[wi];
+            const uint32_t lo = wv & 0xffffu, hi = wv >> 16;
+            const uint32_t q0 = run, q1 = run + lo;
+            run += lo + hi;
+            cnt[wi] = (q0 & 0xffffu) | (q1 << 16);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kDI; ++j) {
+            const int p = tid * kDI + j;
+            if (p < nn) {
+                const int d = (int)((k[j] >> shift) & (kRD - 1));
+                const uint32_t dst = (uint32_t)ctr(cnt, d, tid) + loc[j];
+                sk[kpad(dst < (uint32_t)kDCap ? (int)dst : 0)] = k[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kDI; ++j) {
+            const int p = tid * kDI + j;
+            k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
+        }
+        __syncthreads();
+    }
+    pc.mark(kPhSort);
+    // first of every run of equal keys, compacted into sk in order
+    uint32_t flags = 0, mine = 0;
+    uint32_t prev = (tid > 0 && tid * kDI - 1 < nn) ? sk[kpad(tid * kDI - 1)] : 0u;
+#pragma unroll
+    for (int j = 0; j < kDI; ++j) {
+        const int p = tid * kDI + j;
+        const bool f = (p < nn) & ((p == 0) | (k[j] != prev));
+        flags |= (uint32_t)f << j;
+        mine += f ? 1u : 0u;
+        prev = k[j];
+    }
+    uint32_t d_all;
+    uint32_t pos = block_excl_scan<kDT>(mine, lds_scan, &d_all);
+#pragma unroll
+    for (int j = 0; j < kDI; ++j)
+        if ((flags >> j) & 1u) sk[kpad((int)pos++)] = k[j];
+    __syncthreads();
+    return d_all;
+}
+
+__global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroups per CU: at most 128 VGPRs
     __shared__ uint32_t sk[kSkWords];     // keys, then distinct keys; or the window bitmap
     __shared__ __attribute__((aligned(8))) uint32_t cnt[kCntPadded];  // digit counters; before that, staged tuples
     __shared__ uint32_t lds_scan[kDT / kWave + 1];
@@ -200,84 +300,8 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
         __syncthreads();  // staged tuple data is overwritten by the counters below
         pc.mark(kPhGather);
 
-        // LSD radix sort: 5-bit digits over the significant bits
         const int xbits = (xb - xa - 1) > 0 ? 32 - __clz((uint32_t)(xb - xa - 1)) : 0;
-        const int B = xbits + a.bz > 0 ? xbits + a.bz : 1;
-        const int passes = (B + kRB - 1) / kRB;
-        for (int pass = 0; pass < passes; ++pass) {
-            const int shift = pass * kRB;
-            for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
-            __syncthreads();
-            // count with LDS atomics that return the old value: the updates of
-            // one thread issue back to back instead of as dependent
-            // read-modify-writes (a thread's counter stays below 2^16)
-            uint16_t loc[kDI];
-#pragma unroll
-            for (int j = 0; j < kDI; ++j) {
-                const int p = tid * kDI + j;
-                const int d = (int)((k[j] >> shift) & (kRD - 1));
-                const int ci = d * kDT + tid;
-                const int sh = 16 * (ci & 1);
-                const uint32_t old = atomicAdd(&cnt[cpad(ci >> 1)], (p < nn ? 1u : 0u) << sh);
-                loc[j] = (uint16_t)(old >> sh);
-            }
-            __syncthreads();
-            // raking exclusive scan over [digit][thread]: thread t owns `per`
-            // consecutive counter words (two 16-bit counters each)
-            constexpr int per = kCntWords / kDT;
-            uint32_t s = 0;
-#pragma unroll
-            for (int i = 0; i < per; ++i) {
-                const uint32_t wv = cnt[cpad(tid * per + i)];
-                s += (wv & 0xffffu) + (wv >> 16);
-            }
-            uint32_t all;
-            uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
-#pragma unroll
-            for (int i = 0; i < per; ++i) {
-                const int wi = cpad(tid * per + i);
-                const uint32_t wv = cnt[wi];
-                const uint32_t lo = wv & 0xffffu, hi = wv >> 16;
-                const uint32_t q0 = run, q1 = run + lo;
-                run += lo + hi;
-                cnt[wi] = (q0 & 0xffffu) | (q1 << 16);
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kDI; ++j) {
-                const int p = tid * kDI + j;
-                if (p < nn) {
-                    const int d = (int)((k[j] >> shift) & (kRD - 1));
-                    const uint32_t dst = (uint32_t)ctr(cnt, d, tid) + loc[j];
-                    sk[kpad(dst < (uint32_t)kDCap ? (int)dst : 0)] = k[j];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kDI; ++j) {
-                const int p = tid * kDI + j;
-                k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
-            }
-            __syncthreads();
-        }
-        pc.mark(kPhSort);
-        // first of every run of equal keys, compacted into sk in order
-        uint32_t flags = 0, mine = 0;
-        uint32_t prev = (tid > 0 && tid * kDI - 1 < nn) ? sk[kpad(tid * kDI - 1)] : 0u;
-#pragma unroll
-        for (int j = 0; j < kDI; ++j) {
-            const int p = tid * kDI + j;
-            const bool f = (p < nn) & ((p == 0) | (k[j] != prev));
-            flags |= (uint32_t)f << j;
-            mine += f ? 1u : 0u;
-            prev = k[j];
-        }
-        uint32_t d_all;
-        uint32_t pos = block_excl_scan<kDT>(mine, lds_scan, &d_all);
-#pragma unroll
-        for (int j = 0; j < kDI; ++j)
-            if ((flags >> j) & 1u) sk[kpad((int)pos++)] = k[j];
-        __syncthreads();
+        const uint32_t d_all = sort_unique(k, nn, xbits + a.bz, sk, cnt, lds_scan, pc);
         pc.mark(kPhUnique);
         const int64_t base = a.toff[xa];
         for (uint32_t i = tid; i < d_all; i += kDT) a.stage[base + i] = sk[kpad((int)i)];
@@ -297,87 +321,154 @@ __global__ __launch_bounds__(kDT) void k_dedup(DedupArgs a) {
     const int64_t ws = cdiv(a.dom_z, nw);
     const int64_t zlo = (int64_t)win * ws;
     const int64_t zhi = zlo + ws < a.dom_z ? zlo + ws : a.dom_z;
-    const int64_t wbits = zhi > zlo ? zhi - zlo : 0;  // <= kWinBits
-    const int nwords = (int)cdiv(wbits, 32);
-    for (int i = tid; i < nwords; i += kDT) sk[i] = 0;
     int64_t *lpre = reinterpret_cast<int64_t *>(cnt);  // kListChunk + 1
     int64_t *lbeg = lpre + kListChunk + 1;             // kListChunk
-    __syncthreads();
     const int64_t e0 = a.off_x[x], e1 = a.off_x[x + 1];
-    // lists of x in chunks of kListChunk; the heavy nonzeros of x are one more
-    // list.  `before` counts the candidates of x below zlo (stage offset).
+    // The lists of x, in chunks of kListChunk, plus the heavy nonzeros of x as
+    // one more list.  list_range(l, lo, hi): start (negative: heavy keys at
+    // -1 - start) and length of list l's part in [lo, hi), and how many of
+    // its entries lie below lo.
     const int64_t nlists = (e1 - e0) + 1;
-    int64_t before = 0;
-    for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
-        int64_t b = 0, len = 0, skipped = 0;
-        const int64_t l = l0 + tid;
-        if (l < nlists) {
-            if (l < e1 - e0) {
-                const int64_t e = e0 + l;
-                const int64_t lb = a.lbase[e];
-                const int64_t ln = a.eoff[e + 1] - a.eoff[e];
-                const int32_t *L = a.zlist + lb;
-                const int64_t s0 = lower_bound_dev(L, (int64_t)0, ln, (int32_t)zlo);
-                const int64_t s1 = lower_bound_dev(L, s0, ln, (int32_t)zhi);
-                b = lb + s0;
-                len = s1 - s0;
-                skipped = s0;
-            } else {
-                const int64_t h0 = a.hoff[x], h1 = a.hoff[x + 1];
-                const uint64_t kx = (uint64_t)x << a.bz;
-                const int64_t s0 = lower_bound_dev(a.hkeys, h0, h1, kx | (uint64_t)zlo);
-                const int64_t s1 = lower_bound_dev(a.hkeys, s0, h1, kx | (uint64_t)zhi);
-                b = -1 - s0;  // negative: heavy keys starting at s0
-                len = s1 - s0;
-                skipped = s0 - h0;
-            }
+    auto list_range = [&](int64_t l, int64_t lo, int64_t hi, int64_t &b, int64_t &len, int64_t &below) {
+        b = 0;
+        len = 0;
+        below = 0;
+        if (l >= nlists) return;
+        if (l < e1 - e0) {
+            const int64_t e = e0 + l;
+            const int64_t lb = a.lbase[e];
+            const int64_t ln = a.eoff[e + 1] - a.eoff[e];
+            const int32_t *L = a.zlist + lb;
+            const int64_t s0 = lower_bound_dev(L, (int64_t)0, ln, (int32_t)lo);
+            const int64_t s1 = lower_bound_dev(L, s0, ln, (int32_t)hi);
+            b = lb + s0;
+            len = s1 - s0;
+            below = s0;
+        } else {
+            const int64_t h0 = a.hoff[x], h1 = a.hoff[x + 1];
+            const uint64_t kx = (uint64_t)x << a.bz;
+            const int64_t s0 = lower_bound_dev(a.hkeys, h0, h1, kx | (uint64_t)lo);
+            const int64_t s1 = lower_bound_dev(a.hkeys, s0, h1, kx | (uint64_t)hi);
+            b = -1 - s0;
+            len = s1 - s0;
+            below = s0 - h0;
         }
-        int64_t tot, sk_tot;
-        (void)block_excl_scan<kDT>(skipped, lds_scan64, &sk_tot);
-        before += sk_tot;
+    };
+    // fills lpre / lbeg for lists [l0, l0 + kListChunk) over [lo, hi); returns the chunk's candidates
+    auto load_chunk = [&](int64_t l0, int64_t lo, int64_t hi) -> int64_t {
+        int64_t b, len, below, tot;
+        list_range(l0 + tid, lo, hi, b, len, below);
         const int64_t pre = block_excl_scan<kDT>(len, lds_scan64, &tot);
         lpre[tid] = pre;
         lbeg[tid] = b;
         if (tid == 0) lpre[kListChunk] = tot;
         __syncthreads();
-        const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
-        // kWinBatch candidates per thread per round: searches, then loads, then bits
-        for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
-            int64_t z[kWinBatch];
-#pragma unroll
-            for (int r = 0; r < kWinBatch; ++r) {
-                const int64_t q = q0 + (int64_t)r * kDT;
-                const int64_t p = q < tot ? q : q0;
-                const int64_t li = upper_bound_dev(lpre, (int64_t)0, nl, p) - 1;
-                const int64_t bb = lbeg[li];
-                const int64_t off = p - lpre[li];
-                z[r] = bb >= 0 ? (int64_t)a.zlist[bb + off] : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
-            }
-#pragma unroll
-            for (int r = 0; r < kWinBatch; ++r) {
-                const int64_t zr = z[r] - zlo;
-                if ((q0 + (int64_t)r * kDT < tot) & (zr >= 0) & (zr < wbits)) atomicOr(&sk[zr >> 5], 1u << (zr & 31));
-            }
-        }
-        __syncthreads();
+        return tot;
+    };
+    // z of candidate q of the loaded chunk (nl lists)
+    auto chunk_z = [&](int64_t q, int64_t nl) -> int64_t {
+        const int64_t li = upper_bound_dev(lpre, (int64_t)0, nl, q) - 1;
+        const int64_t bb = lbeg[li];
+        const int64_t off = q - lpre[li];
+        return bb >= 0 ? (int64_t)a.zlist[bb + off] : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
+    };
+
+    // count the window's candidates and those of x below it (stage offset)
+    int64_t before = 0, total = 0;
+    for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
+        int64_t b, len, below, t1, t2;
+        list_range(l0 + tid, zlo, zhi, b, len, below);
+        (void)block_excl_scan<kDT>(below, lds_scan64, &t1);
+        (void)block_excl_scan<kDT>(len, lds_scan64, &t2);
+        before += t1;
+        total += t2;
     }
-    pc.mark(kPhLists);
-    // set bits in z order: thread t owns a contiguous run of words
-    const int per = (nwords + kDT - 1) / kDT;
-    const int w0 = tid * per;
-    const int w1 = w0 + per < nwords ? w0 + per : nwords;
-    uint32_t c = 0;
-    for (int i = w0; i < w1; ++i) c += __popc(sk[i]);
-    uint32_t d_all;
-    uint32_t pos = block_excl_scan<kDT>(c, lds_scan, &d_all);
     const int64_t base = a.toff[x] + before;
-    for (int i = w0; i < w1; ++i) {
-        uint32_t word = sk[i];
-        while (word) {
-            const int bit = __ffs(word) - 1;
-            word &= word - 1;
-            a.stage[base + pos] = (uint32_t)(zlo + (int64_t)i * 32 + bit);  // the unit's x: local 0
-            ++pos;
+    uint32_t d_all = 0;
+    if (total <= kDCap) {
+        // few enough to sort: gather z - zlo into the key buffer, then registers
+        int64_t off = 0;
+        for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
+            const int64_t tot = load_chunk(l0, zlo, zhi);
+            const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
+            for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
+                int64_t z[kWinBatch];
+#pragma unroll
+                for (int r = 0; r < kWinBatch; ++r) {
+                    const int64_t q = q0 + (int64_t)r * kDT;
+                    z[r] = chunk_z(q < tot ? q : q0, nl);
+                }
+#pragma unroll
+                for (int r = 0; r < kWinBatch; ++r) {
+                    const int64_t q = q0 + (int64_t)r * kDT;
+                    const int64_t dst = off + q;
+                    if ((q < tot) & (dst < kDCap)) sk[kpad((int)dst)] = (uint32_t)(z[r] - zlo);
+                }
+            }
+            off += tot;
+            __syncthreads();  // lpre / lbeg are refilled by the next chunk
+        }
+        pc.mark(kPhLists);
+        const int nn = (int)total;
+        uint32_t k[kDI];
+#pragma unroll
+        for (int j = 0; j < kDI; ++j) {
+            const int p = tid * kDI + j;
+            k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
+        }
+        __syncthreads();  // the list tables in the counter space are dead from here
+        const int64_t span = zhi - zlo;
+        const int B = span > 1 ? 64 - __clzll((unsigned long long)(span - 1)) : 1;
+        d_all = sort_unique(k, nn, B, sk, cnt, lds_scan, pc);
+        for (uint32_t i = tid; i < d_all; i += kDT) a.stage[base + i] = (uint32_t)(zlo + sk[kpad((int)i)]);  // local x 0
+    } else {
+        // bitmap of kWinBits z values at a time, set bits read back in z order
+        for (int64_t s0 = zlo; s0 < zhi; s0 += kWinBits) {
+            const int64_t s1 = s0 + kWinBits < zhi ? s0 + kWinBits : zhi;
+            const int64_t wbits = s1 - s0;
+            const int nwords = (int)cdiv(wbits, 32);
+            for (int i = tid; i < nwords; i += kDT) sk[i] = 0;
+            __syncthreads();
+            for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
+                const int64_t tot = load_chunk(l0, s0, s1);
+                const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
+                // kWinBatch candidates per thread per round: searches, then loads, then bits
+                for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
+                    int64_t z[kWinBatch];
+#pragma unroll
+                    for (int r = 0; r < kWinBatch; ++r) {
+                        const int64_t q = q0 + (int64_t)r * kDT;
+                        z[r] = chunk_z(q < tot ? q : q0, nl);
+                    }
+#pragma unroll
+                    for (int r = 0; r < kWinBatch; ++r) {
+                        const int64_t zr = z[r] - s0;
+                        if ((q0 + (int64_t)r * kDT < tot) & (zr >= 0) & (zr < wbits))
+                            atomicOr(&sk[zr >> 5], 1u << (zr & 31));
+                    }
+                }
+                __syncthreads();
+            }
+            pc.mark(kPhLists);
+            // set bits in z order: thread t owns a contiguous run of words
+            const int per = (nwords + kDT - 1) / kDT;
+            const int w0 = tid * per;
+            const int w1 = w0 + per < nwords ? w0 + per : nwords;
+            uint32_t c = 0;
+            for (int i = w0; i < w1; ++i) c += __popc(sk[i]);
+            uint32_t sub;
+            uint32_t pos = d_all + block_excl_scan<kDT>(c, lds_scan, &sub);
+            for (int i = w0; i < w1; ++i) {
+                uint32_t word = sk[i];
+                while (word) {
+                    const int bit = __ffs(word) - 1;
+                    word &= word - 1;
+                    a.stage[base + pos] = (uint32_t)(s0 + (int64_t)i * 32 + bit);  // local x 0
+                    ++pos;
+                }
+            }
+            d_all += sub;
+            __syncthreads();  // the bitmap is cleared again for the next range
         }
     }
     if (tid == 0) {

@@ -203,12 +203,14 @@ def test_spaced_z_ids(jp, spacing):
 
 def test_dedup_unit_class_boundaries(jp):
     """x values whose candidate counts (cnt + cnt // 2 here) sit on both sides
-    of the per-x class limits of the duplicate removal (up to 4096: packed
-    with other x; up to 8192: a unit of its own; more: z windows marked in an
-    LDS bitmap), interleaved, with duplicates inside every x."""
+    of the per-x class limits of the duplicate removal (up to 2560: packed
+    with other x; up to 5120: a unit of its own; up to 20480: z windows
+    sized to fit a unit's sort; more: bitmap windows), plus counts around
+    4096, 8192 and 32768, interleaved, with duplicates inside every x."""
     rng = np.random.default_rng(11)
-    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 1365, 1366, 2730,
-              2731, 2732, 4095, 4096, 4097, 5461, 5462, 9000, 21845, 21846, 3, 700, 512, 5461, 2731, 1366, 512, 2]
+    counts = [1, 2, 63, 64, 65, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 1706, 1707, 1708,
+              2730, 2731, 2732, 3413, 3414, 4095, 4096, 4097, 5461, 5462, 9000, 13653, 13654, 21845, 21846,
+              3, 700, 512, 5461, 2731, 1707, 3414, 512, 2]
     rx, ry, sz, sy = [], [], [], []
     nz = 40000
     for i, cnt in enumerate(counts):
