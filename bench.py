@@ -12,7 +12,10 @@ output in HBM).
 A second leg measures the batched mode on the serving-style set: 512
 independent two-path instances, edge counts log-uniform in [1K, 1M], Zipf
 exponent U[0.6, 1.6], evaluated in one call; it is reported under "batched"
-next to the time of the same instances evaluated one call each.
+next to the time of the same instances evaluated one call each.  Further
+legs: the star query over three 2M-edge Zipf(1.3) relations ("star"), and a
+dense-core self-join of 8 communities ("dense_core"), where the cost model
+sends most witnesses to the matrix product.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 Prints one JSON line.
@@ -63,6 +66,8 @@ def parse():
     p.add_argument("--cpu-sample", type=float, default=0.3, help="fraction of x ids in the oracle sample")
     p.add_argument("--no-batch", action="store_true")
     p.add_argument("--batch-instances", type=int, default=512)
+    p.add_argument("--no-star", action="store_true")
+    p.add_argument("--no-dense", action="store_true")
     return p.parse_args()
 
 
@@ -107,6 +112,64 @@ def batched_leg(h, insts, steps, warmup):
             "ms_per_step": dt * 1e3, "pairs_per_s": n / dt, "instances_per_s": len(insts) / dt,
             "delta1": st["delta1"], "delta2": st["delta2"],
             "per_instance_calls_ms": ds * 1e3, "speedup_vs_per_instance_calls": ds / dt}
+
+
+def star_leg(h, rels, steps):
+    """Star query over three relations: cost-model thresholds, then forced
+    thresholds that give the chained heavy product work."""
+    import torch
+    dev = torch.device("cuda:0")
+    tin = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)) for a, b in rels]
+    h.star_result(tin).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = h.star_result(tin)
+        n, st = r.n, r.stats
+        r.free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "star k=3: 3 relations of 2M distinct edges, 500K x ids, 100K y ids, Zipf(1.3) y "
+                       "(independent y-rank permutations), cost-model thresholds",
+           "n_out": n, "J": st["J"], "ms_per_step": dt * 1e3, "tuples_per_s": n / dt,
+           "delta1": st["delta1"], "delta2": st["delta2"]}
+    d1, d2 = 20, 4  # after dangling tuples go: 119 y heavy in two relations, 13.5K / 3.4K / 0.5K heavy x
+    h.star_result(tin, delta1=d1, delta2=d2).free()
+    r = h.star_result(tin, delta1=d1, delta2=d2, timing=True)
+    nf, sf = r.n, r.stats
+    r.free()
+    if nf != n:
+        raise RuntimeError(f"star output size {nf} at forced thresholds differs from {n}")
+    out["forced"] = {"delta1": d1, "delta2": d2, "ms_total": sf["ms_total"], "ms_bmm": sf["ms_bmm"],
+                     "bmm_ops": sf["bmm_ops"],
+                     "tops": sf["bmm_ops"] / (sf["ms_bmm"] * 1e-3) / 1e12 if sf["ms_bmm"] > 0 else None}
+    return out
+
+
+def dense_leg(h, edges, steps):
+    """Dense-core self-join (communities): the case where the product pays."""
+    import torch
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(edges[0]).to(dev)
+    y = torch.from_numpy(edges[1]).to(dev)
+    h.two_path_result(x, y, x, y).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = h.two_path_result(x, y, x, y)
+        n, st = r.n, r.stats
+        r.free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    r = h.two_path_result(x, y, x, y, timing=True)
+    sp = r.stats
+    r.free()
+    return {"workload": f"dense-core self-join: 8 communities of 4096 x ids by 2048 y ids, edge probability 0.25 "
+                        f"({int(x.numel())} edges), cost-model thresholds",
+            "n_out": n, "closed_form_n_out": 8 * 4096 * 4096, "J": st["J"], "ms_per_step": dt * 1e3,
+            "pairs_per_s": n / dt, "delta1": st["delta1"], "delta2": st["delta2"], "u": sp["u"], "v": sp["v"],
+            "w": sp["w"], "ms_bmm": sp["ms_bmm"],
+            "bmm_tops": sp["bmm_ops"] / (sp["ms_bmm"] * 1e-3) / 1e12 if sp["ms_bmm"] > 0 else None}
 
 
 def main():
@@ -209,6 +272,27 @@ def main():
             f"{batched['pairs_per_s']:.3g} pairs/s; one call per instance: {batched['per_instance_calls_ms']:.1f} ms")
         del insts
 
+    star = None
+    if not a.no_star:
+        t0 = time.time()
+        rels = datagen.star_c3(a.scale)
+        log(f"star input generated in {time.time() - t0:.1f}s")
+        star = star_leg(h, rels, max(1, min(a.steps, 3)))
+        log(f"star: {star['ms_per_step']:.2f} ms/step, |OUT|={star['n_out']} (d1={star['delta1']} d2={star['delta2']}); "
+            f"forced product {star['forced']['ms_bmm']:.2f} ms, {star['forced']['tops'] or 0:.1f} TOP/s")
+        del rels
+
+    dense = None
+    if not a.no_dense and a.scale == 1.0:
+        t0 = time.time()
+        edges = datagen.communities(8, 4096, 2048, 0.25, seed=7)
+        log(f"dense-core input ({edges[0].size} edges) generated in {time.time() - t0:.1f}s")
+        dense = dense_leg(h, edges, max(1, min(a.steps, 3)))
+        log(f"dense core: {dense['ms_per_step']:.2f} ms/step, |OUT|={dense['n_out']} (closed form "
+            f"{dense['closed_form_n_out']}), d1={dense['delta1']} d2={dense['delta2']} u={dense['u']} v={dense['v']} "
+            f"w={dense['w']}, product {dense['ms_bmm']:.2f} ms")
+        del edges
+
     # CPU oracle on a bounded sample of the same workload: R restricted to an
     # x-id range (its outputs are exactly the outputs with x in that range)
     cpu = None
@@ -245,6 +329,8 @@ def main():
         "heavy_bmm": bmm,
         "batched": batched,
         "selector": selector,
+        "star": star,
+        "dense_core": dense,
         "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
     }
     print(json.dumps(out), flush=True)

@@ -49,6 +49,7 @@ constexpr int64_t kWinTarget = 16384;              // candidates per bitmap wind
 constexpr int64_t kWinSort = (3 * kDCap) / 4;      // candidates per sorted window unit, aimed for
 constexpr int kListChunk = kDT;                    // lists handled per round in a window unit
 constexpr int kWinBatch = 4;                       // window candidates per thread with loads in flight
+constexpr int kWriteBatch = 4;                     // distinct keys per thread read from LDS before storing
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -70,7 +71,17 @@ __host__ __device__ inline int64_t windows_of(int64_t tx, int64_t dom_z) {
     return want < 1 ? 1 : want;
 }
 
+// Where a packed unit's candidates are, computed ahead by a setup kernel so
+// the unit starts with one load instead of a chain of dependent ones.
+struct UnitDesc {
+    int64_t e0, e1;  // R tuples of the unit's x range
+    int64_t c0;      // light candidates before tuple e0
+    int64_t h0;      // heavy nonzeros before the unit's first x
+    int64_t nL, n;   // light candidates, all candidates
+};
+
 struct DedupArgs {
+    const UnitDesc *udesc;   // per unit (packed units only)
     const int32_t *ustart;   // x of every unit (first x for packed units); ustart[n_units] = dom_x
     const int32_t *uwin;     // window index of a window unit, -1 for a packed unit
     int64_t n_units;
@@ -224,11 +235,8 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
     if (win < 0) {
         // ------------------------------------------------------------ packed unit
         const int32_t xb = a.ustart[u + 1];
-        const int64_t e0 = a.off_x[xa], e1 = a.off_x[xb];
-        const int64_t c0 = a.eoff[e0];
-        const int64_t nL = a.eoff[e1] - c0;
-        const int64_t h0 = a.hoff[xa];
-        const int64_t n = nL + (a.hoff[xb] - h0);
+        const UnitDesc ud = a.udesc[u];
+        const int64_t e0 = ud.e0, e1 = ud.e1, c0 = ud.c0, nL = ud.nL, h0 = ud.h0, n = ud.n;
         const bool over = n > kDCap;
         if (over && tid == 0) *a.err = 1;
         const int nn = over ? 0 : (int)n;
@@ -304,7 +312,17 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         const uint32_t d_all = sort_unique(k, nn, xbits + a.bz, sk, cnt, lds_scan, pc);
         pc.mark(kPhUnique);
         const int64_t base = a.toff[xa];
-        for (uint32_t i = tid; i < d_all; i += kDT) a.stage[base + i] = sk[kpad((int)i)];
+        for (uint32_t i0 = tid; i0 < d_all; i0 += kDT * kWriteBatch) {  // LDS reads, then stores
+            uint32_t v[kWriteBatch];
+#pragma unroll
+            for (int r = 0; r < kWriteBatch; ++r) {
+                const uint32_t i = i0 + r * kDT;
+                v[r] = sk[kpad((int)(i < d_all ? i : i0))];
+            }
+#pragma unroll
+            for (int r = 0; r < kWriteBatch; ++r)
+                if (i0 + r * kDT < d_all) a.stage[base + i0 + r * kDT] = v[r];
+        }
         if (tid == 0) {
             a.ucount[u] = d_all;
             a.ubase[u] = base;
@@ -420,7 +438,17 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         const int64_t span = zhi - zlo;
         const int B = span > 1 ? 64 - __clzll((unsigned long long)(span - 1)) : 1;
         d_all = sort_unique(k, nn, B, sk, cnt, lds_scan, pc);
-        for (uint32_t i = tid; i < d_all; i += kDT) a.stage[base + i] = (uint32_t)(zlo + sk[kpad((int)i)]);  // local x 0
+        for (uint32_t i0 = tid; i0 < d_all; i0 += kDT * kWriteBatch) {  // local x 0
+            uint32_t v[kWriteBatch];
+#pragma unroll
+            for (int r = 0; r < kWriteBatch; ++r) {
+                const uint32_t i = i0 + r * kDT;
+                v[r] = sk[kpad((int)(i < d_all ? i : i0))];
+            }
+#pragma unroll
+            for (int r = 0; r < kWriteBatch; ++r)
+                if (i0 + r * kDT < d_all) a.stage[base + i0 + r * kDT] = (uint32_t)(zlo + v[r]);
+        }
     } else {
         // bitmap of kWinBits z values at a time, set bits read back in z order
         for (int64_t s0 = zlo; s0 < zhi; s0 += kWinBits) {
@@ -616,6 +644,25 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             uw[nun] = -1;
         });
     }
+    DBuf<UnitDesc> udesc = c.buf<UnitDesc>(n_units + 1);
+    {
+        const int32_t *us = ustart.get(), *uw = uwin.get();
+        const int64_t *ox = in.off_x, *eo = in.eoff, *ho = hoff.get();
+        UnitDesc *ud = udesc.get();
+        for_each(c, n_units, [=] __device__(int64_t u) {
+            UnitDesc d{0, 0, 0, 0, 0, 0};
+            if (uw[u] < 0) {
+                const int32_t xa = us[u], xb = us[u + 1];
+                d.e0 = ox[xa];
+                d.e1 = ox[xb];
+                d.c0 = eo[d.e0];
+                d.nL = eo[d.e1] - d.c0;
+                d.h0 = ho[xa];
+                d.n = d.nL + (ho[xb] - d.h0);
+            }
+            ud[u] = d;
+        });
+    }
     dump(c, "ustart", ustart.get(), n_units + 1);
     dump(c, "uwin", uwin.get(), n_units + 1);
 
@@ -624,6 +671,7 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
     if (n_units > 0) {
         JP_CHECK(n_units < (1ll << 31), JP_EINVAL, "too many dedup units for one launch");
         DedupArgs a;
+        a.udesc = udesc.get();
         a.ustart = ustart.get();
         a.uwin = uwin.get();
         a.n_units = n_units;

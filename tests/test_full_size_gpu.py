@@ -79,7 +79,7 @@ def c3():
     return datagen.star_c3(1.0)
 
 
-@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 2000, "delta2": 8}])
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 20, "delta2": 4}])
 def test_star_3x2m(jp, c3, kw):
     rels = c3
     h = jp.default_handle(0)
@@ -94,13 +94,15 @@ def test_star_3x2m(jp, c3, kw):
     got = rows_with(cols, 0, xs)
     for i in range(3):
         np.testing.assert_array_equal(got[i], exp[:, i])
+    if kw.get("strategy") == "fixed":  # the chained product runs (119 heavy y; 13.5K, 3.4K, 0.5K heavy x)
+        assert st["v"] > 0 and st["u"] > 0 and st["w"] > 0
 
 
 def test_star_sizes_agree_across_thresholds(jp, c3):
     rels = c3
     h = jp.default_handle(0)
     sizes = set()
-    for kw in ({}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 2000, "delta2": 8}):
+    for kw in ({}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 20, "delta2": 4}):
         r = h.star_result([(dev(a), dev(b)) for a, b in rels], **kw)
         sizes.add(r.n)
         r.free()
