@@ -123,7 +123,7 @@ jp_status jp_create(jp_handle **out, int device) {
         int prev = -1;
         (void)hipGetDevice(&prev);
         if (prev != device) (void)hipSetDevice(device);
-        h->pinned = std::make_unique<jp::PinnedScratch>(4096);
+        h->pinned = std::make_unique<jp::PinnedScratch>(1 << 20);
         if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
     }
     jp::default_calibration(&h->cal);

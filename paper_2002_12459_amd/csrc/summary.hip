@@ -146,6 +146,19 @@ __global__ __launch_bounds__(kHistBlock) void k_index_fold(IndexArgs a) {
     a.sums[k * kHist + b] = sm;
 }
 
+// Sizes and data of the index read-back in one block of 64-bit words:
+// [count, nbig, count records of 3 words, nbig pairs], written to mapped host
+// memory when it fits in cap words and nbig is within the list's capacity
+// (else only the two sizes).
+__global__ __launch_bounds__(256) void k_index_to_host(const int64_t *sizes, const int64_t *rec, const int64_t *big,
+                                                       int64_t big_cap, int64_t cap, int64_t *dst) {
+    const int64_t n_rec = 3 * sizes[0], n_big = 2 * sizes[1];
+    const int64_t total = 2 + n_rec + n_big;
+    const int64_t n = (total <= cap) & (sizes[1] <= big_cap) ? total : 2;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = i < 2 ? sizes[i] : (i < 2 + n_rec ? rec[i - 2] : big[i - 2 - n_rec]);
+}
+
 }  // namespace
 
 void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummary &s) {
@@ -203,13 +216,37 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
             },
             S.get());
     }
+    // sizes and, when they fit the handle's mapped host buffer, the data too: one wait
     int64_t hn[2];
-    c.load_n(hn, S.get(), 2);
-    JP_CHECK(hn[1] <= a.big_cap, JP_EINTERNAL, "degree index overflow list exceeds its bound");
-    std::vector<int64_t> r(3 * hn[0]), e(2 * hn[1]);
-    if (hn[0]) JP_HIP(hipMemcpyAsync(r.data(), rec.get(), r.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-    if (hn[1]) JP_HIP(hipMemcpyAsync(e.data(), big.get(), e.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
-    c.sync();
+    std::vector<int64_t> r, e;
+    bool fetched = false;
+    if (c.pinned && c.pinned->host && c.pinned->bytes >= 64) {
+        const int64_t cap = (int64_t)(c.pinned->bytes / sizeof(int64_t));
+        hipLaunchKernelGGL(k_index_to_host, dim3(64), dim3(256), 0, c.stream, (const int64_t *)S.get(),
+                           (const int64_t *)rec.get(), (const int64_t *)big.get(), a.big_cap, cap,
+                           (int64_t *)c.pinned->dev);
+        JP_HIP(hipGetLastError());
+        c.sync();
+        const int64_t *h = (const int64_t *)c.pinned->host;
+        hn[0] = h[0];
+        hn[1] = h[1];
+        JP_CHECK(hn[1] <= a.big_cap, JP_EINTERNAL, "degree index overflow list exceeds its bound");
+        if (2 + 3 * hn[0] + 2 * hn[1] <= cap) {
+            r.assign(h + 2, h + 2 + 3 * hn[0]);
+            e.assign(h + 2 + 3 * hn[0], h + 2 + 3 * hn[0] + 2 * hn[1]);
+            fetched = true;
+        }
+    } else {
+        c.load_n(hn, S.get(), 2);
+        JP_CHECK(hn[1] <= a.big_cap, JP_EINTERNAL, "degree index overflow list exceeds its bound");
+    }
+    if (!fetched) {
+        r.resize(3 * hn[0]);
+        e.resize(2 * hn[1]);
+        if (hn[0]) JP_HIP(hipMemcpyAsync(r.data(), rec.get(), r.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        if (hn[1]) JP_HIP(hipMemcpyAsync(e.data(), big.get(), e.size() * sizeof(int64_t), hipMemcpyDeviceToHost, c.stream));
+        c.sync();
+    }
 
     for (int64_t i = 0; i < hn[0]; ++i) {
         const int64_t b = r[3 * i];
