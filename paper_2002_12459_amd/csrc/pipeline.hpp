@@ -119,6 +119,7 @@ struct Ingest {
     int64_t x_dense_base = INT64_MIN, z_dense_base = INT64_MIN;  // see SegDedupIn
     int64_t zmin = 0, zspan = 0;                                  // range of the z ids kept
     DBuf<int32_t> r_xr, adj_r, adj_s, s2_y, dRy, dSz, xorig, zorig;
+    DBuf<uint32_t> s2_zoff;  // z - zmin of every kept S tuple, in adj_s order
     DBuf<int64_t> off_x, off_y;
 };
 

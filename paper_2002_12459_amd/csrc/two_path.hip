@@ -477,7 +477,6 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         }
     }
     ZS.reset();
-    s2_z.reset();
     // ---- degrees (run lengths of the sorts above) and the full join size J ------
     DBuf<int32_t> dSz = c.buf<int32_t>(dom_z);
     {
@@ -496,6 +495,7 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     g.r_xr = std::move(r_xr);
     g.adj_r = std::move(adj_r);
     g.adj_s = std::move(adj_s);
+    g.s2_zoff = std::move(s2_z);
     g.s2_y = std::move(s2_y);
     g.dRy = std::move(dRy);
     g.dSz = std::move(dSz);
@@ -648,11 +648,20 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     st.v = v;
     st.w = w;
 
-    // Witness lists.  zlist = N_S(y) for all y (adj_s), then for heavy y the
-    // light-z part of N_S(y) (what a heavy R tuple still meets).
+    // The per-x dedup may key z by its offset from the smallest z id instead
+    // of its rank when the id range is at most a few times the number of
+    // distinct z: the output then needs no rank-to-id lookup per pair, and
+    // the witness lists are built in offsets from the start.
+    const int bzr = bits_for((uint64_t)(dom_z - 1)), bzo = bits_for((uint64_t)(g.zspan - 1));
+    const bool z_off = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
+
+    // Witness lists.  zlist = N_S(y) for all y (adj_s, or the z offsets of
+    // the same tuples), then for heavy y the light-z part of N_S(y) (what a
+    // heavy R tuple still meets).
     DBuf<int64_t> lz_off;
     DBuf<int32_t> zlist_own;
-    const int32_t *zlist = adj_s.get();
+    const int32_t *zfull = z_off ? reinterpret_cast<const int32_t *>(g.s2_zoff.get()) : adj_s.get();
+    const int32_t *zlist = zfull;
     int64_t zlist_n = n_s2;
     if (has_heavy) {
         // One scan over S (y-major) of the "light z at heavy y" flags gives
@@ -663,19 +672,20 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
         zlist_own = c.buf<int32_t>(2 * n_s2);
         int32_t *zl = zlist_own.get();
-        JP_HIP(hipMemcpyAsync(zl, as, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
+        JP_HIP(hipMemcpyAsync(zl, zfull, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
         int32_t *la = zl + n_s2;
         struct LzItem {
-            int32_t h, z;  // heavy index of the tuple's y (-1: light), z rank
+            int32_t h, z;  // heavy index of the tuple's y (-1: light), z as the lists hold it
             bool first;    // first tuple of its y
         };
+        const int32_t *zf = zfull;
         scan_exclusive_v(
             c, n_s2,
             [=] __device__(int64_t e) {
                 const int32_t y = syr[e], z = as[e];
                 const int32_t h = hy[y];
                 const bool first = e == 0 || syr[e - 1] != y;
-                return Sum<LzItem>{(int64_t)((h >= 0) & (hz[z] < 0)), LzItem{h, z, first}};
+                return Sum<LzItem>{(int64_t)((h >= 0) & (hz[z] < 0)), LzItem{h, zf[e], first}};
             },
             [=] __device__(int64_t, int64_t p, const Sum<LzItem> &it) {
                 if (it.add) la[p] = it.v.z;
@@ -750,7 +760,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         const int64_t n_lz = hv[1];
         const int32_t *la = zlist_own.get() + n_s2;
         check_monotone(c, "lz_off", lz_off.get(), v + 1, 0, n_lz);
-        check_range(c, "lz lists", la, n_lz, 0, dom_z);
+        check_range(c, "lz lists", la, n_lz, 0, z_off ? g.zspan : dom_z);
         dump(c, "lz_off", lz_off.get(), v + 1);
         dump(c, "lz lists", la, n_lz);
         zlist_n = n_s2 + n_lz;
@@ -767,11 +777,6 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     const int bx = bits_for((uint64_t)(dom_x - 1));
     const double uw = (double)u * (double)w;
     const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, uw) : 0;
-    // The per-x dedup may key z by its offset from the smallest z id instead
-    // of its rank when the id range is at most a few times the number of
-    // distinct z: the output then needs no rank-to-id lookup per pair.
-    const int bzr = bits_for((uint64_t)(dom_z - 1)), bzo = bits_for((uint64_t)(g.zspan - 1));
-    const bool z_off = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
     const int bz = z_off ? bzo : bzr;
     const bool segmented = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bz);
     int64_t nnz = 0;
@@ -780,16 +785,13 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     if (segmented) {
         // ---- heavy nonzeros, sorted; then per-x dedup fused with enumeration ----------
         st.dedup = JP_DEDUP_SEGMENTED;
-        // z offsets (see above): the witness lists and the heavy columns in offsets
-        DBuf<int32_t> zl_off, zo_of_hz;
+        // z offsets (see above): the witness lists are already in offsets; the
+        // heavy columns are mapped here
+        DBuf<int32_t> zo_of_hz;
         const int32_t *zl_used = zlist, *zcol = z_of_hz.get();
         if (z_off) {
-            const int32_t *zo = zorig.get(), *zl = zlist;
+            const int32_t *zo = zorig.get();
             const int64_t zm = g.zmin;
-            zl_off = c.buf<int32_t>((size_t)std::max<int64_t>(zlist_n, 1));
-            int32_t *zlo = zl_off.get();
-            for_each(c, zlist_n, [=] __device__(int64_t i) { zlo[i] = (int32_t)((int64_t)zo[zl[i]] - zm); });
-            zl_used = zlo;
             if (has_heavy) {
                 zo_of_hz = c.buf<int32_t>((size_t)w);
                 int32_t *zh = zo_of_hz.get();
