@@ -40,8 +40,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
 # profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
 # whose SHA-256 is given (None: not measured for the current source).
-DEDUP_TRAFFIC = {"sha256": "9ee83019e833aa523772f5b57f194a2b7c00fa5c19ad27928193f20d79883873",
-                 "bytes_per_launch": 1866438752}
+DEDUP_TRAFFIC = {"sha256": "f26851efa3ea859ad640e0aa01e787d0d343e57262e238ac752373d587393be3",
+                 "bytes_per_launch": 1846603280}
 
 
 def dedup_traffic():
