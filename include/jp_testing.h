@@ -24,6 +24,15 @@ jp_status jp_test_radix_sort_u128(jp_handle *h, uint64_t *keys, int64_t n, int32
 /* out[i] = in[0] + ... + in[i-1]; *total (host) = sum of all n values. */
 jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, int64_t n, int64_t *total);
 
+/* Single-pass scans and compactions (every pipeline uses them) let a tile
+ * wait for a predecessor tile's published status for at most `ticks` of the
+ * device wall clock (hipDeviceAttributeWallClockRate; default 100 us), after
+ * which the waiting wave computes that tile's sum from the input itself.
+ * ticks = 0 makes every such wait fall back at once, so tests can check the
+ * fallback.  Applies to later calls on h; results are the same at any value.
+ * JP_EINVAL for a null handle or negative ticks. */
+jp_status jp_test_set_lookback_wait(jp_handle *h, int64_t ticks);
+
 /* Keeps the first of every run of equal adjacent keys, in order; *n_out (host). */
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out);
 

@@ -19,6 +19,8 @@ struct jp_handle {
     jp::Selector sel;  // after alloc: its buffer returns to the allocator first
     std::map<uint64_t, int> tune;  // heavy-product kernel per shape class
     std::unique_ptr<jp::PinnedScratch> pinned;  // small read-backs
+    jp::StatusPool status_pool;                 // cleared look-back status words
+    int64_t lookback_wait = 10000;              // device wall-clock ticks (100 us)
 };
 
 namespace {
@@ -46,6 +48,8 @@ jp::Ctx make_ctx(jp_handle *h) {
     c.sel = &h->sel;
     c.tune = &h->tune;
     c.pinned = h->pinned.get();
+    c.status_pool = &h->status_pool;
+    c.lookback_wait = h->lookback_wait;
     return c;
 }
 
@@ -92,6 +96,7 @@ jp_status validate_options(jp_handle *h, const jp_options &o) {
 
 // Used by the test hooks (testing.hip).
 jp::Ctx jp_handle_ctx(jp_handle *h) { return make_ctx(h); }
+void jp_handle_set_lookback_wait(jp_handle *h, int64_t ticks) { h->lookback_wait = ticks; }
 jp_status jp_handle_guard(jp_handle *h, void (*fn)(void *), void *arg) {
     return guarded(h, [&] { fn(arg); });
 }
@@ -130,6 +135,10 @@ jp_status jp_create(jp_handle **out, int device) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         h->num_cus = cus;
+    int clock_khz = 0;  // device wall clock, for the 100 us look-back wait
+    if (hipDeviceGetAttribute(&clock_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && clock_khz > 0)
+        h->lookback_wait = (int64_t)clock_khz / 10;
+    (void)hipGetLastError();
     *out = h.release();
     return JP_OK;
 }

@@ -222,6 +222,16 @@ struct PinnedScratch {
     PinnedScratch &operator=(const PinnedScratch &) = delete;
 };
 
+// Cleared status words for the single-pass look-back kernels of one handle.
+// One block is cleared by one launch and handed out in consecutive pieces,
+// one per pass; when a pass needs more than is left, the whole block is
+// cleared again, ordered on the stream after every pass that used it.
+struct StatusPool {
+    static constexpr size_t kWords = 1u << 16;
+    DBuf<uint64_t> block;
+    size_t used = 0;
+};
+
 // Execution context of one call: device, stream, allocator, chip size.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -240,6 +250,28 @@ struct Ctx {
     }
     void sync() const { JP_HIP(hipStreamSynchronize(stream)); }
     PinnedScratch *pinned = nullptr;  // small read-backs go through it when set
+    StatusPool *status_pool = nullptr;  // handle-owned, see take_status
+    // How long a look-back lane waits for a predecessor tile's status before
+    // computing that tile's sum itself, in ticks of the device wall clock.
+    int64_t lookback_wait = 10000;
+    // `words` cleared 64-bit words from the handle's pool, valid for one
+    // launch on this stream; nullptr when there is no pool or the request is
+    // larger than the pool.
+    uint64_t *take_status(size_t words) const {
+        if (!status_pool || words > StatusPool::kWords) return nullptr;
+        StatusPool &p = *status_pool;
+        if (!p.block.get()) {
+            p.block = buf<uint64_t>(StatusPool::kWords);
+            p.used = StatusPool::kWords;
+        }
+        if (p.used + words > StatusPool::kWords) {
+            zero(p.block.get(), StatusPool::kWords);
+            p.used = 0;
+        }
+        uint64_t *r = p.block.get() + p.used;
+        p.used += words;
+        return r;
+    }
     template <class T>
     T load(const T *dev) const {  // small device-to-host read, waits on the stream
         T v;

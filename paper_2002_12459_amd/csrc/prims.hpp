@@ -33,35 +33,51 @@ void for_each(const Ctx &c, int64_t n, F f) {
 // ---------------------------------------------------------------------------
 // Exclusive scan of int64 values produced by get(i); put(i, prefix) receives
 // the exclusive prefix of element i.  One pass with decoupled look-back:
-// tiles of 4096 elements (each wave scans 1024 consecutive elements in 16
-// coalesced rounds of 64) take ordered tickets, publish their sum, and the
-// first wave of each tile sums its predecessors' published values, 64 at a
-// time, back to the nearest tile whose inclusive prefix is already known.
-// Every predecessor holds an earlier ticket, so it is resident or finished
-// and every wait ends.
+// tile t = blockIdx.x holds 256 threads x IT elements (each wave scans 64*IT
+// consecutive elements in IT coalesced rounds of 64), publishes its sum, and
+// the first wave of each tile sums its predecessors' published values, 64 at
+// a time, back to the nearest tile whose inclusive prefix is already known.
+//
+// Nothing orders the start of workgroups, so a predecessor may not be running
+// yet.  A waiting lane gives up after `wait` ticks of the constant-rate device
+// clock, and the wave then computes that predecessor's sum itself from the
+// input (the summands are pure functions of the index).  Every wait therefore
+// ends under any schedule.  With in-order dispatch the fallback is not taken
+// in practice; tests force it with wait = 0.  (An ordered ticket per tile
+// would also guarantee progress, but its device-scope atomics are serialised,
+// about 11 ns each on MI355X: 31 us of a 10M-element pass.)
 // ---------------------------------------------------------------------------
-constexpr int kTileItems = 16;
 constexpr int kTileBlock = 256;
-constexpr int64_t kTile = kTileItems * kTileBlock;
+constexpr int kScanItems = 16;
+constexpr int64_t kScanTile = (int64_t)kScanItems * kTileBlock;
 
 // status word of a tile: (value << 2) | flag, flag 1 = tile sum, 2 = inclusive prefix
 __device__ __forceinline__ void lb_publish(uint64_t *status, int64_t t, int64_t v, uint64_t flag) {
     __hip_atomic_store(status + t, ((uint64_t)v << 2) | flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Exclusive prefix of tile t >= 1, computed by one whole wave (all lanes get it).
-__device__ __forceinline__ int64_t lb_lookback(uint64_t *status, int64_t t) {
+// Exclusive prefix of tile t >= 1, computed by one whole wave (all lanes get
+// it).  agg(tile) returns a tile's sum to every lane of the wave (whole-wave
+// call).
+template <class Agg>
+__device__ __forceinline__ int64_t lb_lookback(uint64_t *status, int64_t t, int64_t wait, Agg agg) {
     const int lane = lane_id();
     int64_t excl = 0;
+    const int64_t start = wall_clock64();
     for (int64_t top = t - 1;; top -= kWave) {
         const int64_t idx = top - lane;
         uint64_t s = 2;  // before tile 0: inclusive prefix 0
         if (idx >= 0) {
             s = __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            while ((s & 3u) == 0) {
+            while ((s & 3u) == 0 && wall_clock64() - start < wait) {
                 __builtin_amdgcn_s_sleep(1);
                 s = __hip_atomic_load(status + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+        }
+        for (uint64_t missing = ballot((s & 3u) == 0); missing; missing &= missing - 1) {
+            const int l = (int)__ffsll((unsigned long long)missing) - 1;
+            const int64_t a = agg(top - l);
+            if (lane == l) s = ((uint64_t)a << 2) | 1u;
         }
         const uint64_t inc = ballot((s & 3u) == 2);
         const int stop = inc ? (int)(__ffsll((unsigned long long)inc) - 1) : kWave;
@@ -71,16 +87,11 @@ __device__ __forceinline__ int64_t lb_lookback(uint64_t *status, int64_t t) {
     return excl;
 }
 
-// Tile index of this workgroup: an ordered ticket, or blockIdx.x for one tile.
-__device__ __forceinline__ int64_t lb_tile(unsigned *ticket, int64_t *sh) {
-    if (threadIdx.x == 0) *sh = ticket ? (int64_t)atomicAdd(ticket, 1u) : (int64_t)blockIdx.x;
-    __syncthreads();
-    return *sh;
-}
-
-// Wave 0 resolves the tile's exclusive prefix from its sum A; returns it to all threads.
+// Wave 0 resolves the exclusive prefix of tile t from its sum A; returns it
+// to all threads.
+template <class Agg>
 __device__ __forceinline__ int64_t lb_resolve(uint64_t *status, int64_t t, int64_t A, int64_t *sh, int64_t *total,
-                                              int64_t ntiles) {
+                                              int64_t ntiles, int64_t wait, Agg agg) {
     if (threadIdx.x < kWave) {
         int64_t excl = 0;
         if (status) {
@@ -88,7 +99,7 @@ __device__ __forceinline__ int64_t lb_resolve(uint64_t *status, int64_t t, int64
                 if (threadIdx.x == 0) lb_publish(status, 0, A, 2);
             } else {
                 if (threadIdx.x == 0) lb_publish(status, t, A, 1);
-                excl = lb_lookback(status, t);
+                excl = lb_lookback(status, t, wait, agg);
                 if (threadIdx.x == 0) lb_publish(status, t, excl + A, 2);
             }
         }
@@ -111,34 +122,41 @@ __device__ __forceinline__ int64_t sum_add(int64_t a) { return a; }
 template <class V>
 __device__ __forceinline__ int64_t sum_add(const Sum<V> &a) { return a.add; }
 
-template <class G, class P>
-__global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put, uint64_t *status, unsigned *ticket,
+template <int IT, class G, class P>
+__global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put, uint64_t *status, int64_t wait,
                                                         int64_t *total) {
     using R = decltype(get((int64_t)0));
+    constexpr int64_t TILE = (int64_t)IT * kTileBlock;
     __shared__ int64_t lds[kTileBlock / kWave + 1];
-    __shared__ int64_t sh_tile, sh_excl;
-    const int64_t t = lb_tile(ticket, &sh_tile);
+    __shared__ int64_t sh_excl;
+    const int64_t t = blockIdx.x;
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
-    int64_t v[kTileItems];
-    R r[kTileItems];
+    const int64_t wbase = t * TILE + (int64_t)w * kWave * IT;
+    int64_t v[IT];
+    R r[IT];
     int64_t wtot = 0;
     // get() on a clamped index for every item, so all loads are in flight at once
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
+    for (int j = 0; j < IT; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
         r[j] = get(i < n ? i : n - 1);
         v[j] = i < n ? sum_add(r[j]) : 0;
     }
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) wtot += v[j];
+    for (int j = 0; j < IT; ++j) wtot += v[j];
     wtot = wave_sum(wtot);
     int64_t A;
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wtot : (int64_t)0, lds, &A);
     wpre = __shfl(wpre, 0);
-    int64_t carry = lb_resolve(status, t, A, &sh_excl, total, gridDim.x) + wpre;
+    auto agg = [&](int64_t tile) {
+        const int64_t b = tile * TILE, e = std::min<int64_t>(n, b + TILE);
+        int64_t a = 0;
+        for (int64_t i = b + lane; i < e; i += kWave) a += sum_add(get(i));
+        return wave_sum(a);
+    };
+    int64_t carry = lb_resolve(status, t, A, &sh_excl, total, gridDim.x, wait, agg) + wpre;
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
+    for (int j = 0; j < IT; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         int64_t inc = wave_incl_scan(v[j]);
         if (i < n) put(i, carry + inc - v[j], r[j]);
@@ -163,19 +181,21 @@ struct PutNoValue {
     __device__ void operator()(int64_t i, int64_t pre, const R &) const { put(i, pre); }
 };
 
-// Cleared tile status words and ticket for a look-back pass over nt tiles
-// (none needed for a single tile).
+// Cleared tile status words for a look-back pass over nt tiles (none needed
+// for a single tile): a piece of the handle's cleared pool, or a buffer of
+// its own when the pass needs more than the pool holds.
 struct LookbackState {
     DBuf<uint64_t> buf;
     uint64_t *status = nullptr;
-    unsigned *ticket = nullptr;
     LookbackState(const Ctx &c, int64_t nt) {
         (void)grid_x(nt, kTileBlock);
         if (nt <= 1) return;
-        buf = c.buf<uint64_t>((size_t)nt + 1);
-        c.zero(buf.get(), (size_t)nt + 1);
-        status = buf.get();
-        ticket = (unsigned *)(buf.get() + nt);
+        status = c.take_status((size_t)nt);
+        if (!status) {
+            buf = c.buf<uint64_t>((size_t)nt);
+            c.zero(buf.get(), (size_t)nt);
+            status = buf.get();
+        }
     }
 };
 
@@ -188,10 +208,10 @@ void scan_exclusive_v(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev 
         if (total_dev) c.zero(total_dev, 1);
         return;
     }
-    const int64_t nt = ceil_div(n, kTile);
+    const int64_t nt = ceil_div(n, kScanTile);
     LookbackState lb(c, nt);
-    hipLaunchKernelGGL((k_scan_lb<G, P>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, get, put, lb.status,
-                       lb.ticket, total_dev);
+    hipLaunchKernelGGL((k_scan_lb<kScanItems, G, P>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, get,
+                       put, lb.status, c.lookback_wait, total_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -227,48 +247,60 @@ void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
 // i gets emit(i, pos, value) with pos its rank among the kept elements.  One
 // pass: ballot + mbcnt inside each wave, block prefix of wave counts, tile
 // prefix by decoupled look-back.  sel() runs for all items of a thread before
-// any emit, so its loads overlap; emit() should only store.
+// any emit, so its loads overlap; emit() should only store.  Tiles and the
+// look-back are those of the scan above.
 // ---------------------------------------------------------------------------
+constexpr int kCompactItems = 16;
+constexpr int64_t kCompactTile = (int64_t)kCompactItems * kTileBlock;
+
 template <class V>
 struct Pick {
     bool keep;
     V v;
 };
 
-template <class Sel, class Em>
-__global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Sel sel, Em emit, uint64_t *status,
-                                                           unsigned *ticket, int64_t *count) {
+template <int IT, class Sel, class Em>
+__global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Sel sel, Em emit, uint64_t *status, int64_t wait,
+                                                           int64_t *count) {
     using V = decltype(sel((int64_t)0).v);
+    static_assert(IT <= 64, "at most 64 items per thread");
+    constexpr int64_t TILE = (int64_t)IT * kTileBlock;
     __shared__ int64_t lds[kTileBlock / kWave + 1];
-    __shared__ int64_t sh_tile, sh_excl;
-    const int64_t t = lb_tile(ticket, &sh_tile);
+    __shared__ int64_t sh_excl;
+    const int64_t t = blockIdx.x;
     const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t wbase = t * kTile + (int64_t)w * kWave * kTileItems;
-    uint32_t flags = 0;
+    const int64_t wbase = t * TILE + (int64_t)w * kWave * IT;
+    uint64_t flags = 0;
     int64_t wcnt = 0;
     // sel() on a clamped index for every item, so all loads are in flight at once
-    bool fs[kTileItems];
-    V vals[kTileItems];
+    bool fs[IT];
+    V vals[IT];
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
+    for (int j = 0; j < IT; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
         const Pick<V> pk = sel(i < n ? i : n - 1);
         fs[j] = pk.keep;
         vals[j] = pk.v;
     }
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
+    for (int j = 0; j < IT; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
         const bool f = (i < n) & fs[j];
-        flags |= (uint32_t)f << j;
+        flags |= (uint64_t)f << j;
         wcnt += __popcll(ballot(f));
     }
     int64_t A;
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wcnt : (int64_t)0, lds, &A);
     wpre = __shfl(wpre, 0);
-    int64_t pos = lb_resolve(status, t, A, &sh_excl, count, gridDim.x) + wpre;
+    auto agg = [&](int64_t tile) {
+        const int64_t b = tile * TILE, e = std::min<int64_t>(n, b + TILE);
+        int64_t a = 0;
+        for (int64_t i = b + lane; i < e; i += kWave) a += sel(i).keep ? 1 : 0;
+        return wave_sum(a);
+    };
+    int64_t pos = lb_resolve(status, t, A, &sh_excl, count, gridDim.x, wait, agg) + wpre;
 #pragma unroll
-    for (int j = 0; j < kTileItems; ++j) {
+    for (int j = 0; j < IT; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
         bool f = (flags >> j) & 1u;
         uint64_t m = ballot(f);
@@ -285,10 +317,10 @@ void compact_v(const Ctx &c, int64_t n, Sel sel, Em emit, int64_t *count_dev) {
         c.zero(count_dev, 1);
         return;
     }
-    const int64_t nt = ceil_div(n, kTile);
+    const int64_t nt = ceil_div(n, kCompactTile);
     LookbackState lb(c, nt);
-    hipLaunchKernelGGL((k_compact_lb<Sel, Em>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n, sel, emit,
-                       lb.status, lb.ticket, count_dev);
+    hipLaunchKernelGGL((k_compact_lb<kCompactItems, Sel, Em>), dim3(grid_x(nt, kTileBlock)), dim3(kTileBlock), 0, c.stream, n,
+                       sel, emit, lb.status, c.lookback_wait, count_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -317,18 +349,16 @@ constexpr int kRsItems = 16;
 constexpr int64_t kRsTile = kRsBlock * kRsItems;
 
 // Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Keys are
-// read coalesced (each wave takes 64 consecutive keys per step); lanes of a
-// wave holding the same digit are matched by ballots and their leader adds
-// the group size to the wave's private histogram, so skewed digits cost no
-// atomic contention.
+// read coalesced (each wave takes 64 consecutive keys per step) and counted
+// with LDS atomic adds; lanes of one instruction that hit the same digit are
+// serialised by the LDS, which costs at most 64 cycles per 64 keys when every
+// key has the same digit.
 template <class K>
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, int shift, uint32_t *counts,
                                                       int64_t ntiles) {
-    constexpr int W = kRsBlock / kWave;
-    __shared__ uint32_t h[W][256];
-    for (int d = threadIdx.x; d < 256; d += kRsBlock)
-#pragma unroll
-        for (int q = 0; q < W; ++q) h[q][d] = 0;
+    static_assert(kRsBlock == 256, "one digit counter per thread");
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
     __syncthreads();
     const int64_t tile = blockIdx.x;
     const int w = threadIdx.x / kWave, lane = lane_id();
@@ -342,29 +372,24 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, 
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        const bool valid = i < n;
-        const uint32_t d = (uint32_t)(k[j] >> shift) & 255u;
-        const uint64_t peers = match_digit<8>(d, ballot(valid));
-        const int leader = peers ? (int)(__ffsll((unsigned long long)peers) - 1) : 0;
-        if (valid && lane == leader) h[w][d] += (uint32_t)__popcll(peers);
+        if (i < n) atomicAdd(&h[(uint32_t)(k[j] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    for (int d = threadIdx.x; d < 256; d += kRsBlock) {
-        uint32_t t = 0;
-#pragma unroll
-        for (int q = 0; q < W; ++q) t += h[q][d];
-        counts[(int64_t)d * ntiles + tile] = t;
-    }
+    counts[(int64_t)threadIdx.x * ntiles + tile] = h[threadIdx.x];
 }
 
+// Stable scatter of one tile: ranks within the tile by wave ballots (lanes
+// with the same digit matched bit by bit, the group leader bumps the wave's
+// digit counter), keys staged in LDS in digit order, then written out in
+// digit runs.  Four workgroups fit a CU (under 40 KB of LDS and at most 128
+// VGPRs for 64-bit keys).
 template <class K>
-__global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const K *in, K *out, int64_t n, int shift,
-                                                         const int64_t *offs, int64_t ntiles) {
+__global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(const K *in, K *out, int64_t n, int shift,
+                                                            const int64_t *offs, int64_t ntiles) {
     constexpr int W = kRsBlock / kWave;
     __shared__ K tk[kRsTile];
     __shared__ uint32_t wcnt[W][256];
-    __shared__ uint32_t bstart[256];
-    __shared__ uint32_t dcount[256];
+    __shared__ uint32_t bstart[257];  // start of each digit's run in the tile, bstart[256] = tile size
     __shared__ int64_t goff[256];
     __shared__ uint32_t lds_scan[W + 1];
     const int64_t tile = blockIdx.x;
@@ -412,10 +437,8 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const K *in, K *out, in
     }
     uint32_t all;
     uint32_t st = block_excl_scan<kRsBlock>(threadIdx.x < 256 ? tot : 0u, lds_scan, &all);
-    if (threadIdx.x < 256) {
-        bstart[threadIdx.x] = st;
-        dcount[threadIdx.x] = tot;
-    }
+    if (threadIdx.x < 256) bstart[threadIdx.x] = st;
+    if (threadIdx.x == 0) bstart[256] = all;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -431,7 +454,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_scatter(const K *in, K *out, in
         K key = tk[p];
         uint32_t d = (uint32_t)(key >> shift) & 255u;
         const uint32_t q = (uint32_t)p - bstart[d];
-        if (q < dcount[d]) out[goff[d] + q] = key;  // stays inside digit d's range
+        if (q < bstart[d + 1] - bstart[d]) out[goff[d] + q] = key;  // stays inside digit d's range
     }
 }
 

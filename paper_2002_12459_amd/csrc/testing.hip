@@ -5,6 +5,7 @@
 
 jp::Ctx jp_handle_ctx(jp_handle *h);
 jp_status jp_handle_guard(jp_handle *h, void (*fn)(void *), void *arg);
+void jp_handle_set_lookback_wait(jp_handle *h, int64_t ticks);
 
 namespace {
 template <class K>
@@ -80,6 +81,11 @@ jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, 
     jp_status st = jp_handle_guard(h, do_scan, &a);
     *total = a.total;
     return st;
+}
+jp_status jp_test_set_lookback_wait(jp_handle *h, int64_t ticks) {
+    if (!h || ticks < 0) return JP_EINVAL;
+    jp_handle_set_lookback_wait(h, ticks);
+    return JP_OK;
 }
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out) {
     if (!h || n < 0 || (n && (!in || !out)) || !n_out) return JP_EINVAL;

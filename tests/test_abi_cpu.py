@@ -67,3 +67,9 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(jp.Options) == 48
     # jp_stats: 7 int64, 4 int32, 8 int64, 10 double, 1 int64
     assert ctypes.sizeof(jp.Stats) == 7 * 8 + 4 * 4 + 8 * 8 + 10 * 8 + 8
+
+
+def test_lookback_wait_hook_rejects_a_null_handle(lib):
+    lib.jp_test_set_lookback_wait.restype = ctypes.c_int
+    lib.jp_test_set_lookback_wait.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+    assert lib.jp_test_set_lookback_wait(None, 0) == 1
