@@ -342,7 +342,7 @@ jp_status jp_result_stats(const jp_result *r, jp_stats *s);
 void jp_result_free(jp_result *r);
 
 /*
- * Heavy-product kernel on its own (Algorithm 1, lines 4-6; Section 2.2's
+ * Heavy-product kernel on its own (the heavy step of Algorithm 1; Section 2.2's
  * Boolean matrix product): A is u x k and Bt is w x k, both 0/1 int8
  * row-major device matrices with row stride `ld` bytes (ld >= k, ld a
  * multiple of 64, padding bytes zero).  For every (i, j) with

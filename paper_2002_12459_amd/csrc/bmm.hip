@@ -1,9 +1,9 @@
 // Heavy part of the method: the 0/1 matrix product M = M1 x M2 over the
-// heavy x / y / z values (Algorithm 1, lines 4-6; the Boolean-product view of
-// Section 2.2).  Every entry is 0 or 1 and every count is at most the number
+// heavy x / y / z values (the heavy step of Algorithm 1; the Boolean-product
+// view of Section 2.2).  Every entry is 0 or 1 and every count is at most the number
 // of heavy y values, so int8 inputs with int32 accumulation are exact.  The
 // product is never stored: the epilogue tests each accumulator for > 0 in
-// registers and appends the nonzero coordinates (one atomic per wave).
+// registers and appends the nonzero coordinates (one atomic per tile).
 //
 // Operands: A = M1 (u rows) and Bt = M2 transposed (w rows), both int8
 // row-major with the heavy-y index contiguous, row stride `ld` bytes (a
@@ -93,6 +93,33 @@ __device__ __forceinline__ void tile_of_block(int64_t t, int64_t tiles_m, int64_
     *tn = in / gm;
 }
 
+// Output slots of one workgroup's tile: the waves' counts are summed in LDS
+// and one device-scope atomic reserves them all.  Atomics on one address are
+// serialised (about 11 ns each on MI355X), so one per wave (3.8M for a
+// 177K x 174K product of 256 x 256 tiles) would cost more than the MFMA
+// work.  Returns this wave's first slot, or -1 when the tile has no nonzero
+// (the same for the whole workgroup).  Must be reached by every thread; the
+// caller's next write to sh/shbase must be separated from this call by a
+// workgroup barrier (each kernel's main loop has one).
+template <int WAVES>
+__device__ __forceinline__ int64_t tile_reserve(uint32_t wtot, unsigned long long *count, uint32_t *sh,
+                                                unsigned long long *shbase) {
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == 0) sh[wv] = wtot;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int q = 0; q < WAVES; ++q) {
+        const uint32_t t = sh[q];
+        before += q < wv ? t : 0u;
+        all += t;
+    }
+    if (all == 0) return -1;
+    if (threadIdx.x == 0) *shbase = atomicAdd(count, (unsigned long long)all);
+    __syncthreads();
+    return (int64_t)*shbase + before;
+}
+
 // With kchunk < ld the K range is split into chunks (split-K, for products
 // with few output tiles and long rows): workgroup item = (tile, chunk), and
 // the epilogue ORs "count > 0" into a u x w bitmap instead of emitting
@@ -104,6 +131,8 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                                                 unsigned long long *count, int64_t kchunk, uint32_t *bitmap) {
     __shared__ __attribute__((aligned(16))) int8_t sA[BM * LDS_STRIDE];
     __shared__ __attribute__((aligned(16))) int8_t sB[BN * LDS_STRIDE];
+    __shared__ uint32_t sh_cnt[4];
+    __shared__ unsigned long long sh_base;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     const int wm = wv >> 1, wn = wv & 1;
     // global -> register staging: each thread moves 4 x 16 B of A and of B
@@ -170,7 +199,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
         }
 
         // Epilogue: C[row][col] with row = 4*(lane/16) + r inside the 16x16
-        // block, col = lane % 16.  Count this lane's nonzeros, one atomic per wave.
+        // block, col = lane % 16.  Count this lane's nonzeros, one atomic per tile.
         if (bitmap) {
 #pragma unroll
             for (int f = 0; f < 4; ++f)
@@ -200,11 +229,9 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                 }
         uint32_t incl = wave_incl_scan(mine);
         uint32_t wtot = __shfl(incl, kWave - 1);
-        if (wtot == 0) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
-        base = __shfl(base, 0);
-        int64_t pos = (int64_t)base + (incl - mine);
+        const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
+        if (base < 0) continue;
+        int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
@@ -243,6 +270,8 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                                                      int64_t tiles_n, Emit emit, int64_t cap,
                                                      unsigned long long *count) {
     extern __shared__ __attribute__((aligned(16))) int8_t lds[];  // 2 stages
+    __shared__ uint32_t sh_cnt[kBig / kWave];
+    __shared__ unsigned long long sh_base;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     const int wm = wv >> 2, wn = wv & 3;
     const int fr = lane % 16, fq = lane / 16;
@@ -327,11 +356,9 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                 }
         const uint32_t incl = wave_incl_scan(mine);
         const uint32_t wtot = __shfl(incl, kWave - 1);
-        if (wtot == 0) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
-        base = __shfl(base, 0);
-        int64_t pos = (int64_t)base + (incl - mine);
+        const int64_t base = tile_reserve<kBig / kWave>(wtot, count, sh_cnt, &sh_base);
+        if (base < 0) continue;
+        int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int f = 0; f < 8; ++f)
 #pragma unroll
@@ -472,6 +499,8 @@ __global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__
                                                     int64_t tiles_n, Emit emit, int64_t cap,
                                                     unsigned long long *count) {
     __shared__ uint64_t sA[PKW][PB], sB[PKW][PB];
+    __shared__ uint32_t sh_cnt[4];
+    __shared__ unsigned long long sh_base;
     const int tid = threadIdx.x, lane = lane_id();
     const int ty = tid / 16, tx = tid % 16;
     const int64_t total = tiles_m * tiles_n;
@@ -518,11 +547,9 @@ __global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__
                 mine += (acc[i][j] > 0 && row0 + ty + 16 * i < u && col0 + tx + 16 * j < w) ? 1u : 0u;
         const uint32_t incl = wave_incl_scan(mine);
         const uint32_t wtot = __shfl(incl, kWave - 1);
-        if (wtot == 0) continue;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
-        base = __shfl(base, 0);
-        int64_t pos = (int64_t)base + (incl - mine);
+        const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
+        if (base < 0) continue;
+        int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int i = 0; i < 8; ++i)
 #pragma unroll

@@ -222,23 +222,39 @@ void scan_exclusive(const Ctx &c, int64_t n, G get, P put, int64_t *total_dev = 
 }
 
 // ---------------------------------------------------------------------------
-// Sum of get(i) over [0,n) added into *out (device, 64-bit).
+// Sum of get(i) over [0,n) stored at *out (device, 64-bit).  Each workgroup
+// writes its partial sum and one workgroup adds them up: device-scope
+// atomics on one address are serialised (about 11 ns each), so thousands of
+// workgroups adding into one word would cost tens of microseconds.
 // ---------------------------------------------------------------------------
 template <class G>
-__global__ __launch_bounds__(256) void k_reduce_sum(int64_t n, G get, unsigned long long *out) {
+__global__ __launch_bounds__(256) void k_reduce_sum(int64_t n, G get, int64_t *part) {
     __shared__ int64_t lds[256 / kWave + 1];
     int64_t s = 0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) s += get(i);
-    int64_t t = block_sum<256>(s, lds);
-    if (threadIdx.x == 0 && t) atomicAdd(out, (unsigned long long)t);
+    const int64_t t = block_sum<256>(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) inline void k_reduce_parts(const int64_t *part, int64_t np, unsigned long long *out) {
+    __shared__ int64_t lds[256 / kWave + 1];
+    int64_t s = 0;
+    for (int64_t i = threadIdx.x; i < np; i += 256) s += part[i];
+    const int64_t t = block_sum<256>(s, lds);
+    if (threadIdx.x == 0) *out = (unsigned long long)t;
 }
 
 template <class G>
 void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
-    c.zero(out_dev, 1);
-    if (n <= 0) return;
-    int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 8);
-    hipLaunchKernelGGL((k_reduce_sum<G>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, get, out_dev);
+    if (n <= 0) {
+        c.zero(out_dev, 1);
+        return;
+    }
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), (int64_t)c.num_cus * 8);
+    DBuf<int64_t> part = c.buf<int64_t>((size_t)blocks);
+    hipLaunchKernelGGL((k_reduce_sum<G>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, get, part.get());
+    JP_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, c.stream, (const int64_t *)part.get(), blocks, out_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -350,19 +366,24 @@ constexpr int64_t kRsTile = kRsBlock * kRsItems;
 
 // Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Keys are
 // read coalesced (each wave takes 64 consecutive keys per step) and counted
-// with LDS atomic adds; lanes of one instruction that hit the same digit are
-// serialised by the LDS, which costs at most 64 cycles per 64 keys when every
-// key has the same digit.
+// with LDS atomic adds into kRsHistCopies copies of the histogram, lane l
+// adding to copy l % kRsHistCopies (copies padded by one word so that equal
+// digits of different copies fall in different banks).  Lanes of one
+// instruction that hit the same counter are serialised by the LDS; the copies
+// divide that cost for skewed digits (a Zipf-distributed id's low byte).
+constexpr int kRsHistCopies = 8;
 template <class K>
 __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, int shift, uint32_t *counts,
                                                       int64_t ntiles) {
-    static_assert(kRsBlock == 256, "one digit counter per thread");
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    static_assert(kRsBlock == 256, "one digit per thread in the final sum");
+    constexpr int kStride = 257;
+    __shared__ uint32_t h[kRsHistCopies * kStride];
+    for (int i = threadIdx.x; i < kRsHistCopies * kStride; i += kRsBlock) h[i] = 0;
     __syncthreads();
     const int64_t tile = blockIdx.x;
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t wbase = tile * kRsTile + (int64_t)w * kWave * kRsItems;
+    uint32_t *mine = h + (lane % kRsHistCopies) * kStride;
     K k[kRsItems];
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -372,10 +393,13 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, 
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        if (i < n) atomicAdd(&h[(uint32_t)(k[j] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&mine[(uint32_t)(k[j] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * ntiles + tile] = h[threadIdx.x];
+    uint32_t t = 0;
+#pragma unroll
+    for (int q = 0; q < kRsHistCopies; ++q) t += h[q * kStride + threadIdx.x];
+    counts[(int64_t)threadIdx.x * ntiles + tile] = t;
 }
 
 // Stable scatter of one tile: ranks within the tile by wave ballots (lanes

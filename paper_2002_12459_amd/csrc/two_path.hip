@@ -28,11 +28,14 @@
 namespace jp {
 namespace {
 
-// min / max of four int32 columns (R x, R y, S z, S y) into out[8]; grid.y
-// selects the column, kMinMaxVec 16-byte loads per thread per step.
+// min / max of four int32 columns (R x, R y, S z, S y); grid.y selects the
+// column, kMinMaxVec 16-byte loads per thread per step.  Each workgroup
+// writes its pair to part[(column * gridDim.x + block) * 2]; k_minmax_fold
+// reduces them into out[8] (device-scope atomics on one cache line would be
+// serialised, about 11 ns each).
 constexpr int kMinMaxVec = 4;
 __global__ __launch_bounds__(256) void k_minmax4(const int32_t *c0, const int32_t *c1, int64_t n01, const int32_t *c2,
-                                                 const int32_t *c3, int64_t n23, int *out) {
+                                                 const int32_t *c3, int64_t n23, int *part) {
     __shared__ int smn[256 / kWave], smx[256 / kWave];
     const int k = blockIdx.y;
     const int32_t *a = k == 0 ? c0 : (k == 1 ? c1 : (k == 2 ? c2 : c3));
@@ -79,17 +82,42 @@ __global__ __launch_bounds__(256) void k_minmax4(const int32_t *c0, const int32_
             mn = smn[i] < mn ? smn[i] : mn;
             mx = smx[i] > mx ? smx[i] : mx;
         }
-        atomicMin(&out[2 * k], mn);
-        atomicMax(&out[2 * k + 1], mx);
+        int *p = part + ((int64_t)k * gridDim.x + blockIdx.x) * 2;
+        p[0] = mn;
+        p[1] = mx;
+    }
+}
+
+// One wave per column: min and max over the workgroup pairs.
+__global__ __launch_bounds__(256) void k_minmax_fold(const int *part, int64_t nblk, int *out) {
+    const int k = threadIdx.x / kWave;
+    int mn = INT_MAX, mx = INT_MIN;
+    for (int64_t b = lane_id(); b < nblk; b += kWave) {
+        const int *p = part + ((int64_t)k * nblk + b) * 2;
+        mn = p[0] < mn ? p[0] : mn;
+        mx = p[1] > mx ? p[1] : mx;
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        int a2 = __shfl_xor(mn, o), b2 = __shfl_xor(mx, o);
+        mn = a2 < mn ? a2 : mn;
+        mx = b2 > mx ? b2 : mx;
+    }
+    if (lane_id() == 0) {
+        out[2 * k] = mn;
+        out[2 * k + 1] = mx;
     }
 }
 
 void minmax4(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz, const int32_t *sy,
              int64_t ns, int *out) {
-    const int64_t n = std::max(nr, ns);
-    if (n <= 0) return;
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256 * 4 * kMinMaxVec), (int64_t)c.num_cus * 2));
-    hipLaunchKernelGGL(k_minmax4, dim3(grid_x(blocks, 256), 4), dim3(256), 0, c.stream, rx, ry, nr, sz, sy, ns, out);
+    const int64_t n = std::max<int64_t>(std::max(nr, ns), 1);
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256 * 4 * kMinMaxVec), (int64_t)c.num_cus * 4));
+    DBuf<int> part = c.buf<int>((size_t)(8 * blocks));
+    hipLaunchKernelGGL(k_minmax4, dim3(grid_x(blocks, 256), 4), dim3(256), 0, c.stream, rx, ry, nr, sz, sy, ns, part.get());
+    JP_HIP(hipGetLastError());
+    static_assert(256 / kWave == 4, "one wave per column");
+    hipLaunchKernelGGL(k_minmax_fold, dim3(1), dim3(256), 0, c.stream, (const int *)part.get(), blocks, out);
     JP_HIP(hipGetLastError());
 }
 
@@ -146,10 +174,6 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     // ---- ranges of the id columns --------------------------------------------
     DBuf<int> mmb = c.buf<int>(8);
     int *mm = mmb.get();
-    for_each(c, 4, [=] __device__(int64_t i) {
-        mm[2 * i] = INT_MAX;
-        mm[2 * i + 1] = INT_MIN;
-    });
     minmax4(c, rx, ry, nr, sz, sy, ns, mm);
     int hmm[8];
     c.load_n(hmm, mm, 8);
