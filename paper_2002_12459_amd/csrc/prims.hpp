@@ -364,6 +364,14 @@ constexpr int kRsBlock = 256;
 constexpr int kRsItems = 16;
 constexpr int64_t kRsTile = kRsBlock * kRsItems;
 
+// Where a pass reads its keys: an array, or (first pass only) a function of
+// the index that builds each key from the caller's columns.
+template <class K>
+struct KeyArray {
+    const K *p;
+    __device__ K operator()(int64_t i) const { return p[i]; }
+};
+
 // Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Keys are
 // read coalesced (each wave takes 64 consecutive keys per step) and counted
 // with LDS atomic adds into kRsHistCopies copies of the histogram, lane l
@@ -372,8 +380,8 @@ constexpr int64_t kRsTile = kRsBlock * kRsItems;
 // instruction that hit the same counter are serialised by the LDS; the copies
 // divide that cost for skewed digits (a Zipf-distributed id's low byte).
 constexpr int kRsHistCopies = 8;
-template <class K>
-__global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, int shift, uint32_t *counts,
+template <class K, class Src>
+__global__ __launch_bounds__(kRsBlock) void k_rs_hist(Src keys, int64_t n, int shift, uint32_t *counts,
                                                       int64_t ntiles) {
     static_assert(kRsBlock == 256, "one digit per thread in the final sum");
     constexpr int kStride = 257;
@@ -388,7 +396,7 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, 
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        k[j] = keys[i < n ? i : n - 1];
+        k[j] = keys(i < n ? i : n - 1);
     }
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -407,8 +415,8 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(const K *keys, int64_t n, 
 // digit counter), keys staged in LDS in digit order, then written out in
 // digit runs.  Four workgroups fit a CU (under 40 KB of LDS and at most 128
 // VGPRs for 64-bit keys).
-template <class K>
-__global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(const K *in, K *out, int64_t n, int shift,
+template <class K, class Src>
+__global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(Src in, K *out, int64_t n, int shift,
                                                             const int64_t *offs, int64_t ntiles) {
     constexpr int W = kRsBlock / kWave;
     __shared__ K tk[kRsTile];
@@ -430,7 +438,7 @@ __global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(const K *in, K *out,
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {  // all loads in flight before the first ballot
         const int64_t i = wbase + (int64_t)j * kWave + lane;
-        k[j] = in[i < n ? i : n - 1];
+        k[j] = in(i < n ? i : n - 1);
     }
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -482,6 +490,44 @@ __global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(const K *in, K *out,
     }
 }
 
+// One stable pass on the digit at `shift`: keys from src into dst.
+template <class K, class Src>
+void radix_pass(const Ctx &c, Src src, K *dst, int64_t n, int shift, uint32_t *counts, int64_t *offs, int64_t nt) {
+    hipLaunchKernelGGL((k_rs_hist<K, Src>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, src, n, shift, counts,
+                       nt);
+    JP_HIP(hipGetLastError());
+    const uint32_t *cp = counts;
+    scan_exclusive(
+        c, 256 * nt, [=] __device__(int64_t i) -> int64_t { return (int64_t)cp[i]; }, ArrayPut{offs});
+    hipLaunchKernelGGL((k_rs_scatter<K, Src>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, src, dst, n, shift,
+                       (const int64_t *)offs, nt);
+    JP_HIP(hipGetLastError());
+}
+
+// Sorts the n keys key0(i), i in [0, n), on their low `bits` bits, with `a`
+// and `b` (n keys each) as ping-pong buffers; returns the one holding the
+// result.  The first pass reads the keys through key0, so they are never
+// stored unsorted.
+template <class K, class F>
+K *radix_sort_from(const Ctx &c, F key0, K *a, K *b, int64_t n, int bits) {
+    if (n <= 0) return a;
+    if (n == 1 || bits <= 0) {
+        for_each(c, n, [=] __device__(int64_t i) { a[i] = key0(i); });
+        return a;
+    }
+    const int passes = (bits + 7) / 8;
+    const int64_t nt = ceil_div(n, kRsTile);
+    DBuf<uint32_t> counts = c.buf<uint32_t>((size_t)(256 * nt));
+    DBuf<int64_t> offs = c.buf<int64_t>((size_t)(256 * nt));
+    radix_pass<K>(c, key0, a, n, 0, counts.get(), offs.get(), nt);
+    K *src = a, *dst = b;
+    for (int p = 1; p < passes; ++p) {
+        radix_pass<K>(c, KeyArray<K>{src}, dst, n, 8 * p, counts.get(), offs.get(), nt);
+        std::swap(src, dst);
+    }
+    return src;
+}
+
 // Sorts n keys on their low `bits` bits.  Uses `keys` and `tmp` as ping-pong
 // buffers and returns the one holding the result.
 template <class K>
@@ -493,16 +539,7 @@ K *radix_sort(const Ctx &c, K *keys, K *tmp, int64_t n, int bits) {
     DBuf<int64_t> offs = c.buf<int64_t>((size_t)(256 * nt));
     K *src = keys, *dst = tmp;
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
-        hipLaunchKernelGGL((k_rs_hist<K>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, (const K *)src, n, shift,
-                           counts.get(), nt);
-        JP_HIP(hipGetLastError());
-        const uint32_t *cp = counts.get();
-        scan_exclusive(
-            c, 256 * nt, [=] __device__(int64_t i) -> int64_t { return (int64_t)cp[i]; }, ArrayPut{offs.get()});
-        hipLaunchKernelGGL((k_rs_scatter<K>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, (const K *)src, dst, n,
-                           shift, (const int64_t *)offs.get(), nt);
-        JP_HIP(hipGetLastError());
+        radix_pass<K>(c, KeyArray<K>{src}, dst, n, 8 * p, counts.get(), offs.get(), nt);
         std::swap(src, dst);
     }
     return src;

@@ -91,11 +91,9 @@ RelRaw ingest_raw(const Ctx &c, const int32_t *x, const int32_t *y, int64_t n, i
                   int yb, int64_t *S) {
     RelRaw r;
     DBuf<uint64_t> ka = c.buf<uint64_t>(n), kb = c.buf<uint64_t>(n);
-    uint64_t *k = ka.get();
-    for_each(c, n, [=] __device__(int64_t i) {
-        k[i] = ((uint64_t)((int64_t)y[i] - ymin) << xb) | (uint64_t)((int64_t)x[i] - xmin);
-    });
-    const uint64_t *s = radix_sort(c, ka.get(), kb.get(), n, xb + yb);
+    const uint64_t *s = radix_sort_from<uint64_t>(
+        c, [=] __device__(int64_t i) { return ((uint64_t)((int64_t)y[i] - ymin) << xb) | (uint64_t)((int64_t)x[i] - xmin); },
+        ka.get(), kb.get(), n, xb + yb);
     r.ty = c.buf<uint32_t>(n);
     r.tx = c.buf<uint32_t>(n);
     uint32_t *ty = r.ty.get(), *tx = r.tx.get();
@@ -182,8 +180,7 @@ RelIdx finish_rel(const Ctx &c, const RelRaw &r, const uint32_t *Yk, int64_t dom
     DBuf<int64_t> xst = c.buf<int64_t>(n + 1);
     {
         DBuf<uint32_t> a = c.buf<uint32_t>(std::max<int64_t>(n, 1)), b = c.buf<uint32_t>(std::max<int64_t>(n, 1));
-        JP_HIP(hipMemcpyAsync(a.get(), kx.get(), n * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
-        const uint32_t *s = radix_sort(c, a.get(), b.get(), n, xb);
+        const uint32_t *s = radix_sort_from<uint32_t>(c, KeyArray<uint32_t>{kx.get()}, a.get(), b.get(), n, xb);
         uint32_t *d = xs.get();
         int64_t *st = xst.get();
         compact(

@@ -187,11 +187,12 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     DBuf<uint64_t> r1;
     {
         DBuf<uint64_t> ka = c.buf<uint64_t>(nr), kb = c.buf<uint64_t>(nr);
-        uint64_t *k = ka.get();
-        for_each(c, nr, [=] __device__(int64_t i) {
-            k[i] = ((uint64_t)((int64_t)rx[i] - xmin) << yb) | (uint64_t)((int64_t)ry[i] - ymin);
-        });
-        const uint64_t *s = radix_sort(c, ka.get(), kb.get(), nr, xb + yb);
+        const uint64_t *s = radix_sort_from<uint64_t>(
+            c,
+            [=] __device__(int64_t i) {
+                return ((uint64_t)((int64_t)rx[i] - xmin) << yb) | (uint64_t)((int64_t)ry[i] - ymin);
+            },
+            ka.get(), kb.get(), nr, xb + yb);
         r1 = c.buf<uint64_t>(nr);
         uint64_t *d = r1.get();
         compact_v(
@@ -206,11 +207,12 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     DBuf<uint64_t> s1;
     {
         DBuf<uint64_t> ka = c.buf<uint64_t>(ns), kb = c.buf<uint64_t>(ns);
-        uint64_t *k = ka.get();
-        for_each(c, ns, [=] __device__(int64_t i) {
-            k[i] = ((uint64_t)((int64_t)sy[i] - ymin) << zb) | (uint64_t)((int64_t)sz[i] - zmin);
-        });
-        const uint64_t *s = radix_sort(c, ka.get(), kb.get(), ns, yb + zb);
+        const uint64_t *s = radix_sort_from<uint64_t>(
+            c,
+            [=] __device__(int64_t i) {
+                return ((uint64_t)((int64_t)sy[i] - ymin) << zb) | (uint64_t)((int64_t)sz[i] - zmin);
+            },
+            ka.get(), kb.get(), ns, yb + zb);
         s1 = c.buf<uint64_t>(ns);
         uint64_t *d = s1.get();
         compact_v(
@@ -229,11 +231,10 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     DBuf<int64_t> rstart = c.buf<int64_t>(n_r1 + 1);
     {
         DBuf<uint32_t> ya = c.buf<uint32_t>(n_r1), yb2 = c.buf<uint32_t>(n_r1);
-        uint32_t *k = ya.get();
         const uint64_t *r = r1.get();
         const uint64_t ym = ymask;
-        for_each(c, n_r1, [=] __device__(int64_t i) { k[i] = (uint32_t)(r[i] & ym); });
-        const uint32_t *s = radix_sort(c, ya.get(), yb2.get(), n_r1, yb);
+        const uint32_t *s = radix_sort_from<uint32_t>(
+            c, [=] __device__(int64_t i) { return (uint32_t)(r[i] & ym); }, ya.get(), yb2.get(), n_r1, yb);
         uint32_t *d = YR.get();
         int64_t *rs = rstart.get();
         compact_v(
@@ -315,37 +316,63 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         }
     }
     rstart.reset();
-    // S tuples kept, y-major: y rank + z offset
+    // Joined y rank of every y value, from a dense table over the y range when
+    // that range is small enough (-1: y not in both relations).
+    const int64_t yspan = ymax - ymin + 1;
+    const bool y_dense = dense_range_ok(yspan, nr + ns);
+    DBuf<int32_t> ymap;
+    if (y_dense) {
+        ymap = c.buf<int32_t>((size_t)yspan);
+        int32_t *ymp = ymap.get();
+        const uint32_t *ys = YS.get();
+        const int32_t *yr = yrank_js.get();
+        for_each(c, yspan, [=] __device__(int64_t y) { ymp[y] = -1; });
+        for_each(c, ny_s, [=] __device__(int64_t j) { ymp[ys[j]] = yr[j]; });
+    }
+    // S tuples kept, y-major: y rank + z offset.  Without the dense table the
+    // y rank comes from the tuple's run index among the distinct y of S.
     DBuf<int32_t> s2_y = c.buf<int32_t>(n_s1);
     DBuf<uint32_t> s2_z = c.buf<uint32_t>(n_s1);
     {
-        DBuf<int32_t> seg = c.buf<int32_t>(n_s1);
         const uint64_t *s = s1.get();
-        int32_t *sg = seg.get();
         const int zbs = zb;
-        auto newy = [=] __device__(int64_t i) -> int64_t {
-            return (i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs)) ? 1 : 0;
-        };
-        scan_exclusive_v(c, n_s1, newy, [=] __device__(int64_t i, int64_t p, int64_t v) { sg[i] = (int32_t)(p + v - 1); });
-        const int32_t *yr = yrank_js.get();
+        const uint64_t zm = zmask;
         int32_t *oy = s2_y.get();
         uint32_t *oz = s2_z.get();
-        const uint64_t zm = zmask;
-        compact_v(
-            c, n_s1,
-            [=] __device__(int64_t i) {
-                const int32_t r = yr[sg[i]];
-                return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(s[i] & zm)};
-            },
-            [=] __device__(int64_t, int64_t p, uint64_t v) {
-                oy[p] = (int32_t)(v >> 32);
-                oz[p] = (uint32_t)v;
-            },
-            S + 5);
+        auto emit = [=] __device__(int64_t, int64_t p, uint64_t v) {
+            oy[p] = (int32_t)(v >> 32);
+            oz[p] = (uint32_t)v;
+        };
+        if (y_dense) {
+            const int32_t *ymc = ymap.get();
+            compact_v(
+                c, n_s1,
+                [=] __device__(int64_t i) {
+                    const uint64_t k = s[i];
+                    const int32_t r = ymc[k >> zbs];
+                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(k & zm)};
+                },
+                emit, S + 5);
+        } else {
+            DBuf<int32_t> seg = c.buf<int32_t>(n_s1);
+            int32_t *sg = seg.get();
+            auto newy = [=] __device__(int64_t i) -> int64_t {
+                return (i == 0 || (s[i] >> zbs) != (s[i - 1] >> zbs)) ? 1 : 0;
+            };
+            scan_exclusive_v(c, n_s1, newy,
+                             [=] __device__(int64_t i, int64_t p, int64_t v) { sg[i] = (int32_t)(p + v - 1); });
+            const int32_t *yr = yrank_js.get();
+            compact_v(
+                c, n_s1,
+                [=] __device__(int64_t i) {
+                    const int32_t r = yr[sg[i]];
+                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(s[i] & zm)};
+                },
+                emit, S + 5);
+        }
     }
-    // R tuples kept, x-major: x offset + y rank.  The y rank of an R tuple
-    // comes from a dense table over the y range when that range is small
-    // enough, else from a binary search in the distinct y of S.
+    // R tuples kept, x-major: x offset + y rank (from the dense table, else
+    // by binary search in the distinct y of S).
     DBuf<uint32_t> r2_x = c.buf<uint32_t>(n_r1);
     DBuf<int32_t> adj_r = c.buf<int32_t>(n_r1);
     {
@@ -357,13 +384,8 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         const uint64_t ym = ymask;
         uint32_t *ox = r2_x.get();
         int32_t *oy = adj_r.get();
-        const int64_t yspan = ymax - ymin + 1;
-        if (dense_range_ok(yspan, nr + ns)) {
-            DBuf<int32_t> ymap = c.buf<int32_t>((size_t)yspan);
-            int32_t *ymp = ymap.get();
-            for_each(c, yspan, [=] __device__(int64_t y) { ymp[y] = -1; });
-            for_each(c, nys, [=] __device__(int64_t j) { ymp[ys[j]] = yr[j]; });
-            const int32_t *ymc = ymp;
+        if (y_dense) {
+            const int32_t *ymc = ymap.get();
             compact_v(
                 c, n_r1,
                 [=] __device__(int64_t i) {
@@ -410,8 +432,7 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     DBuf<int64_t> zstart = c.buf<int64_t>(n_s2 + 1);
     {
         DBuf<uint32_t> za = c.buf<uint32_t>(n_s2), zb2 = c.buf<uint32_t>(n_s2);
-        JP_HIP(hipMemcpyAsync(za.get(), s2_z.get(), n_s2 * sizeof(uint32_t), hipMemcpyDeviceToDevice, c.stream));
-        const uint32_t *s = radix_sort(c, za.get(), zb2.get(), n_s2, zb);
+        const uint32_t *s = radix_sort_from<uint32_t>(c, KeyArray<uint32_t>{s2_z.get()}, za.get(), zb2.get(), n_s2, zb);
         uint32_t *d = ZS.get();
         int64_t *zs0 = zstart.get();
         compact_v(
@@ -732,15 +753,26 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get();
             const int64_t *lo = lz_off.get();
             const int64_t ns2 = n_s2;
+            // per y, the start and length of its light-z list (used at heavy y
+            // only), so that a tuple's loads all depend on its y alone
+            DBuf<int64_t> lzy = c.buf<int64_t>(2 * dom_y);
+            int64_t *lz = lzy.get();
+            for_each(c, dom_y, [=] __device__(int64_t y) {
+                const int32_t h = hy[y];
+                const int32_t hh = h >= 0 ? h : 0;
+                const int64_t l0 = lo[hh], l1 = lo[hh + 1];
+                lz[2 * y] = ns2 + l0;
+                lz[2 * y + 1] = l1 - l0;
+            });
+            const int64_t *lzc = lz;
             for_each(c, n_r2, [=] __device__(int64_t e) {
                 const int32_t y = ar[e];
                 const int32_t hyv = hy[y], hxv = hx[xr[e]];
                 const bool heavy = (hyv | hxv) >= 0;  // both non-negative
-                const int32_t hi2 = heavy ? hyv : 0;
-                const int64_t l0 = lo[hi2], l1 = lo[hi2 + 1];
+                const int64_t a0 = lzc[2 * y], al = lzc[2 * y + 1];
                 const int64_t s0 = oy[y], s1v = oy[y + 1];
-                lb[e] = heavy ? ns2 + l0 : s0;
-                ln[e] = heavy ? l1 - l0 : s1v - s0;
+                lb[e] = heavy ? a0 : s0;
+                ln[e] = heavy ? al : s1v - s0;
             });
         } else {
             for_each(c, n_r2, [=] __device__(int64_t e) {
