@@ -5,12 +5,15 @@
 //
 // All six indexes (y key degree with witness sums, deg_R(y), deg_S(y),
 // deg_R(x) with witness sums, cdfx, deg_S(z)) are built by one histogram
-// launch (grid.y = index, one element per thread): degrees below kLdsBins go
-// to per-workgroup LDS bins, which are flushed into one of kCopies copies of
-// the low global bins (spreading the atomics of thousands of workgroups over
-// the copies) and folded afterwards; degrees below kHist go to global bins,
+// launch (grid.y = index, one element per thread; the x workgroups build
+// both x indexes from one walk over each x's tuples, reading a per-y table of
+// (deg_S(y), key degree) made beforehand): degrees below kLdsBins go to
+// per-workgroup LDS bins, which are flushed into one of kCopies copies of the
+// low global bins (spreading the atomics of thousands of workgroups over the
+// copies) and folded afterwards; degrees below kHist go to global bins,
 // larger ones to an append list.  One compaction keeps the nonzero bins; the
-// host then waits twice (sizes, then data) and merges the append list.
+// host then waits once for sizes and data together and merges the append
+// list.
 #include <algorithm>
 
 #include "pipeline.hpp"
@@ -26,9 +29,14 @@ constexpr int kHistBlock = 256;
 constexpr int kEdgeBatch = 4;        // R tuples of an x read together
 constexpr int kCopies = 16;          // copies of the low global bins
 
+struct YDeg {
+    int64_t ds, key;  // deg_S(y), key degree of y
+};
+
 struct IndexArgs {
     const int32_t *dry, *dsz, *ar;
     const int64_t *oy, *ox;
+    const YDeg *yd;  // per y
     int64_t dom_y, dom_x, dom_z;
     bool ronly;
     unsigned long long *cnt;   // [kIdx][kHist]
@@ -44,7 +52,7 @@ __device__ __forceinline__ int64_t key_deg(const IndexArgs &a, int64_t y) {
     return a.ronly ? dr : (dr > ds ? dr : ds);
 }
 
-// Degree and summed work of element i of index k.
+// Degree and summed work of element i of index k (k != 3, 4).
 __device__ __forceinline__ void index_value(const IndexArgs &a, int k, int64_t i, int64_t &d, unsigned long long &s) {
     s = 0;
     switch (k) {
@@ -56,77 +64,84 @@ __device__ __forceinline__ void index_value(const IndexArgs &a, int k, int64_t i
         }
         case 1: d = a.dry[i]; break;
         case 2: d = a.oy[i + 1] - a.oy[i]; break;
-        case 3: {  // x: deg_R(x), witnesses sum over y of deg_S(y)
-            const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
-            unsigned long long w = 0;
-            for (int64_t e = e0; e < e1; e += kEdgeBatch) {  // kEdgeBatch tuples' loads at once
-                int32_t y[kEdgeBatch];
-#pragma unroll
-                for (int r = 0; r < kEdgeBatch; ++r) y[r] = a.ar[e + r < e1 ? e + r : e0];
-#pragma unroll
-                for (int r = 0; r < kEdgeBatch; ++r)
-                    if (e + r < e1) w += (unsigned long long)(a.oy[y[r] + 1] - a.oy[y[r]]);
-            }
-            d = e1 - e0;
-            s = w;
-            break;
-        }
-        case 4: {  // cdfx: smallest key degree among the y of x
-            const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
-            int64_t m = INT64_MAX;
-            for (int64_t e = e0; e < e1; e += kEdgeBatch) {
-                int32_t y[kEdgeBatch];
-#pragma unroll
-                for (int r = 0; r < kEdgeBatch; ++r) y[r] = a.ar[e + r < e1 ? e + r : e0];
-#pragma unroll
-                for (int r = 0; r < kEdgeBatch; ++r) {
-                    const int64_t kd = key_deg(a, y[r]);
-                    m = (e + r < e1) & (kd < m) ? kd : m;
-                }
-            }
-            d = m;
-            break;
-        }
         default: d = a.dsz[i]; break;
     }
 }
 
+// x index (deg_R(x), witnesses = sum over the y of x of deg_S(y)) and cdfx
+// index (smallest key degree among the y of x) of x = i, from one walk.
+__device__ __forceinline__ void x_values(const IndexArgs &a, int64_t i, int64_t &d, unsigned long long &w, int64_t &m) {
+    const int64_t e0 = a.ox[i], e1 = a.ox[i + 1];
+    w = 0;
+    m = INT64_MAX;
+    for (int64_t e = e0; e < e1; e += kEdgeBatch) {  // kEdgeBatch tuples' loads at once
+        int32_t y[kEdgeBatch];
+#pragma unroll
+        for (int r = 0; r < kEdgeBatch; ++r) y[r] = a.ar[e + r < e1 ? e + r : e0];
+        YDeg t[kEdgeBatch];
+#pragma unroll
+        for (int r = 0; r < kEdgeBatch; ++r) t[r] = a.yd[y[r]];
+#pragma unroll
+        for (int r = 0; r < kEdgeBatch; ++r)
+            if (e + r < e1) {
+                w += (unsigned long long)t[r].ds;
+                m = t[r].key < m ? t[r].key : m;
+            }
+    }
+    d = e1 - e0;
+}
+
 __global__ __launch_bounds__(kHistBlock) void k_index_hist(IndexArgs a) {
-    __shared__ unsigned int lc[kLdsBins];
+    __shared__ unsigned int lc[2][kLdsBins];  // [1]: the cdfx index, in the x workgroups
     __shared__ unsigned long long ls[kLdsBins];
     const int k = blockIdx.y;
-    const int64_t n = k < 3 ? a.dom_y : (k < 5 ? a.dom_x : a.dom_z);
+    if (k == 4) return;  // cdfx comes from the x workgroups
+    const int64_t n = k < 3 ? a.dom_y : (k == 3 ? a.dom_x : a.dom_z);
     if ((int64_t)blockIdx.x * kHistBlock >= n) return;  // whole workgroup idle for this index
     for (int b = threadIdx.x; b < kLdsBins; b += kHistBlock) {
-        lc[b] = 0;
+        lc[0][b] = 0;
+        lc[1][b] = 0;
         ls[b] = 0;
     }
     __syncthreads();
-    unsigned long long *cnt = a.cnt + (int64_t)k * kHist, *sums = a.sums + (int64_t)k * kHist;
-    for (int64_t i = (int64_t)blockIdx.x * kHistBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kHistBlock) {
-        int64_t d;
-        unsigned long long s;
-        index_value(a, k, i, d, s);
+    auto add = [&](int kk, int slot, int64_t d, unsigned long long s) {
         if (d < kLdsBins) {
-            atomicAdd(&lc[d], 1u);
+            atomicAdd(&lc[slot][d], 1u);
             if (s) atomicAdd(&ls[d], s);
         } else if (d < kHist) {
-            atomicAdd(&cnt[d], 1ull);
-            if (s) atomicAdd(&sums[d], s);
+            atomicAdd(&a.cnt[(int64_t)kk * kHist + d], 1ull);
+            if (s) atomicAdd(&a.sums[(int64_t)kk * kHist + d], s);
         } else {
             const unsigned long long p = atomicAdd(a.nbig, 1ull);
             if ((int64_t)p < a.big_cap) {
-                a.big[2 * p] = ((int64_t)k << 56) | (d < (1ll << 56) ? d : (1ll << 56) - 1);
+                a.big[2 * p] = ((int64_t)kk << 56) | (d < (1ll << 56) ? d : (1ll << 56) - 1);
                 a.big[2 * p + 1] = (int64_t)s;
             }
         }
+    };
+    for (int64_t i = (int64_t)blockIdx.x * kHistBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kHistBlock) {
+        if (k == 3) {
+            int64_t d, m;
+            unsigned long long w;
+            x_values(a, i, d, w, m);
+            add(3, 0, d, w);
+            add(4, 1, m, 0);
+        } else {
+            int64_t d;
+            unsigned long long s;
+            index_value(a, k, i, d, s);
+            add(k, 0, d, s);
+        }
     }
     __syncthreads();
-    unsigned long long *lo = a.lo + ((int64_t)(blockIdx.x % kCopies) * kIdx + k) * kLdsBins;
+    const int64_t copy = (int64_t)(blockIdx.x % kCopies);
+    unsigned long long *lo = a.lo + (copy * kIdx + k) * kLdsBins;
     unsigned long long *los = lo + (int64_t)kCopies * kIdx * kLdsBins;
+    unsigned long long *lo4 = a.lo + (copy * kIdx + 4) * kLdsBins;
     for (int b = threadIdx.x; b < kLdsBins; b += kHistBlock) {
-        if (lc[b]) atomicAdd(&lo[b], (unsigned long long)lc[b]);
+        if (lc[0][b]) atomicAdd(&lo[b], (unsigned long long)lc[0][b]);
         if (ls[b]) atomicAdd(&los[b], ls[b]);
+        if (k == 3 && lc[1][b]) atomicAdd(&lo4[b], (unsigned long long)lc[1][b]);
     }
 }
 
@@ -193,6 +208,14 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     c.zero(S.get(), 2);
     a.big = big.get();
     a.nbig = (unsigned long long *)(S.get() + 1);
+    // per y: deg_S(y) and key degree, read by the walk over each x's tuples
+    DBuf<YDeg> yd = c.buf<YDeg>((size_t)std::max<int64_t>(g.dom_y, 1));
+    {
+        YDeg *t = yd.get();
+        const IndexArgs ac = a;
+        for_each(c, g.dom_y, [=] __device__(int64_t y) { t[y] = YDeg{ac.oy[y + 1] - ac.oy[y], key_deg(ac, y)}; });
+    }
+    a.yd = yd.get();
     // one element per thread (up to 2^24 threads per index, then strided)
     const int64_t bx = std::min<int64_t>(ceil_div(nmax, kHistBlock), 1ll << 16);
     hipLaunchKernelGGL(k_index_hist, dim3(grid_x(bx, kHistBlock), kIdx), dim3(kHistBlock), 0, c.stream, a);
