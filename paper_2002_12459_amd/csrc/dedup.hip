@@ -130,20 +130,41 @@ constexpr int kMaxStagedEdges = 1024;  // R tuples of a packed unit staged in LD
 static_assert(4 * (kMaxStagedEdges + 2) + 12 * kMaxStagedEdges <= 4 * kCntPadded, "staging fits the counters");
 
 
+// Exclusive max-scan over the threads of the workgroup (0 for thread 0).
+__device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *lds) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const uint32_t t = __shfl_up(inc, o);
+        if (lane >= o) inc = t > inc ? t : inc;
+    }
+    if (lane == kWave - 1) lds[w] = inc;
+    __syncthreads();
+    uint32_t r = __shfl_up(inc, 1);
+    if (lane == 0) r = 0;
+    for (int q = 0; q < w; ++q) r = lds[q] > r ? lds[q] : r;
+    __syncthreads();
+    return r;
+}
+
 __device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
     const int ci = d * kDT + t;
     return reinterpret_cast<uint16_t *>(cnt)[2 * cpad(ci >> 1) + (ci & 1)];
 }
 
-// Sorts the nn keys in k[] (thread t's slot j holds key t*kDI + j of the
-// current order, valid below nn) on their low B bits by LSD radix sort in
-// LDS: 5-bit digits, per-thread 16-bit counters updated by LDS atomics,
-// raking scan.  Leaves the distinct keys in sk[kpad(0 .. result)), in order.
+// Sorts the nn keys in k[] on their low B bits by LSD radix sort in LDS:
+// 5-bit digits, per-thread 16-bit counters updated by LDS atomics, raking
+// scan.  Thread t's slot j holds key t*kDI + j of the current order (valid
+// below nn), or, when `striped`, key j*kDT + t (valid below nn) on entry;
+// every pass leaves the first layout.  Leaves the distinct keys in
+// sk[kpad(0 .. result)), in order.
 __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int B, uint32_t *sk, uint32_t *cnt,
-                                                uint32_t *lds_scan, PhaseClock &pc) {
+                                                uint32_t *lds_scan, PhaseClock &pc, bool striped = false) {
 const int tid = threadIdx.x;
 const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
     for (int pass = 0; pass < passes; ++pass) {
+        const bool str = striped && pass == 0;
         const int shift = pass * kRB;
         for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
         __syncthreads();
@@ -153,7 +174,7 @@ const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
         uint16_t loc[kDI];
 #pragma unroll
         for (int j = 0; j < kDI; ++j) {
-            const int p = tid * kDI + j;
+            const int p = str ? j * kDT + tid : tid * kDI + j;
             const int d = (int)((k[j] >> shift) & (kRD - 1));
             const int ci = d * kDT + tid;
             const int sh = 16 * (ci & 1);
@@ -184,7 +205,7 @@ const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kDI; ++j) {
-            const int p = tid * kDI + j;
+            const int p = str ? j * kDT + tid : tid * kDI + j;
             if (p < nn) {
                 const int d = (int)((k[j] >> shift) & (kRD - 1));
                 const uint32_t dst = (uint32_t)ctr(cnt, d, tid) + loc[j];
@@ -258,25 +279,74 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         }
         __syncthreads();
 
-        // gather candidates [tid*kDI, tid*kDI + kDI): one search, then a walk
         uint32_t k[kDI];
-        {
+        if (staged) {
+            // Candidate p of the unit belongs to the tuple whose list covers
+            // it: each nonempty tuple i writes i + 1 at its first candidate,
+            // and an inclusive max-scan over the candidates fills the rest
+            // (sk is free until the sort).  Thread t then takes candidates
+            // j*kDT + t, so each load instruction reads 64 consecutive
+            // candidates, mostly consecutive list entries.
+            uint16_t *ct = reinterpret_cast<uint16_t *>(sk);  // kDCap entries
+            for (int i = tid; i < kDCap / 2; i += kDT) sk[i] = 0u;
+            __syncthreads();
+            for (int i = tid; i < ne; i += kDT) {
+                const int32_t s0 = seo[i];
+                if (seo[i + 1] > s0 && s0 < nLc) ct[s0] = (uint16_t)(i + 1);
+            }
+            __syncthreads();
+            uint32_t m = 0;
+#pragma unroll
+            for (int j = 0; j < kDI; ++j) {
+                const uint32_t h = ct[tid * kDI + j];
+                m = h > m ? h : m;
+            }
+            uint32_t run = block_excl_max(m, lds_scan);
+#pragma unroll
+            for (int j = 0; j < kDI; ++j) {
+                const uint32_t h = ct[tid * kDI + j];
+                run = h > run ? h : run;
+                ct[tid * kDI + j] = (uint16_t)run;
+            }
+            __syncthreads();
+            uint32_t src[kDI];
+#pragma unroll
+            for (int j = 0; j < kDI; ++j) {
+                const int p = j * kDT + tid;
+                uint32_t key = 0xffffffffu, sj = 0;
+                if (p < nLc) {
+                    const int e = (int)ct[p] - 1;
+                    key = (uint32_t)sxl[e] << a.bz;
+                    sj = (uint32_t)(slb[e] + (p - seo[e]));
+                } else if (p < nn) {
+                    const uint64_t hk = a.hkeys[h0 + (p - nL)];
+                    key = ((uint32_t)((int64_t)(hk >> a.bz) - xa) << a.bz) | ((uint32_t)hk & a.zmask);
+                }
+                k[j] = key;
+                src[j] = sj;
+            }
+#pragma unroll
+            for (int j = 0; j < kDI; ++j) {
+                const uint32_t z = (uint32_t)a.zlist[src[j]];
+                k[j] = j * kDT + tid < nLc ? (k[j] | z) : k[j];
+            }
+        } else {
+            // tuples not staged: thread t takes candidates [t*kDI, t*kDI + kDI),
+            // found by one search in the offsets and then a walk
             const int p0 = tid * kDI;
             int64_t e = 0;  // relative to e0
-            if (p0 < nLc)
-                e = staged ? upper_bound_dev(seo, (int64_t)0, ne, (int32_t)p0) - 1
-                           : upper_bound_dev(a.eoff, e0, e1, c0 + p0) - 1 - e0;
+            if (p0 < nLc) e = upper_bound_dev(a.eoff, e0, e1, c0 + p0) - 1 - e0;
             int32_t eo = 0, enext = 0;
             int64_t lb = 0;
             uint32_t xl = 0;
             if (p0 < nLc) {
-                eo = staged ? seo[e] : (int32_t)(a.eoff[e0 + e] - c0);
-                enext = staged ? seo[e + 1] : (int32_t)(a.eoff[e0 + e + 1] - c0);
-                lb = staged ? slb[e] : a.lbase[e0 + e];
-                xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
+                eo = (int32_t)(a.eoff[e0 + e] - c0);
+                enext = (int32_t)(a.eoff[e0 + e + 1] - c0);
+                lb = a.lbase[e0 + e];
+                xl = (uint32_t)(a.r_xr[e0 + e] - xa) << a.bz;
             }
-            // list positions first (LDS and arithmetic only), then every
-            // list load in one straight run so all of them are in flight
+            // list positions first, then every list load in one straight run
+            // so all of them are in flight
             uint32_t src[kDI];
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
@@ -286,9 +356,9 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
                     while (p >= enext) {  // next R tuple with a nonempty list
                         ++e;
                         eo = enext;
-                        enext = staged ? seo[e + 1] : (int32_t)(a.eoff[e0 + e + 1] - c0);
-                        lb = staged ? slb[e] : a.lbase[e0 + e];
-                        xl = (uint32_t)(staged ? sxl[e] : a.r_xr[e0 + e] - xa) << a.bz;
+                        enext = (int32_t)(a.eoff[e0 + e + 1] - c0);
+                        lb = a.lbase[e0 + e];
+                        xl = (uint32_t)(a.r_xr[e0 + e] - xa) << a.bz;
                     }
                     key = xl;
                     sj = (uint32_t)(lb + (p - eo));
@@ -309,7 +379,7 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         pc.mark(kPhGather);
 
         const int xbits = (xb - xa - 1) > 0 ? 32 - __clz((uint32_t)(xb - xa - 1)) : 0;
-        const uint32_t d_all = sort_unique(k, nn, xbits + a.bz, sk, cnt, lds_scan, pc);
+        const uint32_t d_all = sort_unique(k, nn, xbits + a.bz, sk, cnt, lds_scan, pc, staged);
         pc.mark(kPhUnique);
         const int64_t base = a.toff[xa];
         for (uint32_t i0 = tid; i0 < d_all; i0 += kDT * kWriteBatch) {  // LDS reads, then stores
