@@ -105,15 +105,19 @@ struct DedupArgs {
 };
 
 // Phase clock: thread 0 adds the cycles since the last mark to clk[phase].
+// The last mark lives in LDS, so that a launch without clocks keeps no
+// timestamp in registers.
 struct PhaseClock {
     unsigned long long *clk;
-    long long t;
-    __device__ explicit PhaseClock(unsigned long long *c) : clk(c), t(clock64()) {}
+    long long *t;  // LDS
+    __device__ PhaseClock(unsigned long long *c, long long *slot) : clk(c), t(slot) {
+        if (clk && threadIdx.x == 0) *t = clock64();
+    }
     __device__ void mark(int phase) {
         if (clk && threadIdx.x == 0) {
             const long long now = clock64();
-            atomicAdd(&clk[phase], (unsigned long long)(now - t));
-            t = now;
+            atomicAdd(&clk[phase], (unsigned long long)(now - *t));
+            *t = now;
         }
     }
 };
@@ -121,9 +125,12 @@ enum { kPhGather, kPhSort, kPhUnique, kPhWritePacked, kPhLists, kPhWriteWin, kPh
        kPhCount };
 
 // LDS layouts padded against bank conflicts: key slot i and counter word w.
-__device__ __forceinline__ int kpad(int i) { return i + (i >> 5); }
+// (one pad word after every kDI keys: thread t's own keys t*kDI + j sit at
+// t*(kDI + 1) + j, one base register and immediate offsets, and an odd row
+// stride puts the 64 lanes of a wave in 64 different banks)
+__device__ __forceinline__ int kpad(int i) { return i + i / kDI; }
 __device__ __forceinline__ int cpad(int w) { return w + (w >> 4); }
-constexpr int kSkWords = kDCap + kDCap / 32;
+constexpr int kSkWords = kDCap + kDCap / kDI;
 constexpr int kCntWords = kRD * kDT / 2;
 constexpr int kCntPadded = kCntWords + kCntWords / 16;
 constexpr int kMaxStagedEdges = 1024;  // R tuples of a packed unit staged in LDS for the gather
@@ -247,8 +254,9 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
     __shared__ uint32_t lds_scan[kDT / kWave + 1];
     __shared__ int64_t lds_scan64[kDT / kWave + 1];
 
+    __shared__ long long clock_slot;
     const int tid = threadIdx.x;
-    PhaseClock pc(a.clk);
+    PhaseClock pc(a.clk, &clock_slot);
     const int64_t u = blockIdx.x;
     const int32_t xa = a.ustart[u];
     const int32_t win = a.uwin[u];
@@ -309,7 +317,9 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
                 ct[tid * kDI + j] = (uint16_t)run;
             }
             __syncthreads();
-            uint32_t src[kDI];
+            // each list load is issued as soon as its position is known (no
+            // array of positions stays live); the ORs come after all loads
+            uint32_t z[kDI];
 #pragma unroll
             for (int j = 0; j < kDI; ++j) {
                 const int p = j * kDT + tid;
@@ -323,13 +333,10 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
                     key = ((uint32_t)((int64_t)(hk >> a.bz) - xa) << a.bz) | ((uint32_t)hk & a.zmask);
                 }
                 k[j] = key;
-                src[j] = sj;
+                z[j] = (uint32_t)a.zlist[sj];
             }
 #pragma unroll
-            for (int j = 0; j < kDI; ++j) {
-                const uint32_t z = (uint32_t)a.zlist[src[j]];
-                k[j] = j * kDT + tid < nLc ? (k[j] | z) : k[j];
-            }
+            for (int j = 0; j < kDI; ++j) k[j] = j * kDT + tid < nLc ? (k[j] | z[j]) : k[j];
         } else {
             // tuples not staged: thread t takes candidates [t*kDI, t*kDI + kDI),
             // found by one search in the offsets and then a walk
