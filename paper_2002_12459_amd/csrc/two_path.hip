@@ -700,9 +700,44 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     const int bzr = bits_for((uint64_t)(dom_z - 1)), bzo = bits_for((uint64_t)(g.zspan - 1));
     const bool z_off = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
 
+    // Heavy matrices: M1 = heavy x by heavy y (R), M2^T = heavy z by heavy y (S).
+    // The pass over R also marks the heavy y that some heavy x meets: only
+    // those y need the light-z part of their list below.
+    DBuf<int8_t> M1, M2t;
+    DBuf<int32_t> need_y;  // per heavy y: 1 if a heavy x meets it
+    int64_t ld = 0;
+    if (has_heavy) {
+        ld = ceil_div(v, kBmmPadK) * kBmmPadK;
+        M1 = c.buf<int8_t>((size_t)(u * ld));
+        M2t = c.buf<int8_t>((size_t)(w * ld));
+        need_y = c.buf<int32_t>(v);
+        c.zero(M1.get(), (size_t)(u * ld));
+        c.zero(M2t.get(), (size_t)(w * ld));
+        c.zero(need_y.get(), (size_t)v);
+        int8_t *m1 = M1.get(), *m2 = M2t.get();
+        int32_t *nd = need_y.get();
+        const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = adj_s.get();
+        const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
+        const int64_t ldl = ld;
+        for_each(c, n_r2, [=] __device__(int64_t e) {
+            const int32_t a = hx[xr[e]];
+            if (a >= 0) {  // the y gather only for heavy x
+                const int32_t b = hy[ar[e]];
+                if (b >= 0) {
+                    m1[(int64_t)a * ldl + b] = 1;
+                    nd[b] = 1;
+                }
+            }
+        });
+        for_each(c, n_s2, [=] __device__(int64_t e) {
+            const int32_t cc = hz[as[e]], b = hy[syr[e]];
+            if ((cc >= 0) & (b >= 0)) m2[(int64_t)(cc >= 0 ? cc : 0) * ldl + (b >= 0 ? b : 0)] = 1;
+        });
+    }
     // Witness lists.  zlist = N_S(y) for all y (adj_s, or the z offsets of
-    // the same tuples), then for heavy y the light-z part of N_S(y) (what a
-    // heavy R tuple still meets).
+    // the same tuples), then for heavy y the light-z part of N_S(y) (what an
+    // R tuple with heavy x and heavy y still meets; empty for heavy y that no
+    // heavy x meets, since no tuple reads it).
     DBuf<int64_t> lz_off;
     DBuf<int32_t> zlist_own;
     const int32_t *zfull = z_off ? reinterpret_cast<const int32_t *>(g.s2_zoff.get()) : adj_s.get();
@@ -715,6 +750,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         lz_off = c.buf<int64_t>(v + 1);
         int64_t *lo = lz_off.get();
         const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
+        const int32_t *ndc = need_y.get();
         zlist_own = c.buf<int32_t>(2 * n_s2);
         int32_t *zl = zlist_own.get();
         JP_HIP(hipMemcpyAsync(zl, zfull, n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
@@ -730,7 +766,9 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
                 const int32_t y = syr[e], z = as[e];
                 const int32_t h = hy[y];
                 const bool first = e == 0 || syr[e - 1] != y;
-                return Sum<LzItem>{(int64_t)((h >= 0) & (hz[z] < 0)), LzItem{h, zf[e], first}};
+                // light z at a heavy y that a heavy x meets (z looked up only there)
+                const bool keep = h >= 0 && ndc[h] != 0 && hz[z] < 0;
+                return Sum<LzItem>{(int64_t)keep, LzItem{h, zf[e], first}};
             },
             [=] __device__(int64_t, int64_t p, const Sum<LzItem> &it) {
                 if (it.add) la[p] = it.v.z;
@@ -753,26 +791,15 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get();
             const int64_t *lo = lz_off.get();
             const int64_t ns2 = n_s2;
-            // per y, the start and length of its light-z list (used at heavy y
-            // only), so that a tuple's loads all depend on its y alone
-            DBuf<int64_t> lzy = c.buf<int64_t>(2 * dom_y);
-            int64_t *lz = lzy.get();
-            for_each(c, dom_y, [=] __device__(int64_t y) {
-                const int32_t h = hy[y];
-                const int32_t hh = h >= 0 ? h : 0;
-                const int64_t l0 = lo[hh], l1 = lo[hh + 1];
-                lz[2 * y] = ns2 + l0;
-                lz[2 * y + 1] = l1 - l0;
-            });
-            const int64_t *lzc = lz;
             for_each(c, n_r2, [=] __device__(int64_t e) {
                 const int32_t y = ar[e];
                 const int32_t hyv = hy[y], hxv = hx[xr[e]];
                 const bool heavy = (hyv | hxv) >= 0;  // both non-negative
-                const int64_t a0 = lzc[2 * y], al = lzc[2 * y + 1];
+                const int32_t hi2 = heavy ? hyv : 0;
+                const int64_t l0 = lo[hi2], l1 = lo[hi2 + 1];
                 const int64_t s0 = oy[y], s1v = oy[y + 1];
-                lb[e] = heavy ? a0 : s0;
-                ln[e] = heavy ? al : s1v - s0;
+                lb[e] = heavy ? ns2 + l0 : s0;
+                ln[e] = heavy ? l1 - l0 : s1v - s0;
             });
         } else {
             for_each(c, n_r2, [=] __device__(int64_t e) {
@@ -784,28 +811,6 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         int64_t *eo = eoff.get();
         scan_exclusive(c, n_r2, ArrayGet{ln}, ArrayPut{eo}, eo + n_r2);
         JP_HIP(hipMemcpyAsync(S + 15, eo + n_r2, sizeof(int64_t), hipMemcpyDeviceToDevice, c.stream));
-    }
-    // heavy matrices: M1 = heavy x by heavy y (R), M2^T = heavy z by heavy y (S)
-    DBuf<int8_t> M1, M2t;
-    int64_t ld = 0;
-    if (has_heavy) {
-        ld = ceil_div(v, kBmmPadK) * kBmmPadK;
-        M1 = c.buf<int8_t>((size_t)(u * ld));
-        M2t = c.buf<int8_t>((size_t)(w * ld));
-        c.zero(M1.get(), (size_t)(u * ld));
-        c.zero(M2t.get(), (size_t)(w * ld));
-        int8_t *m1 = M1.get(), *m2 = M2t.get();
-        const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = adj_s.get();
-        const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
-        const int64_t ldl = ld;
-        for_each(c, n_r2, [=] __device__(int64_t e) {
-            const int32_t a = hx[xr[e]], b = hy[ar[e]];
-            if ((a >= 0) & (b >= 0)) m1[(int64_t)(a >= 0 ? a : 0) * ldl + (b >= 0 ? b : 0)] = 1;
-        });
-        for_each(c, n_s2, [=] __device__(int64_t e) {
-            const int32_t cc = hz[as[e]], b = hy[syr[e]];
-            if ((cc >= 0) & (b >= 0)) m2[(int64_t)(cc >= 0 ? cc : 0) * ldl + (b >= 0 ? b : 0)] = 1;
-        });
     }
     // Light and heavy witnesses partition the full join: J_H = J - J_L.
     int64_t J_L = 0;
