@@ -427,19 +427,21 @@ __global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(Src in, K *out, int6
     const int64_t tile = blockIdx.x;
     const int64_t tbase = tile * kRsTile;
     const int w = threadIdx.x / kWave, lane = lane_id();
+    K k[kRsItems];
+    uint32_t rank[kRsItems];
+    const int64_t wbase = tbase + (int64_t)w * kWave * kRsItems;
+    // the tile's keys and its 256 digit offsets (one cache line each: the
+    // offsets are digit-major) are all in flight before the first wait
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const int64_t i = wbase + (int64_t)j * kWave + lane;
+        k[j] = in(i < n ? i : n - 1);
+    }
     for (int d = threadIdx.x; d < 256; d += kRsBlock) {
         for (int q = 0; q < W; ++q) wcnt[q][d] = 0;
         goff[d] = offs[(int64_t)d * ntiles + tile];
     }
     __syncthreads();
-    K k[kRsItems];
-    uint32_t rank[kRsItems];
-    const int64_t wbase = tbase + (int64_t)w * kWave * kRsItems;
-#pragma unroll
-    for (int j = 0; j < kRsItems; ++j) {  // all loads in flight before the first ballot
-        const int64_t i = wbase + (int64_t)j * kWave + lane;
-        k[j] = in(i < n ? i : n - 1);
-    }
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         int64_t i = wbase + (int64_t)j * kWave + lane;
