@@ -434,8 +434,19 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
             const int64_t lb = a.lbase[e];
             const int64_t ln = a.eoff[e + 1] - a.eoff[e];
             const int32_t *L = a.zlist + lb;
-            const int64_t s0 = lower_bound_dev(L, (int64_t)0, ln, (int32_t)lo);
-            const int64_t s1 = lower_bound_dev(L, s0, ln, (int32_t)hi);
+            // first entries >= lo and >= hi, searched in lockstep (two
+            // independent loads per step instead of two chains of steps):
+            // p0 / p1 end at the last entry below lo / hi
+            int64_t p0 = -1, p1 = -1;
+            for (int64_t step = ln > 0 ? (int64_t)1 << (63 - __clzll((unsigned long long)ln)) : 0; step > 0;
+                 step >>= 1) {
+                const int64_t q0 = p0 + step, q1 = p1 + step;
+                const int64_t v0 = q0 < ln ? (int64_t)L[q0] : INT64_MAX;
+                const int64_t v1 = q1 < ln ? (int64_t)L[q1] : INT64_MAX;
+                p0 = v0 < lo ? q0 : p0;
+                p1 = v1 < hi ? q1 : p1;
+            }
+            const int64_t s0 = p0 + 1, s1 = p1 + 1;
             b = lb + s0;
             len = s1 - s0;
             below = s0;
@@ -468,23 +479,31 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         return bb >= 0 ? (int64_t)a.zlist[bb + off] : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
     };
 
-    // count the window's candidates and those of x below it (stage offset)
+    // count the window's candidates and those of x below it (stage offset);
+    // with one chunk of lists, its table for the gather is kept
     int64_t before = 0, total = 0;
+    const bool one_chunk = nlists <= kListChunk;
     for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
         int64_t b, len, below, t1, t2;
         list_range(l0 + tid, zlo, zhi, b, len, below);
         (void)block_excl_scan<kDT>(below, lds_scan64, &t1);
-        (void)block_excl_scan<kDT>(len, lds_scan64, &t2);
+        const int64_t pre = block_excl_scan<kDT>(len, lds_scan64, &t2);
+        if (one_chunk) {
+            lpre[tid] = pre;
+            lbeg[tid] = b;
+            if (tid == 0) lpre[kListChunk] = t2;
+        }
         before += t1;
         total += t2;
     }
+    __syncthreads();
     const int64_t base = a.toff[x] + before;
     uint32_t d_all = 0;
     if (total <= kDCap) {
         // few enough to sort: gather z - zlo into the key buffer, then registers
         int64_t off = 0;
         for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
-            const int64_t tot = load_chunk(l0, zlo, zhi);
+            const int64_t tot = one_chunk ? total : load_chunk(l0, zlo, zhi);
             const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
             for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
                 int64_t z[kWinBatch];
