@@ -553,8 +553,10 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
             const int nwords = (int)cdiv(wbits, 32);
             for (int i = tid; i < nwords; i += kDT) sk[i] = 0;
             __syncthreads();
+            // the counting pass's table is this range's when the window is one range of one chunk
+            const bool reuse = one_chunk && s0 == zlo && s1 == zhi;
             for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
-                const int64_t tot = load_chunk(l0, s0, s1);
+                const int64_t tot = reuse ? total : load_chunk(l0, s0, s1);
                 const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
                 // kWinBatch candidates per thread per round: searches, then loads, then bits
                 for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
