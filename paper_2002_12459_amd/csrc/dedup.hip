@@ -471,9 +471,23 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         __syncthreads();
         return tot;
     };
-    // z of candidate q of the loaded chunk (nl lists)
-    auto chunk_z = [&](int64_t q, int64_t nl) -> int64_t {
-        const int64_t li = upper_bound_dev(lpre, (int64_t)0, nl, q) - 1;
+    // z of candidate q of the loaded chunk (nl lists).  li is the caller's
+    // list of its previous candidate (-1: none); a thread's candidates come
+    // in increasing order, so a short forward walk usually finds the list,
+    // else a search in the rest of the table.
+    auto chunk_z = [&](int64_t q, int64_t nl, int64_t &li) -> int64_t {
+        if (li < 0) {
+            li = upper_bound_dev(lpre, (int64_t)0, nl, q) - 1;
+        } else {
+            int steps = 0;
+            while (li + 1 < nl && lpre[li + 1] <= q) {
+                ++li;
+                if (++steps == 4) {
+                    li = upper_bound_dev(lpre, li, nl, q) - 1;
+                    break;
+                }
+            }
+        }
         const int64_t bb = lbeg[li];
         const int64_t off = q - lpre[li];
         return bb >= 0 ? (int64_t)a.zlist[bb + off] : (int64_t)((uint32_t)a.hkeys[-1 - bb + off] & a.zmask);
@@ -505,12 +519,13 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
             const int64_t tot = one_chunk ? total : load_chunk(l0, zlo, zhi);
             const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
+            int64_t li = -1;
             for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
                 int64_t z[kWinBatch];
 #pragma unroll
                 for (int r = 0; r < kWinBatch; ++r) {
                     const int64_t q = q0 + (int64_t)r * kDT;
-                    z[r] = chunk_z(q < tot ? q : q0, nl);
+                    z[r] = chunk_z(q < tot ? q : tot - 1, nl, li);
                 }
 #pragma unroll
                 for (int r = 0; r < kWinBatch; ++r) {
@@ -558,13 +573,14 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
             for (int64_t l0 = 0; l0 < nlists; l0 += kListChunk) {
                 const int64_t tot = reuse ? total : load_chunk(l0, s0, s1);
                 const int64_t nl = (nlists - l0) < kListChunk ? (nlists - l0) : kListChunk;
+                int64_t li = -1;
                 // kWinBatch candidates per thread per round: searches, then loads, then bits
                 for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kDT * kWinBatch) {
                     int64_t z[kWinBatch];
 #pragma unroll
                     for (int r = 0; r < kWinBatch; ++r) {
                         const int64_t q = q0 + (int64_t)r * kDT;
-                        z[r] = chunk_z(q < tot ? q : q0, nl);
+                        z[r] = chunk_z(q < tot ? q : tot - 1, nl, li);
                     }
 #pragma unroll
                     for (int r = 0; r < kWinBatch; ++r) {
