@@ -102,6 +102,11 @@ struct DedupArgs {
     int64_t *ubase;          // where the unit's pairs start in stage
     int64_t *err;
     unsigned long long *clk; // optional per-phase cycle totals (JP_PHASE_CLOCKS)
+    // Window boundaries in the lists of every large x: for list l of x and
+    // boundary b (0..nw), wpos[wposx[x] + l*(nw + 1) + b] is the first entry
+    // of the list at or above min(b*ws, dom_z) (ws = window width).
+    const uint32_t *wpos;    // (list positions are below 2^32); nullptr: search instead
+    const int64_t *wposx;    // dom_x + 1
 };
 
 // Phase clock: thread 0 adds the cycles since the last mark to clk[phase].
@@ -429,7 +434,14 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
         len = 0;
         below = 0;
         if (l >= nlists) return;
-        if (l < e1 - e0) {
+        if (a.wpos && l < e1 - e0 && lo == zlo && hi == zhi) {  // the window itself: from the boundary table
+            const int64_t e = e0 + l;
+            const uint32_t *P = a.wpos + a.wposx[x] + l * (nw + 1) + win;
+            const int64_t s0 = P[0], s1 = P[1];
+            b = a.lbase[e] + s0;
+            len = s1 - s0;
+            below = s0;
+        } else if (l < e1 - e0) {
             const int64_t e = e0 + l;
             const int64_t lb = a.lbase[e];
             const int64_t ln = a.eoff[e + 1] - a.eoff[e];
@@ -621,6 +633,27 @@ __global__ __launch_bounds__(kDT, 4) void k_dedup(DedupArgs a) {  // 4 workgroup
     if (a.clk && tid == 0) atomicAdd(&a.clk[kPhUnitsWin], 1ull);
 }
 
+// Window boundary table (see DedupArgs::wpos): entry i belongs to the large
+// x whose range of wposx holds it; one binary search in one list per entry.
+struct WposArgs {
+    const int64_t *wposx, *toff, *off_x, *eoff, *lbase;
+    const int32_t *zlist;
+    int64_t dom_x, dom_z, n;
+    uint32_t *wpos;
+};
+__global__ __launch_bounds__(256) void k_window_bounds(WposArgs a) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t x = upper_bound_dev(a.wposx, (int64_t)0, a.dom_x, i) - 1;
+    const int64_t nw = windows_of(a.toff[x + 1] - a.toff[x], a.dom_z);
+    const int64_t ws = cdiv(a.dom_z, nw);
+    const int64_t r = i - a.wposx[x], l = r / (nw + 1), bnd = r % (nw + 1);
+    const int64_t e = a.off_x[x] + l;
+    const int64_t ln = a.eoff[e + 1] - a.eoff[e];
+    const int64_t z = bnd * ws < a.dom_z ? bnd * ws : a.dom_z;
+    a.wpos[i] = (uint32_t)lower_bound_dev(a.zlist + a.lbase[e], (int64_t)0, ln, (int32_t)z);
+}
+
 // Copies every unit's pairs from the stage to its output offset, turning
 // the unit-local keys back into ids: one workgroup per unit, coalesced reads
 // and writes, id lookups in the rank tables.
@@ -737,9 +770,41 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             },
             ArrayPut{nu}, nu + dom_x);
     }
-    int64_t hn[2];
-    c.load_scalars({nunits_x.get() + dom_x, toff.get() + dom_x}, hn);
-    const int64_t n_units = hn[0], n_cand = hn[1];
+    // window boundary table: (lists + 1 boundaries) entries per large x
+    DBuf<int64_t> wposx = c.buf<int64_t>(dom_x + 1);
+    {
+        const int64_t *to = toff.get(), *ox = in.off_x;
+        const int64_t dz = dom_z;
+        int64_t *wx = wposx.get();
+        scan_exclusive(
+            c, dom_x,
+            [=] __device__(int64_t x) -> int64_t {
+                const int64_t t = to[x + 1] - to[x];
+                return t > kSoloCap ? (ox[x + 1] - ox[x]) * (windows_of(t, dz) + 1) : 0;
+            },
+            ArrayPut{wx}, wx + dom_x);
+    }
+    int64_t hn[3];
+    c.load_scalars({nunits_x.get() + dom_x, toff.get() + dom_x, wposx.get() + dom_x}, hn);
+    const int64_t n_units = hn[0], n_cand = hn[1], n_wpos = hn[2];
+    // (beyond 2^31 entries the window units search their lists instead)
+    const bool use_wpos = n_wpos > 0 && n_wpos < (1ll << 31);
+    DBuf<uint32_t> wpos = c.buf<uint32_t>((size_t)(use_wpos ? n_wpos : 1));
+    if (use_wpos) {
+        WposArgs w;
+        w.wposx = wposx.get();
+        w.toff = toff.get();
+        w.off_x = in.off_x;
+        w.eoff = in.eoff;
+        w.lbase = in.lbase;
+        w.zlist = in.zlist;
+        w.dom_x = dom_x;
+        w.dom_z = dom_z;
+        w.n = n_wpos;
+        w.wpos = wpos.get();
+        hipLaunchKernelGGL(k_window_bounds, dim3(grid_x(ceil_div(n_wpos, 256), 256)), dim3(256), 0, c.stream, w);
+        JP_HIP(hipGetLastError());
+    }
     DBuf<int32_t> ustart = c.buf<int32_t>(n_units + 1), uwin = c.buf<int32_t>(n_units + 1);
     {
         const int64_t *to = toff.get(), *nu = nunits_x.get();
@@ -807,6 +872,8 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
         a.ucount = ucount.get();
         a.ubase = ubase.get();
         a.err = S + 1;
+        a.wpos = use_wpos ? wpos.get() : nullptr;
+        a.wposx = wposx.get();
         DBuf<unsigned long long> clk;
         a.clk = nullptr;
         if (std::getenv("JP_PHASE_CLOCKS")) {
