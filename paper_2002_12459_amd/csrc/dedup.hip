@@ -173,13 +173,15 @@ __device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
 // sk[kpad(0 .. result)), in order.
 __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int B, uint32_t *sk, uint32_t *cnt,
                                                 uint32_t *lds_scan, PhaseClock &pc, bool striped = false) {
-const int tid = threadIdx.x;
-const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
+    const int tid = threadIdx.x;
+    const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
+    // counters cleared here for the first pass, then by each pass's read-back
+    // for the next (no barrier of their own)
+    for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
+    __syncthreads();
     for (int pass = 0; pass < passes; ++pass) {
         const bool str = striped && pass == 0;
         const int shift = pass * kRB;
-        for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
-        __syncthreads();
         // count with LDS atomics that return the old value: the updates of
         // one thread issue back to back instead of as dependent
         // read-modify-writes (a thread's counter stays below 2^16)
@@ -230,6 +232,8 @@ const int passes = (B > 0 ? B + kRB - 1 : kRB) / kRB;
             const int p = tid * kDI + j;
             k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
         }
+        if (pass + 1 < passes)
+            for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
         __syncthreads();
     }
     pc.mark(kPhSort);

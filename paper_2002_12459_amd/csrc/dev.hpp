@@ -38,28 +38,26 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 // Exclusive scan over the threads of a block of BLOCK threads.  `lds` needs
-// BLOCK/64 + 1 elements.  *total receives the block sum.
+// BLOCK/64 + 1 elements.  *total receives the block sum.  Every thread adds
+// up the wave totals itself (BLOCK/64 LDS reads), so the scan takes two
+// barriers: one before the reads, one before `lds` may be written again.
 template <int BLOCK, class T>
 __device__ __forceinline__ T block_excl_scan(T v, T *lds, T *total) {
     constexpr int W = BLOCK / kWave;
-    T inc = wave_incl_scan(v);
+    const T inc = wave_incl_scan(v);
     const int w = threadIdx.x / kWave;
     if (lane_id() == kWave - 1) lds[w] = inc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        T run = 0;
-        for (int i = 0; i < W; ++i) {
-            T t = lds[i];
-            lds[i] = run;
-            run += t;
-        }
-        lds[W] = run;
+    T pre = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const T t = lds[i];
+        pre += i < w ? t : T(0);
+        all += t;
     }
+    *total = all;
     __syncthreads();
-    T r = inc - v + lds[w];
-    *total = lds[W];
-    __syncthreads();
-    return r;
+    return inc - v + pre;
 }
 
 template <int BLOCK, class T>
