@@ -49,7 +49,7 @@ constexpr int64_t kWinTarget = 16384;              // candidates per bitmap wind
 constexpr int64_t kWinSort = (3 * kDCap) / 4;      // candidates per sorted window unit, aimed for
 constexpr int kListChunk = kDT;                    // lists handled per round in a window unit
 constexpr int kWinBatch = 4;                       // window candidates per thread with loads in flight
-constexpr int kWriteBatch = 4;                     // distinct keys per thread read from LDS before storing
+constexpr int kWriteBatch = 8;                     // distinct keys per thread read from LDS before storing
 
 __host__ __device__ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -676,7 +676,7 @@ struct CopyArgs {
     int64_t *err;
 };
 constexpr int kCopyBlock = 256;
-constexpr int kCopyBatch = 8;  // keys per thread whose loads are in flight together
+constexpr int kCopyBatch = 16;  // keys per thread whose loads are in flight together
 __global__ __launch_bounds__(kCopyBlock) void k_stage_copy(CopyArgs a) {
     const int64_t u = blockIdx.x;
     const int64_t n = a.ucount[u], src = a.ubase[u], dst = a.uoff[u];
