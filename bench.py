@@ -40,8 +40,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
 # profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
 # whose SHA-256 is given (None: not measured for the current source).
-DEDUP_TRAFFIC = {"sha256": "3f3334efe9c109f854446b4e120351c850d9a1602cc7b82e469cdfb73a4e65d9",
-                 "bytes_per_launch": 1847756504}
+DEDUP_TRAFFIC = {"sha256": "cedd46b7cd64643ae3792863910c17c705b8b783a54ef84ad37b3a7bfffe960f",
+                 "bytes_per_launch": 1842695832}
 
 
 def dedup_traffic():
