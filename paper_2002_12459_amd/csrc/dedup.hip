@@ -207,23 +207,41 @@ __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int 
         }
         uint32_t all;
         uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
+        // write-back in groups of eight words: the group's reads are issued
+        // together, then its writes (one LDS round trip per group)
+        constexpr int kGrp = 8;
+        static_assert(per % kGrp == 0, "whole groups");
 #pragma unroll
-        for (int i = 0; i < per; ++i) {
-            const int wi = cpad(tid * per + i);
-            const uint32_t wv = cnt[wi];
-            const uint32_t lo = wv & 0xffffu, hi = wv >> 16;
-            const uint32_t q0 = run, q1 = run + lo;
-            run += lo + hi;
-            cnt[wi] = (q0 & 0xffffu) | (q1 << 16);
+        for (int g = 0; g < per; g += kGrp) {
+            uint32_t wv[kGrp];
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i) {
+                const uint32_t lo = wv[i] & 0xffffu, hi = wv[i] >> 16;
+                const uint32_t q0 = run, q1 = run + lo;
+                run += lo + hi;
+                cnt[cpad(tid * per + g + i)] = (q0 & 0xffffu) | (q1 << 16);
+            }
         }
         __syncthreads();
+        // scatter without branches, in groups whose counter reads issue
+        // together: a slot past nn writes the last row's pad word, which no
+        // key slot uses
+        constexpr int kScatGrp = 5;
+        static_assert(kDI % kScatGrp == 0, "whole groups");
 #pragma unroll
-        for (int j = 0; j < kDI; ++j) {
-            const int p = str ? j * kDT + tid : tid * kDI + j;
-            if (p < nn) {
-                const int d = (int)((k[j] >> shift) & (kRD - 1));
-                const uint32_t dst = (uint32_t)ctr(cnt, d, tid) + loc[j];
-                sk[kpad(dst < (uint32_t)kDCap ? (int)dst : 0)] = k[j];
+        for (int g = 0; g < kDI; g += kScatGrp) {
+            uint32_t cb[kScatGrp];
+#pragma unroll
+            for (int i = 0; i < kScatGrp; ++i) cb[i] = ctr(cnt, (int)((k[g + i] >> shift) & (kRD - 1)), tid);
+#pragma unroll
+            for (int i = 0; i < kScatGrp; ++i) {
+                const int j = g + i;
+                const int p = str ? j * kDT + tid : tid * kDI + j;
+                const uint32_t dst = cb[i] + loc[j];
+                const int slot = p < nn ? kpad(dst < (uint32_t)kDCap ? (int)dst : 0) : kSkWords - 1;
+                sk[slot] = k[j];
             }
         }
         __syncthreads();
