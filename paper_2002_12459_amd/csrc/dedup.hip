@@ -199,18 +199,21 @@ __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int 
         // raking exclusive scan over [digit][thread]: thread t owns `per`
         // consecutive counter words (two 16-bit counters each)
         constexpr int per = kCntWords / kDT;
+        constexpr int kGrp = 8;
+        static_assert(per % kGrp == 0, "whole groups");
         uint32_t s = 0;
 #pragma unroll
-        for (int i = 0; i < per; ++i) {
-            const uint32_t wv = cnt[cpad(tid * per + i)];
-            s += (wv & 0xffffu) + (wv >> 16);
+        for (int g = 0; g < per; g += kGrp) {
+            uint32_t wv[kGrp];
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
+#pragma unroll
+            for (int i = 0; i < kGrp; ++i) s += (wv[i] & 0xffffu) + (wv[i] >> 16);
         }
         uint32_t all;
         uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
-        // write-back in groups of eight words: the group's reads are issued
-        // together, then its writes (one LDS round trip per group)
-        constexpr int kGrp = 8;
-        static_assert(per % kGrp == 0, "whole groups");
+        // write-back in groups of eight words as well: the group's reads are
+        // issued together, then its writes (one LDS round trip per group)
 #pragma unroll
         for (int g = 0; g < per; g += kGrp) {
             uint32_t wv[kGrp];

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace jp {
 
@@ -19,15 +20,32 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Inclusive scan over the 64 lanes of a wave.  32-bit values use DPP:
+// shifts by 1, 2, 4 and 8 lanes within each row of 16 (lanes with no
+// source add 0), then lane 15's total added to rows 1 and 3 (row_bcast:15)
+// and lane 31's to rows 2 and 3 (row_bcast:31); VALU only.  Wider values
+// use lane shuffles.
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-    const int lane = lane_id();
+    static_assert(std::is_integral<T>::value, "integer scans only");
+    if constexpr (sizeof(T) == 4) {
+        int x = (int)v;
+        x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+        x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+        x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+        x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+        x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15 into rows 1, 3
+        x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
+        return (T)x;
+    } else {
+        const int lane = lane_id();
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        T t = __shfl_up(v, o);
-        if (lane >= o) v += t;
+        for (int o = 1; o < kWave; o <<= 1) {
+            T t = __shfl_up(v, o);
+            if (lane >= o) v += t;
+        }
+        return v;
     }
-    return v;
 }
 
 template <class T>
