@@ -20,14 +20,23 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// x + (x moved by the DPP control CTRL in the rows of ROWS), 64-bit: both
+// halves moved, then one 64-bit add.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp_add64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROWS, 0xf, false);
+    return x + (((uint64_t)hi << 32) | lo);
+}
+
 // Inclusive scan over the 64 lanes of a wave.  32-bit values use DPP:
 // shifts by 1, 2, 4 and 8 lanes within each row of 16 (lanes with no
 // source add 0), then lane 15's total added to rows 1 and 3 (row_bcast:15)
-// and lane 31's to rows 2 and 3 (row_bcast:31); VALU only.  Wider values
-// use lane shuffles.
+// and lane 31's to rows 2 and 3 (row_bcast:31); VALU only.  64-bit values
+// take the same steps on both halves with a 64-bit add.
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-    static_assert(std::is_integral<T>::value, "integer scans only");
+    static_assert(std::is_integral<T>::value && (sizeof(T) == 4 || sizeof(T) == 8), "32- or 64-bit integers");
     if constexpr (sizeof(T) == 4) {
         int x = (int)v;
         x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
@@ -38,13 +47,14 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
         x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31 into rows 2, 3
         return (T)x;
     } else {
-        const int lane = lane_id();
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            T t = __shfl_up(v, o);
-            if (lane >= o) v += t;
-        }
-        return v;
+        uint64_t x = (uint64_t)v;
+        x = dpp_add64<0x111, 0xf>(x);  // row_shr:1
+        x = dpp_add64<0x112, 0xf>(x);  // row_shr:2
+        x = dpp_add64<0x114, 0xf>(x);  // row_shr:4
+        x = dpp_add64<0x118, 0xf>(x);  // row_shr:8
+        x = dpp_add64<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
+        x = dpp_add64<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3
+        return (T)x;
     }
 }
 
