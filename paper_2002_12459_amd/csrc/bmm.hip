@@ -228,7 +228,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                     mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
                 }
         uint32_t incl = wave_incl_scan(mine);
-        uint32_t wtot = __shfl(incl, kWave - 1);
+        uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
         if (base < 0) continue;
         int64_t pos = base + (incl - mine);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                     mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
                 }
         const uint32_t incl = wave_incl_scan(mine);
-        const uint32_t wtot = __shfl(incl, kWave - 1);
+        const uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<kBig / kWave>(wtot, count, sh_cnt, &sh_base);
         if (base < 0) continue;
         int64_t pos = base + (incl - mine);
@@ -403,7 +403,7 @@ __global__ __launch_bounds__(256) void k_emit_bitmap(const uint32_t *bitmap, int
         const uint32_t word = q < nwords ? bitmap[q] : 0u;
         const uint32_t mine = (uint32_t)__popc(word);
         const uint32_t incl = wave_incl_scan(mine);
-        const uint32_t wtot = __shfl(incl, kWave - 1);
+        const uint32_t wtot = wave_lane(incl, kWave - 1);
         if (wtot == 0) continue;
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(count, (unsigned long long)wtot);
@@ -546,7 +546,7 @@ __global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__
             for (int j = 0; j < 8; ++j)
                 mine += (acc[i][j] > 0 && row0 + ty + 16 * i < u && col0 + tx + 16 * j < w) ? 1u : 0u;
         const uint32_t incl = wave_incl_scan(mine);
-        const uint32_t wtot = __shfl(incl, kWave - 1);
+        const uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
         if (base < 0) continue;
         int64_t pos = base + (incl - mine);

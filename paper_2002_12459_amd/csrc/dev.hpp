@@ -58,11 +58,24 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
     }
 }
 
+// Value of lane `lane` (the same for the whole wave) to every lane, by
+// v_readlane (no LDS crossbar).  The wave must be converged.
+template <class T>
+__device__ __forceinline__ T wave_lane(T v, int lane) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_readlane((int)v, lane);
+    } else {
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, lane);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), lane);
+        return (T)(((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Sum over the wave, in every lane (the last lane of the inclusive scan).
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return wave_lane(wave_incl_scan(v), kWave - 1);
 }
 
 // Exclusive scan over the threads of a block of BLOCK threads.  `lds` needs

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put,
     wtot = wave_sum(wtot);
     int64_t A;
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wtot : (int64_t)0, lds, &A);
-    wpre = __shfl(wpre, 0);
+    wpre = wave_lane(wpre, 0);
     auto agg = [&](int64_t tile) {
         const int64_t b = tile * TILE, e = std::min<int64_t>(n, b + TILE);
         int64_t a = 0;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(kTileBlock) void k_scan_lb(int64_t n, G get, P put,
         int64_t i = wbase + (int64_t)j * kWave + lane;
         int64_t inc = wave_incl_scan(v[j]);
         if (i < n) put(i, carry + inc - v[j], r[j]);
-        carry += __shfl(inc, kWave - 1);
+        carry += wave_lane(inc, kWave - 1);
     }
 }
 
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kTileBlock) void k_compact_lb(int64_t n, Sel sel, E
     }
     int64_t A;
     int64_t wpre = block_excl_scan<kTileBlock>(lane == 0 ? wcnt : (int64_t)0, lds, &A);
-    wpre = __shfl(wpre, 0);
+    wpre = wave_lane(wpre, 0);
     auto agg = [&](int64_t tile) {
         const int64_t b = tile * TILE, e = std::min<int64_t>(n, b + TILE);
         int64_t a = 0;
