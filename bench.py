@@ -40,8 +40,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
 # profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
 # whose SHA-256 is given (None: not measured for the current source).
-DEDUP_TRAFFIC = {"sha256": "cedd46b7cd64643ae3792863910c17c705b8b783a54ef84ad37b3a7bfffe960f",
-                 "bytes_per_launch": 1842695832}
+DEDUP_TRAFFIC = {"sha256": "af19fdffbaab20918b65d1b099140e1e5a69e58e2c9d16c4241f78bd584c2654",
+                 "bytes_per_launch": 1843326376}
 
 
 def dedup_traffic():

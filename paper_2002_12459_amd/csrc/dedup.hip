@@ -142,15 +142,25 @@ constexpr int kMaxStagedEdges = 1024;  // R tuples of a packed unit staged in LD
 static_assert(4 * (kMaxStagedEdges + 2) + 12 * kMaxStagedEdges <= 4 * kCntPadded, "staging fits the counters");
 
 
-// Exclusive max-scan over the threads of the workgroup (0 for thread 0).
+// max(x, x moved by the DPP control CTRL in the rows of ROWS); a lane with
+// no source (or in a row outside ROWS) takes 0, which leaves x unchanged.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_max(uint32_t x) {
+    const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROWS, 0xf, false);
+    return t > x ? t : x;
+}
+
+// Exclusive max-scan over the threads of the workgroup (0 for thread 0); the
+// wave part by DPP in the steps of wave_incl_scan.
 __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *lds) {
     const int lane = lane_id(), w = threadIdx.x / kWave;
     uint32_t inc = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const uint32_t t = __shfl_up(inc, o);
-        if (lane >= o) inc = t > inc ? t : inc;
-    }
+    inc = dpp_max<0x111, 0xf>(inc);  // row_shr:1
+    inc = dpp_max<0x112, 0xf>(inc);  // row_shr:2
+    inc = dpp_max<0x114, 0xf>(inc);  // row_shr:4
+    inc = dpp_max<0x118, 0xf>(inc);  // row_shr:8
+    inc = dpp_max<0x142, 0xa>(inc);  // row_bcast:15 into rows 1, 3
+    inc = dpp_max<0x143, 0xc>(inc);  // row_bcast:31 into rows 2, 3
     if (lane == kWave - 1) lds[w] = inc;
     __syncthreads();
     uint32_t r = __shfl_up(inc, 1);
