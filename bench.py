@@ -175,7 +175,7 @@ def dense_leg(h, edges, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {a.gpus}); nothing in this build uses more than one.",
+        print(f"bench.py runs on one GPU only (asked for {a.gpus}); the library runs on a single GPU.",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
