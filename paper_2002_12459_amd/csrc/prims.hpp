@@ -236,11 +236,12 @@ __global__ __launch_bounds__(256) void k_reduce_sum(int64_t n, G get, int64_t *p
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(256) inline void k_reduce_parts(const int64_t *part, int64_t np, unsigned long long *out) {
-    __shared__ int64_t lds[256 / kWave + 1];
+template <int BLOCK>  // (a template, so that every translation unit may define it)
+__global__ __launch_bounds__(BLOCK) void k_reduce_parts(const int64_t *part, int64_t np, unsigned long long *out) {
+    __shared__ int64_t lds[BLOCK / kWave + 1];
     int64_t s = 0;
-    for (int64_t i = threadIdx.x; i < np; i += 256) s += part[i];
-    const int64_t t = block_sum<256>(s, lds);
+    for (int64_t i = threadIdx.x; i < np; i += BLOCK) s += part[i];
+    const int64_t t = block_sum<BLOCK>(s, lds);
     if (threadIdx.x == 0) *out = (unsigned long long)t;
 }
 
@@ -254,7 +255,7 @@ void reduce_sum(const Ctx &c, int64_t n, G get, unsigned long long *out_dev) {
     DBuf<int64_t> part = c.buf<int64_t>((size_t)blocks);
     hipLaunchKernelGGL((k_reduce_sum<G>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, n, get, part.get());
     JP_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, c.stream, (const int64_t *)part.get(), blocks, out_dev);
+    hipLaunchKernelGGL(k_reduce_parts<256>, dim3(1), dim3(256), 0, c.stream, (const int64_t *)part.get(), blocks, out_dev);
     JP_HIP(hipGetLastError());
 }
 
@@ -413,10 +414,10 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(Src keys, int64_t n, int s
 // Stable scatter of one tile: ranks within the tile by wave ballots (lanes
 // with the same digit matched bit by bit, the group leader bumps the wave's
 // digit counter), keys staged in LDS in digit order, then written out in
-// digit runs.  Four workgroups fit a CU (under 40 KB of LDS and at most 128
-// VGPRs for 64-bit keys).
+// digit runs.  Four workgroups fit a CU for keys of up to 8 bytes (under
+// 40 KB of LDS and at most 128 VGPRs); 16-byte keys need twice the LDS.
 template <class K, class Src>
-__global__ __launch_bounds__(kRsBlock, 4) void k_rs_scatter(Src in, K *out, int64_t n, int shift,
+__global__ __launch_bounds__(kRsBlock, sizeof(K) <= 8 ? 4 : 2) void k_rs_scatter(Src in, K *out, int64_t n, int shift,
                                                             const int64_t *offs, int64_t ntiles) {
     constexpr int W = kRsBlock / kWave;
     __shared__ K tk[kRsTile];

@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_index_to_host(const int64_t *sizes, con
                                                        int64_t big_cap, int64_t cap, int64_t *dst) {
     const int64_t n_rec = 3 * sizes[0], n_big = 2 * sizes[1];
     const int64_t total = 2 + n_rec + n_big;
-    const int64_t n = (total <= cap) & (sizes[1] <= big_cap) ? total : 2;
+    const int64_t n = ((total <= cap) & (sizes[1] <= big_cap)) ? total : 2;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
         dst[i] = i < 2 ? sizes[i] : (i < 2 + n_rec ? rec[i - 2] : big[i - 2 - n_rec]);
 }
