@@ -1,6 +1,8 @@
 """Algorithm 2 (Section 5) in the library, on the host, against its numpy
-restatement under oracle/ (a second implementation: the paper prints no
-optimizer numbers, so beyond these invariants the search is parity-unpinned)."""
+restatement under oracle/.  The paper prints no optimizer numbers, so both
+are pinned to hand-worked searches on hand-made degree summaries: every cost
+term, the step of Delta1, the Delta2 rule with its rounding, the tie rule of
+each mode and the plain-join rule, each worked out on paper."""
 import numpy as np
 import pytest
 
@@ -69,3 +71,94 @@ def test_summary_validation():
     if len(s["y"][0]) > 1:
         with pytest.raises(jp.JoinProjectError):
             jp.plan_summary(bad)
+
+
+def _hand_summary():
+    """A degree summary written by hand (no instance behind it), small enough
+    that every cost of the search can be worked out on paper.  N = 100 and an
+    output estimate of 1000 give Delta2 = floor(Delta1 / 10), at least 1."""
+    i64 = lambda *v: np.array(v, dtype=np.int64)
+    f64 = lambda *v: np.array(v, dtype=np.float64)
+    return dict(
+        n_r=100, n_s=100, dom_x=10, dom_y=5, dom_z=10, J=5000, out_est=1000.0,
+        y=(i64(2, 50), i64(3, 2), f64(12.0, 4988.0)),   # key degrees; sums of deg_R * deg_S
+        x=(i64(5, 20), i64(6, 4), f64(600.0, 4400.0)),  # deg_R(x); witnesses per degree
+        xcdf=(i64(2, 50), i64(7, 3), None),
+        z=(i64(5, 20), i64(6, 4), None),
+    )
+
+
+def _hand_cal(literal):
+    # light cost = witnesses only; heavy cost = u * v * w (one product entry, p = 1)
+    return dict(t_witness=1.0, t_seq=0.0, t_byte=0.0, t_x=0.0, eps=0.5, literal=literal,
+                mm_p=[1.0], mm_s=[1.0])
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_search(impl):
+    """Algorithm 2 on a hand-made summary, with the costs worked out by hand.
+
+    Light-only cost: all 5000 + 5000 witnesses = 10000.  Non-literal search
+    (eps = 0.5), starting at the largest key degree:
+      (50, 5): light 5000 + 600, v = 0 heavy y, no product        -> 5600
+      (25, 2): light 12, product 10 x 2 x 10                      -> 212
+      (12, 1), (6, 1), (3, 1): the same sets, 212 (ties continue)
+      (1, 1): light 0, product 10 x 5 x 10 = 500 > 212            -> stop at (3, 1).
+    Literal search (eps = 0.95, ties stop), starting at Delta1 = N = 100:
+      (100, 10): 5600;  (5, 1): 212;  next Delta1 = floor(0.25) = 0 -> stop at (5, 1).
+    """
+    s = _hand_summary()
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    for literal, want in ((0, (3, 1)), (1, (5, 1))):
+        d1, d2, c, clo = plan(s, _hand_cal(literal))
+        assert (d1, d2) == want, (literal, d1, d2)
+        assert c == pytest.approx(212.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_no_gain(impl):
+    """The same summary with a product 100 times dearer: (25, 2) then costs
+    12 + 20000, more than (50, 5) at 5600, so the search stops at once; 5600
+    beats the light-only 10000, so (50, 5) is returned.  With the product 10^4
+    times dearer and J below 20 N the plain join is kept instead."""
+    s = _hand_summary()
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    cal = dict(_hand_cal(0), mm_s=[100.0])
+    d1, d2, c, clo = plan(s, cal)
+    assert (d1, d2) == (50, 5) and c == pytest.approx(5600.0, rel=1e-12)
+    small = dict(s, J=2000)  # J <= 20 N
+    d1, d2, c, clo = plan(small, dict(_hand_cal(0), mm_s=[1e4]))
+    assert (d1, d2) == (None, None) and c == pytest.approx(10000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_all_terms(impl):
+    """Every term of the cost at 1 (T_I, T_m per x, T_s, T_m per byte):
+    light-only = 10000 + 10 + 10 * 10 = 10110.  (50, 5): 5600 + 10 + 10 * 10
+    = 5710.  (25, 2): 12 + 10 + 7 * 10 (x whose smallest key degree is at
+    most 25) + product 200 + bytes 10 * 2 + 10 * 2 = 332, the same down to
+    (3, 1); (1, 1): 0 + 10 + 0 + 500 + 100 = 610 stops the search."""
+    s = _hand_summary()
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    cal = dict(_hand_cal(0), t_x=1.0, t_seq=1.0, t_byte=1.0)
+    d1, d2, c, clo = plan(s, cal)
+    assert (d1, d2) == (3, 1)
+    assert c == pytest.approx(332.0, rel=1e-12) and clo == pytest.approx(10110.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_delta2_rounding(impl):
+    """A summary where the search ends at a Delta2 that rounding decides.
+    Key degrees 2 (x3), 20, 50; x and z degrees 3 (x6) and 20 (x4); product
+    cost 5 u v w.  (50, 5): 5600 with no heavy y.  (25, floor 2.5 = 2): light
+    12 + 400, product 5 * 10 * 1 * 10 -> 912.  (12, 1): light 12, product
+    5 * 10 * 2 * 10 -> 1012, worse: the search stops at (25, 2).  Rounding
+    Delta2 up instead would take (25, 3) at 1092 and end at (3, 1)."""
+    i64 = lambda *v: np.array(v, dtype=np.int64)
+    f64 = lambda *v: np.array(v, dtype=np.float64)
+    s = dict(_hand_summary(), y=(i64(2, 20, 50), i64(3, 1, 1), f64(12.0, 400.0, 4588.0)),
+             x=(i64(3, 20), i64(6, 4), f64(600.0, 4400.0)), z=(i64(3, 20), i64(6, 4), None))
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    d1, d2, c, clo = plan(s, dict(_hand_cal(0), mm_s=[5.0]))
+    assert (d1, d2) == (25, 2)
+    assert c == pytest.approx(912.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
