@@ -12,7 +12,10 @@ witness count, heavy product nonzeros) against the paper's definitions:
   is light in every other relation, R_i^+ the rest; the heavy part is the
   product of the grouped matrices V and W.
 * Lemma 3 (Section 3.1 analysis): closed-form thresholds for omega = 2.
-* Section 5: output-size estimate from |dom x| and the full join size.
+* Section 5: output-size estimate from |dom x| and the full join size, the
+  degree indexes, and Algorithm 2's cost-based threshold search (the paper
+  prints no numbers for it; tests/test_planner_cpu.py pins it to searches
+  worked out by hand).
 
 Readings of the paper where it is ambiguous (y classification shared by both
 relations with the larger degree deciding, light means degree <= threshold,
