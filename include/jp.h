@@ -201,6 +201,25 @@ jp_status jp_plan_summary(const jp_two_path_summary *s, const jp_calibration *ca
                           int64_t *delta2, double *cost, double *cost_light_only);
 
 /*
+ * Lemma 3 (Section 3.1 analysis, omega = 2): the minimisers of
+ * f(D1, D2) = N + N D1 + OUT D2 + N^2 / (D2 min(D1, D2)), namely
+ *   OUT <= N:  D1 = OUT^(1/3),  D2 = N / OUT^(2/3);
+ *   OUT >  N:  D1 = D2 = (2 N^2 / (N + OUT))^(1/3),
+ * rounded down to integers and clamped to [1, N] (integer degrees make the
+ * floor exact).  n = max(|R|, |S|), out = the output-size estimate.  Writes
+ * JP_DELTA_INF to both when n <= 0 or out <= 0.  Host only; JP_EINVAL when a
+ * pointer is NULL or out is not finite.
+ */
+jp_status jp_plan_theory(int64_t n, double out, int64_t *delta1, int64_t *delta2);
+
+/*
+ * Section 5 output-size estimate: the geometric mean of the lower bound
+ * max(|dom x|, (J / N)^2) and the upper bound min(|dom x| |dom z|, J), the
+ * lower bound first capped at the upper one.  0 when J <= 0.  Host only.
+ */
+double jp_estimate_out(int64_t dom_x, int64_t dom_z, int64_t J, int64_t n);
+
+/*
  * Index and summarise a two-path instance on the GPU (the first phase of
  * jp_two_path) and return the optimizer's thresholds plus 16 features for a
  * learned selector: log N_R, log N_S, log estimated |OUT|, y-degree quantiles

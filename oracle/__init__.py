@@ -7,6 +7,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``two_path`` / ``star`` / ``join_size``: plain C (``oracle.c``), the query
   definitions of Section 2.1 evaluated as Proposition 1 says (full join, then
   project and deduplicate by sorting).
+* ``two_path_par`` / ``star_par``: the same computation split over OpenMP
+  threads by ranges of the first output column (timed CPU baseline, and the
+  check of full-size outputs).
 * ``reference``: numpy restatements of the method's intermediate quantities
   (degrees, heavy/light partition, light witness count, heavy counts,
   thresholds), used to check the GPU path's statistics.
@@ -29,7 +32,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         src = os.path.join(_HERE, "oracle.c")
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, src])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, src])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -51,6 +54,14 @@ def _load():
         lib.orc_star.argtypes = [ctypes.c_int, ctypes.POINTER(i32p), ctypes.POINTER(i32p),
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32p),
                                  ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_two_path_par.restype = ctypes.c_int
+        lib.orc_two_path_par.argtypes = [i32p, i32p, ctypes.c_int64, i32p, i32p, ctypes.c_int64, ctypes.c_int,
+                                         ctypes.POINTER(i32p), ctypes.POINTER(i32p),
+                                         ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_star_par.restype = ctypes.c_int
+        lib.orc_star_par.argtypes = [ctypes.c_int, ctypes.POINTER(i32p), ctypes.POINTER(i32p),
+                                     ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.POINTER(i32p),
+                                     ctypes.POINTER(ctypes.c_int64)]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -76,8 +87,19 @@ def join_size(rx, ry, sz, sy) -> int:
     return int(j)
 
 
-def two_path(rx, ry, sz, sy):
-    """Distinct (x, z) of Q(x,z) = R(x,y), S(z,y), sorted by (x, z) signed."""
+def cores() -> int:
+    """Host threads this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+def two_path(rx, ry, sz, sy, threads: int = 0):
+    """Distinct (x, z) of Q(x,z) = R(x,y), S(z,y), sorted by (x, z) signed.
+
+    threads = 0: the plain single-thread oracle; threads >= 1: the OpenMP
+    variant with that many threads."""
     lib = _load()
     rx, ry, sz, sy = map(_col, (rx, ry, sz, sy))
     if rx.size != ry.size or sz.size != sy.size:
@@ -85,8 +107,12 @@ def two_path(rx, ry, sz, sy):
     ox = ctypes.POINTER(ctypes.c_int32)()
     oz = ctypes.POINTER(ctypes.c_int32)()
     n = ctypes.c_int64(0)
-    rc = lib.orc_two_path(_ptr(rx), _ptr(ry), rx.size, _ptr(sz), _ptr(sy), sz.size,
-                          ctypes.byref(ox), ctypes.byref(oz), ctypes.byref(n))
+    if threads:
+        rc = lib.orc_two_path_par(_ptr(rx), _ptr(ry), rx.size, _ptr(sz), _ptr(sy), sz.size, int(threads),
+                                  ctypes.byref(ox), ctypes.byref(oz), ctypes.byref(n))
+    else:
+        rc = lib.orc_two_path(_ptr(rx), _ptr(ry), rx.size, _ptr(sz), _ptr(sy), sz.size,
+                              ctypes.byref(ox), ctypes.byref(oz), ctypes.byref(n))
     if rc != 0:
         raise MemoryError(f"orc_two_path failed ({rc})")
     try:
@@ -99,10 +125,21 @@ def two_path(rx, ry, sz, sy):
     return x, z
 
 
-def star(rels):
+def two_path_par(rx, ry, sz, sy, threads: int | None = None):
+    """``two_path`` on ``threads`` OpenMP threads (default: all cores)."""
+    return two_path(rx, ry, sz, sy, threads=threads or cores())
+
+
+def star_par(rels, threads: int | None = None):
+    """``star`` on ``threads`` OpenMP threads (default: all cores)."""
+    return star(rels, threads=threads or cores())
+
+
+def star(rels, threads: int = 0):
     """Distinct tuples of the star query over ``rels = [(x_i, y_i), ...]``.
 
     Returns an int32 array of shape (n_out, k), rows sorted lexicographically.
+    threads as for ``two_path``.
     """
     lib = _load()
     k = len(rels)
@@ -118,7 +155,10 @@ def star(rels):
     ns = (ctypes.c_int64 * k)(*[a.size for a, _ in cols])
     out = P()
     n = ctypes.c_int64(0)
-    rc = lib.orc_star(k, xs, ys, ns, ctypes.byref(out), ctypes.byref(n))
+    if threads:
+        rc = lib.orc_star_par(k, xs, ys, ns, int(threads), ctypes.byref(out), ctypes.byref(n))
+    else:
+        rc = lib.orc_star(k, xs, ys, ns, ctypes.byref(out), ctypes.byref(n))
     if rc != 0:
         raise MemoryError(f"orc_star failed ({rc})")
     try:

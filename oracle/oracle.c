@@ -2,8 +2,10 @@
  * CPU oracle for the join-project queries.  TEST INFRASTRUCTURE ONLY: only
  * tests, the smoke check and the benchmark's CPU-baseline leg use it.
  *
- * Plain C, single thread, qsort + binary search.  Nothing here is blocked,
- * fused or reordered beyond the definitions it follows:
+ * Plain C, qsort + binary search, one thread (the *_par variants at the end
+ * split the same computation by first-column ranges over OpenMP threads).
+ * Nothing here is blocked, fused or reordered beyond the definitions it
+ * follows:
  *   - query definitions: paper Section 2.1 (two-path and star queries);
  *   - evaluation: Proposition 1 (Section 2.3): enumerate the full join with a
  *     worst-case optimal strategy, then project and deduplicate.
@@ -13,6 +15,9 @@
 
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
     uint32_t y; /* join value, biased so unsigned order == signed order */
@@ -232,6 +237,224 @@ int orc_star(int k, const int32_t *const *x, const int32_t *const *y,
 
 done:
     free(tup);
+    for (int i = 0; i < k; ++i) free(Rel[i]);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Multi-threaded variants (timed CPU baseline, and the check of full-size
+ * outputs).  The result is the same set, computed the same way, split by the
+ * value of the first output column: R (R_1 for the star) is sorted by that
+ * value, cut into ranges of whole values, and each range is joined, sorted
+ * and deduplicated on its own by one OpenMP thread.  Output tuples with
+ * different first values never coincide and the ranges are in ascending
+ * order, so concatenating the per-range results gives the sorted distinct
+ * output (Section 2.1: an output tuple's first value comes from R).
+ * ------------------------------------------------------------------------ */
+
+static int cmp_pair_by_v(const void *a, const void *b)
+{
+    const orc_pair *p = (const orc_pair *)a, *q = (const orc_pair *)b;
+    if (p->v != q->v) return p->v < q->v ? -1 : 1;
+    if (p->y != q->y) return p->y < q->y ? -1 : 1;
+    return 0;
+}
+
+/* Distinct rows of a relation sorted by (v, y); cut points of `nchunk`
+ * ranges of whole v values into cut[0..nchunk]. */
+static orc_pair *by_value_chunks(const int32_t *v, const int32_t *y, int64_t n, int64_t *nd, int nchunk,
+                                 int64_t *cut)
+{
+    orc_pair *p = (orc_pair *)malloc((size_t)(n > 0 ? n : 1) * sizeof(orc_pair));
+    if (!p) return NULL;
+    for (int64_t i = 0; i < n; ++i) {
+        p[i].y = bias(y[i]);
+        p[i].v = bias(v[i]);
+    }
+    qsort(p, (size_t)n, sizeof(orc_pair), cmp_pair_by_v);
+    int64_t m = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (m == 0 || cmp_pair_by_v(&p[m - 1], &p[i]) != 0) p[m++] = p[i];
+    *nd = m;
+    cut[0] = 0;
+    for (int c = 1; c < nchunk; ++c) {
+        int64_t at = m * c / nchunk;
+        if (at < cut[c - 1]) at = cut[c - 1];
+        while (at > cut[c - 1] && at < m && p[at].v == p[at - 1].v) ++at;
+        cut[c] = at;
+    }
+    cut[nchunk] = m;
+    return p;
+}
+
+static int chunks_for(int nthreads) { return nthreads > 1 ? 8 * nthreads : 1; }
+
+int orc_two_path_par(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                     const int32_t *s_z, const int32_t *s_y, int64_t n_s, int nthreads,
+                     int32_t **out_x, int32_t **out_z, int64_t *n_out)
+{
+    if (!out_x || !out_z || !n_out || n_r < 0 || n_s < 0 || nthreads < 1) return -1;
+    if ((n_r && (!r_x || !r_y)) || (n_s && (!s_z || !s_y))) return -1;
+    *out_x = *out_z = NULL;
+    *n_out = 0;
+    const int nchunk = chunks_for(nthreads);
+    int64_t *cut = (int64_t *)malloc((size_t)(nchunk + 1) * sizeof(int64_t));
+    uint64_t **ck = (uint64_t **)calloc((size_t)nchunk, sizeof(uint64_t *));
+    int64_t *cm = (int64_t *)calloc((size_t)nchunk + 1, sizeof(int64_t));
+    int64_t nr, ns;
+    orc_pair *R = NULL, *S = NULL;
+    int rc = 0;
+    if (!cut || !ck || !cm) { rc = -2; goto done; }
+    R = by_value_chunks(r_x, r_y, n_r, &nr, nchunk, cut);
+    S = index_by_y(s_z, s_y, n_s, &ns);
+    if (!R || !S) { rc = -2; goto done; }
+
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int c = 0; c < nchunk; ++c) {
+        int64_t J = 0;
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
+            int64_t lo = lower_y(S, ns, R[i].y), hi = lo;
+            while (hi < ns && S[hi].y == R[i].y) ++hi;
+            J += hi - lo;
+        }
+        uint64_t *key = (uint64_t *)malloc((size_t)(J > 0 ? J : 1) * sizeof(uint64_t));
+        if (!key) { cm[c] = -1; continue; }
+        int64_t w = 0;
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i)
+            for (int64_t j = lower_y(S, ns, R[i].y); j < ns && S[j].y == R[i].y; ++j)
+                key[w++] = ((uint64_t)R[i].v << 32) | (uint64_t)S[j].v;
+        qsort(key, (size_t)w, sizeof(uint64_t), cmp_u64);
+        int64_t m = 0;
+        for (int64_t i = 0; i < w; ++i)
+            if (m == 0 || key[m - 1] != key[i]) key[m++] = key[i];
+        ck[c] = key;
+        cm[c] = m;
+    }
+
+    int64_t total = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        if (cm[c] < 0) { rc = -2; goto done; }
+        total += cm[c];
+    }
+    int32_t *ox = (int32_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(int32_t));
+    int32_t *oz = (int32_t *)malloc((size_t)(total > 0 ? total : 1) * sizeof(int32_t));
+    if (!ox || !oz) { free(ox); free(oz); rc = -2; goto done; }
+    int64_t at = 0;
+    for (int c = 0; c < nchunk; ++c)
+        for (int64_t i = 0; i < cm[c]; ++i, ++at) {
+            ox[at] = unbias((uint32_t)(ck[c][i] >> 32));
+            oz[at] = unbias((uint32_t)(ck[c][i] & 0xffffffffu));
+        }
+    *out_x = ox;
+    *out_z = oz;
+    *n_out = total;
+
+done:
+    if (ck)
+        for (int c = 0; c < nchunk; ++c) free(ck[c]);
+    free(ck);
+    free(cm);
+    free(cut);
+    free(R);
+    free(S);
+    return rc;
+}
+
+int orc_star_par(int k, const int32_t *const *x, const int32_t *const *y,
+                 const int64_t *n, int nthreads, int32_t **out, int64_t *n_out)
+{
+    if (k < 1 || k > 8 || !x || !y || !n || !out || !n_out || nthreads < 1) return -1;
+    for (int i = 0; i < k; ++i)
+        if (n[i] < 0 || (n[i] && (!x[i] || !y[i]))) return -1;
+    *out = NULL;
+    *n_out = 0;
+    const int nchunk = chunks_for(nthreads);
+    int64_t *cut = (int64_t *)malloc((size_t)(nchunk + 1) * sizeof(int64_t));
+    uint32_t **ck = (uint32_t **)calloc((size_t)nchunk, sizeof(uint32_t *));
+    int64_t *cm = (int64_t *)calloc((size_t)nchunk + 1, sizeof(int64_t));
+    orc_pair *Rel[8] = {0};
+    int64_t nd[8] = {0};
+    int rc = 0;
+    if (!cut || !ck || !cm) { rc = -2; goto done; }
+    /* relation 1 by its free value (chunked), the others by y */
+    Rel[0] = by_value_chunks(x[0], y[0], n[0], &nd[0], nchunk, cut);
+    if (!Rel[0]) rc = -2;
+    for (int i = 1; i < k; ++i) {
+        Rel[i] = index_by_y(x[i], y[i], n[i], &nd[i]);
+        if (!Rel[i]) rc = -2;
+    }
+    if (rc) goto done;
+    g_k = k; /* read-only below */
+
+#pragma omp parallel for num_threads(nthreads) schedule(dynamic, 1)
+    for (int c = 0; c < nchunk; ++c) {
+        /* Per tuple (a, b) of relation 1, every combination of the other
+         * relations' neighbour lists of b. */
+        int64_t J = 0;
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
+            int64_t prod = 1;
+            for (int r = 1; r < k && prod; ++r) {
+                int64_t lo = lower_y(Rel[r], nd[r], Rel[0][i].y), hi = lo;
+                while (hi < nd[r] && Rel[r][hi].y == Rel[0][i].y) ++hi;
+                prod *= hi - lo;
+            }
+            J += prod;
+        }
+        uint32_t *tup = (uint32_t *)malloc((size_t)(J > 0 ? J : 1) * (size_t)k * sizeof(uint32_t));
+        if (!tup) { cm[c] = -1; continue; }
+        int64_t w = 0;
+        for (int64_t i = cut[c]; i < cut[c + 1]; ++i) {
+            const uint32_t b = Rel[0][i].y;
+            int64_t lo[8], hi[8], cur[8];
+            int empty = 0;
+            for (int r = 1; r < k; ++r) {
+                lo[r] = lower_y(Rel[r], nd[r], b);
+                hi[r] = lo[r];
+                while (hi[r] < nd[r] && Rel[r][hi[r]].y == b) ++hi[r];
+                if (hi[r] == lo[r]) empty = 1;
+                cur[r] = lo[r];
+            }
+            if (empty) continue;
+            for (;;) {
+                tup[w * k] = Rel[0][i].v;
+                for (int r = 1; r < k; ++r) tup[w * k + r] = Rel[r][cur[r]].v;
+                ++w;
+                int r = k - 1;
+                while (r >= 1 && ++cur[r] == hi[r]) { cur[r] = lo[r]; --r; }
+                if (r < 1) break;
+            }
+        }
+        qsort(tup, (size_t)w, (size_t)k * sizeof(uint32_t), cmp_tuple);
+        int64_t m = 0;
+        for (int64_t t = 0; t < w; ++t) {
+            if (m == 0 || cmp_tuple(&tup[(m - 1) * k], &tup[t * k]) != 0) {
+                if (m != t) memcpy(&tup[m * k], &tup[t * k], (size_t)k * sizeof(uint32_t));
+                ++m;
+            }
+        }
+        ck[c] = tup;
+        cm[c] = m;
+    }
+
+    int64_t total = 0;
+    for (int c = 0; c < nchunk; ++c) {
+        if (cm[c] < 0) { rc = -2; goto done; }
+        total += cm[c];
+    }
+    int32_t *o = (int32_t *)malloc((size_t)(total > 0 ? total : 1) * (size_t)k * sizeof(int32_t));
+    if (!o) { rc = -2; goto done; }
+    int64_t at = 0;
+    for (int c = 0; c < nchunk; ++c)
+        for (int64_t t = 0; t < cm[c] * k; ++t) o[at++] = unbias(ck[c][t]);
+    *out = o;
+    *n_out = total;
+
+done:
+    if (ck)
+        for (int c = 0; c < nchunk; ++c) free(ck[c]);
+    free(ck);
+    free(cm);
+    free(cut);
     for (int i = 0; i < k; ++i) free(Rel[i]);
     return rc;
 }

@@ -46,6 +46,16 @@ int orc_two_path(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
 int orc_star(int k, const int32_t *const *x, const int32_t *const *y,
              const int64_t *n, int32_t **out, int64_t *n_out);
 
+/* The same results computed by `nthreads` threads (OpenMP), each joining,
+ * sorting and deduplicating the tuples of R (of R_1 for the star) in one
+ * range of whole first-column values; the per-range results are disjoint
+ * and in ascending order, so they are concatenated.  nthreads >= 1. */
+int orc_two_path_par(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                     const int32_t *s_z, const int32_t *s_y, int64_t n_s, int nthreads,
+                     int32_t **out_x, int32_t **out_z, int64_t *n_out);
+int orc_star_par(int k, const int32_t *const *x, const int32_t *const *y,
+                 const int64_t *n, int nthreads, int32_t **out, int64_t *n_out);
+
 void orc_free(void *p);
 
 #ifdef __cplusplus

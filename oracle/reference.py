@@ -127,15 +127,18 @@ def two_path_stats(rx, ry, sz, sy, delta1, delta2, y_rule=Y_RULE_MAX):
     )
 
 
-def star_stats(rels, delta1, delta2):
-    """Star partition of Section 3.2 for k relations at (delta1, delta2).
+def star_parts(rels, delta1, delta2):
+    """The Section 3.2 partition of every relation of a star query.
 
-    A tuple (a,b) of R_i is in R_i^- when a has degree <= delta2 in R_i, in
-    R_i^diamond when b has degree <= delta1 in every other relation, and in
-    R_i^+ otherwise.  A witness (a_1..a_k, b) is heavy when every tuple is in
-    its R_i^+.  Returns J, J_L, J_H, the heavy x counts u_i, the number of
-    y values that can carry a heavy witness, the distinct heavy tuples and the
-    distinct light tuples.
+    After dropping tuples whose y is missing from some relation (they join
+    nothing), relation i is split as the paper defines it:
+      R_i^-       tuples (a, b) whose a has degree <= delta2 in R_i;
+      R_i^diamond tuples (a, b) whose b has degree <= delta1 in every OTHER
+                  relation R_j, j != i (R_i's own y-degree is not consulted);
+      R_i^+       R_i minus (R_i^- union R_i^diamond).
+    R_i^- and R_i^diamond may overlap.  Returns (relations as lists of
+    distinct (a, b) tuples, per-relation dicts of the three sets, x-degree
+    and y-degree maps).
     """
     k = len(rels)
     R = [distinct_edges(a, b) for a, b in rels]
@@ -145,44 +148,57 @@ def star_stats(rels, delta1, delta2):
     R = [(a[np.isin(b, common)], b[np.isin(b, common)]) for a, b in R]
     dx = [_deg(a) for a, _ in R]
     dy = [_deg(b) for _, b in R]
+    tuples = [list(zip(a.tolist(), b.tolist())) for a, b in R]
+    parts = []
+    for i in range(k):
+        minus = {(a, b) for a, b in tuples[i] if dx[i][a] <= delta2}
+        diamond = {(a, b) for a, b in tuples[i] if all(dy[j][b] <= delta1 for j in range(k) if j != i)}
+        plus = set(tuples[i]) - minus - diamond
+        parts.append({"minus": minus, "diamond": diamond, "plus": plus})
+    return tuples, parts, dx, dy
+
+
+def star_stats(rels, delta1, delta2):
+    """Witness classes of the star method of Section 3.2 at (delta1, delta2).
+
+    A witness (a_1..a_k, b) of the full join goes to the matrix product when
+    every (a_i, b) lies in R_i^+ (step 3); otherwise some tuple lies in R_i^-
+    or R_i^diamond and steps 1-2 enumerate it.  Returns J, J_L, J_H, the
+    heavy x counts u_i (x with degree > delta2), the number of y that carry a
+    heavy witness, the distinct heavy and light output tuples, and the
+    partition itself (see star_parts).
+    """
+    k = len(rels)
+    tuples, parts, dx, dy = star_parts(rels, delta1, delta2)
     by = []
-    for a, b in R:
+    for i in range(k):
         m = {}
-        for p, q in zip(a.tolist(), b.tolist()):
-            m.setdefault(q, []).append(p)
+        for a, b in tuples[i]:
+            m.setdefault(b, []).append(a)
         by.append(m)
     J = J_L = J_H = 0
     heavy, light = set(), set()
     hy = 0
-    for b in np.unique(common).tolist():
-        heavy_in = [dy[i][b] > delta1 for i in range(k)]
+    for b in sorted(by[0]):
         lists = [by[i][b] for i in range(k)]
-
-        def plus(i, a):
-            # a heavy in R_i and b heavy in some other relation
-            return dx[i][a] > delta2 and any(heavy_in[j] for j in range(k) if j != i)
-
         n_hw = 1
-        Hs = []
         for i in range(k):
-            H = [a for a in lists[i] if plus(i, a)]
-            Hs.append(H)
-            n_hw *= len(H)
+            n_hw *= sum(1 for a in lists[i] if (a, b) in parts[i]["plus"])
         tot = 1
         for L in lists:
             tot *= len(L)
         J += tot
         J_H += n_hw
         J_L += tot - n_hw
-        if sum(heavy_in) >= 2:
+        if n_hw:
             hy += 1
         for t in itertools.product(*lists):
-            if all(plus(i, t[i]) for i in range(k)):
+            if all((t[i], b) in parts[i]["plus"] for i in range(k)):
                 heavy.add(t)
             else:
                 light.add(t)
     u = [sum(1 for a, d in dx[i].items() if d > delta2) for i in range(k)]
-    return dict(J=J, J_L=J_L, J_H=J_H, u=u, v=hy, heavy=heavy, light=light)
+    return dict(J=J, J_L=J_L, J_H=J_H, u=u, v=hy, heavy=heavy, light=light, parts=parts)
 
 
 def theory_thresholds(n: int, out: float):
@@ -191,10 +207,13 @@ def theory_thresholds(n: int, out: float):
     Case OUT <= N: D1 = OUT^(1/3), D2 = N / OUT^(2/3).
     Case OUT > N:  D1 = D2 = (2 N^2 / (N + OUT))^(1/3).
     Real-valued (before rounding to integers).
+    Cube roots are the real cube root (np.cbrt), exact on perfect cubes, so
+    that rounding down an exact cube gives the cube root itself.
     """
     if out <= n:
-        return out ** (1.0 / 3.0), n / out ** (2.0 / 3.0)
-    d = (2.0 * n * n / (n + out)) ** (1.0 / 3.0)
+        c = float(np.cbrt(out))
+        return c, n / (c * c)
+    d = float(np.cbrt(2.0 * n * n / (n + out)))
     return d, d
 
 

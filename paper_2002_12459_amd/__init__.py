@@ -18,7 +18,7 @@ import threading
 __all__ = [
     "LIB_PATH", "JoinProjectError", "Handle", "Result", "two_path", "star", "bool_matmul",
     "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF", "selector_cells", "mlp_param_count",
-    "SELECTOR_PATH", "load_selector_file",
+    "SELECTOR_PATH", "load_selector_file", "plan_theory", "estimate_out",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -144,6 +144,9 @@ def _load():
                                         ctypes.POINTER(ctypes.c_double)]
         lib.jp_plan_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(i64),
                                          ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_float)]
+        lib.jp_plan_theory.argtypes = [i64, ctypes.c_double, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.jp_estimate_out.argtypes = [i64, i64, i64, i64]
+        lib.jp_estimate_out.restype = ctypes.c_double
         lib.jp_two_path_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Instance), ctypes.POINTER(Options),
                                           ctypes.POINTER(P)]
         lib.jp_result_batch_offsets.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(i64)]
@@ -164,7 +167,7 @@ def _load():
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
-                  "jp_two_path_batch", "jp_result_batch_offsets"):
+                  "jp_two_path_batch", "jp_result_batch_offsets", "jp_plan_theory"):
             getattr(lib, f).restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -572,6 +575,22 @@ def default_calibration():
     c = Calibration()
     _load().jp_default_calibration(ctypes.byref(c))
     return c.as_dict()
+
+
+def plan_theory(n, out):
+    """Lemma 3 thresholds (integers, None = infinity) for N = n and output
+    estimate out.  Runs on the host."""
+    d1, d2 = ctypes.c_int64(), ctypes.c_int64()
+    st = _load().jp_plan_theory(int(n), float(out), ctypes.byref(d1), ctypes.byref(d2))
+    if st != 0:
+        raise JoinProjectError(st, "jp_plan_theory failed")
+    inf = lambda v: None if v == DELTA_INF else v
+    return inf(d1.value), inf(d2.value)
+
+
+def estimate_out(dom_x, dom_z, J, n):
+    """Section 5 output-size estimate (host)."""
+    return float(_load().jp_estimate_out(int(dom_x), int(dom_z), int(J), int(n)))
 
 
 def plan_summary(summary, cal=None):

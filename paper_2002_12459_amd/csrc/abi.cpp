@@ -312,6 +312,18 @@ jp_status jp_plan_summary(const jp_two_path_summary *s, const jp_calibration *ca
     }
 }
 
+jp_status jp_plan_theory(int64_t n, double out, int64_t *delta1, int64_t *delta2) {
+    if (!delta1 || !delta2 || !std::isfinite(out)) return JP_EINVAL;
+    const jp::Thresholds th = jp::theory_thresholds(n, out);
+    *delta1 = th.d1;
+    *delta2 = th.d2;
+    return JP_OK;
+}
+
+double jp_estimate_out(int64_t dom_x, int64_t dom_z, int64_t J, int64_t n) {
+    return jp::estimate_out(dom_x, dom_z, J, n);
+}
+
 jp_status jp_plan_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
                            const int32_t *s_y, int64_t n_s, const jp_options *opt, int64_t *delta1,
                            int64_t *delta2, float *features) {

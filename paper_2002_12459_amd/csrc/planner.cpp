@@ -42,7 +42,7 @@ Thresholds theory_thresholds(int64_t N, double out) {
     double d1, d2;
     if (out <= (double)N) {
         d1 = std::cbrt(out);
-        d2 = (double)N / std::pow(out, 2.0 / 3.0);
+        d2 = (double)N / (d1 * d1);
     } else {
         d1 = d2 = std::cbrt(2.0 * (double)N * (double)N / ((double)N + out));
     }

@@ -325,3 +325,155 @@ def test_out_estimate_within_bounds():
         dom = np.unique(x).size
         est = ref.out_estimate(dom, dom, J, len(x))
         assert dom <= est <= min(dom * dom, J)
+
+
+# ---------------------------------------------------------------------------
+# Star partition (Section 3.2) pinned to hand-worked cases
+# ---------------------------------------------------------------------------
+
+def _example_star_rels():
+    R, S, _ = _example_two_path()
+    rows = load_golden("star_example.txt")
+    T = [(int(r[1]), int(r[2])) for r in rows if r[0] == "T"]
+    U = [(int(r[1]), int(r[2])) for r in rows if r[0] == "U"]
+    rel = lambda E: (np.array([e[0] for e in E]), np.array([e[1] for e in E]))
+    return rel([r[:2] for r in R]), rel([s[:2] for s in S]), rel(T), rel(U)
+
+
+def test_star_example_partition_by_hand():
+    """The star example at Delta1 = Delta2 = 2, worked by hand from the
+    Section 3.2 definitions.
+
+    x-degrees in R: x1 1, x2 2, x3 2, x4 3, x5 3, x6 3, so R^- holds the
+    tuples of x1, x2, x3.  y-degrees (R, S, T, U): y1 (2,1,2,1), y2 (2,2,2,1),
+    y3 (1,2,2,1), y4 (3,2,3,3), y5 (3,3,3,4), y6 (3,4,3,3).  The y light in
+    every other relation (S, T for Q*_3; S, T, U for Q*_4) are y1, y2, y3, so
+    R^diamond holds the R tuples at those y.  The example's remark that R^-
+    equals R^diamond does not hold under the definitions.
+    J = sum over y of the degree products: Q*_3 4+8+4+18+27+36 = 97,
+    Q*_4 4+8+4+54+108+108 = 286.
+    """
+    Rr, Sr, Tr, Ur = _example_star_rels()
+    minus = {(1, 6), (2, 1), (2, 2), (3, 5), (3, 3)}
+    diamond = {(2, 1), (2, 2), (3, 3), (4, 1), (6, 2)}
+    for rels, J in (([Rr, Sr, Tr], 97), ([Rr, Sr, Tr, Ur], 286)):
+        _, parts, _, _ = ref.star_parts(rels, 2, 2)
+        assert parts[0]["minus"] == minus
+        assert parts[0]["diamond"] == diamond
+        assert parts[0]["plus"] == {(4, 4), (4, 6), (5, 4), (5, 5), (5, 6), (6, 4), (6, 5)}
+        st = ref.star_stats(rels, 2, 2)
+        assert st["J"] == J and st["J_L"] + st["J_H"] == J
+
+
+def test_star_plus_needs_y_heavy_in_some_other_relation():
+    """R_i^+ = R_i minus R_i^- minus R_i^diamond: heavy x and y heavy in at
+    least one OTHER relation.  Delta1 = Delta2 = 1.
+
+    Case A: y0 and y1 each have degree 2 in R1 and R2 and 1 in R3; x0, x1
+    have degree 2 in R1 and R2, x0 degree 2 in R3.  Every tuple sees its y
+    heavy in another relation (R3's tuples see R1 and R2), so all
+    2*2*1 witnesses per y are heavy: J = J_H = 8.  (Requiring y heavy in
+    every other relation would make J_H = 0.)
+    Case B: R2 = R3 = {(0,0), (0,1)}: y light in R2 and R3, so R1's tuples are
+    in R1^diamond and no witness is heavy: J = 4, J_H = 0.  (Counting R1's own
+    y-degree would make J_H = 4.)
+    """
+    full = (np.array([0, 1, 0, 1]), np.array([0, 0, 1, 1]))
+    one = (np.array([0, 0]), np.array([0, 1]))
+    st = ref.star_stats([full, full, one], 1, 1)
+    assert (st["J"], st["J_L"], st["J_H"]) == (8, 0, 8)
+    assert st["u"] == [2, 2, 1] and st["v"] == 2
+    assert st["heavy"] == {(0, 0, 0), (0, 1, 0), (1, 0, 0), (1, 1, 0)}
+    st = ref.star_stats([full, one, one], 1, 1)
+    assert (st["J"], st["J_L"], st["J_H"]) == (4, 4, 0)
+    assert st["heavy"] == set()
+    _, parts, _, _ = ref.star_parts([full, one, one], 1, 1)
+    assert parts[0]["diamond"] == {(0, 0), (1, 0), (0, 1), (1, 1)}
+    assert parts[1]["plus"] == {(0, 0), (0, 1)}
+
+
+# ---------------------------------------------------------------------------
+# Section 5 indexes and the output estimate, pinned to a hand-made instance
+# ---------------------------------------------------------------------------
+
+HAND_R = ([1, 1, 2, 3, 3, 4], [10, 11, 10, 11, 12, 13])
+HAND_S = ([7, 8, 7, 9, 7, 8, 9, 8], [10, 10, 11, 12, 12, 12, 13, 14])
+
+
+def test_degree_summary_by_hand():
+    """Worked by hand.  S's (8, 14) is dangling (no y 14 in R) and dropped.
+    deg_R(y): 10:2 11:2 12:1 13:1; deg_S(y): 10:2 11:1 12:3 13:1.
+    Key degree (larger of the two): 10:2 11:2 12:3 13:1.
+      y index: degree 1 -> {13}, sum 1*1 = 1; degree 2 -> {10, 11}, sum
+               2*2 + 2*1 = 6; degree 3 -> {12}, sum 1*3 = 3.
+      x index: deg_R(x) x1:2 x2:1 x3:2 x4:1; witnesses of x (sum of deg_S
+               over its y): x1 2+1 = 3, x2 2, x3 1+3 = 4, x4 1; degree 1 ->
+               count 2, sum 3; degree 2 -> count 2, sum 7.
+      cdfx:    smallest key degree among the y of x: x1 2, x2 2, x3 2, x4 1.
+      z index: deg_S(z) z7:3 z8:2 z9:2.
+    J = 4 + 2 + 3 + 1 = 10, N = max(6, 7) = 7.
+    With deg_R alone as the key: y keys 10:2 11:2 12:1 13:1, y index
+    degree 1 -> {12, 13}, sum 3 + 1 = 4; degree 2 -> sum 6; cdfx x3 -> 1.
+    """
+    d = ref.degree_summary(*HAND_R, *HAND_S)
+    assert (d["n_r"], d["n_s"], d["dom_x"], d["dom_y"], d["dom_z"], d["J"]) == (6, 7, 4, 4, 3, 10)
+
+    def same(idx, deg, cnt, sm=None):
+        np.testing.assert_array_equal(idx[0], deg)
+        np.testing.assert_array_equal(idx[1], cnt)
+        if sm is None:
+            assert idx[2] is None
+        else:
+            np.testing.assert_array_equal(idx[2], sm)
+
+    same(d["y"], [1, 2, 3], [1, 2, 1], [1.0, 6.0, 3.0])
+    same(d["x"], [1, 2], [2, 2], [3.0, 7.0])
+    same(d["xcdf"], [1, 2], [1, 3])
+    same(d["z"], [2, 3], [2, 1])
+    r = ref.degree_summary(*HAND_R, *HAND_S, y_rule=ref.Y_RULE_R_ONLY)
+    same(r["y"], [1, 2], [2, 2], [4.0, 6.0])
+    same(r["xcdf"], [1, 2], [2, 2])
+    same(r["x"], [1, 2], [2, 2], [3.0, 7.0])
+
+
+def test_out_estimate_by_hand():
+    """Section 5 estimate on the hand-made instance: lower bound
+    max(|dom x|, (J/N)^2) = max(4, (10/7)^2) = 4, upper bound
+    min(|dom x| |dom z|, J) = min(12, 10) = 10, geometric mean sqrt(40).
+    (The arithmetic mean would be 7.)  The true |OUT| is 8: x1 {7,8},
+    x2 {7,8}, x3 {7,8,9}, x4 {9}."""
+    d = ref.degree_summary(*HAND_R, *HAND_S)
+    assert d["out_est"] == pytest.approx(np.sqrt(40.0), rel=1e-12)
+    assert ref.out_estimate(4, 3, 10, 7) == pytest.approx(6.324555320336759, rel=1e-12)
+    ox, oz = oracle.two_path(*HAND_R, *HAND_S)
+    assert as_pairs(ox, oz) == [(1, 7), (1, 8), (2, 7), (2, 8), (3, 7), (3, 8), (3, 9), (4, 9)]
+    # (J/N)^2 as the lower bound: |dom x| = 5, |dom z| = 1000, J = 2000,
+    # N = 100: lo = max(5, 400) = 400, hi = min(5000, 2000) = 2000
+    assert ref.out_estimate(5, 1000, 2000, 100) == pytest.approx(np.sqrt(400.0 * 2000.0), rel=1e-12)
+    # bounds that cross (lo > hi) collapse to the upper bound
+    assert ref.out_estimate(5, 1000, 1000, 10) == pytest.approx(1000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_parallel_oracle_matches_plain(threads):
+    """The multi-threaded variants split R (R_1) by first-column ranges; they
+    must give exactly the single-thread result, including signed extremes
+    and repeated rows."""
+    for seed in range(4):
+        rx, ry = datagen.random_small(400, 60, 25, seed, dup=True, signed=seed % 2 == 1)
+        sz, sy = datagen.random_small(380, 60, 25, seed + 9, dup=True, signed=seed % 2 == 1)
+        if seed % 2:
+            sy = ry[np.random.default_rng(seed).integers(0, ry.size, sy.size)]
+        a = oracle.two_path(rx, ry, sz, sy)
+        b = oracle.two_path(rx, ry, sz, sy, threads=threads)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        rels = [datagen.random_small(150, 20, 8, seed * 3 + i, dup=True) for i in range(3)]
+        np.testing.assert_array_equal(oracle.star(rels), oracle.star(rels, threads=threads))
+    e = np.zeros(0, np.int32)
+    assert oracle.two_path(e, e, [1], [2], threads=threads)[0].size == 0
+    x, y = datagen.selfjoin_c1()
+    a = oracle.two_path(x, y, x, y)
+    b = oracle.two_path(x, y, x, y, threads=threads)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])

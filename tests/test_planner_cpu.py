@@ -162,3 +162,37 @@ def test_algorithm2_hand_worked_delta2_rounding(impl):
     d1, d2, c, clo = plan(s, dict(_hand_cal(0), mm_s=[5.0]))
     assert (d1, d2) == (25, 2)
     assert c == pytest.approx(912.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("n,out", [(1e6, 1e3), (1e6, 1e5), (1e6, 1e6), (1e6, 3e7), (1e5, 1e9), (1e4, 1e12),
+                                   (2000, 8301), (10, 0.5), (7, 6.324555320336759)])
+def test_library_theory_thresholds_match_lemma3(n, out):
+    """The library's THEORY thresholds are Lemma 3's minimisers (the
+    restatement, itself checked against a grid minimisation in
+    test_oracle.py) rounded down and clamped to [1, N]."""
+    n = int(n)
+    a, b = ref.theory_thresholds(n, out)
+    clamp = lambda t: 1 if t < 1 else (n if t >= n else int(np.floor(t)))
+    assert jp.plan_theory(n, out) == (clamp(a), clamp(b))
+
+
+def test_library_theory_hand_values():
+    """Worked by hand: N = 10^6, OUT = 10^3 (OUT <= N): Delta1 = 10^(3/3) = 10,
+    Delta2 = 10^6 / 10^2 = 10^4.  N = 1000, OUT = 10^6 (OUT > N):
+    Delta1 = Delta2 = (2 10^6 / 1001000)^(1/3) = 1.2594..., floor 1.
+    N = 10^6, OUT = 7 10^6: (2 10^12 / 8 10^6)^(1/3) = 250000^(1/3) = 62.99."""
+    assert jp.plan_theory(10**6, 1e3) == (10, 10**4)
+    assert jp.plan_theory(1000, 1e6) == (1, 1)
+    assert jp.plan_theory(10**6, 7e6) == (62, 62)
+    assert jp.plan_theory(0, 5.0) == (None, None)
+    assert jp.plan_theory(100, 0.0) == (None, None)
+
+
+def test_library_out_estimate_by_hand():
+    """The hand-made instance of test_oracle.py: sqrt(4 * 10) for
+    |dom x| = 4, |dom z| = 3, J = 10, N = 7; (J/N)^2 as the lower bound;
+    crossing bounds collapse to the upper bound; empty join gives 0."""
+    assert jp.estimate_out(4, 3, 10, 7) == pytest.approx(np.sqrt(40.0), rel=1e-12)
+    assert jp.estimate_out(5, 1000, 2000, 100) == pytest.approx(np.sqrt(400.0 * 2000.0), rel=1e-12)
+    assert jp.estimate_out(5, 1000, 1000, 10) == pytest.approx(1000.0, rel=1e-12)
+    assert jp.estimate_out(5, 5, 0, 10) == 0.0
