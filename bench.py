@@ -199,7 +199,7 @@ def main():
     dev = torch.device("cuda:0")
     T = lambda v: torch.from_numpy(np.ascontiguousarray(v, dtype=np.int32)).to(dev)
     Rx, Ry, Sz, Sy = T(rx), T(ry), T(sz), T(sy)
-    h = jp.Handle(0)
+    h = jp.Handle(0, allocator="builtin")  # the library's own pool: no Python callback per buffer
 
     def step(**kw):
         r = h.two_path_result(Rx, Ry, Sz, Sy, **kw)

@@ -177,6 +177,27 @@ void jp_destroy(jp_handle *h);
  * means the default stream). */
 jp_status jp_set_stream(jp_handle *h, void *stream);
 
+/*
+ * Source of the handle's device memory.  Every device buffer a later call of
+ * this handle needs (working buffers and result columns) is requested with
+ * alloc_fn(bytes, user) and returned with free_fn(ptr, user); the library
+ * keeps nothing cached from them.  alloc_fn must return memory of the
+ * handle's device, aligned to 256 bytes, usable on the handle's stream, or
+ * NULL when it has none: the call then fails with JP_ENOMEM after returning
+ * every block it got.  A buffer is released once the work that used it has
+ * been queued on the stream, so the allocator must order reuse after that
+ * work (a stream-ordered caching allocator such as PyTorch's does).  Both
+ * functions NULL restore the built-in caching pool (the default).  Mixing
+ * NULL and non-NULL is JP_EINVAL.  The call waits for the handle's stream,
+ * releases the built-in pool's cached blocks and moves the handle's own
+ * buffers (selector weights) to the new source; results that are still
+ * alive return their columns to the source they came from, which must stay
+ * valid until they are freed.  This lets the library and the caller's
+ * framework (PyTorch's caching allocator) draw on one pool of device memory.
+ */
+jp_status jp_set_allocator(jp_handle *h, void *(*alloc_fn)(size_t bytes, void *user),
+                           void (*free_fn)(void *ptr, void *user), void *user);
+
 /* Message describing the last non-OK status returned for this handle. */
 const char *jp_last_error(const jp_handle *h);
 
@@ -364,7 +385,7 @@ void jp_result_free(jp_result *r);
  * Heavy-product kernel on its own (the heavy step of Algorithm 1; Section 2.2's
  * Boolean matrix product): A is u x k and Bt is w x k, both 0/1 int8
  * row-major device matrices with row stride `ld` bytes (ld >= k, ld a
- * multiple of 64, padding bytes zero).  For every (i, j) with
+ * multiple of 128, padding bytes zero).  For every (i, j) with
  * sum_t A[i][t] * Bt[j][t] > 0 the pair (i, j) is written to rows[] / cols[]
  * (device int32 arrays of capacity `cap`), in no particular order, and the
  * count to *nnz.  If the count exceeds cap, JP_ECAPACITY is returned with

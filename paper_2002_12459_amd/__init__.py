@@ -18,7 +18,7 @@ import threading
 __all__ = [
     "LIB_PATH", "JoinProjectError", "Handle", "Result", "two_path", "star", "bool_matmul",
     "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF", "selector_cells", "mlp_param_count",
-    "SELECTOR_PATH", "load_selector_file", "plan_theory", "estimate_out",
+    "SELECTOR_PATH", "load_selector_file", "plan_theory", "estimate_out", "DeviceAllocator", "torch_allocator",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -100,6 +100,9 @@ class Instance(ctypes.Structure):
                 ("s_z", ctypes.c_void_p), ("s_y", ctypes.c_void_p), ("n_s", ctypes.c_int64)]
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 _lib = None
 _lock = threading.Lock()
 
@@ -120,6 +123,7 @@ def _load():
         lib.jp_destroy.argtypes = [P]
         lib.jp_destroy.restype = None
         lib.jp_set_stream.argtypes = [P, P]
+        lib.jp_set_allocator.argtypes = [P, _ALLOC_FN, _FREE_FN, P]
         lib.jp_last_error.argtypes = [P]
         lib.jp_last_error.restype = ctypes.c_char_p
         lib.jp_default_options.argtypes = [ctypes.POINTER(Options)]
@@ -163,7 +167,7 @@ def _load():
         lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
         f32 = ctypes.c_float
         lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
-        for f in ("jp_create", "jp_set_stream", "jp_two_path", "jp_star", "jp_result_size",
+        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
@@ -259,21 +263,77 @@ def load_selector_file(path=SELECTOR_PATH):
     return d["params"], d["mean"], d["scale"]
 
 
+class DeviceAllocator:
+    """Allocation callbacks handed to ``jp_set_allocator``.
+
+    ``alloc(nbytes) -> int`` returns a device address (0 when out of memory)
+    and ``free(ptr)`` takes it back.  The wrapper counts live bytes, the peak
+    and the calls, and turns a Python exception in ``alloc`` into NULL (the
+    library then reports JP_ENOMEM)."""
+
+    def __init__(self, alloc, free):
+        self._alloc, self._free = alloc, free
+        self.live = {}
+        self.live_bytes = self.peak_bytes = self.n_alloc = self.n_free = 0
+
+        def a(nbytes, _user):
+            try:
+                ptr = int(self._alloc(int(nbytes)) or 0)
+            except Exception:
+                ptr = 0
+            if ptr:
+                self.live[ptr] = int(nbytes)
+                self.live_bytes += int(nbytes)
+                self.peak_bytes = max(self.peak_bytes, self.live_bytes)
+                self.n_alloc += 1
+            return ptr or None
+
+        def f(ptr, _user):
+            if not ptr:
+                return
+            self.live_bytes -= self.live.pop(ptr, 0)
+            self.n_free += 1
+            try:
+                self._free(ptr)
+            except Exception:
+                pass
+
+        self.c_alloc = _ALLOC_FN(a)
+        self.c_free = _FREE_FN(f)
+
+
+def torch_allocator(device: int) -> DeviceAllocator:
+    """PyTorch's caching allocator, on torch's current stream of ``device``."""
+    torch = _torch()
+
+    def alloc(nbytes):
+        return torch.cuda.caching_allocator_alloc(nbytes, device, torch.cuda.current_stream(device))
+
+    return DeviceAllocator(alloc, torch.cuda.caching_allocator_delete)
+
+
 class Handle:
     """One library handle per device; work goes to torch's current stream.
 
     ``selector="default"`` installs the packaged MI355X selector weights when
     the file exists (used by strategy "mlp"); None leaves the handle without
-    a selector, so "mlp" behaves as "auto"."""
+    a selector, so "mlp" behaves as "auto".  ``allocator``: "torch"
+    (PyTorch's caching allocator: the library and torch share one pool of
+    device memory), "builtin" (the library's own caching pool, which saves
+    the Python callback of each of the 60 to 90 buffers of an evaluation) or
+    a ``DeviceAllocator``."""
 
-    def __init__(self, device: int = 0, selector="default"):
+    def __init__(self, device: int = 0, selector="default", allocator="torch"):
         lib = _load()
         self.device = device
+        self.allocator = None
         p = ctypes.c_void_p()
         st = lib.jp_create(ctypes.byref(p), device)
         if st != 0:
             raise JoinProjectError(st, f"jp_create({device}) failed")
         self._p = p
+        if allocator != "builtin":
+            self.set_allocator(torch_allocator(device) if allocator == "torch" else allocator)
         if selector == "default":
             if os.path.exists(SELECTOR_PATH):
                 self.set_selector(*load_selector_file(SELECTOR_PATH))
@@ -283,6 +343,19 @@ class Handle:
     def _check(self, st):
         if st != 0:
             raise JoinProjectError(st, _load().jp_last_error(self._p).decode())
+
+    def set_allocator(self, allocator):
+        """Route the handle's device memory through ``allocator`` (a
+        DeviceAllocator), or back to the built-in pool with None."""
+        lib = _load()
+        if allocator is None:
+            self._check(lib.jp_set_allocator(self._p, _ALLOC_FN(), _FREE_FN(), None))
+        else:
+            self._check(lib.jp_set_allocator(self._p, allocator.c_alloc, allocator.c_free, None))
+        # results made with the previous allocator hold this handle, and the
+        # handle holds every allocator it used, so callbacks outlive them
+        self._old_allocators = getattr(self, "_old_allocators", []) + [self.allocator]
+        self.allocator = allocator
 
     def _bind_stream(self):
         torch = _torch()

@@ -123,7 +123,7 @@ jp_status jp_create(jp_handle **out, int device) {
     }
     auto h = std::make_unique<jp_handle>();
     h->device = device;
-    h->alloc = std::make_shared<jp::Allocator>(device);
+    h->alloc = std::make_shared<jp::PoolAllocator>(device);
     {
         int prev = -1;
         (void)hipGetDevice(&prev);
@@ -164,6 +164,37 @@ jp_status jp_set_stream(jp_handle *h, void *stream) {
             // cached blocks were last used on the old stream
             JP_HIP(hipStreamSynchronize(h->stream));
             h->stream = s;
+        }
+    });
+}
+
+jp_status jp_set_allocator(jp_handle *h, void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
+                           void *user) {
+    if (!h) return JP_EINVAL;
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) {
+        h->err = "alloc and free must both be given or both be NULL";
+        return JP_EINVAL;
+    }
+    return guarded(h, [&] {
+        // Work queued on the stream may still use blocks of the old source.
+        JP_HIP(hipStreamSynchronize(h->stream));
+        std::shared_ptr<jp::Allocator> a;
+        if (alloc_fn) a = std::make_shared<jp::UserAllocator>(h->device, alloc_fn, free_fn, user);
+        else a = std::make_shared<jp::PoolAllocator>(h->device);
+        // Buffers the handle keeps between calls come from the new source
+        // from now on; live results keep the source they came from.
+        h->status_pool.block.reset();
+        h->status_pool.used = 0;
+        h->alloc->release_cached();
+        h->alloc = std::move(a);
+        if (h->sel.ready()) {
+            const int64_t np = jp::mlp_param_count(h->sel.n_out);
+            jp::Ctx c = make_ctx(h);
+            jp::DBuf<float> p = c.buf<float>((size_t)np);
+            JP_HIP(hipMemcpyAsync(p.get(), h->sel.params.get(), (size_t)np * sizeof(float),
+                                  hipMemcpyDeviceToDevice, c.stream));
+            c.sync();
+            h->sel.params = std::move(p);
         }
     });
 }
@@ -495,17 +526,13 @@ jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt, int64_
     jp_status st = guarded(h, [&] {
         jp::Ctx c = make_ctx(h);
         jp::DBuf<unsigned long long> cnt = c.buf<unsigned long long>(1);
-        hipEvent_t e0, e1;
-        JP_HIP(hipEventCreate(&e0));
-        JP_HIP(hipEventCreate(&e1));
-        JP_HIP(hipEventRecord(e0, c.stream));
+        jp::EventPair ev;
+        JP_HIP(hipEventRecord(ev.a, c.stream));
         jp::bool_matmul_pairs(c, A, Bt, u, w, ld, kind, rows, cols, cap, cnt.get());
-        JP_HIP(hipEventRecord(e1, c.stream));
+        JP_HIP(hipEventRecord(ev.b, c.stream));
         unsigned long long v = c.load(cnt.get());
         float f = 0;
-        JP_HIP(hipEventElapsedTime(&f, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        JP_HIP(hipEventElapsedTime(&f, ev.a, ev.b));
         count = (int64_t)v;
         t = f;
     });

@@ -632,17 +632,13 @@ static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int
                     const BmmVariant cand[2] = {v, BmmVariant::BITPOP};
                     float best = -1;
                     for (BmmVariant q : cand) {
-                        hipEvent_t e0, e1;
-                        JP_HIP(hipEventCreate(&e0));
-                        JP_HIP(hipEventCreate(&e1));
-                        JP_HIP(hipEventRecord(e0, c.stream));
+                        EventPair ev;
+                        JP_HIP(hipEventRecord(ev.a, c.stream));
                         run_variant(c, q, A, Bt, u, w, ld, emit, 0, count_dev);  // count only
-                        JP_HIP(hipEventRecord(e1, c.stream));
-                        JP_HIP(hipEventSynchronize(e1));
+                        JP_HIP(hipEventRecord(ev.b, c.stream));
+                        JP_HIP(hipEventSynchronize(ev.b));
                         float ms = 0;
-                        JP_HIP(hipEventElapsedTime(&ms, e0, e1));
-                        (void)hipEventDestroy(e0);
-                        (void)hipEventDestroy(e1);
+                        JP_HIP(hipEventElapsedTime(&ms, ev.a, ev.b));
                         if (best < 0 || ms < best) {
                             best = ms;
                             v = q;

@@ -9,6 +9,7 @@
 #include <cstdint>
 #include <cstring>
 #include <initializer_list>
+#include <iterator>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -41,17 +42,34 @@ struct Error {
         if (!(cond)) ::jp::fail((st), (msg));         \
     } while (0)
 
-// Caching device allocator.  Blocks are rounded (powers of two below 1 MiB,
-// 2 MiB multiples above), kept on release, and reused best-fit for requests
-// at least 2/3 of their size.  When hipMalloc fails the cache is emptied and
-// the request retried once.  All blocks are used on one stream at a time, so
-// reuse after release is ordered by that stream.
+// Source of every device buffer of a call.  Buffers are used on one stream at
+// a time, so a released block may be handed out again at once: later work on
+// that stream is ordered after the work that used it.
 class Allocator {
   public:
     explicit Allocator(int device) : device_(device) {}
-    ~Allocator() { release_cached(); }
+    virtual ~Allocator() = default;
+    // Raises JP_ENOMEM when no memory can be had; never returns nullptr.
+    virtual void *alloc(size_t bytes) = 0;
+    virtual void release(void *p) = 0;
+    // Returns cached blocks to the device (no-op where nothing is cached).
+    virtual void release_cached() {}
+    int device() const { return device_; }
 
-    void *alloc(size_t bytes) {
+  private:
+    int device_;
+};
+
+// Built-in caching allocator.  Blocks are rounded (powers of two below 1 MiB,
+// 2 MiB multiples above), kept on release, and reused best-fit for requests
+// at least 2/3 of their size.  When hipMalloc fails the cache is emptied and
+// the request retried once.
+class PoolAllocator final : public Allocator {
+  public:
+    explicit PoolAllocator(int device) : Allocator(device) {}
+    ~PoolAllocator() override { release_cached(); }
+
+    void *alloc(size_t bytes) override {
         if (bytes == 0) bytes = 1;
         size_t r = round(bytes);
         std::lock_guard<std::mutex> g(mu_);
@@ -78,7 +96,7 @@ class Allocator {
         return p;
     }
 
-    void release(void *p) {
+    void release(void *p) override {
         if (!p) return;
         std::lock_guard<std::mutex> g(mu_);
         auto it = live_.find(p);
@@ -88,12 +106,10 @@ class Allocator {
         live_.erase(it);
     }
 
-    void release_cached() {
+    void release_cached() override {
         std::lock_guard<std::mutex> g(mu_);
         release_cached_locked();
     }
-
-    int device() const { return device_; }
 
   private:
     static size_t round(size_t b) {
@@ -111,11 +127,98 @@ class Allocator {
         cached_ = 0;
     }
 
-    int device_;
     std::mutex mu_;
     std::multimap<size_t, void *> free_;
     std::unordered_map<void *, size_t> live_;
     size_t cached_ = 0;
+};
+
+// Caller-supplied allocation functions (jp_set_allocator).  Every request goes
+// to the caller; a NULL return becomes JP_ENOMEM.  Requests are rounded up to
+// 256 bytes so that every buffer keeps the alignment the kernels assume.
+class UserAllocator final : public Allocator {
+  public:
+    using AllocFn = void *(*)(size_t, void *);
+    using FreeFn = void (*)(void *, void *);
+    UserAllocator(int device, AllocFn a, FreeFn f, void *user) : Allocator(device), a_(a), f_(f), user_(user) {}
+
+    void *alloc(size_t bytes) override {
+        const size_t r = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        void *p = a_(r, user_);
+        if (!p) fail(JP_ENOMEM, "the caller's allocator returned NULL for " + std::to_string(r) + " bytes");
+        if ((uintptr_t)p % 256 != 0) {
+            f_(p, user_);
+            fail(JP_EINVAL, "the caller's allocator returned a pointer not aligned to 256 bytes");
+        }
+        return p;
+    }
+    void release(void *p) override {
+        if (p) f_(p, user_);
+    }
+
+  private:
+    AllocFn a_;
+    FreeFn f_;
+    void *user_;
+};
+
+// First-fit allocator over one fixed device region (the no-allocation entry
+// point).  Free ranges are kept by offset and merged with their neighbours on
+// release; a request that fits no free range raises JP_ENOMEM.  Nothing is
+// ever taken from the device runtime.
+class ArenaAllocator final : public Allocator {
+  public:
+    ArenaAllocator(int device, void *base, size_t bytes) : Allocator(device), base_((uint8_t *)base), bytes_(bytes) {
+        if (bytes_) free_[0] = bytes_;
+    }
+    void *alloc(size_t bytes) override {
+        const size_t r = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < r) continue;
+            const size_t off = it->first, len = it->second;
+            free_.erase(it);
+            if (len > r) free_[off + r] = len - r;
+            live_[off] = r;
+            in_use_ += r;
+            peak_ = std::max(peak_, in_use_);
+            return base_ + off;
+        }
+        fail(JP_ENOMEM, "the static scratch of " + std::to_string(bytes_ >> 20) + " MiB has no free range of " +
+                            std::to_string(r) + " bytes (" + std::to_string(in_use_) + " bytes in use): the input is "
+                            "too large for the no-allocation entry point");
+    }
+    void release(void *p) override {
+        if (!p) return;
+        const size_t off = (size_t)((uint8_t *)p - base_);
+        auto lt = live_.find(off);
+        if (lt == live_.end()) return;
+        size_t start = off, len = lt->second;
+        live_.erase(lt);
+        in_use_ -= len;
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && next->first == start + len) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+    }
+    size_t peak() const { return peak_; }
+    size_t in_use() const { return in_use_; }
+
+  private:
+    uint8_t *base_;
+    size_t bytes_;
+    std::map<size_t, size_t> free_;  // offset -> length
+    std::map<size_t, size_t> live_;  // offset -> length
+    size_t in_use_ = 0, peak_ = 0;
 };
 
 // Owning device buffer of n elements of T from an Allocator.
@@ -332,6 +435,26 @@ struct Ctx {
         hipLaunchKernelGGL(k_zero_words<W>, dim3(grid_x(blocks, 256)), dim3(256), 0, stream, p, (int64_t)n);
         JP_HIP(hipGetLastError());
     }
+};
+
+// Two HIP events destroyed with their owner (also when a call fails between
+// their creation and use).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        JP_HIP(hipEventCreate(&a));
+        hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            fail(JP_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
+        }
+    }
+    ~EventPair() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
 };
 
 // Device-time phase markers (HIP events on the call's stream).

@@ -133,7 +133,7 @@ jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst,
 jp_result *run_star(const Ctx &c, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
                     const jp_options &o);
 
-// Heavy product: A (u x ld) and Bt (w x ld) int8 0/1, K = ld (multiple of 64).
+// Heavy product: A (u x ld) and Bt (w x ld) int8 0/1, K = ld (multiple of 128).
 // For every nonzero C[i][j] calls the emitter through a pair buffer: writes
 // rows/cols into out_i / out_j (capacity cap) and counts into *count_dev.
 void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
