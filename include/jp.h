@@ -326,6 +326,33 @@ jp_status jp_two_path(jp_handle *h,
                       const int32_t *s_z, const int32_t *s_y, int64_t n_s,
                       const jp_options *opt, jp_result **out);
 
+/*
+ * jp_two_path without device allocation, for callers that cannot allocate
+ * device memory (code that forbids hipMalloc/hipFree, tight serving loops).
+ * Same inputs and options as jp_two_path; the distinct sorted pairs are
+ * written to the caller's device columns out_x / out_z (capacity cap each)
+ * and their count to *n_out; *stats (may be NULL) receives the statistics.
+ * Working memory is a fixed 256 MiB device array inside the library, one per
+ * GPU, held from the first jp_create on that GPU until the process ends; no
+ * call here allocates or frees device memory.
+ *  - Inputs of more than 2^19 edges per relation: JP_EINVAL.
+ *  - Working memory exhausted (an input whose joins need more than the
+ *    array): JP_ENOMEM; use jp_two_path.
+ *  - More pairs than cap: JP_ECAPACITY with *n_out = the number needed and
+ *    nothing written to out_x / out_z.
+ * The array keeps the contents of the previous call; whatever must start at
+ * zero is cleared by the call.  Calls on one GPU share the array: calls from
+ * threads of one process are serialised by the library (each returns after
+ * its device work is complete), and calls that overlap on one GPU through
+ * any other route race.  The timing flag is ignored, and JP_BMM_AUTO picks
+ * the product kernel by shape without the timed race.
+ */
+jp_status jp_two_path_static(jp_handle *h,
+                             const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                             const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+                             const jp_options *opt, int32_t *out_x, int32_t *out_z, int64_t cap,
+                             int64_t *n_out, jp_stats *stats);
+
 /* One two-path instance of a batch: device columns as for jp_two_path. */
 typedef struct jp_instance {
     const int32_t *r_x, *r_y;

@@ -129,6 +129,8 @@ def _load():
         lib.jp_default_options.argtypes = [ctypes.POINTER(Options)]
         lib.jp_default_options.restype = None
         lib.jp_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(P)]
+        lib.jp_two_path_static.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), P, P, i64,
+                                           ctypes.POINTER(i64), ctypes.POINTER(Stats)]
         lib.jp_star.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64),
                                 ctypes.POINTER(Options), ctypes.POINTER(P)]
         lib.jp_result_size.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32)]
@@ -167,7 +169,7 @@ def _load():
         lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
         f32 = ctypes.c_float
         lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
-        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_star", "jp_result_size",
+        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
@@ -399,6 +401,29 @@ class Handle:
             return x, z, r.stats
         finally:
             r.free()
+
+    def two_path_static(self, rx, ry, sz, sy, out_x, out_z, delta1=None, delta2=None, strategy=None, bmm="auto",
+                        y_rule="max", dedup="auto", seed=None):
+        """jp_two_path_static: the pairs go into the caller's int32 CUDA
+        tensors out_x / out_z (capacity = their length) and the library
+        allocates no device memory.  Returns (n_out, stats); raises
+        JoinProjectError (JP_ECAPACITY with .n_out set when they are too short)."""
+        rx, ry, sz, sy, out_x, out_z = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y"),
+                                                                 (out_x, "out_x"), (out_z, "out_z")))
+        if rx.numel() != ry.numel() or sz.numel() != sy.numel() or out_x.numel() != out_z.numel():
+            raise ValueError("column lengths differ")
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, False, seed)
+        n = ctypes.c_int64()
+        s = Stats()
+        st = _load().jp_two_path_static(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(),
+                                        ctypes.byref(o), _ptr(out_x), _ptr(out_z), out_x.numel(), ctypes.byref(n),
+                                        ctypes.byref(s))
+        if st != 0:
+            err = JoinProjectError(st, _load().jp_last_error(self._p).decode())
+            err.n_out = n.value
+            raise err
+        return n.value, s.as_dict()
 
     def two_path_batch_result(self, instances, delta1=None, delta2=None, strategy=None, bmm="auto", y_rule="max",
                               dedup="auto", timing=False, seed=None) -> Result:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <memory>
+#include <mutex>
 #include <string>
 
 #include "pipeline.hpp"
@@ -24,6 +25,43 @@ struct jp_handle {
 };
 
 namespace {
+
+// Working memory of the no-allocation entry point (jp_two_path_static): a
+// fixed device array per GPU, the largest input it takes, and one lock per
+// device so that calls in this process never overlap on one array.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+constexpr int64_t kStaticMaxEdges = int64_t(1) << 19;  // per relation
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+struct StaticScratch {
+    std::mutex init_mu;
+    std::mutex call_mu[kMaxDevices];
+    void *ptr[kMaxDevices] = {};       // device address of `scratch` on each device
+    hipError_t err[kMaxDevices] = {};  // result of the address query
+    bool done[kMaxDevices] = {};
+};
+StaticScratch g_scratch;
+
+// Looks up the device address of `scratch` once per device, with that device
+// current (each GPU holds its own copy of the array).  Host code uses only
+// this address: the array's name is a host-side stand-in.
+void static_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> g(g_scratch.init_mu);
+    if (g_scratch.done[device]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) (void)hipGetLastError();
+    g_scratch.ptr[device] = e == hipSuccess ? p : nullptr;
+    g_scratch.err[device] = e;
+    g_scratch.done[device] = true;
+}
 
 // Makes the handle's device current for the scope of one call.
 struct DeviceScope {
@@ -129,6 +167,7 @@ jp_status jp_create(jp_handle **out, int device) {
         (void)hipGetDevice(&prev);
         if (prev != device) (void)hipSetDevice(device);
         h->pinned = std::make_unique<jp::PinnedScratch>(1 << 20);
+        static_scratch_init(device);
         if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
     }
     jp::default_calibration(&h->cal);
@@ -222,6 +261,79 @@ jp_status jp_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int6
     jp_status st = guarded(h, [&] { r = jp::run_two_path(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o); });
     if (st == JP_OK) *out = r;
     return st;
+}
+
+jp_status jp_two_path_static(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                             const int32_t *s_y, int64_t n_s, const jp_options *opt, int32_t *out_x, int32_t *out_z,
+                             int64_t cap, int64_t *n_out, jp_stats *stats) {
+    if (!h) return JP_EINVAL;
+    if (!n_out || cap < 0 || bad_col(out_x, cap) || bad_col(out_z, cap)) {
+        h->err = "n_out is NULL, or an output column is NULL with cap > 0, or cap < 0";
+        return JP_EINVAL;
+    }
+    *n_out = 0;
+    if (bad_col(r_x, n_r) || bad_col(r_y, n_r) || bad_col(s_z, n_s) || bad_col(s_y, n_s)) {
+        h->err = "relation column is NULL or its length is negative";
+        return JP_EINVAL;
+    }
+    if (n_r > kStaticMaxEdges || n_s > kStaticMaxEdges) {
+        h->err = "jp_two_path_static takes at most " + std::to_string(kStaticMaxEdges) +
+                 " edges per relation (its working memory is a fixed " + std::to_string(kStaticScratchBytes >> 20) +
+                 " MiB device array); use jp_two_path";
+        return JP_EINVAL;
+    }
+    if (h->device >= kMaxDevices || !g_scratch.done[h->device] || !g_scratch.ptr[h->device]) {
+        h->err = std::string("static scratch unavailable on this device: ") +
+                 (h->device < kMaxDevices && g_scratch.done[h->device] ? hipGetErrorString(g_scratch.err[h->device])
+                                                                      : "device index out of range");
+        return JP_EHIP;
+    }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    o.flags &= ~JP_FLAG_TIMING;  // no event objects
+    std::lock_guard<std::mutex> lock(g_scratch.call_mu[h->device]);
+    int64_t n = 0;
+    jp_stats st{};
+    jp_status status = guarded(h, [&] {
+        jp::Ctx c = make_ctx(h);
+        // Every buffer of the call is carved from the device's static array;
+        // the look-back status words too (cleared when first handed out).
+        auto arena = std::make_shared<jp::ArenaAllocator>(h->device, g_scratch.ptr[h->device], kStaticScratchBytes);
+        jp::StatusPool pool;
+        c.alloc = arena;
+        c.status_pool = &pool;
+        c.tune = nullptr;  // kernel by shape: no timed race
+        std::unique_ptr<jp_result> r;
+        try {
+            r.reset(jp::run_two_path(c, r_x, r_y, n_r, s_z, s_y, n_s, o));
+            n = r->n;
+            st = r->stats;
+            if (n > 0 && n <= cap) {
+                JP_HIP(hipMemcpyAsync(out_x, r->cols[0].get(), (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                      c.stream));
+                JP_HIP(hipMemcpyAsync(out_z, r->cols[1].get(), (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                      c.stream));
+            }
+            c.sync();
+        } catch (...) {
+            // the array is reused by the next call: let queued work finish
+            (void)hipStreamSynchronize(c.stream);
+            (void)hipGetLastError();
+            throw;
+        }
+    });
+    if (status != JP_OK) return status;
+    *n_out = n;
+    if (stats) *stats = st;
+    if (n > cap) {
+        h->err = "output capacity " + std::to_string(cap) + " is smaller than the " + std::to_string(n) +
+                 " distinct pairs (reported in *n_out)";
+        return JP_ECAPACITY;
+    }
+    return JP_OK;
 }
 
 jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
