@@ -33,6 +33,13 @@ jp_status jp_test_exclusive_scan(jp_handle *h, const int64_t *in, int64_t *out, 
  * JP_EINVAL for a null handle or negative ticks. */
 jp_status jp_test_set_lookback_wait(jp_handle *h, int64_t ticks);
 
+/* Stage-by-stage validation of intermediate index arrays (process-wide; the
+ * JP_CHECKS environment variable sets the initial value): on = 1 checks every
+ * stage's index arrays on the device and turns a violation into
+ * JP_EINTERNAL, on = 0 runs the pipelines as shipped.  Returns the previous
+ * setting (0 or 1). */
+int32_t jp_test_set_checks(int32_t on);
+
 /* Keeps the first of every run of equal adjacent keys, in order; *n_out (host). */
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out);
 

@@ -14,11 +14,11 @@
 
 namespace jp {
 
-inline bool checks_on() {
-    static int on = -1;
-    if (on < 0) on = std::getenv("JP_CHECKS") ? 1 : 0;
-    return on == 1;
+inline int &checks_flag() {
+    static int on = std::getenv("JP_CHECKS") ? 1 : 0;
+    return on;
 }
+inline bool checks_on() { return checks_flag() == 1; }
 inline bool dump_on() {
     static int on = -1;
     if (on < 0) on = std::getenv("JP_DEBUG_DUMP") ? 1 : 0;

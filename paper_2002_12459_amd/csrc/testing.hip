@@ -1,5 +1,6 @@
 // Test hooks: the device primitives behind a C entry point each.
 #include "../../include/jp_testing.h"
+#include "debug.hpp"
 #include "pipeline.hpp"
 #include "prims.hpp"
 
@@ -86,6 +87,11 @@ jp_status jp_test_set_lookback_wait(jp_handle *h, int64_t ticks) {
     if (!h || ticks < 0) return JP_EINVAL;
     jp_handle_set_lookback_wait(h, ticks);
     return JP_OK;
+}
+int32_t jp_test_set_checks(int32_t on) {
+    const int32_t prev = jp::checks_flag();
+    jp::checks_flag() = on ? 1 : 0;
+    return prev;
 }
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out) {
     if (!h || n < 0 || (n && (!in || !out)) || !n_out) return JP_EINVAL;

@@ -6,7 +6,7 @@ import pytest
 import datagen
 import oracle
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("checks_mode")]
 
 
 @pytest.fixture(scope="module")

@@ -11,7 +11,7 @@ import oracle
 from oracle import reference as ref
 from tests.conftest import load_golden
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("checks_mode")]
 
 
 @pytest.fixture(scope="module")
