@@ -7,6 +7,10 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 * ``two_path`` / ``star`` / ``join_size``: plain C (``oracle.c``), the query
   definitions of Section 2.1 evaluated as Proposition 1 says (full join, then
   project and deduplicate by sorting).
+* ``ssj`` / ``bsi``: the set-similarity join (pairs with at least c common
+  elements, with their overlap; plain or ordered by overlap) and Boolean set
+  intersection (one answer per queried pair) of Section 2.1, by their
+  definitions (full join and run lengths; a merge of the two sets per query).
 * ``two_path_par`` / ``star_par``: the same computation split over OpenMP
   threads by ranges of the first output column (timed CPU baseline, and the
   check of full-size outputs).
@@ -62,6 +66,13 @@ def _load():
         lib.orc_star_par.argtypes = [ctypes.c_int, ctypes.POINTER(i32p), ctypes.POINTER(i32p),
                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.POINTER(i32p),
                                      ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_ssj.restype = ctypes.c_int
+        lib.orc_ssj.argtypes = [i32p, i32p, ctypes.c_int64, i32p, i32p, ctypes.c_int64, ctypes.c_int64, ctypes.c_int,
+                                ctypes.POINTER(i32p), ctypes.POINTER(i32p), ctypes.POINTER(i32p),
+                                ctypes.POINTER(ctypes.c_int64)]
+        lib.orc_bsi.restype = ctypes.c_int
+        lib.orc_bsi.argtypes = [i32p, i32p, ctypes.c_int64, i32p, i32p, ctypes.c_int64, i32p, i32p,
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_uint8)]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [ctypes.c_void_p]
         _lib = lib
@@ -167,3 +178,42 @@ def star(rels, threads: int = 0):
     finally:
         lib.orc_free(out)
     return t.reshape(m, k)
+
+
+def ssj(rx, ry, sz, sy, c: int = 1, order: int = 0):
+    """Set similarity join: (x, z, overlap) int32 arrays of the pairs whose
+    sets share at least ``c`` elements; order 0 by (x, z), order 1 by overlap
+    descending then (x, z)."""
+    lib = _load()
+    rx, ry, sz, sy = map(_col, (rx, ry, sz, sy))
+    if rx.size != ry.size or sz.size != sy.size:
+        raise ValueError("column lengths differ")
+    P = ctypes.POINTER(ctypes.c_int32)
+    ox, oz, oc = P(), P(), P()
+    n = ctypes.c_int64(0)
+    rc = lib.orc_ssj(_ptr(rx), _ptr(ry), rx.size, _ptr(sz), _ptr(sy), sz.size, int(c), int(order),
+                     ctypes.byref(ox), ctypes.byref(oz), ctypes.byref(oc), ctypes.byref(n))
+    if rc != 0:
+        raise (ValueError if rc == -1 else MemoryError)(f"orc_ssj failed ({rc})")
+    try:
+        m = n.value
+        out = [np.ctypeslib.as_array(p, shape=(max(m, 1),))[:m].copy() for p in (ox, oz, oc)]
+    finally:
+        for p in (ox, oz, oc):
+            lib.orc_free(p)
+    return tuple(out)
+
+
+def bsi(rx, ry, sz, sy, tx, tz):
+    """Boolean set intersection: a bool array, True where the set of tx[i] in
+    R and the set of tz[i] in S intersect."""
+    lib = _load()
+    rx, ry, sz, sy, tx, tz = map(_col, (rx, ry, sz, sy, tx, tz))
+    if rx.size != ry.size or sz.size != sy.size or tx.size != tz.size:
+        raise ValueError("column lengths differ")
+    ans = np.zeros(max(tx.size, 1), dtype=np.uint8)
+    rc = lib.orc_bsi(_ptr(rx), _ptr(ry), rx.size, _ptr(sz), _ptr(sy), sz.size, _ptr(tx), _ptr(tz), tx.size,
+                     ans.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if rc != 0:
+        raise (ValueError if rc == -1 else MemoryError)(f"orc_bsi failed ({rc})")
+    return ans[: tx.size].astype(bool)

@@ -35,6 +35,8 @@ static int cmp_pair(const void *a, const void *b)
     return 0;
 }
 
+static int cmp_pair_by_v(const void *a, const void *b);
+
 static int cmp_u64(const void *a, const void *b)
 {
     uint64_t p = *(const uint64_t *)a, q = *(const uint64_t *)b;
@@ -239,6 +241,138 @@ done:
     free(tup);
     for (int i = 0; i < k; ++i) free(Rel[i]);
     return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Set similarity join (Section 2.1, "Set Similarity"): the pairs (a, c)
+ * whose sets N_R(a) = {b : (a,b) in R} and N_S(c) share at least min_c
+ * elements, each with its overlap |N_R(a) & N_S(c)|.  Evaluated as the full
+ * join followed by sorting: over distinct edges every element b common to
+ * both sets is exactly one witness (a, b, c), so the length of the run of
+ * the key (a, c) in the sorted witness list is the overlap.  order = 0:
+ * pairs ascending by (a, c); order = 1 (the ordered variant): by overlap
+ * descending, ties by (a, c) ascending.
+ * ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint64_t key; /* biased (a, c) */
+    int64_t cnt;
+} orc_counted;
+
+static int cmp_counted_desc(const void *a, const void *b)
+{
+    const orc_counted *p = (const orc_counted *)a, *q = (const orc_counted *)b;
+    if (p->cnt != q->cnt) return p->cnt > q->cnt ? -1 : 1;
+    return (p->key > q->key) - (p->key < q->key);
+}
+
+int orc_ssj(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+            const int32_t *s_z, const int32_t *s_y, int64_t n_s, int64_t min_c, int order,
+            int32_t **out_x, int32_t **out_z, int32_t **out_cnt, int64_t *n_out)
+{
+    if (!out_x || !out_z || !out_cnt || !n_out || n_r < 0 || n_s < 0 || min_c < 1) return -1;
+    if ((n_r && (!r_x || !r_y)) || (n_s && (!s_z || !s_y)) || (order != 0 && order != 1)) return -1;
+    *out_x = *out_z = *out_cnt = NULL;
+    *n_out = 0;
+    int64_t nr, ns;
+    orc_pair *R = index_by_y(r_x, r_y, n_r, &nr);
+    orc_pair *S = index_by_y(s_z, s_y, n_s, &ns);
+    if (!R || !S) { free(R); free(S); return -2; }
+    int64_t J = 0;
+    for (int64_t i = 0; i < nr; ++i) {
+        int64_t lo = lower_y(S, ns, R[i].y), hi = lo;
+        while (hi < ns && S[hi].y == R[i].y) ++hi;
+        J += hi - lo;
+    }
+    uint64_t *key = (uint64_t *)malloc((size_t)(J > 0 ? J : 1) * sizeof(uint64_t));
+    if (!key) { free(R); free(S); return -2; }
+    int64_t w = 0;
+    for (int64_t i = 0; i < nr; ++i)
+        for (int64_t j = lower_y(S, ns, R[i].y); j < ns && S[j].y == R[i].y; ++j)
+            key[w++] = ((uint64_t)R[i].v << 32) | (uint64_t)S[j].v;
+    free(R);
+    free(S);
+    qsort(key, (size_t)w, sizeof(uint64_t), cmp_u64);
+
+    /* run lengths of equal keys, filtered by the overlap threshold */
+    orc_counted *res = (orc_counted *)malloc((size_t)(w > 0 ? w : 1) * sizeof(orc_counted));
+    if (!res) { free(key); return -2; }
+    int64_t m = 0;
+    for (int64_t i = 0; i < w;) {
+        int64_t j = i;
+        while (j < w && key[j] == key[i]) ++j;
+        if (j - i >= min_c) {
+            res[m].key = key[i];
+            res[m].cnt = j - i;
+            ++m;
+        }
+        i = j;
+    }
+    free(key);
+    if (order == 1) qsort(res, (size_t)m, sizeof(orc_counted), cmp_counted_desc);
+    int32_t *ox = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *oz = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    int32_t *oc = (int32_t *)malloc((size_t)(m > 0 ? m : 1) * sizeof(int32_t));
+    if (!ox || !oz || !oc) { free(ox); free(oz); free(oc); free(res); return -2; }
+    for (int64_t i = 0; i < m; ++i) {
+        ox[i] = unbias((uint32_t)(res[i].key >> 32));
+        oz[i] = unbias((uint32_t)(res[i].key & 0xffffffffu));
+        oc[i] = (int32_t)res[i].cnt;
+    }
+    free(res);
+    *out_x = ox;
+    *out_z = oz;
+    *out_cnt = oc;
+    *n_out = m;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Boolean set intersection (Section 2.1, "Boolean Set Intersection"; the
+ * batched workload of Section 3.3): for every query i, answers[i] = 1 when
+ * the sets N_R(t_x[i]) and N_S(t_z[i]) have a common element, else 0.  Each
+ * query is answered on its own by a merge of the two sorted sets.
+ * ------------------------------------------------------------------------ */
+
+/* First index in p[0..n) whose v is >= key (p sorted by (v, y)). */
+static int64_t lower_v(const orc_pair *p, int64_t n, uint32_t key)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (p[mid].v < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+int orc_bsi(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+            const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+            const int32_t *t_x, const int32_t *t_z, int64_t n_t, uint8_t *answers)
+{
+    if (n_r < 0 || n_s < 0 || n_t < 0 || (n_t && (!t_x || !t_z || !answers))) return -1;
+    if ((n_r && (!r_x || !r_y)) || (n_s && (!s_z || !s_y))) return -1;
+    /* both relations sorted by their set id, then element */
+    orc_pair *R = (orc_pair *)malloc((size_t)(n_r > 0 ? n_r : 1) * sizeof(orc_pair));
+    orc_pair *S = (orc_pair *)malloc((size_t)(n_s > 0 ? n_s : 1) * sizeof(orc_pair));
+    if (!R || !S) { free(R); free(S); return -2; }
+    for (int64_t i = 0; i < n_r; ++i) { R[i].v = bias(r_x[i]); R[i].y = bias(r_y[i]); }
+    for (int64_t i = 0; i < n_s; ++i) { S[i].v = bias(s_z[i]); S[i].y = bias(s_y[i]); }
+    qsort(R, (size_t)n_r, sizeof(orc_pair), cmp_pair_by_v);
+    qsort(S, (size_t)n_s, sizeof(orc_pair), cmp_pair_by_v);
+    for (int64_t q = 0; q < n_t; ++q) {
+        const uint32_t a = bias(t_x[q]), c = bias(t_z[q]);
+        int64_t i = lower_v(R, n_r, a), j = lower_v(S, n_s, c);
+        uint8_t hit = 0;
+        while (!hit && i < n_r && j < n_s && R[i].v == a && S[j].v == c) {
+            if (R[i].y == S[j].y) hit = 1;
+            else if (R[i].y < S[j].y) ++i;
+            else ++j;
+        }
+        answers[q] = hit;
+    }
+    free(R);
+    free(S);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------

@@ -8,6 +8,7 @@
  * What it computes is the plain definition of the query result:
  *   two-path  Q(x,z)      = { (a,c) : exists b, (a,b) in R and (c,b) in S }
  *   star      Q(x1..xk)   = { (a1..ak) : exists b, (ai,b) in Ri for all i }
+ *   set similarity (overlap c) and Boolean set intersection (Section 2.1)
  * (paper, Section 2.1 problem definitions; Section 2.2 Boolean-product view),
  * evaluated the way Proposition 1 (Section 2.3) describes: enumerate the full
  * join with a worst-case optimal strategy (here: per y value, all
@@ -55,6 +56,20 @@ int orc_two_path_par(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
                      int32_t **out_x, int32_t **out_z, int64_t *n_out);
 int orc_star_par(int k, const int32_t *const *x, const int32_t *const *y,
                  const int64_t *n, int nthreads, int32_t **out, int64_t *n_out);
+
+/* Set similarity join (Section 2.1): pairs (a, c) with
+ * |{b : (a,b) in R} & {b : (c,b) in S}| >= min_c (min_c >= 1), with that
+ * overlap in *out_cnt.  order 0: by (a, c); order 1: by overlap descending,
+ * then (a, c).  Full join, sort, run lengths. */
+int orc_ssj(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+            const int32_t *s_z, const int32_t *s_y, int64_t n_s, int64_t min_c, int order,
+            int32_t **out_x, int32_t **out_z, int32_t **out_cnt, int64_t *n_out);
+
+/* Boolean set intersection (Section 2.1): answers[i] = 1 iff the sets of
+ * t_x[i] in R and of t_z[i] in S intersect (answers: n_t bytes, caller's). */
+int orc_bsi(const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+            const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+            const int32_t *t_x, const int32_t *t_z, int64_t n_t, uint8_t *answers);
 
 void orc_free(void *p);
 

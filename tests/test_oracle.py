@@ -477,3 +477,97 @@ def test_parallel_oracle_matches_plain(threads):
     b = oracle.two_path(x, y, x, y, threads=threads)
     np.testing.assert_array_equal(a[0], b[0])
     np.testing.assert_array_equal(a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# Set similarity join and Boolean set intersection (Section 2.1): pinned by
+# brute force over all set pairs (Python sets), the worked example's overlaps
+# worked out by hand, and closed forms.
+# ---------------------------------------------------------------------------
+
+def brute_overlaps(rx, ry, sz, sy):
+    nx, nz = {}, {}
+    for a, b in zip(np.asarray(rx).tolist(), np.asarray(ry).tolist()):
+        nx.setdefault(a, set()).add(b)
+    for c, b in zip(np.asarray(sz).tolist(), np.asarray(sy).tolist()):
+        nz.setdefault(c, set()).add(b)
+    return {(a, c): len(nx[a] & nz[c]) for a in nx for c in nz if nx[a] & nz[c]}
+
+
+def example_relations():
+    rows = load_golden("two_path_example.txt")
+    R = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "R"])
+    S = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "S"])
+    return R[:, 0], R[:, 1], S[:, 0], S[:, 1]
+
+
+def test_ssj_worked_example_by_hand():
+    rx, ry, sz, sy = example_relations()
+    hand = {(int(a), int(b)): int(c) for a, b, c in load_golden("ssj_example.txt")}
+    assert len(hand) == 26 and sum(hand.values()) == 35
+    for c in (1, 2, 3, 4):
+        x, z, n = oracle.ssj(rx, ry, sz, sy, c=c)
+        want = sorted((k, v) for k, v in hand.items() if v >= c)
+        assert list(zip(zip(x.tolist(), z.tolist()), n.tolist())) == want
+    x, z, n = oracle.ssj(rx, ry, sz, sy, c=2, order=1)
+    assert list(zip(x.tolist(), z.tolist(), n.tolist()))[:2] == [(5, 5, 3), (4, 4, 2)]
+    assert len(x) == 8
+
+
+def two_relations(n, n_x, n_y, seed, signed):
+    """R and S drawn as one relation split by row parity, so that with signed
+    ids both use the same element ids."""
+    x, y = datagen.random_small(2 * n, n_x, n_y, seed=seed, dup=True, signed=signed)
+    return x[0::2], y[0::2], x[1::2], y[1::2]
+
+
+@pytest.mark.parametrize("seed", range(8))
+@pytest.mark.parametrize("c", [1, 2, 3])
+def test_ssj_matches_brute_force(seed, c):
+    rx, ry, sz, sy = two_relations(60 + 7 * seed, 15, 12, 500 + seed, seed % 2 == 1)
+    ov = brute_overlaps(rx, ry, sz, sy)
+    x, z, n = oracle.ssj(rx, ry, sz, sy, c=c)
+    assert list(zip(zip(x.tolist(), z.tolist()), n.tolist())) == sorted((k, v) for k, v in ov.items() if v >= c)
+    # ordered: overlap descending, ties by (x, z)
+    x, z, n = oracle.ssj(rx, ry, sz, sy, c=c, order=1)
+    want = sorted(((k, v) for k, v in ov.items() if v >= c), key=lambda kv: (-kv[1], kv[0]))
+    assert list(zip(zip(x.tolist(), z.tolist()), n.tolist())) == want
+
+
+def test_ssj_overlap_one_is_the_two_path_and_counts_sum_to_j():
+    rx, ry = datagen.zipf_edges(3000, 300, 80, 1.2, 71)
+    sz, sy = datagen.zipf_edges(2500, 250, 80, 1.2, 72)
+    x, z, n = oracle.ssj(rx, ry, sz, sy, c=1)
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    np.testing.assert_array_equal(x, ex)
+    np.testing.assert_array_equal(z, ez)
+    assert int(n.sum()) == oracle.join_size(rx, ry, sz, sy)
+    assert (n >= 1).all()
+
+
+def test_ssj_communities_closed_form():
+    # c communities of m sets over g elements each, every set holds all g
+    # elements of its community: every in-community pair overlaps in g.
+    c_, m, g = 5, 7, 4
+    xs = np.repeat(np.arange(c_ * m), g)
+    ys = (np.arange(c_ * m)[:, None] // m * g + np.arange(g)[None, :]).ravel()
+    for c in (1, g, g + 1):
+        x, z, n = oracle.ssj(xs, ys, xs, ys, c=c)
+        assert x.size == (c_ * m * m if c <= g else 0)
+        assert (n == g).all()
+
+
+def test_bsi_matches_brute_force_and_the_example():
+    rx, ry, sz, sy = example_relations()
+    q = [(4, 3, 0), (4, 4, 1), (1, 3, 0), (2, 2, 0), (3, 6, 1), (6, 2, 0), (7, 1, 0), (5, 5, 1), (1, 1, 1)]
+    got = oracle.bsi(rx, ry, sz, sy, [a for a, _, _ in q], [b for _, b, _ in q])
+    assert got.tolist() == [bool(v) for _, _, v in q]
+    for seed in range(6):
+        rx, ry, sz, sy = two_relations(80, 20, 15, 700 + seed, seed % 2 == 0)
+        ov = brute_overlaps(rx, ry, sz, sy)
+        rng = np.random.default_rng(seed)
+        tx = np.concatenate([rng.choice(rx, 40), rng.integers(-5, 30, 10)]).astype(np.int32)
+        tz = np.concatenate([rng.choice(sz, 40), rng.integers(-5, 30, 10)]).astype(np.int32)
+        got = oracle.bsi(rx, ry, sz, sy, tx, tz)
+        assert got.tolist() == [(a, b) in ov for a, b in zip(tx.tolist(), tz.tolist())]
+    assert oracle.bsi(rx, ry, sz, sy, [], []).size == 0
