@@ -353,6 +353,26 @@ jp_status jp_two_path_static(jp_handle *h,
                              const jp_options *opt, int32_t *out_x, int32_t *out_z, int64_t cap,
                              int64_t *n_out, jp_stats *stats);
 
+/*
+ * Set similarity join (Section 2.1, "Set Similarity"; Section 4, the heavy
+ * and light parts of SizeAware++ and the ordered variant): R(x, y) says set
+ * x holds element y, S(z, y) that set z holds y; the result is every pair
+ * (a, c) with |{b : (a,b) in R} & {b : (c,b) in S}| >= min_overlap, with
+ * that overlap.  Evaluated by Algorithm 1 with counts kept: the light
+ * witnesses are counted per pair after one sort, the heavy part adds the
+ * product's exact int32 counts C[a][c] (light and heavy witnesses partition
+ * the join, so the sum is the overlap).  min_overlap = 1 gives the two-path
+ * result.  Options as for jp_two_path (the dedup field is ignored).
+ * On JP_OK *out holds a result of arity 3: column 0 = x, column 1 = z,
+ * column 2 = overlap (int32).  order 0: pairs ascending by (x, z); order 1
+ * (ordered SSJ): by overlap descending, ties by (x, z) ascending.
+ * JP_EINVAL for min_overlap < 1 or an order other than 0 and 1.
+ */
+jp_status jp_ssj(jp_handle *h,
+                 const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                 const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+                 int64_t min_overlap, int32_t order, const jp_options *opt, jp_result **out);
+
 /* One two-path instance of a batch: device columns as for jp_two_path. */
 typedef struct jp_instance {
     const int32_t *r_x, *r_y;

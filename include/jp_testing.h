@@ -40,6 +40,12 @@ jp_status jp_test_set_lookback_wait(jp_handle *h, int64_t ticks);
  * setting (0 or 1). */
 int32_t jp_test_set_checks(int32_t on);
 
+/* jp_ssj builds 64-bit candidate and order keys when the pair ranks and the
+ * counts fit in 64 bits, else 128-bit keys.  on = 1 makes later calls use
+ * 128-bit keys always (process-wide), so tests reach that path on small
+ * inputs.  Returns the previous setting. */
+int32_t jp_test_set_wide_overlap_keys(int32_t on);
+
 /* Keeps the first of every run of equal adjacent keys, in order; *n_out (host). */
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out);
 

@@ -131,6 +131,8 @@ def _load():
         lib.jp_two_path.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), ctypes.POINTER(P)]
         lib.jp_two_path_static.argtypes = [P, P, P, i64, P, P, i64, ctypes.POINTER(Options), P, P, i64,
                                            ctypes.POINTER(i64), ctypes.POINTER(Stats)]
+        lib.jp_ssj.argtypes = [P, P, P, i64, P, P, i64, i64, ctypes.c_int32, ctypes.POINTER(Options),
+                               ctypes.POINTER(P)]
         lib.jp_star.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64),
                                 ctypes.POINTER(Options), ctypes.POINTER(P)]
         lib.jp_result_size.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32)]
@@ -169,7 +171,7 @@ def _load():
         lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
         f32 = ctypes.c_float
         lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
-        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_star", "jp_result_size",
+        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_ssj", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
@@ -424,6 +426,28 @@ class Handle:
             err.n_out = n.value
             raise err
         return n.value, s.as_dict()
+
+    def ssj_result(self, rx, ry, sz, sy, min_overlap=1, ordered=False, delta1=None, delta2=None, strategy=None,
+                   bmm="auto", y_rule="max", timing=False, seed=None) -> Result:
+        """Set similarity join: pairs whose sets share >= min_overlap elements."""
+        rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+        if rx.numel() != ry.numel() or sz.numel() != sy.numel():
+            raise ValueError("column lengths differ")
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, "global", timing, seed)
+        out = ctypes.c_void_p()
+        self._check(_load().jp_ssj(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(),
+                                   int(min_overlap), 1 if ordered else 0, ctypes.byref(o), ctypes.byref(out)))
+        return Result(self, out)
+
+    def ssj(self, rx, ry, sz, sy, **kw):
+        """(x, z, overlap, stats): int32 tensors of the pairs and their overlaps."""
+        r = self.ssj_result(rx, ry, sz, sy, **kw)
+        try:
+            x, z, cnt = r.to_torch()
+            return x, z, cnt, r.stats
+        finally:
+            r.free()
 
     def two_path_batch_result(self, instances, delta1=None, delta2=None, strategy=None, bmm="auto", y_rule="max",
                               dedup="auto", timing=False, seed=None) -> Result:

@@ -263,6 +263,39 @@ jp_status jp_two_path(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int6
     return st;
 }
 
+jp_status jp_ssj(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                 const int32_t *s_y, int64_t n_s, int64_t min_overlap, int32_t order, const jp_options *opt,
+                 jp_result **out) {
+    if (!h) return JP_EINVAL;
+    if (!out) {
+        h->err = "out is NULL";
+        return JP_EINVAL;
+    }
+    *out = nullptr;
+    if (bad_col(r_x, n_r) || bad_col(r_y, n_r) || bad_col(s_z, n_s) || bad_col(s_y, n_s)) {
+        h->err = "relation column is NULL or its length is negative";
+        return JP_EINVAL;
+    }
+    if (min_overlap < 1 || (order != 0 && order != 1)) {
+        h->err = "min_overlap must be >= 1 and order 0 or 1";
+        return JP_EINVAL;
+    }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    o.dedup = JP_DEDUP_GLOBAL;  // counts come from one sort of all witnesses
+    jp::OverlapSpec spec;
+    spec.min_c = min_overlap;
+    spec.order = order;
+    spec.force_wide = jp::wide_overlap_keys_flag() != 0;
+    jp_result *r = nullptr;
+    jp_status st = guarded(h, [&] { r = jp::run_two_path(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, o, &spec); });
+    if (st == JP_OK) *out = r;
+    return st;
+}
+
 jp_status jp_two_path_static(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
                              const int32_t *s_y, int64_t n_s, const jp_options *opt, int32_t *out_x, int32_t *out_z,
                              int64_t cap, int64_t *n_out, jp_stats *stats) {

@@ -24,19 +24,36 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr int BM = 128, BN = 128, BK = 128;
 constexpr int LDS_STRIDE = BK + 16;
 
+// Epilogue functors: emit(pos, i, j, cnt) stores the nonzero C[i][j] = cnt
+// at output slot pos.  kCounts: the functor uses cnt (the split-K path, which
+// keeps only cnt > 0, is then not taken).
 struct KeyEmit {  // nonzero (i, j) -> (rowmap[i] << shift) | colmap[j]
+    static constexpr bool kCounts = false;
     const int32_t *rowmap, *colmap;
     int shift;
     uint64_t *keys;
-    __device__ void operator()(int64_t pos, int64_t i, int64_t j) const {
+    __device__ void operator()(int64_t pos, int64_t i, int64_t j, uint32_t) const {
         keys[pos] = ((uint64_t)(uint32_t)rowmap[i] << shift) | (uint64_t)(uint32_t)colmap[j];
     }
 };
 struct PairEmit {  // nonzero (i, j) -> rows[pos] = i, cols[pos] = j
+    static constexpr bool kCounts = false;
     int32_t *rows, *cols;
-    __device__ void operator()(int64_t pos, int64_t i, int64_t j) const {
+    __device__ void operator()(int64_t pos, int64_t i, int64_t j, uint32_t) const {
         rows[pos] = (int32_t)i;
         cols[pos] = (int32_t)j;
+    }
+};
+
+template <class K>
+struct CountKeyEmit {  // nonzero (i, j) -> ((rowmap[i] << shift | colmap[j]) << wshift) | C[i][j]
+    static constexpr bool kCounts = true;
+    const int32_t *rowmap, *colmap;
+    int shift, wshift;
+    K *keys;
+    __device__ void operator()(int64_t pos, int64_t i, int64_t j, uint32_t cnt) const {
+        const K pair = ((K)(uint32_t)rowmap[i] << shift) | (K)(uint32_t)colmap[j];
+        keys[pos] = (pair << wshift) | (K)cnt;
     }
 };
 
@@ -57,11 +74,12 @@ struct PairRows {  // row (a1, a2) = M1[a1,:] AND M2[a2,:] (0/1 bytes), a1 = r /
 };
 template <class K>
 struct TripleEmit {  // nonzero ((a1,a2), a3) -> x1 << s1 | x2 << s2 | x3
+    static constexpr bool kCounts = false;
     const int32_t *x1_of, *x2_of, *x3_of;
     int64_t u2;
     int s1, s2;
     K *keys;
-    __device__ void operator()(int64_t pos, int64_t i, int64_t j) const {
+    __device__ void operator()(int64_t pos, int64_t i, int64_t j, uint32_t) const {
         const int64_t a1 = i / u2, a2 = i - a1 * u2;
         keys[pos] = ((K)(uint32_t)x1_of[a1] << s1) | ((K)(uint32_t)x2_of[a2] << s2) | (K)(uint32_t)x3_of[j];
     }
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                     int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
                     int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
                     if (acc[f][g][r] > 0 && i < u && j < w) {
-                        if (pos < cap) emit(pos, i, j);
+                        if (pos < cap) emit(pos, i, j, (uint32_t)acc[f][g][r]);
                         ++pos;
                     }
                 }
@@ -368,7 +386,7 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                     const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
                     const int64_t j = col0 + wn * 64 + g * 16 + fr;
                     if (acc[f][g][r] > 0 && i < u && j < w) {
-                        if (pos < cap) emit(pos, i, j);
+                        if (pos < cap) emit(pos, i, j, (uint32_t)acc[f][g][r]);
                         ++pos;
                     }
                 }
@@ -414,7 +432,7 @@ __global__ __launch_bounds__(256) void k_emit_bitmap(const uint32_t *bitmap, int
             const int b = __ffs(bits) - 1;
             bits &= bits - 1;
             const int64_t e = q * 32 + b;
-            if (pos < cap) emit(pos, e / w, e % w);
+            if (pos < cap) emit(pos, e / w, e % w, 0u);  // split-K: only cnt > 0 is known
             ++pos;
         }
     }
@@ -433,7 +451,7 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
     // rows are long: about two workgroups per compute unit, chunks of at least
     // 1024 bytes.
     int64_t kchunk = ld;
-    if (tiles < c.num_cus && ld >= 4 * 1024) {
+    if (!Emit::kCounts && tiles < c.num_cus && ld >= 4 * 1024) {
         const int64_t want = std::max<int64_t>(1, (2 * c.num_cus) / tiles);
         kchunk = std::max<int64_t>(1024, ceil_div(ceil_div(ld, want), BK) * BK);
     }
@@ -556,7 +574,7 @@ __global__ __launch_bounds__(256) void k_bmm_bitpop(const uint64_t *__restrict__
             for (int j = 0; j < 8; ++j) {
                 const int64_t gi = row0 + ty + 16 * i, gj = col0 + tx + 16 * j;
                 if (acc[i][j] > 0 && gi < u && gj < w) {
-                    if (pos < cap) emit(pos, gi, gj);
+                    if (pos < cap) emit(pos, gi, gj, acc[i][j]);
                     ++pos;
                 }
             }
@@ -662,6 +680,19 @@ void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,
                       unsigned long long *count_dev) {
     bool_matmul_any(c, A, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
+}
+
+void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
+                            int kind, const int32_t *rowmap, const int32_t *colmap, int shift, int wshift, void *keys,
+                            bool wide, int64_t cap, unsigned long long *count_dev) {
+    if (wide)
+        bool_matmul_any(c, A, Bt, u, w, ld, kind,
+                        CountKeyEmit<unsigned __int128>{rowmap, colmap, shift, wshift, (unsigned __int128 *)keys}, cap,
+                        count_dev);
+    else
+        bool_matmul_any(c, A, Bt, u, w, ld, kind, CountKeyEmit<uint64_t>{rowmap, colmap, shift, wshift,
+                                                                          (uint64_t *)keys},
+                        cap, count_dev);
 }
 
 void star_bmm_keys(const Ctx &c, const int8_t *M1, const int8_t *M2, const int8_t *M3, int64_t u1, int64_t u2,

@@ -126,9 +126,23 @@ struct Ingest {
 // Builds the Section 5 degree indexes of an indexed instance (summary.hip).
 void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummary &s);
 
+// Set similarity output of a two-path instance (Section 2.1): pairs whose
+// sets share at least min_c elements, with the overlap as a third column;
+// order 1 sorts by overlap descending, then (x, z).
+struct OverlapSpec {
+    int64_t min_c = 1;
+    int order = 0;
+    bool force_wide = false;  // 128-bit candidate and order keys even when 64 bits hold them (tests)
+};
+// Process-wide switch behind force_wide (jp_test_set_wide_overlap_keys).
+inline int &wide_overlap_keys_flag() {
+    static int on = 0;
+    return on;
+}
+
 // Pipelines.
 jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
-                        const int32_t *sy, int64_t ns, const jp_options &o);
+                        const int32_t *sy, int64_t ns, const jp_options &o, const OverlapSpec *ov = nullptr);
 jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst, const jp_options &o);
 jp_result *run_star(const Ctx &c, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
                     const jp_options &o);
@@ -138,6 +152,11 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *x, const int32_t 
 // rows/cols into out_i / out_j (capacity cap) and counts into *count_dev.
 void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
                        int kind, int32_t *out_i, int32_t *out_j, int64_t cap, unsigned long long *count_dev);
+// Same, emitting ((rowmap[i] << shift | colmap[j]) << wshift) | C[i][j]: the
+// key of the pair with its count (u64 keys, or 128-bit keys when wide).
+void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
+                            int kind, const int32_t *rowmap, const int32_t *colmap, int shift, int wshift, void *keys,
+                            bool wide, int64_t cap, unsigned long long *count_dev);
 // Same, emitting packed keys (rowmap[i] << shift) | colmap[j] (u64).
 void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,

@@ -93,6 +93,11 @@ int32_t jp_test_set_checks(int32_t on) {
     jp::checks_flag() = on ? 1 : 0;
     return prev;
 }
+int32_t jp_test_set_wide_overlap_keys(int32_t on) {
+    const int32_t prev = jp::wide_overlap_keys_flag();
+    jp::wide_overlap_keys_flag() = on ? 1 : 0;
+    return prev;
+}
 jp_status jp_test_unique_u64(jp_handle *h, const uint64_t *in, int64_t n, uint64_t *out, int64_t *n_out) {
     if (!h || n < 0 || (n && (!in || !out)) || !n_out) return JP_EINVAL;
     UniqArgs a{h, in, out, n, 0};

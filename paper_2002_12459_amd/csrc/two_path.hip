@@ -140,10 +140,12 @@ struct ExpandArgs {
     const int32_t *zlist;  // concatenated z-rank lists
     int64_t zlist_n;
     int bz;
-    uint64_t *out;
+    int wshift;            // > 0: key = (pair << wshift) | 1 (a counted witness of weight 1)
+    void *out;             // K keys
     int64_t *err;          // set when an index falls outside zlist
 };
 
+template <class K>
 __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
     const int64_t o0 = (int64_t)blockIdx.x * kExpTile;
     const int64_t olast = std::min<int64_t>(o0 + kExpTile, a.J_L) - 1;
@@ -157,7 +159,8 @@ __global__ __launch_bounds__(kExpBlock) void k_light_expand(ExpandArgs a) {
             const bool ok = idx >= 0 && idx < a.zlist_n;
             const int32_t z = a.zlist[ok ? idx : 0];
             if (!ok) *a.err = 1;
-            a.out[o] = ((uint64_t)(uint32_t)a.r_xr[e] << a.bz) | (uint64_t)(uint32_t)z;
+            const K pair = ((K)(uint32_t)a.r_xr[e] << a.bz) | (K)(uint32_t)z;
+            reinterpret_cast<K *>(a.out)[o] = a.wshift ? ((pair << a.wshift) | (K)1) : pair;
         }
     }
 }
@@ -555,25 +558,177 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     return true;
 }
 
+// ---- overlap output (set similarity join) ---------------------------------
+// Every distinct pair with its number of witnesses |N_R(x) & N_S(z)|: the
+// light witnesses and the heavy product partition the full join (Algorithm 1),
+// so a pair's overlap is its light witness count plus its heavy count C[x][z].
+// Candidates carry a weight in their low bits: 1 for a light witness, C[x][z]
+// (at most v) for a heavy nonzero; after one sort the run of a pair holds its
+// light witnesses and at most one heavy entry, which sorts last, so the
+// overlap is (run length - 1) + the last entry's weight.
+struct OverlapIn {
+    ExpandArgs ex;  // light witnesses; out / wshift / err are set here
+    int64_t J_L = 0, cap_h = 0;
+    bool has_heavy = false;
+    const int8_t *M1 = nullptr, *M2t = nullptr;
+    int64_t u = 0, v = 0, w = 0, ld = 0;
+    const int32_t *x_of_hx = nullptr, *z_of_hz = nullptr;
+    int bmm_kind = 0;
+    int bx = 0, bz = 0;
+    int64_t dom_x = 0, dom_y = 0, dom_z = 0;
+    const int32_t *xorig = nullptr, *zorig = nullptr;
+    int64_t min_c = 1;
+    int order = 0;
+    bool force_wide = false;
+};
+
+// Ordered variant: selected pairs as (max - overlap) << pbits | pair keys,
+// sorted, then unranked.
+template <class K, class K2>
+static int64_t overlap_ordered(const Ctx &c, const OverlapIn &in, const K *s, const int64_t *en, int64_t n_pairs,
+                               int wb, jp_result *res, int64_t *S) {
+    const int pbits = in.bx + in.bz;
+    const int64_t cmax = std::max<int64_t>(in.dom_y, 1);  // an overlap is at most |dom y|
+    const int cb = bits_for((uint64_t)cmax);
+    DBuf<K2> k2 = c.buf<K2>(std::max<int64_t>(n_pairs, 1)), t2 = c.buf<K2>(std::max<int64_t>(n_pairs, 1));
+    K2 *kk = k2.get();
+    const K wmask = ((K)1 << wb) - 1;
+    const int64_t minc = in.min_c;
+    const int wbs = wb, pb = pbits;
+    compact_v(
+        c, n_pairs,
+        [=] __device__(int64_t p) {
+            const int64_t e = en[p], prev = en[p > 0 ? p - 1 : 0], b = p > 0 ? prev + 1 : 0;
+            const int64_t cnt = (e - b) + (int64_t)(s[e] & wmask);
+            const K2 pair = (K2)(s[e] >> wbs);
+            return Pick<K2>{cnt >= minc, ((K2)(uint64_t)(cmax - cnt) << pb) | pair};
+        },
+        [=] __device__(int64_t, int64_t q, K2 key) { kk[q] = key; }, S + 22);
+    const int64_t n = c.load(S + 22);
+    const K2 *sorted = radix_sort(c, kk, t2.get(), n, pbits + cb);
+    for (int i = 0; i < 3; ++i) res->cols[i] = c.buf<int32_t>(std::max<int64_t>(n, 1));
+    int32_t *ox = res->cols[0].get(), *oz = res->cols[1].get(), *oc = res->cols[2].get();
+    const int32_t *xo = in.xorig, *zo = in.zorig;
+    const uint64_t zm = (1ull << in.bz) - 1;
+    const int bzs = in.bz;
+    const uint64_t nx = (uint64_t)in.dom_x, nz = (uint64_t)in.dom_z;
+    int64_t *err = S + 20;
+    c.zero(err, 1);
+    for_each(c, n, [=] __device__(int64_t i) {
+        const K2 k = sorted[i];
+        const uint64_t pair = (uint64_t)(k & (((K2)1 << pb) - 1));
+        const uint64_t xi = pair >> bzs, zi = pair & zm;
+        const bool ok = (xi < nx) & (zi < nz);
+        if (!ok) *err = 1;
+        ox[i] = xo[ok ? xi : 0];
+        oz[i] = zo[ok ? zi : 0];
+        oc[i] = (int32_t)(cmax - (int64_t)(uint64_t)(k >> pb));
+    });
+    JP_CHECK(c.load(err) == 0, JP_EINTERNAL, "overlap output key outside the rank tables");
+    return n;
+}
+
+template <class K>
+static void overlap_output(const Ctx &c, const OverlapIn &in, jp_result *res, jp_stats &st, int64_t *S) {
+    const int wb = bits_for((uint64_t)std::max<int64_t>(in.v, 1));  // heavy counts are at most v
+    const int pbits = in.bx + in.bz;
+    const int64_t cap = in.J_L + in.cap_h;
+    DBuf<K> cand = c.buf<K>(std::max<int64_t>(cap, 1));
+    if (in.J_L > 0) {
+        ExpandArgs a = in.ex;
+        a.wshift = wb;
+        a.out = cand.get();
+        a.err = S + 19;
+        c.zero(S + 19, 1);
+        const int64_t blocks = ceil_div(in.J_L, kExpTile);
+        hipLaunchKernelGGL(k_light_expand<K>, dim3(grid_x(blocks, kExpBlock)), dim3(kExpBlock), 0, c.stream, a);
+        JP_HIP(hipGetLastError());
+        JP_CHECK(c.load(S + 19) == 0, JP_EINTERNAL, "light expansion index outside the witness lists");
+    }
+    int64_t nnz = 0;
+    if (in.has_heavy) {
+        int used = JP_BMM_I8_MFMA;
+        Ctx cb = c;
+        cb.bmm_used = &used;
+        bool_matmul_count_keys(cb, in.M1, in.M2t, in.u, in.w, in.ld, in.bmm_kind, in.x_of_hx, in.z_of_hz, in.bz, wb,
+                               cand.get() + in.J_L, sizeof(K) == 16, in.cap_h, (unsigned long long *)(S + 17));
+        nnz = c.load(S + 17);
+        JP_CHECK(nnz <= in.cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
+        st.bmm = used;
+        st.bmm_ops = 2.0 * (double)in.u * (double)in.v * (double)in.w;
+    }
+    st.nnz_heavy = nnz;
+    const int64_t total = in.J_L + nnz;
+    DBuf<K> tmp = c.buf<K>(std::max<int64_t>(total, 1));
+    const K *s = radix_sort(c, cand.get(), tmp.get(), total, pbits + wb);
+    // last index of every run of equal pairs
+    DBuf<int64_t> ends = c.buf<int64_t>(std::max<int64_t>(total, 1));
+    int64_t *en = ends.get();
+    const int wbs = wb;
+    compact(
+        c, total,
+        [=] __device__(int64_t i) {
+            const K next = s[i + 1 < total ? i + 1 : i];  // clamped: loads stay in range
+            return (i + 1 == total) | ((s[i] >> wbs) != (next >> wbs));
+        },
+        [=] __device__(int64_t i, int64_t p) { en[p] = i; }, S + 21);
+    const int64_t n_pairs = c.load(S + 21);
+    st.J_H = st.J - st.J_L;
+    if (in.order == 1) {
+        const int cb = bits_for((uint64_t)std::max<int64_t>(in.dom_y, 1));
+        res->n = pbits + cb <= 64 && !in.force_wide ? overlap_ordered<K, uint64_t>(c, in, s, en, n_pairs, wb, res, S)
+                                  : overlap_ordered<K, unsigned __int128>(c, in, s, en, n_pairs, wb, res, S);
+        return;
+    }
+    for (int i = 0; i < 3; ++i) res->cols[i] = c.buf<int32_t>(std::max<int64_t>(n_pairs, 1));
+    int32_t *ox = res->cols[0].get(), *oz = res->cols[1].get(), *oc = res->cols[2].get();
+    const int32_t *xo = in.xorig, *zo = in.zorig;
+    const K wmask = ((K)1 << wb) - 1;
+    const uint64_t zm = (1ull << in.bz) - 1;
+    const int bzs = in.bz;
+    const uint64_t nx = (uint64_t)in.dom_x, nz = (uint64_t)in.dom_z;
+    const int64_t minc = in.min_c;
+    int64_t *err = S + 20;
+    c.zero(err, 1);
+    compact(
+        c, n_pairs,
+        [=] __device__(int64_t p) {
+            const int64_t e = en[p], prev = en[p > 0 ? p - 1 : 0], b = p > 0 ? prev + 1 : 0;
+            return (e - b) + (int64_t)(s[e] & wmask) >= minc;
+        },
+        [=] __device__(int64_t p, int64_t q) {
+            const int64_t e = en[p], prev = en[p > 0 ? p - 1 : 0], b = p > 0 ? prev + 1 : 0;
+            const uint64_t pair = (uint64_t)(s[e] >> wbs);
+            const uint64_t xi = pair >> bzs, zi = pair & zm;
+            const bool ok = (xi < nx) & (zi < nz);
+            if (!ok) *err = 1;
+            ox[q] = xo[ok ? xi : 0];
+            oz[q] = zo[ok ? zi : 0];
+            oc[q] = (int32_t)((e - b) + (int64_t)(s[e] & wmask));
+        },
+        S + 18);
+    JP_CHECK(c.load(err) == 0, JP_EINTERNAL, "overlap output key outside the rank tables");
+    res->n = c.load(S + 18);
+}
+
 jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
-                        const int32_t *sy, int64_t ns, const jp_options &o) {
+                        const int32_t *sy, int64_t ns, const jp_options &o, const OverlapSpec *ov) {
     const bool timing = (o.flags & JP_FLAG_TIMING) != 0;
     Timeline tl(c, timing);
     const int ev_start = tl.mark();
     auto res = std::make_unique<jp_result>();
     res->alloc = c.alloc;
-    res->arity = 2;
+    res->arity = ov ? 3 : 2;
     jp_stats &st = res->stats;
     std::memset(&st, 0, sizeof(st));
-    st.arity = 2;
+    st.arity = res->arity;
     st.delta1 = st.delta2 = JP_DELTA_INF;
     st.strategy = o.strategy;
     st.dedup = JP_DEDUP_GLOBAL;
 
     auto finish_empty = [&]() {
         res->n = 0;
-        res->cols[0] = c.buf<int32_t>(1);
-        res->cols[1] = c.buf<int32_t>(1);
+        for (int i = 0; i < res->arity; ++i) res->cols[i] = c.buf<int32_t>(1);
         return res.release();
     };
     if (nr == 0 || ns == 0) return finish_empty();
@@ -698,7 +853,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     // distinct z: the output then needs no rank-to-id lookup per pair, and
     // the witness lists are built in offsets from the start.
     const int bzr = bits_for((uint64_t)(dom_z - 1)), bzo = bits_for((uint64_t)(g.zspan - 1));
-    const bool z_off = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
+    const bool z_off = !ov && o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bzo) && g.zspan <= 4 * dom_z;
 
     // Heavy matrices: M1 = heavy x by heavy y (R), M2^T = heavy z by heavy y (S).
     // The pass over R also marks the heavy y that some heavy x meets: only
@@ -839,11 +994,50 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     const double uw = (double)u * (double)w;
     const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, uw) : 0;
     const int bz = z_off ? bzo : bzr;
-    const bool segmented = o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bz);
+    const bool segmented = !ov && o.dedup != JP_DEDUP_GLOBAL && segmented_dedup_fits(bz);
     int64_t nnz = 0;
     int ev_light = ev_plan, ev_bmm0 = ev_plan, ev_bmm1 = ev_plan, ev_heavy = ev_plan;
 
-    if (segmented) {
+    if (ov) {
+        // ---- overlap counts: counted light witnesses + heavy counts, one sort ---------
+        OverlapIn in;
+        ExpandArgs &a = in.ex;
+        a.eoff = eoff.get();
+        a.n_e = n_r2;
+        a.J_L = J_L;
+        a.r_xr = r_xr.get();
+        a.lbase = lbase.get();
+        a.zlist = zlist;
+        a.zlist_n = zlist_n;
+        a.bz = bz;
+        in.J_L = J_L;
+        in.cap_h = cap_h;
+        in.has_heavy = has_heavy;
+        in.M1 = M1.get();
+        in.M2t = M2t.get();
+        in.u = u;
+        in.v = v;
+        in.w = w;
+        in.ld = ld;
+        in.x_of_hx = x_of_hx.get();
+        in.z_of_hz = z_of_hz.get();
+        in.bmm_kind = o.bmm;
+        in.bx = bx;
+        in.bz = bz;
+        in.dom_x = dom_x;
+        in.dom_y = dom_y;
+        in.dom_z = dom_z;
+        in.xorig = xorig.get();
+        in.zorig = zorig.get();
+        in.min_c = ov->min_c;
+        in.order = ov->order;
+        const int wb = bits_for((uint64_t)std::max<int64_t>(v, 1));
+        in.force_wide = ov->force_wide;
+        if (bx + bz + wb <= 64 && !ov->force_wide) overlap_output<uint64_t>(c, in, res.get(), st, S);
+        else overlap_output<unsigned __int128>(c, in, res.get(), st, S);
+        nnz = st.nnz_heavy;
+        st.n_out = res->n;
+    } else if (segmented) {
         // ---- heavy nonzeros, sorted; then per-x dedup fused with enumeration ----------
         st.dedup = JP_DEDUP_SEGMENTED;
         // z offsets (see above): the witness lists are already in offsets; the
@@ -921,11 +1115,13 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             a.zlist = zlist;
             a.zlist_n = zlist_n;
             a.bz = bz;
+            a.wshift = 0;
             a.out = cand.get();
             a.err = S + 19;
             c.zero(S + 19, 1);
             const int64_t blocks = ceil_div(J_L, kExpTile);
-            hipLaunchKernelGGL(k_light_expand, dim3(grid_x(blocks, kExpBlock)), dim3(kExpBlock), 0, c.stream, a);
+            hipLaunchKernelGGL(k_light_expand<uint64_t>, dim3(grid_x(blocks, kExpBlock)), dim3(kExpBlock), 0, c.stream,
+                               a);
             JP_HIP(hipGetLastError());
         }
         ev_light = tl.mark();

@@ -1,0 +1,104 @@
+"""Set similarity join through the C ABI (jp_ssj) against the oracle.
+
+Every pair with at least c common elements and its exact overlap must match
+the oracle bit for bit, in both output orders, at thresholds that send the
+overlaps through the light path only, through the heavy product's counts,
+and through both; 64-bit and 128-bit candidate keys.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from tests.conftest import load_golden
+
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("checks_mode")]
+
+
+@pytest.fixture(scope="module")
+def jp():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2002_12459_amd as jp
+    return jp
+
+
+@pytest.fixture(params=["keys64", "keys128"])
+def key_width(request, jp):
+    lib = jp._load()
+    lib.jp_test_set_wide_overlap_keys.argtypes = [ctypes.c_int32]
+    lib.jp_test_set_wide_overlap_keys.restype = ctypes.c_int32
+    prev = lib.jp_test_set_wide_overlap_keys(1 if request.param == "keys128" else 0)
+    yield request.param
+    lib.jp_test_set_wide_overlap_keys(prev)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.int32))).cuda()
+
+
+def check(jp, rx, ry, sz, sy, c, ordered, **kw):
+    ex, ez, en = oracle.ssj(rx, ry, sz, sy, c=c, order=1 if ordered else 0)
+    x, z, n, st = jp.default_handle(0).ssj(dev(rx), dev(ry), dev(sz), dev(sy), min_overlap=c, ordered=ordered, **kw)
+    assert x.numel() == ex.size, (x.numel(), ex.size, c, ordered, kw)
+    np.testing.assert_array_equal(x.cpu().numpy(), ex)
+    np.testing.assert_array_equal(z.cpu().numpy(), ez)
+    np.testing.assert_array_equal(n.cpu().numpy(), en)
+    return st
+
+
+def example():
+    rows = load_golden("two_path_example.txt")
+    R = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "R"])
+    S = np.array([(int(r[1]), int(r[2])) for r in rows if r[0] == "S"])
+    return R[:, 0], R[:, 1], S[:, 0], S[:, 1]
+
+
+@pytest.mark.parametrize("ordered", [False, True])
+@pytest.mark.parametrize("c", [1, 2, 3, 4])
+@pytest.mark.parametrize("kw", [{"delta1": 2, "delta2": 2}, {"strategy": "light"}, {"delta1": 1, "delta2": 1}])
+def test_worked_example(jp, key_width, c, ordered, kw):
+    st = check(jp, *example(), c, ordered, **kw)
+    if kw.get("delta1") == 2:
+        assert (st["u"], st["v"], st["w"], st["nnz_heavy"]) == (3, 3, 3, 9)
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("d", [1, 2, 3, None])
+def test_random_small(jp, key_width, seed, d):
+    x, y = datagen.random_small(600, 60, 40, seed=900 + seed, dup=True, signed=seed % 2 == 1)
+    rx, ry, sz, sy = x[0::2], y[0::2], x[1::2], y[1::2]
+    kw = {"strategy": "light"} if d is None else {"delta1": d, "delta2": d}
+    for c in (1, 2, 3):
+        check(jp, rx, ry, sz, sy, c, c == 2, **kw)
+
+
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"delta1": 30, "delta2": 8},
+                                {"delta1": 30, "delta2": 8, "bmm": "bitpop"}, {"delta1": 5, "delta2": 3}])
+def test_zipf(jp, kw):
+    rx, ry = datagen.zipf_edges(30_000, 3_000, 600, 1.2, 31)
+    sz, sy = datagen.zipf_edges(30_000, 3_000, 600, 1.2, 32)
+    for c, ordered in ((1, False), (2, True), (3, False), (5, True)):
+        check(jp, rx, ry, sz, sy, c, ordered, **kw)
+
+
+def test_communities_closed_form(jp, key_width):
+    # 6 communities of 40 sets over 20 elements, each set holding 12 of them:
+    # heavy at small thresholds, overlaps up to 12
+    rx, ry = datagen.communities(6, 40, 20, 0.6, seed=5)
+    for kw in ({"delta1": 1, "delta2": 1}, {"strategy": "light"}, {}):
+        for c in (1, 4, 8):
+            check(jp, rx, ry, rx, ry, c, True, **kw)
+
+
+def test_arguments(jp):
+    h = jp.default_handle(0)
+    a = dev([1, 2])
+    with pytest.raises(jp.JoinProjectError) as e:
+        h.ssj(a, a, a, a, min_overlap=0)
+    assert e.value.status == 1
+    x, z, n, _ = h.ssj(dev([]), dev([]), a, a, min_overlap=2)
+    assert x.numel() == z.numel() == n.numel() == 0
