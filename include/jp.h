@@ -373,6 +373,25 @@ jp_status jp_ssj(jp_handle *h,
                  const int32_t *s_z, const int32_t *s_y, int64_t n_s,
                  int64_t min_overlap, int32_t order, const jp_options *opt, jp_result **out);
 
+/*
+ * Batched Boolean set intersection (Section 2.1, "Boolean Set Intersection";
+ * Section 3.3): R(x, y) says set x holds element y, S(z, y) likewise; the
+ * batch holds n_t queries (t_x[i], t_z[i]), device int32 columns.  For every
+ * i, answers[i] (device, n_t bytes, caller-owned) becomes 1 when the sets
+ * {b : (t_x[i], b) in R} and {b : (t_z[i], b) in S} intersect, else 0.  As
+ * in the paper's experiments, the batch filters R to the queried x and S to
+ * the queried z, the filtered two-path query runs through Algorithm 1 with
+ * the given options, and each query is answered from its sorted output.
+ * Queries may repeat and may name ids absent from the relations (answer 0).
+ * *stats (may be NULL) receives the statistics of the filtered two-path
+ * evaluation.  The call returns after the answers are written.
+ */
+jp_status jp_bsi(jp_handle *h,
+                 const int32_t *r_x, const int32_t *r_y, int64_t n_r,
+                 const int32_t *s_z, const int32_t *s_y, int64_t n_s,
+                 const int32_t *t_x, const int32_t *t_z, int64_t n_t,
+                 const jp_options *opt, uint8_t *answers, jp_stats *stats);
+
 /* One two-path instance of a batch: device columns as for jp_two_path. */
 typedef struct jp_instance {
     const int32_t *r_x, *r_y;

@@ -133,6 +133,8 @@ def _load():
                                            ctypes.POINTER(i64), ctypes.POINTER(Stats)]
         lib.jp_ssj.argtypes = [P, P, P, i64, P, P, i64, i64, ctypes.c_int32, ctypes.POINTER(Options),
                                ctypes.POINTER(P)]
+        lib.jp_bsi.argtypes = [P, P, P, i64, P, P, i64, P, P, i64, ctypes.POINTER(Options), P,
+                               ctypes.POINTER(Stats)]
         lib.jp_star.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64),
                                 ctypes.POINTER(Options), ctypes.POINTER(P)]
         lib.jp_result_size.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32)]
@@ -171,7 +173,7 @@ def _load():
         lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
         f32 = ctypes.c_float
         lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
-        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_ssj", "jp_star", "jp_result_size",
+        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_ssj", "jp_bsi", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
@@ -448,6 +450,24 @@ class Handle:
             return x, z, cnt, r.stats
         finally:
             r.free()
+
+    def bsi(self, rx, ry, sz, sy, tx, tz, delta1=None, delta2=None, strategy=None, bmm="auto", y_rule="max",
+            dedup="auto", timing=False, seed=None):
+        """Batched Boolean set intersection: (answers, stats), answers a uint8
+        CUDA tensor with answers[i] = 1 iff the set of tx[i] in R and the set
+        of tz[i] in S intersect."""
+        torch = _torch()
+        rx, ry, sz, sy, tx, tz = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y"),
+                                                          (tx, "t_x"), (tz, "t_z")))
+        if rx.numel() != ry.numel() or sz.numel() != sy.numel() or tx.numel() != tz.numel():
+            raise ValueError("column lengths differ")
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed)
+        ans = torch.empty(tx.numel(), dtype=torch.uint8, device=tx.device)
+        s = Stats()
+        self._check(_load().jp_bsi(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(), _ptr(tx),
+                                   _ptr(tz), tx.numel(), ctypes.byref(o), _ptr(ans), ctypes.byref(s)))
+        return ans, s.as_dict()
 
     def two_path_batch_result(self, instances, delta1=None, delta2=None, strategy=None, bmm="auto", y_rule="max",
                               dedup="auto", timing=False, seed=None) -> Result:

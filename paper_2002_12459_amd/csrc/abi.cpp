@@ -296,6 +296,23 @@ jp_status jp_ssj(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n
     return st;
 }
 
+jp_status jp_bsi(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
+                 const int32_t *s_y, int64_t n_s, const int32_t *t_x, const int32_t *t_z, int64_t n_t,
+                 const jp_options *opt, uint8_t *answers, jp_stats *stats) {
+    if (!h) return JP_EINVAL;
+    if (bad_col(r_x, n_r) || bad_col(r_y, n_r) || bad_col(s_z, n_s) || bad_col(s_y, n_s) || bad_col(t_x, n_t) ||
+        bad_col(t_z, n_t) || bad_col(answers, n_t)) {
+        h->err = "a column or the answer array is NULL, or a length is negative";
+        return JP_EINVAL;
+    }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    return guarded(h, [&] { jp::run_bsi(make_ctx(h), r_x, r_y, n_r, s_z, s_y, n_s, t_x, t_z, n_t, o, answers, stats); });
+}
+
 jp_status jp_two_path_static(jp_handle *h, const int32_t *r_x, const int32_t *r_y, int64_t n_r, const int32_t *s_z,
                              const int32_t *s_y, int64_t n_s, const jp_options *opt, int32_t *out_x, int32_t *out_z,
                              int64_t cap, int64_t *n_out, jp_stats *stats) {

@@ -144,6 +144,11 @@ inline int &wide_overlap_keys_flag() {
 jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz,
                         const int32_t *sy, int64_t ns, const jp_options &o, const OverlapSpec *ov = nullptr);
 jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst, const jp_options &o);
+// Batched Boolean set intersection (bsi.hip): answers[i] (device, nt bytes)
+// = 1 iff the sets of tx[i] in R and of tz[i] in S intersect.
+void run_bsi(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, const int32_t *sz, const int32_t *sy,
+             int64_t ns, const int32_t *tx, const int32_t *tz, int64_t nt, const jp_options &o, uint8_t *answers,
+             jp_stats *stats);
 jp_result *run_star(const Ctx &c, int k, const int32_t *const *x, const int32_t *const *y, const int64_t *n,
                     const jp_options &o);
 
