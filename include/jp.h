@@ -422,9 +422,15 @@ jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *ins
 jp_status jp_result_batch_offsets(const jp_result *r, int32_t *n_inst, int64_t *offsets);
 
 /*
- * Star join-project Q*_k (Section 3.2), 2 <= k <= 3.  Relation i has columns
+ * Star join-project Q*_k (Section 3.2), 2 <= k <= 8.  Relation i has columns
  * x[i], y[i] of n[i] rows (host arrays of device pointers).  On JP_OK, *out
- * holds a result of arity k; column i holds x_i.
+ * holds a result of arity k; column i holds x_i.  k = 2 is jp_two_path.  The
+ * heavy part is the product V x W^T of Section 3.2, V over the first
+ * ceil(k/2) relations and W over the rest.  Thresholds: FIXED, LIGHT_ONLY,
+ * or (any other strategy) Section 3.2's balance of the light, output and
+ * product costs with |OUT| estimated by J, light only when J <= 20 N.
+ * JP_EINVAL when k is out of range or the k dense rank widths of the output
+ * exceed 128 bits; JP_ENOMEM when the join has 2^40 or more witnesses.
  */
 jp_status jp_star(jp_handle *h, int k,
                   const int32_t *const *x, const int32_t *const *y, const int64_t *n,

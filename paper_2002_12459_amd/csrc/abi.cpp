@@ -431,8 +431,8 @@ jp_status jp_star(jp_handle *h, int k, const int32_t *const *x, const int32_t *c
         return JP_EINVAL;
     }
     *out = nullptr;
-    if (k < 2 || k > 3 || !x || !y || !n) {
-        h->err = "k must be 2 or 3 and x, y, n non-NULL";
+    if (k < 2 || k > 8 || !x || !y || !n) {
+        h->err = "k must be in [2, 8] and x, y, n non-NULL";
         return JP_EINVAL;
     }
     for (int i = 0; i < k; ++i)

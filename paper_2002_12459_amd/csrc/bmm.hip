@@ -63,25 +63,52 @@ struct PlainRows {  // A stored row-major
     int64_t ld;
     __device__ v4i load(int64_t r, int64_t k) const { return *(const v4i *)(A + r * ld + k); }
 };
-struct PairRows {  // row (a1, a2) = M1[a1,:] AND M2[a2,:] (0/1 bytes), a1 = r / u2, a2 = r % u2
-    const int8_t *M1, *M2;
-    int64_t ld, u2;
+// Row (a_0, ..., a_{N-1}) of a product of N factor matrices (the V and W of
+// the star query, Section 3.2): the AND of the factors' rows M_i[a_i, :] (0/1
+// bytes), with r = mixed-radix number of the a_i over the factor heights
+// u_i, the last factor varying fastest.  V and W are never stored.
+template <int N>
+struct TupleRows {
+    const int8_t *M[N];
+    int64_t u[N];
+    int64_t ld;
     __device__ v4i load(int64_t r, int64_t k) const {
-        const int64_t a1 = r / u2, a2 = r - a1 * u2;
-        const v4i p = *(const v4i *)(M1 + a1 * ld + k), q = *(const v4i *)(M2 + a2 * ld + k);
-        return p & q;
+        v4i acc = {-1, -1, -1, -1};
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+            const int64_t a = i > 0 ? r % u[i] : r;
+            if (i > 0) r /= u[i];
+            acc &= *(const v4i *)(M[i] + a * ld + k);
+        }
+        return acc;
     }
 };
-template <class K>
-struct TripleEmit {  // nonzero ((a1,a2), a3) -> x1 << s1 | x2 << s2 | x3
+
+// Nonzero (i, j) of V x W^T: i numbers (a_0..a_{G-1}) over u[0..G), j numbers
+// (a_G..a_{G+H-1}) over u[G..G+H) (last fastest); the key is the k-tuple of
+// their x ranks, x_t << s[t] for every position t.
+template <class K, int G, int H>
+struct TupleEmit {
     static constexpr bool kCounts = false;
-    const int32_t *x1_of, *x2_of, *x3_of;
-    int64_t u2;
-    int s1, s2;
+    const int32_t *xof[G + H];
+    int64_t u[G + H];
+    int s[G + H];
     K *keys;
     __device__ void operator()(int64_t pos, int64_t i, int64_t j, uint32_t) const {
-        const int64_t a1 = i / u2, a2 = i - a1 * u2;
-        keys[pos] = ((K)(uint32_t)x1_of[a1] << s1) | ((K)(uint32_t)x2_of[a2] << s2) | (K)(uint32_t)x3_of[j];
+        K key = 0;
+#pragma unroll
+        for (int t = G - 1; t >= 0; --t) {
+            const int64_t a = t > 0 ? i % u[t] : i;
+            if (t > 0) i /= u[t];
+            key |= (K)(uint32_t)xof[t][a] << s[t];
+        }
+#pragma unroll
+        for (int t = G + H - 1; t >= G; --t) {
+            const int64_t a = t > G ? j % u[t] : j;
+            if (t > G) j /= u[t];
+            key |= (K)(uint32_t)xof[t][a] << s[t];
+        }
+        keys[pos] = key;
     }
 };
 
@@ -143,8 +170,8 @@ __device__ __forceinline__ int64_t tile_reserve(uint32_t wtot, unsigned long lon
 // the epilogue ORs "count > 0" into a u x w bitmap instead of emitting
 // (entries are sums of non-negative chunk counts, so the OR of the chunk
 // tests is the test of the sum).
-template <class ARows, class Emit>
-__global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__restrict__ Bt, int64_t u, int64_t w,
+template <class ARows, class BRows, class Emit>
+__global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_t u, int64_t w,
                                                 int64_t ld, int64_t tiles_m, int64_t tiles_n, Emit emit, int64_t cap,
                                                 unsigned long long *count, int64_t kchunk, uint32_t *bitmap) {
     __shared__ __attribute__((aligned(16))) int8_t sA[BM * LDS_STRIDE];
@@ -176,7 +203,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, const int8_t *__res
                 int64_t r = row0 + lr + 32 * q;
                 ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
                 int64_t c = col0 + lr + 32 * q;
-                rb[q] = c < w ? *(const v4i *)(Bt + c * ld + k0 + lc) : v4i{0, 0, 0, 0};
+                rb[q] = c < w ? brows.load(c, k0 + lc) : v4i{0, 0, 0, 0};
             }
         };
         auto store_stage = [&]() {
@@ -438,13 +465,12 @@ __global__ __launch_bounds__(256) void k_emit_bitmap(const uint32_t *bitmap, int
     }
 }
 
-template <class ARows, class Emit>
-void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind, Emit emit,
-                int64_t cap, unsigned long long *count_dev) {
+template <class ARows, class BRows, class Emit>
+void launch_bmm_rows(const Ctx &c, ARows arows, BRows brows, int64_t u, int64_t w, int64_t ld, Emit emit, int64_t cap,
+                     unsigned long long *count_dev) {
     JP_CHECK(ld % kBmmPadK == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 128");
     c.zero(count_dev, 1);
     if (u <= 0 || w <= 0 || ld <= 0) return;
-    (void)kind;
     const int64_t tm = ceil_div(u, BM), tn = ceil_div(w, BN);
     const int64_t tiles = tm * tn;
     // Split K when the tiles alone would leave most of the chip idle and the
@@ -460,21 +486,27 @@ void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t 
     constexpr int64_t kMaxGrid = 1ll << 22;  // items beyond this are looped over (multiple of 8)
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
     if (nchunks == 1) {
-        hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, Bt, u, w,
-                           ld, tm, tn, emit, cap, count_dev, kchunk, (uint32_t *)nullptr);
+        hipLaunchKernelGGL((k_bmm_i8<ARows, BRows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows,
+                           brows, u, w, ld, tm, tn, emit, cap, count_dev, kchunk, (uint32_t *)nullptr);
         JP_HIP(hipGetLastError());
         return;
     }
     const int64_t nwords = ceil_div(u * w, 32);
     DBuf<uint32_t> bitmap = c.buf<uint32_t>((size_t)nwords);
     c.zero(bitmap.get(), (size_t)nwords);
-    hipLaunchKernelGGL((k_bmm_i8<ARows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, Bt, u, w, ld,
-                       tm, tn, emit, cap, count_dev, kchunk, bitmap.get());
+    hipLaunchKernelGGL((k_bmm_i8<ARows, BRows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), 0, c.stream, arows, brows,
+                       u, w, ld, tm, tn, emit, cap, count_dev, kchunk, bitmap.get());
     JP_HIP(hipGetLastError());
     const int64_t eb = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nwords, 256), (int64_t)c.num_cus * 4));
     hipLaunchKernelGGL((k_emit_bitmap<Emit>), dim3(grid_x(eb, 256)), dim3(256), 0, c.stream,
                        (const uint32_t *)bitmap.get(), u, w, emit, cap, count_dev);
     JP_HIP(hipGetLastError());
+}
+
+template <class ARows, class Emit>
+void launch_bmm(const Ctx &c, ARows arows, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, Emit emit, int64_t cap,
+                unsigned long long *count_dev) {
+    launch_bmm_rows(c, arows, PlainRows{Bt, ld}, u, w, ld, emit, cap, count_dev);
 }
 
 }  // namespace
@@ -619,7 +651,7 @@ static void run_variant(const Ctx &c, BmmVariant v, const int8_t *A, const int8_
     switch (v) {
         case BmmVariant::T256: launch_bmm_big(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
         case BmmVariant::BITPOP: launch_bitpop(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
-        default: launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, JP_BMM_I8_MFMA, emit, cap, count_dev); break;
+        default: launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, emit, cap, count_dev); break;
     }
 }
 
@@ -695,17 +727,57 @@ void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int
                         cap, count_dev);
 }
 
-void star_bmm_keys(const Ctx &c, const int8_t *M1, const int8_t *M2, const int8_t *M3, int64_t u1, int64_t u2,
-                   int64_t u3, int64_t ld, const int32_t *x1_of, const int32_t *x2_of, const int32_t *x3_of, int s1,
-                   int s2, void *keys, bool wide, int64_t cap, unsigned long long *count_dev) {
-    const PairRows rows{M1, M2, ld, u2};
-    if (wide)
-        launch_bmm(c, rows, M3, u1 * u2, u3, ld, JP_BMM_I8_MFMA,
-                   TripleEmit<unsigned __int128>{x1_of, x2_of, x3_of, u2, s1, s2, (unsigned __int128 *)keys}, cap,
-                   count_dev);
-    else
-        launch_bmm(c, rows, M3, u1 * u2, u3, ld, JP_BMM_I8_MFMA,
-                   TripleEmit<uint64_t>{x1_of, x2_of, x3_of, u2, s1, s2, (uint64_t *)keys}, cap, count_dev);
+// Star query heavy product C = V x W^T (Section 3.2) over k factor matrices
+// M_t (u[t] x ld, 0/1): V rows are the ceil(k/2)-tuples of the first factors,
+// W rows the floor(k/2)-tuples of the rest, both generated from the factors'
+// rows as they are loaded.  Nonzeros become k-tuple keys (xof[t][a_t] << s[t]).
+template <class K, int G, int H>
+static void star_product(const Ctx &c, const int8_t *const *M, const int64_t *u, int64_t ld, const int32_t *const *xof,
+                         const int *s, void *keys, int64_t cap, unsigned long long *count_dev) {
+    TupleRows<G> a;
+    TupleRows<H> b;
+    TupleEmit<K, G, H> e;
+    int64_t rows_a = 1, rows_b = 1;
+    for (int t = 0; t < G; ++t) {
+        a.M[t] = M[t];
+        a.u[t] = u[t];
+        rows_a *= u[t];
+    }
+    for (int t = 0; t < H; ++t) {
+        b.M[t] = M[G + t];
+        b.u[t] = u[G + t];
+        rows_b *= u[G + t];
+    }
+    a.ld = b.ld = ld;
+    for (int t = 0; t < G + H; ++t) {
+        e.xof[t] = xof[t];
+        e.u[t] = u[t];
+        e.s[t] = s[t];
+    }
+    e.keys = (K *)keys;
+    launch_bmm_rows(c, a, b, rows_a, rows_b, ld, e, cap, count_dev);
+}
+
+template <class K>
+static void star_product_k(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
+                           const int32_t *const *xof, const int *s, void *keys, int64_t cap,
+                           unsigned long long *count_dev) {
+    switch (k) {
+        case 3: star_product<K, 2, 1>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 4: star_product<K, 2, 2>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 5: star_product<K, 3, 2>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 6: star_product<K, 3, 3>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 7: star_product<K, 4, 3>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 8: star_product<K, 4, 4>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        default: fail(JP_EINTERNAL, "star product needs 3 <= k <= 8");
+    }
+}
+
+void star_bmm_keys(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
+                   const int32_t *const *xof, const int *s, void *keys, bool wide, int64_t cap,
+                   unsigned long long *count_dev) {
+    if (wide) star_product_k<unsigned __int128>(c, k, M, u, ld, xof, s, keys, cap, count_dev);
+    else star_product_k<uint64_t>(c, k, M, u, ld, xof, s, keys, cap, count_dev);
 }
 
 }  // namespace jp

@@ -1,26 +1,27 @@
-// Star join-project Q*_3(x1,x2,x3) = R1(x1,y), R2(x2,y), R3(x3,y)
-// (Section 3.2).  k = 2 is the two-path query and goes to run_two_path.
+// Star join-project Q*_k(x1..xk) = R1(x1,y), ..., Rk(xk,y) (Section 3.2),
+// 3 <= k <= 8.  k = 2 is the two-path query and goes to run_two_path.
 //
 //  ingest     every relation becomes a set indexed by y; y missing from any
 //             relation is dropped; y and each x_i get dense ranks; degrees.
 //  partition  x_i heavy iff deg_i(x_i) > Delta2.  A tuple (a, b) of R_i is in
 //             R_i^- when a is light, in R_i^diamond when b has degree
 //             <= Delta1 in every other relation, in R_i^+ otherwise.  A
-//             witness (a1, a2, a3, b) is heavy iff all three tuples are in
-//             R_i^+, i.e. every a_i is heavy and b is heavy (degree > Delta1)
-//             in at least two relations ("star-heavy").
-//  light      per y, the witness box N1 x N2 x N3 when y is not star-heavy,
-//             else the box minus H1 x H2 x H3, written as the disjoint boxes
-//             L1 x N2 x N3, H1 x L2 x N3, H1 x H2 x L3 over lists that hold
-//             light x first; every box is enumerated into packed keys
-//             x1 << (b2+b3) | x2 << b3 | x3 with the output index space cut
+//             witness (a1..ak, b) is heavy iff all k tuples are in R_i^+,
+//             i.e. every a_i is heavy and b is heavy (degree > Delta1) in at
+//             least two relations ("star-heavy").
+//  light      per y, the witness box N1 x ... x Nk when y is not star-heavy,
+//             else the box minus H1 x ... x Hk, written as the k disjoint
+//             boxes H1 x .. x H(t-1) x Lt x N(t+1) x .. x Nk (t = 1..k) over
+//             lists that hold light x first; every box is enumerated into
+//             packed keys x1 << s1 | ... | xk with the output index space cut
 //             evenly across workgroups.
-//  heavy      C[(a1,a2), a3] = sum_b M1[a1,b] M2[a2,b] M3[a3,b] over heavy a_i
-//             and star-heavy b: the product V x W^T of Section 3.2 with V's
-//             rows (a1, a2) generated on the fly as M1[a1,:] AND M2[a2,:]
-//             (V is never stored); nonzeros become keys.
+//  heavy      C[(a1..ag), (a(g+1)..ak)] = sum_b prod_i M_i[a_i, b] over heavy
+//             a_i and star-heavy b, g = ceil(k/2): the product V x W^T of
+//             Section 3.2 with the rows of V and W generated from the factor
+//             matrices as they are loaded (neither is stored); nonzeros
+//             become keys.
 //  union      one radix sort of light + heavy keys (64-bit, or 128-bit when
-//             the three rank widths exceed 64 bits), unique, unrank.
+//             the rank widths exceed 64 bits), unique, unrank.
 #include <climits>
 
 #include "debug.hpp"
@@ -241,36 +242,45 @@ void partition_light_first(const Ctx &c, RelIdx &r, int64_t dom_y, int64_t d2, D
     r.adj = std::move(out);
 }
 
-// Light witness boxes, three per y (sizes 0 when unused).
+// Light witness boxes, k per y (sizes 0 when unused).
+constexpr int kMaxStar = 8;
 struct BoxArgs {
-    const int64_t *boff;  // exclusive offsets of the 3 * dom_y box sizes (+1)
+    const int64_t *boff;  // exclusive offsets of the k * dom_y box sizes (+1)
     int64_t n_box, J_L;
-    const int64_t *off1, *off2, *off3;
-    const int64_t *nl1, *nl2, *nl3;
+    int k;
+    const int64_t *off[kMaxStar];
+    const int64_t *nl[kMaxStar];
+    const int32_t *adj[kMaxStar];
     const uint8_t *sh;    // star-heavy flag per y
-    const int32_t *adj1, *adj2, *adj3;
-    int s1, s2;           // shifts: key = x1 << s1 | x2 << s2 | x3
+    int s[kMaxStar];      // key = sum of x_i << s[i]
     void *out;
-    int wide;             // 1: 128-bit keys
     int64_t *err;
 };
 
-// Ranges (start, length) of the three lists of box t of y.
-__device__ __forceinline__ void box_ranges(const BoxArgs &a, int64_t y, int t, int64_t *A0, int64_t *An, int64_t *B0,
-                                           int64_t *Bn, int64_t *C0, int64_t *Cn) {
-    const int64_t o1 = a.off1[y], d1 = a.off1[y + 1] - o1, l1 = a.nl1[y];
-    const int64_t o2 = a.off2[y], d2 = a.off2[y + 1] - o2, l2 = a.nl2[y];
-    const int64_t o3 = a.off3[y], d3 = a.off3[y + 1] - o3, l3 = a.nl3[y];
+// Range (start, length) of relation i's list in box t of y.  Not star-heavy:
+// box 0 = N1 x ... x Nk, the others empty.  Star-heavy: box t takes the heavy
+// part of the lists before t, the light part of list t, all of the lists
+// after t.
+__device__ __forceinline__ void box_list(const BoxArgs &a, int64_t y, int t, int i, int64_t *b0, int64_t *bn) {
+    const int64_t o = a.off[i][y], d = a.off[i][y + 1] - o, l = a.nl[i][y];
     const bool h = a.sh[y] != 0;
-    // not star-heavy: box 0 = N1 x N2 x N3.  Star-heavy: box 0 = L1 x N2 x N3,
-    // box 1 = H1 x L2 x N3, box 2 = H1 x H2 x L3.
-    const bool t0 = t == 0, t1 = t == 1, t2 = t == 2;
-    *A0 = t0 ? o1 : o1 + l1;
-    *An = t0 ? (h ? l1 : d1) : (h ? d1 - l1 : 0);
-    *B0 = t2 ? o2 + l2 : o2;
-    *Bn = t0 ? d2 : (t1 ? l2 : d2 - l2);
-    *C0 = o3;
-    *Cn = t2 ? l3 : d3;
+    const int64_t hs = i < t ? o + l : o;
+    const int64_t hn = i < t ? d - l : (i == t ? l : d);
+    *b0 = h ? hs : o;
+    *bn = h ? hn : (t == 0 ? d : 0);
+}
+
+// Product of the box's list lengths, saturated at 2^40 (the caller refuses
+// joins that large).
+__device__ __forceinline__ int64_t box_size(const BoxArgs &a, int64_t y, int t) {
+    int64_t p = 1;
+    for (int i = 0; i < a.k; ++i) {
+        int64_t b0, bn;
+        box_list(a, y, t, i, &b0, &bn);
+        const int64_t cap = (int64_t)1 << 40;
+        p = (bn != 0 && p > cap / bn) ? cap : p * bn;
+    }
+    return p;
 }
 
 template <class K>
@@ -284,22 +294,23 @@ __global__ __launch_bounds__(256) void k_star_expand(BoxArgs a) {
         const int64_t o = o0 + (int64_t)j * 256 + threadIdx.x;
         if (o <= olast) {
             const int64_t b = upper_bound_dev(a.boff, lo, hi, o) - 1;
-            const int64_t y = b / 3;
-            const int t = (int)(b - 3 * y);
-            int64_t A0, An, B0, Bn, C0, Cn;
-            box_ranges(a, y, t, &A0, &An, &B0, &Bn, &C0, &Cn);
+            const int64_t y = b / a.k;
+            const int t = (int)(b - (int64_t)a.k * y);
             int64_t q = o - a.boff[b];
-            const bool ok = (An > 0) & (Bn > 0) & (Cn > 0) & (q < An * Bn * Cn);
+            K key = 0;
+            bool ok = true;
+            for (int i = a.k - 1; i >= 0; --i) {  // last list varies fastest
+                int64_t b0, bn;
+                box_list(a, y, t, i, &b0, &bn);
+                ok &= bn > 0;
+                const int64_t n1 = bn > 0 ? bn : 1;
+                const int64_t idx = q % n1;
+                q /= n1;
+                key |= (K)(uint32_t)a.adj[i][bn > 0 ? b0 + idx : 0] << a.s[i];
+            }
+            ok &= q == 0;
             if (!ok) *a.err = 1;
-            const int64_t cn = Cn > 0 ? Cn : 1, bn = Bn > 0 ? Bn : 1;
-            const int64_t ci = q % cn;
-            q /= cn;
-            const int64_t bi = q % bn;
-            const int64_t ai = q / bn;
-            const int32_t x1 = a.adj1[ok ? A0 + ai : 0];
-            const int32_t x2 = a.adj2[ok ? B0 + bi : 0];
-            const int32_t x3 = a.adj3[ok ? C0 + ci : 0];
-            out[o] = ((K)(uint32_t)x1 << a.s1) | ((K)(uint32_t)x2 << a.s2) | (K)(uint32_t)x3;
+            out[o] = key;
         }
     }
 }
@@ -307,52 +318,98 @@ __global__ __launch_bounds__(256) void k_star_expand(BoxArgs a) {
 }  // namespace
 
 // Heavy product of the star query (bmm.hip).
-void star_bmm_keys(const Ctx &c, const int8_t *M1, const int8_t *M2, const int8_t *M3, int64_t u1, int64_t u2,
-                   int64_t u3, int64_t ld, const int32_t *x1_of, const int32_t *x2_of, const int32_t *x3_of, int s1,
-                   int s2, void *keys, bool wide, int64_t cap, unsigned long long *count_dev);
+void star_bmm_keys(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
+                   const int32_t *const *xof, const int *s, void *keys, bool wide, int64_t cap,
+                   unsigned long long *count_dev);
+
+namespace {
+
+// Sorts the candidate keys, removes repeats and writes the k id columns.
+template <class K>
+int64_t star_union(const Ctx &c, int k, K *cand, int64_t total, int bits, const int *shift, const int *bx,
+                   const RelIdx *rel, jp_result *res, int64_t *S) {
+    DBuf<K> tmp = c.buf<K>(std::max<int64_t>(total, 1));
+    const K *s = radix_sort(c, cand, tmp.get(), total, bits);
+    struct Unrank {
+        const int32_t *xo[kMaxStar];
+        int32_t *col[kMaxStar];
+        uint64_t n[kMaxStar];
+        int sh[kMaxStar];
+        uint64_t mask[kMaxStar];
+        int k;
+    } u;
+    for (int i = 0; i < k; ++i) {
+        res->cols[i] = c.buf<int32_t>(std::max<int64_t>(total, 1));
+        u.xo[i] = rel[i].xorig.get();
+        u.col[i] = res->cols[i].get();
+        u.n[i] = (uint64_t)rel[i].dom_x;
+        u.sh[i] = shift[i];
+        u.mask[i] = bx[i] >= 64 ? ~0ull : ((1ull << bx[i]) - 1);
+    }
+    u.k = k;
+    int64_t *err = S + 11;
+    c.zero(err, 1);
+    compact(
+        c, total, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i > 0 ? i - 1 : 0]; },
+        [=] __device__(int64_t i, int64_t p) {
+            const K kk = s[i];
+            bool ok = true;
+            for (int t = 0; t < u.k; ++t) {
+                const uint64_t r = (uint64_t)(kk >> u.sh[t]) & u.mask[t];
+                ok &= r < u.n[t];
+                u.col[t][p] = u.xo[t][r < u.n[t] ? r : 0];
+            }
+            if (!ok) *err = 1;
+        },
+        S + 12);
+    JP_CHECK(c.load(err) == 0, JP_EINTERNAL, "star output key outside the rank tables");
+    return c.load(S + 12);
+}
+
+}  // namespace
 
 jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t *const *Y, const int64_t *N,
                     const jp_options &o) {
     if (k == 2) return run_two_path(c, X[0], Y[0], N[0], X[1], Y[1], N[1], o);
-    JP_CHECK(k == 3, JP_EINVAL, "star queries with k = 2 or 3 are supported");
+    JP_CHECK(k >= 3 && k <= kMaxStar, JP_EINVAL, "star queries with 2 <= k <= 8 relations are supported");
     const bool timing = (o.flags & JP_FLAG_TIMING) != 0;
     Timeline tl(c, timing);
     const int ev_start = tl.mark();
     auto res = std::make_unique<jp_result>();
     res->alloc = c.alloc;
-    res->arity = 3;
+    res->arity = k;
     jp_stats &st = res->stats;
     std::memset(&st, 0, sizeof(st));
-    st.arity = 3;
+    st.arity = k;
     st.delta1 = st.delta2 = JP_DELTA_INF;
     st.strategy = o.strategy;
     st.dedup = JP_DEDUP_GLOBAL;
     auto finish_empty = [&]() {
         res->n = 0;
-        for (int i = 0; i < 3; ++i) res->cols[i] = c.buf<int32_t>(1);
+        for (int i = 0; i < k; ++i) res->cols[i] = c.buf<int32_t>(1);
         return res.release();
     };
-    for (int i = 0; i < 3; ++i)
+    for (int i = 0; i < k; ++i)
         if (N[i] == 0) return finish_empty();
 
     DBuf<int64_t> scal = c.buf<int64_t>(32);
     int64_t *S = scal.get();
     // ranges
-    DBuf<int> mmb = c.buf<int>(12);
+    DBuf<int> mmb = c.buf<int>(4 * k);
     int *mm = mmb.get();
-    for_each(c, 6, [=] __device__(int64_t i) {
+    for_each(c, 2 * k, [=] __device__(int64_t i) {
         mm[2 * i] = INT_MAX;
         mm[2 * i + 1] = INT_MIN;
     });
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < k; ++i) {
         minmax3(c, X[i], N[i], mm + 4 * i);
         minmax3(c, Y[i], N[i], mm + 4 * i + 2);
     }
-    int hmm[12];
-    c.load_n(hmm, mm, 12);
+    int hmm[4 * kMaxStar];
+    c.load_n(hmm, mm, 4 * k);
     int64_t ymin = INT64_MAX, ymax = INT64_MIN;
-    int64_t xmin[3], xb[3];
-    for (int i = 0; i < 3; ++i) {
+    int64_t xmin[kMaxStar], xb[kMaxStar];
+    for (int i = 0; i < k; ++i) {
         xmin[i] = hmm[4 * i];
         xb[i] = bits_for((uint64_t)((int64_t)hmm[4 * i + 1] - hmm[4 * i]));
         ymin = std::min<int64_t>(ymin, hmm[4 * i + 2]);
@@ -360,61 +417,92 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
     }
     const int yb = bits_for((uint64_t)(ymax - ymin));
 
-    RelRaw raw[3];
-    for (int i = 0; i < 3; ++i) raw[i] = ingest_raw(c, X[i], Y[i], N[i], xmin[i], (int)xb[i], ymin, yb, S);
-    // y present in all three
+    RelRaw raw[kMaxStar];
+    for (int i = 0; i < k; ++i) raw[i] = ingest_raw(c, X[i], Y[i], N[i], xmin[i], (int)xb[i], ymin, yb, S);
+    // y present in every relation
     DBuf<uint32_t> Yk = c.buf<uint32_t>(std::max<int64_t>(raw[0].ny, 1));
     {
-        const uint32_t *y0 = raw[0].ys.get(), *y1 = raw[1].ys.get(), *y2 = raw[2].ys.get();
-        const int64_t n1 = raw[1].ny, n2 = raw[2].ny;
+        struct Lists {
+            const uint32_t *p[kMaxStar];
+            int64_t n[kMaxStar];
+            int k;
+        } L;
+        for (int i = 0; i < k; ++i) {
+            L.p[i] = raw[i].ys.get();
+            L.n[i] = raw[i].ny;
+        }
+        L.k = k;
         uint32_t *d = Yk.get();
-        auto in = [=] __device__(const uint32_t *a, int64_t n, uint32_t v) -> bool {
-            const int64_t p = lower_bound_dev(a, (int64_t)0, n, v);
-            const int64_t q = p < n ? p : n - 1;
-            return (p < n) & (a[q] == v);
-        };
         compact(
-            c, raw[0].ny, [=] __device__(int64_t j) { return (int)in(y1, n1, y0[j]) & (int)in(y2, n2, y0[j]); },
-            [=] __device__(int64_t j, int64_t p) { d[p] = y0[j]; }, S + 1);
+            c, raw[0].ny,
+            [=] __device__(int64_t j) {
+                const uint32_t v = L.p[0][j];
+                bool all = true;
+                for (int i = 1; i < L.k; ++i) {
+                    const int64_t n = L.n[i];
+                    const int64_t p = lower_bound_dev(L.p[i], (int64_t)0, n, v);
+                    all &= (p < n) & (L.p[i][p < n ? p : n - 1] == v);
+                }
+                return all;
+            },
+            [=] __device__(int64_t j, int64_t p) { d[p] = L.p[0][j]; }, S + 1);
     }
     const int64_t dom_y = c.load(S + 1);
     if (dom_y == 0) return finish_empty();
-    RelIdx rel[3];
-    for (int i = 0; i < 3; ++i) {
+    RelIdx rel[kMaxStar];
+    for (int i = 0; i < k; ++i) {
         rel[i] = finish_rel(c, raw[i], Yk.get(), dom_y, xmin[i], (int)xb[i], S + 2);
         raw[i] = RelRaw();
     }
-    // J = sum over y of d1 d2 d3
+    // J = sum over y of the product of the k degrees (each term saturated at 2^40)
+    BoxArgs ba;
+    ba.k = k;
+    for (int i = 0; i < k; ++i) {
+        ba.off[i] = rel[i].off.get();
+        ba.adj[i] = rel[i].adj.get();
+    }
     {
-        const int64_t *o1 = rel[0].off.get(), *o2 = rel[1].off.get(), *o3 = rel[2].off.get();
+        const BoxArgs bb = ba;
         reduce_sum(
             c, dom_y,
             [=] __device__(int64_t y) -> int64_t {
-                return (o1[y + 1] - o1[y]) * (o2[y + 1] - o2[y]) * (o3[y + 1] - o3[y]);
+                int64_t p = 1;
+                const int64_t cap = (int64_t)1 << 40;
+                for (int i = 0; i < bb.k; ++i) {
+                    const int64_t d = bb.off[i][y + 1] - bb.off[i][y];
+                    p = (d != 0 && p > cap / d) ? cap : p * d;
+                }
+                return p;
             },
             (unsigned long long *)(S + 3));
     }
     const int64_t J = c.load(S + 3);
+    JP_CHECK(J < ((int64_t)1 << 40), JP_ENOMEM, "the star join has 2^40 or more witnesses");
     const int ev_ingest = tl.mark();
-    st.n_r = rel[0].n + rel[1].n + rel[2].n;
+    int64_t n_all = 0, Nmax = 0;
+    for (int i = 0; i < k; ++i) {
+        n_all += rel[i].n;
+        Nmax = std::max(Nmax, rel[i].n);
+    }
+    st.n_r = n_all;
     st.dom_y = dom_y;
     st.dom_x = rel[0].dom_x;
-    st.dom_z = rel[2].dom_x;
+    st.dom_z = rel[k - 1].dom_x;
     st.J = J;
 
-    // thresholds: FIXED or LIGHT_ONLY; otherwise the k = 3 analysis of
-    // Section 3.2 balances N D1^2 = OUT D2 = (N/D2)^3 (its example gives
-    // D2 = N^(6/16), D1 = N^(7/16) at OUT = N^(3/2)); with OUT estimated as J
-    // this is D2 = (N^3 / J)^(1/4), D1 = sqrt(J D2 / N).
+    // thresholds: FIXED or LIGHT_ONLY; otherwise Section 3.2's balance of the
+    // three costs N D1^(k-1) = OUT D2 = (N/D2)^k (the product term with
+    // omega = 2; its k = 3 example gives D2 = N^(6/16), D1 = N^(7/16) at
+    // OUT = N^(3/2)), with OUT estimated as J: D2 = (N^k / J)^(1/(k+1)),
+    // D1 = (J D2 / N)^(1/(k-1)).  J <= 20 N: light only (Section 5's switch).
     int64_t d1 = JP_DELTA_INF, d2 = JP_DELTA_INF;
-    const int64_t Nmax = std::max(rel[0].n, std::max(rel[1].n, rel[2].n));
     if (o.strategy == JP_STRATEGY_FIXED) {
         d1 = o.delta1;
         d2 = o.delta2;
     } else if (o.strategy != JP_STRATEGY_LIGHT_ONLY && (double)J > 20.0 * (double)Nmax) {
         const double n = (double)Nmax, jj = (double)J;
-        const double t2 = std::pow(n * n * n / jj, 0.25);
-        const double t1 = std::sqrt(jj * t2 / n);
+        const double t2 = std::pow(std::pow(n, (double)k) / jj, 1.0 / (double)(k + 1));
+        const double t1 = std::pow(jj * t2 / n, 1.0 / (double)(k - 1));
         d2 = std::max<int64_t>(1, std::min<int64_t>(Nmax, (int64_t)t2));
         d1 = std::max<int64_t>(1, std::min<int64_t>(Nmax, (int64_t)t1));
     }
@@ -422,26 +510,31 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
     st.delta2 = d2;
 
     // partition
-    DBuf<int64_t> nl[3];
-    for (int i = 0; i < 3; ++i) partition_light_first(c, rel[i], dom_y, d2, &nl[i], S + 4);
+    DBuf<int64_t> nl[kMaxStar];
+    for (int i = 0; i < k; ++i) partition_light_first(c, rel[i], dom_y, d2, &nl[i], S + 4);
+    for (int i = 0; i < k; ++i) {
+        ba.adj[i] = rel[i].adj.get();  // reordered: light x first per y
+        ba.nl[i] = nl[i].get();
+    }
     DBuf<uint8_t> sh = c.buf<uint8_t>(dom_y);
     {
-        uint8_t *s = sh.get();
-        const int64_t *o1 = rel[0].off.get(), *o2 = rel[1].off.get(), *o3 = rel[2].off.get();
+        uint8_t *sp = sh.get();
+        const BoxArgs bb = ba;
         const int64_t dd1 = d1;
         for_each(c, dom_y, [=] __device__(int64_t y) {
-            const int hcnt = (int)((o1[y + 1] - o1[y]) > dd1) + (int)((o2[y + 1] - o2[y]) > dd1) +
-                             (int)((o3[y + 1] - o3[y]) > dd1);
-            s[y] = hcnt >= 2 ? 1 : 0;
+            int hcnt = 0;
+            for (int i = 0; i < bb.k; ++i) hcnt += (int)((bb.off[i][y + 1] - bb.off[i][y]) > dd1);
+            sp[y] = hcnt >= 2 ? 1 : 0;
         });
     }
-    // heavy ids of x_i and of star-heavy y
-    int64_t u[3] = {0, 0, 0}, v = 0;
-    DBuf<int32_t> hid[3], xof[3];
+    ba.sh = sh.get();
+    // heavy ids of the x_i and of the star-heavy y
+    int64_t u[kMaxStar] = {0}, v = 0;
+    DBuf<int32_t> hid[kMaxStar], xof[kMaxStar];
     DBuf<int32_t> hy = c.buf<int32_t>(dom_y);
     const bool any_heavy = d2 != JP_DELTA_INF;
     if (any_heavy) {
-        for (int i = 0; i < 3; ++i) {
+        for (int i = 0; i < k; ++i) {
             const int64_t nx = rel[i].dom_x;
             hid[i] = c.buf<int32_t>(nx);
             xof[i] = c.buf<int32_t>(nx);
@@ -454,53 +547,44 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
                     h[x] = (int32_t)p;
                     xo[p] = (int32_t)x;
                 },
-                S + 5 + i);
+                S + 13 + i);
         }
         int32_t *hyp = hy.get();
-        const uint8_t *s = sh.get();
+        const uint8_t *sp = sh.get();
         for_each(c, dom_y, [=] __device__(int64_t y) { hyp[y] = -1; });
         compact(
-            c, dom_y, [=] __device__(int64_t y) { return s[y] != 0; },
-            [=] __device__(int64_t y, int64_t p) { hyp[y] = (int32_t)p; }, S + 8);
-        int64_t h4[4];
-        c.load_n(h4, S + 5, 4);
-        u[0] = h4[0];
-        u[1] = h4[1];
-        u[2] = h4[2];
-        v = h4[3];
+            c, dom_y, [=] __device__(int64_t y) { return sp[y] != 0; },
+            [=] __device__(int64_t y, int64_t p) { hyp[y] = (int32_t)p; }, S + 21);
+        int64_t hv[kMaxStar + 1];
+        c.load_n(hv, S + 13, (size_t)kMaxStar + 1);
+        for (int i = 0; i < k; ++i) u[i] = hv[i];
+        v = hv[kMaxStar];
     }
-    const bool has_heavy = u[0] > 0 && u[1] > 0 && u[2] > 0 && v > 0;
-    st.u = u[0] * u[1];
+    bool has_heavy = v > 0;
+    double rows_v = 1, rows_w = 1;
+    const int g = (k + 1) / 2;
+    for (int i = 0; i < k; ++i) {
+        has_heavy &= u[i] > 0;
+        (i < g ? rows_v : rows_w) *= (double)u[i];
+    }
+    st.u = (int64_t)std::min(rows_v, 9.2e18);
     st.v = v;
-    st.w = u[2];
+    st.w = (int64_t)std::min(rows_w, 9.2e18);
 
     // light boxes
-    DBuf<int64_t> boff = c.buf<int64_t>(3 * dom_y + 1);
-    BoxArgs ba;
-    ba.off1 = rel[0].off.get();
-    ba.off2 = rel[1].off.get();
-    ba.off3 = rel[2].off.get();
-    ba.nl1 = nl[0].get();
-    ba.nl2 = nl[1].get();
-    ba.nl3 = nl[2].get();
-    ba.sh = sh.get();
-    ba.adj1 = rel[0].adj.get();
-    ba.adj2 = rel[1].adj.get();
-    ba.adj3 = rel[2].adj.get();
+    DBuf<int64_t> boff = c.buf<int64_t>(k * dom_y + 1);
     {
         const BoxArgs bb = ba;
         int64_t *bo = boff.get();
         scan_exclusive(
-            c, 3 * dom_y,
+            c, k * dom_y,
             [=] __device__(int64_t b) -> int64_t {
-                const int64_t y = b / 3;
-                int64_t A0, An, B0, Bn, C0, Cn;
-                box_ranges(bb, y, (int)(b - 3 * y), &A0, &An, &B0, &Bn, &C0, &Cn);
-                return An * Bn * Cn;
+                const int64_t y = b / bb.k;
+                return box_size(bb, y, (int)(b - (int64_t)bb.k * y));
             },
-            ArrayPut{bo}, bo + 3 * dom_y);
+            ArrayPut{bo}, bo + k * dom_y);
     }
-    const int64_t J_L = c.load(boff.get() + 3 * dom_y);
+    const int64_t J_L = c.load(boff.get() + k * dom_y);
     JP_CHECK(J_L >= 0 && J_L <= J, JP_EINTERNAL, "light witness count exceeds the join size");
     const int64_t J_H = J - J_L;
     JP_CHECK(has_heavy || J_H == 0, JP_EINTERNAL, "heavy witnesses without a heavy part");
@@ -508,21 +592,25 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
     st.J_H = J_H;
     const int ev_plan = tl.mark();
 
-    const int b1 = rel[0].bx, b2 = rel[1].bx, b3 = rel[2].bx;
-    const int bits = b1 + b2 + b3;
+    int bxs[kMaxStar], shift[kMaxStar];
+    int bits = 0;
+    for (int i = k - 1; i >= 0; --i) {
+        bxs[i] = rel[i].bx;
+        shift[i] = bits;
+        bits += rel[i].bx;
+    }
+    JP_CHECK(bits <= 128, JP_EINVAL, "the star output's rank widths need more than 128 bits");
     const bool wide = bits > 64;
-    const int s1 = b2 + b3, s2 = b3;
+    for (int i = 0; i < k; ++i) ba.s[i] = shift[i];
     const size_t ksz = wide ? sizeof(u128) : sizeof(uint64_t);
-    const int64_t cap = J_L + J_H;
+    const int64_t cap_h = has_heavy ? (int64_t)std::min<double>((double)J_H, rows_v * rows_w) : 0;
+    const int64_t cap = J_L + cap_h;
     DBuf<uint8_t> cand = c.buf<uint8_t>((size_t)std::max<int64_t>(cap, 1) * ksz);
     if (J_L > 0) {
         ba.boff = boff.get();
-        ba.n_box = 3 * dom_y;
+        ba.n_box = k * dom_y;
         ba.J_L = J_L;
-        ba.s1 = s1;
-        ba.s2 = s2;
         ba.out = cand.get();
-        ba.wide = wide;
         ba.err = S + 9;
         c.zero(S + 9, 1);
         const int64_t blocks = ceil_div(J_L, 4096);
@@ -538,8 +626,10 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
     int ev_b0 = ev_light, ev_b1 = ev_light;
     if (has_heavy) {
         const int64_t ld = ceil_div(v, kBmmPadK) * kBmmPadK;
-        DBuf<int8_t> M[3];
-        for (int i = 0; i < 3; ++i) {
+        DBuf<int8_t> M[kMaxStar];
+        const int8_t *Mp[kMaxStar];
+        const int32_t *xp[kMaxStar];
+        for (int i = 0; i < k; ++i) {
             M[i] = c.buf<int8_t>((size_t)(u[i] * ld));
             c.zero(M[i].get(), (size_t)(u[i] * ld));
             int8_t *m = M[i].get();
@@ -551,61 +641,25 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
                 const int32_t a = h[adj[e]], b = hyp[y];
                 if ((a >= 0) & (b >= 0)) m[(int64_t)(a >= 0 ? a : 0) * ldl + (b >= 0 ? b : 0)] = 1;
             });
+            Mp[i] = M[i].get();
+            xp[i] = xof[i].get();
         }
         ev_b0 = tl.mark();
-        star_bmm_keys(c, M[0].get(), M[1].get(), M[2].get(), u[0], u[1], u[2], ld, xof[0].get(), xof[1].get(),
-                      xof[2].get(), s1, s2, cand.get() + (size_t)J_L * ksz, wide, J_H,
+        star_bmm_keys(c, k, Mp, u, ld, xp, shift, cand.get() + (size_t)J_L * ksz, wide, cap_h,
                       (unsigned long long *)(S + 10));
         ev_b1 = tl.mark();
         nnz = c.load(S + 10);
-        JP_CHECK(nnz <= J_H, JP_EINTERNAL, "star heavy product produced more nonzeros than its bound");
+        JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "star heavy product produced more nonzeros than its bound");
         st.bmm = JP_BMM_I8_MFMA;
-        st.bmm_ops = 2.0 * (double)u[0] * (double)u[1] * (double)v * (double)u[2];
+        st.bmm_ops = 2.0 * rows_v * (double)v * rows_w;
     }
     st.nnz_heavy = nnz;
     const int ev_heavy = tl.mark();
 
     // union + duplicate removal + unrank
     const int64_t total = J_L + nnz;
-    DBuf<uint8_t> tmp = c.buf<uint8_t>((size_t)std::max<int64_t>(total, 1) * ksz);
-    for (int i = 0; i < 3; ++i) res->cols[i] = c.buf<int32_t>(std::max<int64_t>(total, 1));
-    int32_t *c0 = res->cols[0].get(), *c1 = res->cols[1].get(), *c2 = res->cols[2].get();
-    const int32_t *xo0 = rel[0].xorig.get(), *xo1 = rel[1].xorig.get(), *xo2 = rel[2].xorig.get();
-    const uint64_t m2 = (1ull << b2) - 1, m3 = (1ull << b3) - 1;
-    const int64_t n0 = rel[0].dom_x, n1 = rel[1].dom_x, n2 = rel[2].dom_x;
-    int64_t *err = S + 11;
-    c.zero(err, 1);
-    if (wide) {
-        const u128 *s = radix_sort(c, (u128 *)cand.get(), (u128 *)tmp.get(), total, bits);
-        compact(
-            c, total, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                const u128 kk = s[i];
-                const uint64_t a = (uint64_t)(kk >> s1), b = (uint64_t)(kk >> s2) & m2, cc = (uint64_t)kk & m3;
-                const bool ok = (a < (uint64_t)n0) & (b < (uint64_t)n1) & (cc < (uint64_t)n2);
-                if (!ok) *err = 1;
-                c0[p] = xo0[ok ? a : 0];
-                c1[p] = xo1[ok ? b : 0];
-                c2[p] = xo2[ok ? cc : 0];
-            },
-            S + 12);
-    } else {
-        const uint64_t *s = radix_sort(c, (uint64_t *)cand.get(), (uint64_t *)tmp.get(), total, bits);
-        compact(
-            c, total, [=] __device__(int64_t i) { return i == 0 || s[i] != s[i - 1]; },
-            [=] __device__(int64_t i, int64_t p) {
-                const uint64_t kk = s[i];
-                const uint64_t a = kk >> s1, b = (kk >> s2) & m2, cc = kk & m3;
-                const bool ok = (a < (uint64_t)n0) & (b < (uint64_t)n1) & (cc < (uint64_t)n2);
-                if (!ok) *err = 1;
-                c0[p] = xo0[ok ? a : 0];
-                c1[p] = xo1[ok ? b : 0];
-                c2[p] = xo2[ok ? cc : 0];
-            },
-            S + 12);
-    }
-    JP_CHECK(c.load(err) == 0, JP_EINTERNAL, "star output key outside the rank tables");
-    res->n = c.load(S + 12);
+    res->n = wide ? star_union<u128>(c, k, (u128 *)cand.get(), total, bits, shift, bxs, rel, res.get(), S)
+                  : star_union<uint64_t>(c, k, (uint64_t *)cand.get(), total, bits, shift, bxs, rel, res.get(), S);
     st.n_out = res->n;
     const int ev_end = tl.mark();
     if (timing) {

@@ -123,3 +123,72 @@ def test_star_wide_keys(jp):
         y = (np.arange(n) // 2).astype(np.int32)
         rels.append((x, y))
     check(jp, rels, strategy="light")
+
+
+# ---------------------------------------------------------------------------
+# k > 3: V over the first ceil(k/2) relations, W over the rest (Section 3.2)
+# ---------------------------------------------------------------------------
+
+def example_rels4():
+    rows = load_golden("star_example.txt")
+    U = [(int(r[1]), int(r[2])) for r in rows if r[0] == "U"]
+    return example_rels() + [(np.array([e[0] for e in U]), np.array([e[1] for e in U]))]
+
+
+def test_worked_example_star4(jp):
+    """Q*_4 over R, S, T, U: 237 output tuples and 286 witnesses at every
+    threshold pair; the light / heavy split matches the restatement."""
+    rels = example_rels4()
+    for d1, d2 in itertools.product([1, 2, 3, None], [1, 2, 3, None]):
+        st = check(jp, rels, delta1=d1, delta2=d2, strategy="fixed")
+        assert st["n_out"] == 237 and st["J"] == 286
+        if d1 is not None and d2 is not None:
+            r = ref.star_stats(rels, d1, d2)
+            assert (st["J_L"], st["J_H"]) == (r["J_L"], r["J_H"]), (d1, d2)
+    st = check(jp, rels, delta1=2, delta2=2)
+    assert st["J_H"] > 0 and st["nnz_heavy"] > 0
+
+
+@pytest.mark.parametrize("k", [4, 5, 6])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_small_star_k(jp, k, seed):
+    rng = np.random.default_rng(100 * k + seed)
+    signed = seed % 2 == 1
+    rels = [datagen.random_small(int(rng.integers(1, 60)), 20, 8, 1000 * k + seed * 11 + i, dup=True, signed=signed)
+            for i in range(k)]
+    if signed:  # share y ids so the signed case still joins
+        for i in range(1, k):
+            rels[i] = (rels[i][0], rels[0][1][rng.integers(0, rels[0][1].size, rels[i][1].size)])
+    for d1, d2 in [(1, 1), (2, 2), (3, 1), (None, None)]:
+        st = check(jp, rels, delta1=d1, delta2=d2, strategy="fixed")
+        if d1 is not None and seed < 2:
+            r = ref.star_stats(rels, d1, d2)
+            assert (st["J"], st["J_L"], st["J_H"]) == (r["J"], r["J_L"], r["J_H"])
+
+
+@pytest.mark.parametrize("kw", [dict(strategy="light"), dict(strategy="auto"), dict(delta1=50, delta2=6),
+                                dict(delta1=10, delta2=4)])
+def test_star4_zipf(jp, kw):
+    """Four 20K-edge Zipf(1.2) relations with independent y orders (J = 4.6M)."""
+    rels = [datagen.zipf_edges(20_000, 5_000, 2_000, 1.2, 50 + i) for i in range(4)]
+    check(jp, rels, **kw)
+
+
+@pytest.mark.parametrize("k", [4, 5])
+def test_star_k_communities_closed_form(jp, k):
+    """Dense communities: every in-community k-tuple is an output (c m^k);
+    with low thresholds the product of generated V and W rows carries them."""
+    x, y = datagen.communities(3, 8, 6, 1.0, seed=4)
+    st = check(jp, [(x, y)] * k, delta1=2, delta2=2)
+    assert st["n_out"] == 3 * 8 ** k and st["nnz_heavy"] > 0
+    st = check(jp, [(x, y)] * k, strategy="light")
+    assert st["n_out"] == 3 * 8 ** k
+
+
+def test_star4_wide_keys(jp):
+    """Four rank widths of 18 bits (72 > 64) use 128-bit keys, light and heavy."""
+    n = 140_000
+    rng = np.random.default_rng(8)
+    rels = [(rng.permutation(n).astype(np.int32), (np.arange(n) // 2).astype(np.int32)) for _ in range(4)]
+    check(jp, rels, strategy="light")
+    check(jp, rels, delta1=1, delta2=1)
