@@ -80,6 +80,7 @@ def parse():
     p.add_argument("--batch-instances", type=int, default=512)
     p.add_argument("--no-star", action="store_true")
     p.add_argument("--no-dense", action="store_true")
+    p.add_argument("--no-ssj", action="store_true", help="skip the set-similarity and set-intersection legs")
     return p.parse_args()
 
 
@@ -155,6 +156,95 @@ def star_leg(h, rels, steps):
     out["forced"] = {"delta1": d1, "delta2": d2, "ms_total": sf["ms_total"], "ms_bmm": sf["ms_bmm"],
                      "bmm_ops": sf["bmm_ops"],
                      "tops": sf["bmm_ops"] / (sf["ms_bmm"] * 1e-3) / 1e12 if sf["ms_bmm"] > 0 else None}
+    return out
+
+
+def ssj_leg(h, T, steps):
+    """Set similarity join on the two-path input: pairs sharing >= 2 and >= 3
+    elements, plain and ordered by overlap."""
+    import torch
+    Rx, Ry, Sz, Sy = T
+    out = {"workload": "set similarity join on the 10M two-path input (overlap >= c), cost-model thresholds"}
+    for c, ordered in ((2, False), (2, True), (3, False)):
+        h.ssj_result(Rx, Ry, Sz, Sy, min_overlap=c, ordered=ordered).free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = h.ssj_result(Rx, Ry, Sz, Sy, min_overlap=c, ordered=ordered)
+            n, st = r.n, r.stats
+            r.free()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"c{c}{'_ordered' if ordered else ''}"] = {"ms_per_step": dt * 1e3, "n_out": n, "J": st["J"],
+                                                      "witnesses_per_s": st["J"] / dt,
+                                                      "delta1": st["delta1"], "delta2": st["delta2"]}
+    return out
+
+
+def bsi_leg(h, T, host, steps):
+    """Batched set intersection over the two-path input's relations: batches
+    of 1K, 10K and 100K queries."""
+    import numpy as np
+    import torch
+    import datagen
+    Rx, Ry, Sz, Sy = T
+    out = {"workload": "batched Boolean set intersection over the 10M relations (half the queries share a sampled "
+                       "element, 3/8 independent set ids, 1/8 absent ids), cost-model thresholds"}
+    for b in (1_000, 10_000, 100_000):
+        tx, tz = datagen.bsi_batch(*host, b, seed=b)
+        Tx = torch.from_numpy(tx).cuda()
+        Tz = torch.from_numpy(tz).cuda()
+        h.bsi(Rx, Ry, Sz, Sy, Tx, Tz)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ans, st = h.bsi(Rx, Ry, Sz, Sy, Tx, Tz)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[f"batch{b}"] = {"ms_per_batch": dt * 1e3, "queries_per_s": b / dt,
+                            "answered_true": int(ans.sum().item()), "filtered_edges_r": st["n_r"],
+                            "pairs_of_filtered_query": st["n_out"]}
+    return out
+
+
+def star4_leg(h, rels, steps):
+    """Star query with k = 4: cost-model thresholds, then forced thresholds
+    that give the product of generated V and W rows work."""
+    import torch
+    dev = torch.device("cuda:0")
+    tin = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)) for a, b in rels]
+    h.star_result(tin).free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = h.star_result(tin)
+        n, st = r.n, r.stats
+        r.free()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out = {"workload": "star k=4: 4 relations of 500K distinct edges, 125K x ids, 25K y ids, Zipf(1.3) y "
+                       "(independent y-rank permutations), cost-model thresholds",
+           "n_out": n, "J": st["J"], "ms_per_step": dt * 1e3, "tuples_per_s": n / dt,
+           "delta1": st["delta1"], "delta2": st["delta2"]}
+    # the product's own workload: dense communities, where every witness is
+    # heavy at Delta1 = Delta2 = 1 (4 communities of 64 x ids by 512 y ids,
+    # p = 0.5: |OUT| = 4 * 64^4 by closed form, J / |OUT| = 32)
+    import datagen
+    x, y = datagen.communities(4, 64, 512, 0.5, seed=12)
+    X, Y = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    dense = [(X, Y)] * 4
+    h.star_result(dense, delta1=1, delta2=1).free()
+    r = h.star_result(dense, delta1=1, delta2=1, timing=True)
+    nf, sf = r.n, r.stats
+    r.free()
+    out["dense_product"] = {"workload": "k=4 star over 4 communities of 64 x ids by 512 y ids at p=0.5 "
+                                        f"({x.size} edges per relation), Delta1 = Delta2 = 1",
+                            "n_out": nf, "closed_form_n_out": 4 * 64 ** 4, "J": sf["J"], "rows_v": sf["u"],
+                            "v": sf["v"], "rows_w": sf["w"], "ms_total": sf["ms_total"], "ms_bmm": sf["ms_bmm"],
+                            "bmm_ops": sf["bmm_ops"],
+                            "tops": sf["bmm_ops"] / (sf["ms_bmm"] * 1e-3) / 1e12 if sf["ms_bmm"] > 0 else None}
+    if nf != 4 * 64 ** 4:
+        raise RuntimeError(f"k=4 dense star output size {nf} differs from the closed form")
     return out
 
 
@@ -307,6 +397,23 @@ def main():
             f"forced product {star['forced']['ms_bmm']:.2f} ms, {star['forced']['tops'] or 0:.1f} TOP/s")
         del rels
 
+    ssj = bsi = None
+    if not a.no_ssj:
+        ssj = ssj_leg(h, (Rx, Ry, Sz, Sy), max(1, min(a.steps, 3)))
+        log("ssj: " + ", ".join(f"{k} {v['ms_per_step']:.2f} ms ({v['n_out']} pairs)" for k, v in ssj.items()
+                                if isinstance(v, dict)))
+        bsi = bsi_leg(h, (Rx, Ry, Sz, Sy), (rx, ry, sz, sy), max(1, min(a.steps, 3)))
+        log("bsi: " + ", ".join(f"{k} {v['ms_per_batch']:.2f} ms" for k, v in bsi.items() if isinstance(v, dict)))
+
+    star4 = None
+    if not a.no_star:
+        rels4 = datagen.star4_c(a.scale)
+        star4 = star4_leg(h, rels4, max(1, min(a.steps, 3)))
+        dp = star4["dense_product"]
+        log(f"star k=4: {star4['ms_per_step']:.2f} ms/step, |OUT|={star4['n_out']}; dense product "
+            f"{dp['ms_bmm']:.2f} ms, {dp['tops'] or 0:.1f} TOP/s, whole call {dp['ms_total']:.2f} ms")
+        del rels4
+
     dense = None
     if not a.no_dense and a.scale == 1.0:
         t0 = time.time()
@@ -380,6 +487,9 @@ def main():
         "selector": selector,
         "star": star,
         "dense_core": dense,
+        "ssj": ssj,
+        "bsi": bsi,
+        "star_k4": star4,
         "phases_ms": {k[3:]: ph[k] for k in ph if k.startswith("ms_")},
     }
     print(json.dumps(out), flush=True)

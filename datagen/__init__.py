@@ -30,6 +30,8 @@ __all__ = [
     "selfjoin_c1",
     "twopath_c2",
     "star_c3",
+    "star4_c",
+    "bsi_batch",
     "batch_c4",
     "batch_instance",
     "selector_instance",
@@ -184,6 +186,42 @@ def star_c3(scale: float = 1.0):
     nx = max(1, int(500_000 * scale))
     ny = max(1, int(100_000 * scale))
     return [zipf_edges(n, nx, ny, 1.3, seed=4 + i) for i in range(3)]
+
+
+def star4_c(scale: float = 1.0):
+    """Four-relation star input (k = 4): 500K edges each, 125K x ids, 25K y
+    ids, Zipf(1.3) y with independent y orders (seeds 60..63); about 2.1e8
+    witnesses."""
+    n = int(500_000 * scale)
+    nx = max(1, int(125_000 * scale))
+    ny = max(1, int(25_000 * scale))
+    return [zipf_edges(n, nx, ny, 1.3, seed=60 + i) for i in range(4)]
+
+
+def bsi_batch(rx, ry, sz, sy, n: int, seed: int):
+    """A batch of n set-intersection queries (a, c) over R(x, y) and S(z, y):
+    half are drawn by picking a row (a, b) of R and then a row (c, b) of S
+    with the same element b (a query that shares at least b), 3/8 pick a and
+    c independently from the rows of R and S (sets in proportion to their
+    size), and 1/8 name ids drawn uniformly from the int32 range."""
+    rng = np.random.default_rng(seed)
+    rx, ry, sz, sy = (np.asarray(v) for v in (rx, ry, sz, sy))
+    order = np.argsort(sy, kind="stable")
+    sy_sorted = sy[order]
+    n_share = n // 2
+    n_abs = n // 8
+    n_ind = n - n_share - n_abs
+    i = rng.integers(0, rx.size, 4 * n_share + 16)
+    lo = np.searchsorted(sy_sorted, ry[i], side="left")
+    hi = np.searchsorted(sy_sorted, ry[i], side="right")
+    ok = hi > lo
+    i, lo, hi = i[ok][:n_share], lo[ok][:n_share], hi[ok][:n_share]
+    j = order[lo + (rng.random(i.size) * (hi - lo)).astype(np.int64)]
+    n_ind += n_share - i.size
+    tx = np.concatenate([rx[i], rng.choice(rx, n_ind), rng.integers(-2**31, 2**31 - 1, n_abs)])
+    tz = np.concatenate([sz[j], rng.choice(sz, n_ind), rng.integers(-2**31, 2**31 - 1, n_abs)])
+    p = rng.permutation(n)
+    return tx[p].astype(np.int32), tz[p].astype(np.int32)
 
 
 def batch_instance(i: int, lo: float = 1e3, hi: float = 1e6, seed0: int = 1000):

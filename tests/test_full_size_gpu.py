@@ -116,3 +116,65 @@ def test_batch_512(jp, c4, checks_mode):
         results = list(ex.map(check, order))
     bad = [(i, e, g) for i, e, g, ok in results if not ok]
     assert not bad, f"instances differing from the oracle (index, oracle size, GPU size): {bad[:10]}"
+
+
+# ---------------------------------------------------------------------------
+# The further rows at their benchmark sizes: set similarity join and batched
+# set intersection on the 10M input, the k = 4 star on 4 x 500K edges.
+# ---------------------------------------------------------------------------
+
+def test_ssj_10m(jp, c2, checks_mode):
+    """Pairs sharing >= 2 elements, with overlaps, in both orders."""
+    (rx, ry), (sz, sy) = c2
+    ex, ez, en = oracle.ssj(rx, ry, sz, sy, c=2)
+    h = jp.default_handle(0)
+    x, z, n, st = h.ssj(dev(rx), dev(ry), dev(sz), dev(sy), min_overlap=2)
+    np.testing.assert_array_equal(x.cpu().numpy(), ex)
+    np.testing.assert_array_equal(z.cpu().numpy(), ez)
+    np.testing.assert_array_equal(n.cpu().numpy(), en)
+    order = np.lexsort((ez, ex, -en.astype(np.int64)))  # overlap descending, then (x, z)
+    x, z, n, st = h.ssj(dev(rx), dev(ry), dev(sz), dev(sy), min_overlap=2, ordered=True, delta1=1000, delta2=12)
+    assert st["nnz_heavy"] > 0
+    np.testing.assert_array_equal(x.cpu().numpy(), ex[order])
+    np.testing.assert_array_equal(z.cpu().numpy(), ez[order])
+    np.testing.assert_array_equal(n.cpu().numpy(), en[order])
+
+
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"delta1": 1000, "delta2": 12}])
+def test_bsi_10m(jp, c2, checks_mode, kw):
+    (rx, ry), (sz, sy) = c2
+    tx, tz = datagen.bsi_batch(rx, ry, sz, sy, 100_000, seed=17)
+    want = oracle.bsi(rx, ry, sz, sy, tx, tz)
+    ans, _ = jp.default_handle(0).bsi(dev(rx), dev(ry), dev(sz), dev(sy), dev(tx), dev(tz), **kw)
+    np.testing.assert_array_equal(ans.cpu().numpy().astype(bool), want)
+    assert 0.45 < want.mean() < 0.6
+
+
+@pytest.fixture(scope="module")
+def s4():
+    return datagen.star4_c(1.0)
+
+
+@pytest.fixture(scope="module")
+def s4_oracle(s4):
+    return oracle.star_par(s4, threads=host_threads())
+
+
+@pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"strategy": "fixed", "delta1": 200, "delta2": 10}])
+def test_star4_4x500k(jp, s4, s4_oracle, checks_mode, kw):
+    h = jp.default_handle(0)
+    cols, st = h.star([(dev(a), dev(b)) for a, b in s4], **kw)
+    assert st["n_out"] == cols[0].numel() == s4_oracle.shape[0]
+    for i in range(4):
+        np.testing.assert_array_equal(cols[i].cpu().numpy(), s4_oracle[:, i])
+    assert st["J_L"] + st["J_H"] == st["J"] == oracle_star_join_size(s4)
+
+
+def oracle_star_join_size(rels):
+    """sum over y of the product of the k degrees, over distinct edges."""
+    degs = []
+    for a, b in rels:
+        e = np.unique((a.astype(np.int64) << 32) | (b.astype(np.int64) & 0xffffffff))
+        degs.append(np.bincount((e & 0xffffffff).astype(np.int64), minlength=1 << 20))
+    n = min(d.size for d in degs)
+    return int(np.prod(np.stack([d[:n] for d in degs]).astype(np.float64), axis=0).sum())

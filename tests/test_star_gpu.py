@@ -192,3 +192,13 @@ def test_star4_wide_keys(jp):
     rels = [(rng.permutation(n).astype(np.int32), (np.arange(n) // 2).astype(np.int32)) for _ in range(4)]
     check(jp, rels, strategy="light")
     check(jp, rels, delta1=1, delta2=1)
+
+
+def test_star4_dense_core_product(jp):
+    """k = 4 over dense communities (2 of 32 x ids by 128 y ids, p = 0.5):
+    J / |OUT| = 8, every witness heavy at Delta1 = Delta2 = 1, so the whole
+    output comes from the product of generated 4,096-row V and W (24 of the
+    2 * 32^4 in-community tuples share no y at this seed)."""
+    x, y = datagen.communities(2, 32, 128, 0.5, seed=11)
+    st = check(jp, [(x, y)] * 4, delta1=1, delta2=1)
+    assert st["J_L"] == 0 and st["nnz_heavy"] == st["n_out"] == 2 * 32 ** 4 - 24
