@@ -415,6 +415,53 @@ typedef struct jp_instance {
 jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
                             jp_result **out);
 
+/*
+ * A reusable, graph-captured evaluation of a batch of two-path instances
+ * (the serving form of jp_two_path_batch).  Making the plan runs the batch
+ * once, recording every value the pipeline reads back from the device and
+ * its peak working memory, then runs it again under HIP stream capture with
+ * every working buffer carved from one device arena, which gives one HIP
+ * graph of the whole evaluation (no host waits, no allocation, no host
+ * decisions inside it).  jp_plan_launch replays the graph on the handle's
+ * stream.
+ *  - arena: device memory of arena_bytes (256-byte aligned) owned by the
+ *    caller and used by the plan until jp_plan_free, or NULL: the plan takes
+ *    arena_bytes from the handle's allocator.
+ *  - JP_ECAPACITY: arena_bytes is too small for this batch; *arena_needed
+ *    receives a size that suffices (make the plan again with it).  On JP_OK
+ *    *arena_needed receives the size the plan needed.
+ *  - The plan keeps the instance descriptors: the graph reads the same
+ *    device columns at every launch.  Its host decisions (thresholds, grid
+ *    and buffer sizes) are those of the recorded run, so a launch is valid
+ *    only for the contents the plan was made on: jp_plan_launch first
+ *    fingerprints the columns on the device and returns JP_ECAPACITY without
+ *    replaying when they changed (make a new plan); inside the graph every
+ *    recorded read-back is compared with the live value and a difference
+ *    raises a device flag (JP_EINTERNAL after the replay).
+ * Options as for jp_two_path_batch; the timing flag is ignored.
+ */
+typedef struct jp_plan jp_plan;
+jp_status jp_two_path_batch_plan(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
+                                 void *arena, int64_t arena_bytes, jp_plan **plan, int64_t *arena_needed);
+
+/* Replay the plan's graph on the handle's stream and wait for it.  The
+ * handle must be on the plan's device.  JP_ECAPACITY: the inputs changed
+ * since the plan was made (nothing replayed). */
+jp_status jp_plan_launch(jp_handle *h, jp_plan *plan);
+
+/* The plan's output after a launch: cols receives 2 device column pointers
+ * (x, z; valid until the next launch or jp_plan_free), *n_tuples their
+ * length, offsets (n_inst + 1 host values, may be NULL) the instance slices
+ * as in jp_result_batch_offsets.  Any argument but plan may be NULL. */
+jp_status jp_plan_result(const jp_plan *plan, const int32_t **cols, int64_t *n_tuples, int64_t *offsets);
+
+/* Copy the plan's output into caller-allocated device columns (2 pointers,
+ * each with room for n_tuples int32), ordered on the handle's stream. */
+jp_status jp_plan_copy(jp_handle *h, const jp_plan *plan, int32_t *const *cols);
+
+/* Release a plan (its graph, stream and device buffers).  NULL is a no-op. */
+void jp_plan_free(jp_plan *plan);
+
 /* Slices of a batched result: *n_inst receives the instance count; when
  * offsets is not NULL it receives n_inst + 1 host values, instance i owning
  * tuples [offsets[i], offsets[i+1]).  A result that is not batched reports
@@ -452,6 +499,18 @@ jp_status jp_result_stats(const jp_result *r, jp_stats *s);
 
 /* Release a result.  NULL is a no-op. */
 void jp_result_free(jp_result *r);
+
+/*
+ * Product kernel choice by shape (the project's autotuner, autotune.py,
+ * writes the table).  JP_BMM_AUTO keeps one kernel per shape class, the
+ * log2 buckets of (u, w, ld) given by jp_product_shape_class; a class
+ * without an entry is raced once on the handle (its int8 kernel against the
+ * popcount kernel, timed) and the faster kept.  jp_set_product_table enters
+ * n classes with their kernel (JP_BMM_I8_T128, JP_BMM_I8_T256 or
+ * JP_BMM_BITPOP; host arrays, copied), so that no race is needed for them.
+ */
+uint64_t jp_product_shape_class(int64_t u, int64_t w, int64_t ld);
+jp_status jp_set_product_table(jp_handle *h, int32_t n, const uint64_t *classes, const int32_t *kinds);
 
 /*
  * Heavy-product kernel on its own (the heavy step of Algorithm 1; Section 2.2's

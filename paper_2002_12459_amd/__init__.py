@@ -19,12 +19,15 @@ __all__ = [
     "LIB_PATH", "JoinProjectError", "Handle", "Result", "two_path", "star", "bool_matmul",
     "default_handle", "STRATEGY", "BMM", "Y_RULE", "DEDUP", "DELTA_INF", "selector_cells", "mlp_param_count",
     "SELECTOR_PATH", "load_selector_file", "plan_theory", "estimate_out", "DeviceAllocator", "torch_allocator",
+    "product_shape_class", "load_product_table", "PRODUCT_TABLE_PATH",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libjoinproject.so")
 # Trained threshold-selector weights for MI355X (written by selector.py).
 SELECTOR_PATH = os.path.join(_HERE, "selector_mi355x.json")
+# Product kernel per shape class measured on MI355X (written by autotune.py).
+PRODUCT_TABLE_PATH = os.path.join(_HERE, "autotune_mi355x.json")
 N_FEATURES = 16
 N_CELLS = 65
 
@@ -135,6 +138,17 @@ def _load():
                                ctypes.POINTER(P)]
         lib.jp_bsi.argtypes = [P, P, P, i64, P, P, i64, P, P, i64, ctypes.POINTER(Options), P,
                                ctypes.POINTER(Stats)]
+        lib.jp_two_path_batch_plan.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Instance), ctypes.POINTER(Options),
+                                               P, i64, ctypes.POINTER(P), ctypes.POINTER(i64)]
+        lib.jp_plan_launch.argtypes = [P, P]
+        lib.jp_plan_result.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.jp_plan_copy.argtypes = [P, P, ctypes.POINTER(P)]
+        lib.jp_plan_free.argtypes = [P]
+        lib.jp_plan_free.restype = None
+        lib.jp_product_shape_class.argtypes = [i64, i64, i64]
+        lib.jp_product_shape_class.restype = ctypes.c_uint64
+        lib.jp_set_product_table.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
+                                             ctypes.POINTER(ctypes.c_int32)]
         lib.jp_star.argtypes = [P, ctypes.c_int, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(i64),
                                 ctypes.POINTER(Options), ctypes.POINTER(P)]
         lib.jp_result_size.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int32)]
@@ -173,7 +187,8 @@ def _load():
         lib.jp_mlp_grad.argtypes = [P, P, ctypes.c_int32, P, P, P, i64, P, P]
         f32 = ctypes.c_float
         lib.jp_mlp_adam.argtypes = [P, P, P, P, P, i64, ctypes.c_int32, f32, f32, f32, f32]
-        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_ssj", "jp_bsi", "jp_star", "jp_result_size",
+        for f in ("jp_create", "jp_set_stream", "jp_set_allocator", "jp_two_path", "jp_two_path_static", "jp_ssj", "jp_bsi", "jp_two_path_batch_plan",
+                  "jp_plan_launch", "jp_plan_result", "jp_plan_copy", "jp_set_product_table", "jp_star", "jp_result_size",
                   "jp_result_columns", "jp_result_copy", "jp_result_stats", "jp_bool_matmul",
                   "jp_set_calibration", "jp_get_calibration", "jp_plan_summary", "jp_plan_two_path",
                   "jp_plan_cells", "jp_set_selector", "jp_mlp_forward", "jp_mlp_grad", "jp_mlp_adam",
@@ -252,6 +267,45 @@ class Result:
             pass
 
 
+class Plan:
+    """A graph-captured batched evaluation; ``launch()`` replays it."""
+
+    def __init__(self, handle, ptr, n_inst, keep, arena, arena_needed):
+        self._h, self._p, self.n_inst = handle, ptr, n_inst
+        self._keep, self._arena = keep, arena  # the graph reads these columns / this arena
+        self.arena_needed = arena_needed
+
+    def launch(self):
+        self._h._bind_stream()
+        self._h._check(_load().jp_plan_launch(self._h._p, self._p))
+
+    def outputs(self):
+        """[(x, z), ...] per instance: copies of the plan's output columns."""
+        torch = _torch()
+        n = ctypes.c_int64()
+        offs = (ctypes.c_int64 * (self.n_inst + 1))()
+        self._h._check(_load().jp_plan_result(self._p, None, ctypes.byref(n), offs))
+        dev = torch.device("cuda", self._h.device)
+        x = torch.empty(n.value, dtype=torch.int32, device=dev)
+        z = torch.empty(n.value, dtype=torch.int32, device=dev)
+        if n.value:
+            self._h._bind_stream()
+            arr = (ctypes.c_void_p * 2)(x.data_ptr(), z.data_ptr())
+            self._h._check(_load().jp_plan_copy(self._h._p, self._p, arr))
+        return [(x[offs[i]:offs[i + 1]], z[offs[i]:offs[i + 1]]) for i in range(self.n_inst)]
+
+    def free(self):
+        if self._p:
+            _load().jp_plan_free(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 def _f32(t, name, n=None):
     torch = _torch()
     if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
@@ -259,6 +313,19 @@ def _f32(t, name, n=None):
     if n is not None and t.numel() != n:
         raise ValueError(f"{name} must hold {n} values")
     return t
+
+
+def product_shape_class(u, w, ld):
+    """Shape class of a u x ld by w x ld product (JP_BMM_AUTO's table key)."""
+    return int(_load().jp_product_shape_class(int(u), int(w), int(ld)))
+
+
+def load_product_table(path=PRODUCT_TABLE_PATH):
+    """{shape class: kind name} of an autotune file (JSON)."""
+    import json
+    with open(path) as fh:
+        d = json.load(fh)
+    return {int(e["class"]): e["kind"] for e in d["entries"]}
 
 
 def load_selector_file(path=SELECTOR_PATH):
@@ -327,9 +394,11 @@ class Handle:
     (PyTorch's caching allocator: the library and torch share one pool of
     device memory), "builtin" (the library's own caching pool, which saves
     the Python callback of each of the 60 to 90 buffers of an evaluation) or
-    a ``DeviceAllocator``."""
+    a ``DeviceAllocator``.  ``product_table="default"`` installs the packaged
+    autotuned product kernel table (autotune.py) when the file exists; a
+    dict {shape class: kind name} installs that one; None none."""
 
-    def __init__(self, device: int = 0, selector="default", allocator="torch"):
+    def __init__(self, device: int = 0, selector="default", allocator="torch", product_table="default"):
         lib = _load()
         self.device = device
         self.allocator = None
@@ -340,6 +409,11 @@ class Handle:
         self._p = p
         if allocator != "builtin":
             self.set_allocator(torch_allocator(device) if allocator == "torch" else allocator)
+        if product_table == "default":
+            if os.path.exists(PRODUCT_TABLE_PATH):
+                self.set_product_table(load_product_table(PRODUCT_TABLE_PATH))
+        elif product_table is not None:
+            self.set_product_table(product_table)
         if selector == "default":
             if os.path.exists(SELECTOR_PATH):
                 self.set_selector(*load_selector_file(SELECTOR_PATH))
@@ -486,6 +560,34 @@ class Handle:
         self._check(_load().jp_two_path_batch(self._p, len(instances), descs, ctypes.byref(o), ctypes.byref(out)))
         return Result(self, out)
 
+    def batch_plan(self, instances, arena_bytes=0, arena=None, delta1=None, delta2=None, strategy=None,
+                   bmm="auto", y_rule="max", dedup="auto", seed=None):
+        """A graph-captured plan of the batch (see jp_two_path_batch_plan).
+        arena: an optional uint8 CUDA tensor used as the plan's arena.
+        Raises JoinProjectError with .arena_needed set on JP_ECAPACITY."""
+        descs = (Instance * max(len(instances), 1))()
+        keep = []
+        for i, (rx, ry, sz, sy) in enumerate(instances):
+            rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
+            if rx.numel() != ry.numel() or sz.numel() != sy.numel():
+                raise ValueError(f"instance {i}: column lengths differ")
+            keep.extend([rx, ry, sz, sy])
+            descs[i] = Instance(_ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel())
+        if arena is not None:
+            arena_bytes = arena.numel() * arena.element_size()
+        self._bind_stream()
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, False, seed)
+        p = ctypes.c_void_p()
+        need = ctypes.c_int64()
+        st = _load().jp_two_path_batch_plan(self._p, len(instances), descs, ctypes.byref(o),
+                                            _ptr(arena) if arena is not None else None, int(arena_bytes),
+                                            ctypes.byref(p), ctypes.byref(need))
+        if st != 0:
+            err = JoinProjectError(st, _load().jp_last_error(self._p).decode())
+            err.arena_needed = need.value
+            raise err
+        return Plan(self, p, len(instances), keep, arena, need.value)
+
     def two_path_batch(self, instances, **kw):
         """Per-instance outputs [(x, z), ...] (views of two shared tensors) and the stats."""
         r = self.two_path_batch_result(instances, **kw)
@@ -562,6 +664,13 @@ class Handle:
         if st not in (0, 4):  # JP_ECAPACITY reports the count
             self._check(st)
         return nnz.value, ms.value
+
+    def set_product_table(self, table):
+        """Product kernel per shape class: {class (int): "i8_t128" | "i8_t256" | "bitpop"}."""
+        items = list(table.items())
+        cls = (ctypes.c_uint64 * max(len(items), 1))(*[int(k) for k, _ in items])
+        kinds = (ctypes.c_int32 * max(len(items), 1))(*[BMM[v] for _, v in items])
+        self._check(_load().jp_set_product_table(self._p, len(items), cls, kinds))
 
     def set_calibration(self, cal):
         c = cal if isinstance(cal, Calibration) else Calibration.from_dict(cal)

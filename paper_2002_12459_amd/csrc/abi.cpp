@@ -7,6 +7,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
+#include <vector>
 
 #include "pipeline.hpp"
 
@@ -22,6 +24,30 @@ struct jp_handle {
     std::unique_ptr<jp::PinnedScratch> pinned;  // small read-backs
     jp::StatusPool status_pool;                 // cleared look-back status words
     int64_t lookback_wait = 10000;              // device wall-clock ticks (100 us)
+};
+
+// A recorded and captured batched evaluation (jp_two_path_batch_plan).
+struct jp_plan {
+    int device = 0;
+    int32_t n_inst = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    jp::DBuf<uint8_t> arena_own;  // the arena, when the library allocated it
+    jp::DBuf<uint8_t> dev_values, dev_uploads;
+    jp::DBuf<int> flag;
+    jp::DBuf<jp_instance> dev_inst;
+    jp::DBuf<unsigned long long> dev_print;
+    jp::Replay replay;
+    jp::StatusPool pool;
+    std::unique_ptr<jp_result> result;  // its columns live in the arena
+    unsigned long long print = 0;       // fingerprint of the inputs at plan time
+    int64_t nmax = 1;                   // longest input column
+    ~jp_plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -129,6 +155,69 @@ jp_status validate_options(jp_handle *h, const jp_options &o) {
     }
     return JP_OK;
 }
+
+// Order-independent 64-bit fingerprint of every instance's four input
+// columns: the sum over elements of a mixed (instance, column, index, value).
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+__global__ __launch_bounds__(256) void k_fingerprint(const jp_instance *inst, unsigned long long *out) {
+    const jp_instance q = inst[blockIdx.y];
+    const unsigned long long salt = (unsigned long long)blockIdx.y << 40;
+    unsigned long long h = 0;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < q.n_r; e += stride) {
+        h += mix64(salt ^ ((unsigned long long)e << 2) ^ ((unsigned long long)(uint32_t)q.r_x[e] << 42));
+        h += mix64(salt ^ ((unsigned long long)e << 2 | 1) ^ ((unsigned long long)(uint32_t)q.r_y[e] << 42));
+    }
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < q.n_s; e += stride) {
+        h += mix64(salt ^ ((unsigned long long)e << 2 | 2) ^ ((unsigned long long)(uint32_t)q.s_z[e] << 42));
+        h += mix64(salt ^ ((unsigned long long)e << 2 | 3) ^ ((unsigned long long)(uint32_t)q.s_y[e] << 42));
+    }
+    for (int o = 32; o > 0; o >>= 1) h += __shfl_xor(h, o);
+    if ((threadIdx.x & 63) == 0) atomicAdd(out, h);
+}
+
+unsigned long long fingerprint(const jp::Ctx &c, jp_plan *p, int64_t nmax) {
+    c.zero(p->dev_print.get(), 1);
+    const unsigned gx = (unsigned)std::max<int64_t>(1, std::min<int64_t>(jp::ceil_div(nmax, 256 * 8), 64));
+    hipLaunchKernelGGL(k_fingerprint, dim3(gx, (unsigned)p->n_inst), dim3(256), 0, c.stream,
+                       (const jp_instance *)p->dev_inst.get(), p->dev_print.get());
+    JP_HIP(hipGetLastError());
+    return c.load(p->dev_print.get());
+}
+
+// Device memory through another allocator, counting the largest amount live
+// at once (rounded to 256 bytes, as the arena hands it out).
+class PeakAllocator final : public jp::Allocator {
+  public:
+    explicit PeakAllocator(std::shared_ptr<jp::Allocator> inner) : Allocator(inner->device()), in_(std::move(inner)) {}
+    void *alloc(size_t bytes) override {
+        void *p = in_->alloc(bytes);
+        const size_t r = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+        live_[p] = r;
+        cur_ += r;
+        peak_ = std::max(peak_, cur_);
+        return p;
+    }
+    void release(void *p) override {
+        auto it = live_.find(p);
+        if (it != live_.end()) {
+            cur_ -= it->second;
+            live_.erase(it);
+        }
+        in_->release(p);
+    }
+    size_t peak() const { return peak_; }
+
+  private:
+    std::shared_ptr<jp::Allocator> in_;
+    std::unordered_map<void *, size_t> live_;
+    size_t cur_ = 0, peak_ = 0;
+};
 
 }  // namespace
 
@@ -415,6 +504,187 @@ jp_status jp_two_path_batch(jp_handle *h, int32_t n_inst, const jp_instance *ins
     return st;
 }
 
+jp_status jp_two_path_batch_plan(jp_handle *h, int32_t n_inst, const jp_instance *inst, const jp_options *opt,
+                                 void *arena, int64_t arena_bytes, jp_plan **out, int64_t *arena_needed) {
+    if (!h) return JP_EINVAL;
+    if (!out || !arena_needed || arena_bytes < 0 || (arena && arena_bytes == 0) || ((uintptr_t)arena % 256) != 0) {
+        h->err = "out / arena_needed NULL, arena_bytes negative, or an arena that is empty or not 256-byte aligned";
+        return JP_EINVAL;
+    }
+    *out = nullptr;
+    *arena_needed = 0;
+    if (n_inst < 1 || n_inst > 65535 || !inst) {
+        h->err = "a plan needs 1 to 65535 instances";
+        return JP_EINVAL;
+    }
+    for (int32_t i = 0; i < n_inst; ++i)
+        if (bad_col(inst[i].r_x, inst[i].n_r) || bad_col(inst[i].r_y, inst[i].n_r) ||
+            bad_col(inst[i].s_z, inst[i].n_s) || bad_col(inst[i].s_y, inst[i].n_s)) {
+            h->err = "instance " + std::to_string(i) + ": relation column is NULL or its length is negative";
+            return JP_EINVAL;
+        }
+    jp_options o;
+    jp_default_options(&o);
+    if (opt) o = *opt;
+    jp_status v = validate_options(h, o);
+    if (v != JP_OK) return v;
+    o.flags &= ~JP_FLAG_TIMING;
+    auto plan = std::make_unique<jp_plan>();
+    plan->device = h->device;
+    plan->n_inst = n_inst;
+    int64_t needed = 0;
+    jp_status st = guarded(h, [&] {
+        jp::Ctx c = make_ctx(h);
+        int64_t nmax = 1;
+        for (int32_t i = 0; i < n_inst; ++i) nmax = std::max(nmax, std::max(inst[i].n_r, inst[i].n_s));
+        plan->dev_inst = c.buf<jp_instance>((size_t)n_inst);
+        plan->dev_print = c.buf<unsigned long long>(1);
+        plan->flag = c.buf<int>(1);
+        JP_HIP(hipMemcpyAsync(plan->dev_inst.get(), inst, (size_t)n_inst * sizeof(jp_instance), hipMemcpyHostToDevice,
+                              c.stream));
+        plan->nmax = nmax;
+        plan->print = fingerprint(c, plan.get(), nmax);
+        // 1. the recorded run, measuring its peak working memory
+        {
+            jp::Ctx rc = c;
+            auto peak = std::make_shared<PeakAllocator>(h->alloc);
+            jp::StatusPool pool;
+            rc.alloc = peak;
+            rc.status_pool = &pool;
+            plan->replay.mode = jp::Replay::RECORD;
+            rc.replay = &plan->replay;
+            std::unique_ptr<jp_result> r(jp::run_two_path_batch(rc, n_inst, inst, o));
+            r.reset();
+            pool.block.reset();
+            needed = (int64_t)(peak->peak() + peak->peak() / 8 + (size_t(1) << 20));
+        }
+        if (arena_bytes < needed) return;  // JP_ECAPACITY below
+        uint8_t *base = (uint8_t *)arena;
+        if (!base) {
+            plan->arena_own = c.buf<uint8_t>((size_t)arena_bytes);
+            base = plan->arena_own.get();
+        }
+        // 2. recorded read-backs and uploads on the device, for the capture
+        jp::Replay &rp = plan->replay;
+        plan->dev_values = c.buf<uint8_t>(std::max<size_t>(rp.values.size(), 1));
+        plan->dev_uploads = c.buf<uint8_t>(std::max<size_t>(rp.uploads.size(), 1));
+        if (!rp.values.empty())
+            JP_HIP(hipMemcpyAsync(plan->dev_values.get(), rp.values.data(), rp.values.size(), hipMemcpyHostToDevice,
+                                  c.stream));
+        if (!rp.uploads.empty())
+            JP_HIP(hipMemcpyAsync(plan->dev_uploads.get(), rp.uploads.data(), rp.uploads.size(),
+                                  hipMemcpyHostToDevice, c.stream));
+        c.sync();
+        rp.mode = jp::Replay::CAPTURE;
+        rp.pos = rp.upos = 0;
+        rp.dev_values = plan->dev_values.get();
+        rp.dev_uploads = plan->dev_uploads.get();
+        rp.flag = plan->flag.get();
+        // 3. the capture: the same run on a stream of the plan, every buffer
+        // from the arena
+        JP_HIP(hipStreamCreateWithFlags(&plan->cap_stream, hipStreamNonBlocking));
+        jp::Ctx cc = c;
+        cc.stream = plan->cap_stream;
+        cc.alloc = std::make_shared<jp::ArenaAllocator>(h->device, base, (size_t)arena_bytes);
+        cc.status_pool = &plan->pool;
+        cc.pinned = nullptr;
+        cc.replay = &rp;
+        JP_HIP(hipStreamBeginCapture(plan->cap_stream, hipStreamCaptureModeRelaxed));
+        try {
+            cc.zero(plan->flag.get(), 1);
+            plan->result.reset(jp::run_two_path_batch(cc, n_inst, inst, o));
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(plan->cap_stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            throw;
+        }
+        JP_HIP(hipStreamEndCapture(plan->cap_stream, &plan->graph));
+        JP_CHECK(rp.pos == rp.values.size() && rp.upos == rp.uploads.size(), JP_EINTERNAL,
+                 "plan capture diverged from the recorded run");
+        JP_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    });
+    if (st == JP_ENOMEM && plan->result == nullptr && arena_bytes >= needed && needed > 0) {
+        // the arena's free ranges were too fragmented for the run
+        *arena_needed = 2 * needed;
+        h->err = "the arena of " + std::to_string(arena_bytes) + " bytes is too small for the plan; about " +
+                 std::to_string(2 * needed) + " bytes are needed";
+        return JP_ECAPACITY;
+    }
+    if (st != JP_OK) return st;
+    if (arena_bytes < needed) {
+        *arena_needed = needed;
+        h->err = "the arena of " + std::to_string(arena_bytes) + " bytes is too small for the plan; " +
+                 std::to_string(needed) + " bytes are needed";
+        return JP_ECAPACITY;
+    }
+    *arena_needed = needed;
+    *out = plan.release();
+    return JP_OK;
+}
+
+jp_status jp_plan_launch(jp_handle *h, jp_plan *p) {
+    if (!h || !p) return JP_EINVAL;
+    if (p->device != h->device) {
+        h->err = "the plan was made on another device";
+        return JP_EINVAL;
+    }
+    bool changed = false;
+    jp_status st = guarded(h, [&] {
+        jp::Ctx c = make_ctx(h);
+        if (fingerprint(c, p, p->nmax) != p->print) {
+            changed = true;
+            return;
+        }
+        JP_HIP(hipGraphLaunch(p->exec, c.stream));
+        JP_CHECK(c.load(p->flag.get()) == 0, JP_EINTERNAL, "a replayed read-back differs from the recorded one");
+    });
+    if (st != JP_OK) return st;
+    if (changed) {
+        h->err = "the instances' contents changed since the plan was made; make a new plan";
+        return JP_ECAPACITY;
+    }
+    return JP_OK;
+}
+
+jp_status jp_plan_result(const jp_plan *p, const int32_t **cols, int64_t *n_tuples, int64_t *offsets) {
+    if (!p || !p->result) return JP_EINVAL;
+    if (cols) {
+        cols[0] = p->result->cols[0].get();
+        cols[1] = p->result->cols[1].get();
+    }
+    if (n_tuples) *n_tuples = p->result->n;
+    if (offsets)
+        for (size_t i = 0; i < p->result->batch_off.size(); ++i) offsets[i] = p->result->batch_off[i];
+    return JP_OK;
+}
+
+jp_status jp_plan_copy(jp_handle *h, const jp_plan *p, int32_t *const *cols) {
+    if (!h) return JP_EINVAL;
+    if (!p || !p->result || !cols || (p->result->n > 0 && (!cols[0] || !cols[1]))) {
+        h->err = "plan, its result or a destination column is NULL";
+        return JP_EINVAL;
+    }
+    return guarded(h, [&] {
+        const int64_t n = p->result->n;
+        for (int i = 0; i < 2; ++i)
+            if (n > 0)
+                JP_HIP(hipMemcpyAsync(cols[i], p->result->cols[i].get(), (size_t)n * sizeof(int32_t),
+                                      hipMemcpyDeviceToDevice, h->stream));
+    });
+}
+
+void jp_plan_free(jp_plan *p) {
+    if (!p) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(p->device);
+    if (p->cap_stream) (void)hipStreamSynchronize(p->cap_stream);
+    delete p;
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
 jp_status jp_result_batch_offsets(const jp_result *r, int32_t *n_inst, int64_t *offsets) {
     if (!r || !n_inst) return JP_EINVAL;
     *n_inst = r->batch_off.empty() ? 0 : (int32_t)(r->batch_off.size() - 1);
@@ -672,6 +942,27 @@ jp_status jp_result_stats(const jp_result *r, jp_stats *s) {
 }
 
 void jp_result_free(jp_result *r) { delete r; }
+
+uint64_t jp_product_shape_class(int64_t u, int64_t w, int64_t ld) {
+    return (u < 0 || w < 0 || ld < 0) ? 0 : jp::product_shape_class(u, w, ld);
+}
+
+jp_status jp_set_product_table(jp_handle *h, int32_t n, const uint64_t *classes, const int32_t *kinds) {
+    if (!h) return JP_EINVAL;
+    if (n < 0 || (n > 0 && (!classes || !kinds))) {
+        h->err = "bad product table";
+        return JP_EINVAL;
+    }
+    for (int32_t i = 0; i < n; ++i)
+        if (kinds[i] != JP_BMM_BITPOP && kinds[i] != JP_BMM_I8_T128 && kinds[i] != JP_BMM_I8_T256) {
+            h->err = "product table kinds must be JP_BMM_BITPOP, JP_BMM_I8_T128 or JP_BMM_I8_T256";
+            return JP_EINVAL;
+        }
+    // kept as the variant codes of the kernel choice (T128 = 0, T256 = 1, BITPOP = 2)
+    for (int32_t i = 0; i < n; ++i)
+        h->tune[classes[i]] = kinds[i] == JP_BMM_I8_T128 ? 0 : (kinds[i] == JP_BMM_I8_T256 ? 1 : 2);
+    return JP_OK;
+}
 
 jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t k,
                          int64_t ld, int32_t kind, int32_t *rows, int32_t *cols, int64_t cap, int64_t *nnz,

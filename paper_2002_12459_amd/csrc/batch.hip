@@ -159,7 +159,7 @@ jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst,
     if (NR == 0 || NS == 0) return empty();
 
     DBuf<BatchDesc> dd = c.buf<BatchDesc>((size_t)n_inst);
-    JP_HIP(hipMemcpyAsync(dd.get(), hd.data(), hd.size() * sizeof(BatchDesc), hipMemcpyHostToDevice, c.stream));
+    c.upload(dd.get(), hd.data(), hd.size() * sizeof(BatchDesc));
     DBuf<int> mmb = c.buf<int>((size_t)6 * n_inst);
     int *mm = mmb.get();
     for_each(c, 6 * (int64_t)n_inst, [=] __device__(int64_t i) { mm[i] = (i & 1) ? INT_MIN : INT_MAX; });
@@ -195,10 +195,8 @@ jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst,
     DBuf<int32_t> Rx = c.buf<int32_t>(NR), Ry = c.buf<int32_t>(NR), Sz = c.buf<int32_t>(NS), Sy = c.buf<int32_t>(NS);
     RankTable tx, tz;
     if (!ranked) {
-        JP_HIP(hipMemcpyAsync(addd.get(), add.data(), add.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                              c.stream));
-        JP_HIP(hipMemcpyAsync(offd.get(), offx.data(), offx.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                              c.stream));
+        c.upload(addd.get(), add.data(), add.size() * sizeof(int64_t));
+        c.upload(offd.get(), offx.data(), offx.size() * sizeof(int64_t));
         hipLaunchKernelGGL(k_batch_pack, dim3(gx, (unsigned)n_inst), dim3(kBatchBlock), 0, c.stream,
                            (const BatchDesc *)dd.get(), (const int64_t *)addd.get(), Rx.get(), Ry.get(), Sz.get(),
                            Sy.get());
@@ -240,8 +238,7 @@ jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst,
             std::vector<BatchDesc> hs = hd;
             for (auto &q : hs) q.s_base += NR;
             DBuf<BatchDesc> ds = c.buf<BatchDesc>((size_t)n_inst);
-            JP_HIP(hipMemcpyAsync(ds.get(), hs.data(), hs.size() * sizeof(BatchDesc), hipMemcpyHostToDevice,
-                                  c.stream));
+            c.upload(ds.get(), hs.data(), hs.size() * sizeof(BatchDesc));
             hipLaunchKernelGGL(k_batch_keys, dim3(gx, (unsigned)n_inst), dim3(kBatchBlock), 0, c.stream,
                                (const BatchDesc *)ds.get(), 2, ky.get());
             JP_HIP(hipGetLastError());

@@ -656,6 +656,11 @@ static void run_variant(const Ctx &c, BmmVariant v, const int8_t *A, const int8_
 }
 
 // Shape class: log2 buckets of u, w and the stride.
+uint64_t product_shape_class(int64_t u, int64_t w, int64_t ld) {
+    return ((uint64_t)bits_for((uint64_t)u) << 16) | ((uint64_t)bits_for((uint64_t)w) << 8) |
+           (uint64_t)bits_for((uint64_t)ld);
+}
+
 static uint64_t shape_class(int64_t u, int64_t w, int64_t ld) {
     return ((uint64_t)bits_for((uint64_t)u) << 16) | ((uint64_t)bits_for((uint64_t)w) << 8) |
            (uint64_t)bits_for((uint64_t)ld);

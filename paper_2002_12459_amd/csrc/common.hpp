@@ -335,6 +335,36 @@ struct StatusPool {
     size_t used = 0;
 };
 
+// Compares n bytes of live device data with the recorded bytes of a plan and
+// raises *flag on any difference (captured-plan replays).
+__global__ __launch_bounds__(256) inline void k_replay_check(const uint8_t *live, const uint8_t *rec, int64_t n,
+                                                             int *flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        bad |= live[i] != rec[i];
+    if (bad) *flag = 1;
+}
+
+// Recording and capture of one pipeline run for a reusable plan (a captured
+// HIP graph).  RECORD: the run executes normally and every value the host
+// reads back from the device, and every block it uploads, is kept in order.
+// CAPTURE: the same host code runs again while the stream is being captured;
+// read-backs return the recorded values (no wait) and add a check node that
+// compares the live device bytes with them at replay time, and uploads come
+// from a device copy of the recorded blocks, so the graph references no host
+// memory.  The host decisions of the run (thresholds, grid sizes, buffer
+// sizes) are therefore those of the recorded run.
+struct Replay {
+    enum Mode { RECORD, CAPTURE } mode = RECORD;
+    std::vector<uint8_t> values;  // read-back bytes, in order
+    size_t pos = 0;
+    std::vector<uint8_t> uploads;  // uploaded bytes, in order
+    size_t upos = 0;
+    const uint8_t *dev_values = nullptr;   // device copies (capture)
+    const uint8_t *dev_uploads = nullptr;
+    int *flag = nullptr;                   // device: raised by a failed check
+};
+
 // Execution context of one call: device, stream, allocator, chip size.
 struct Ctx {
     hipStream_t stream = nullptr;
@@ -351,7 +381,27 @@ struct Ctx {
     DBuf<T> buf(size_t n) const {
         return DBuf<T>(alloc, n);
     }
-    void sync() const { JP_HIP(hipStreamSynchronize(stream)); }
+    void sync() const {
+        if (replay && replay->mode == Replay::CAPTURE) return;  // nothing to wait for while capturing
+        JP_HIP(hipStreamSynchronize(stream));
+    }
+    Replay *replay = nullptr;  // set while a plan is recorded or captured
+    bool capturing() const { return replay && replay->mode == Replay::CAPTURE; }
+    // Host-to-device copy of n bytes whose source may be released once the
+    // call's next wait returns (in a captured plan: a copy of the recorded block).
+    void upload(void *dev, const void *host, size_t bytes) const {
+        if (!bytes) return;
+        if (capturing()) {
+            Replay &r = *replay;
+            JP_CHECK(r.upos + bytes <= r.uploads.size() && std::memcmp(r.uploads.data() + r.upos, host, bytes) == 0,
+                     JP_EINTERNAL, "plan capture diverged from the recorded run (upload)");
+            JP_HIP(hipMemcpyAsync(dev, r.dev_uploads + r.upos, bytes, hipMemcpyDeviceToDevice, stream));
+            r.upos += bytes;
+            return;
+        }
+        if (replay) replay->uploads.insert(replay->uploads.end(), (const uint8_t *)host, (const uint8_t *)host + bytes);
+        JP_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream));
+    }
     PinnedScratch *pinned = nullptr;  // small read-backs go through it when set
     StatusPool *status_pool = nullptr;  // handle-owned, see take_status
     // How long a look-back lane waits for a predecessor tile's status before
@@ -404,9 +454,30 @@ struct Ctx {
         alloc->release(tmp);
         if (e != hipSuccess) fail(JP_EHIP, std::string("scalar gather failed: ") + hipGetErrorString(e));
     }
+    // unordered: the device holds these values in an order that may differ
+    // between runs (appended with atomics), so a captured plan does not
+    // compare them byte by byte.
     template <class T>
-    void load_n(T *host, const T *dev, size_t n) const {
+    void load_n(T *host, const T *dev, size_t n, bool unordered = false) const {
         if (!n) return;
+        const size_t bytes = n * sizeof(T);
+        if (capturing()) {
+            Replay &r = *replay;
+            JP_CHECK(r.pos + bytes <= r.values.size(), JP_EINTERNAL, "plan capture diverged from the recorded run");
+            const int64_t blocks = std::min<int64_t>(((int64_t)bytes + 255) / 256, 64);
+            if (!unordered)
+                hipLaunchKernelGGL(k_replay_check, dim3((unsigned)blocks), dim3(256), 0, stream, (const uint8_t *)dev,
+                                   r.dev_values + r.pos, (int64_t)bytes, r.flag);
+            JP_HIP(hipGetLastError());
+            std::memcpy(host, r.values.data() + r.pos, bytes);
+            r.pos += bytes;
+            return;
+        }
+        load_n_now(host, dev, n);
+        if (replay) replay->values.insert(replay->values.end(), (const uint8_t *)host, (const uint8_t *)host + bytes);
+    }
+    template <class T>
+    void load_n_now(T *host, const T *dev, size_t n) const {
         const size_t bytes = n * sizeof(T);
         if (pinned && pinned->host && bytes <= pinned->bytes && bytes <= 4096) {
             hipLaunchKernelGGL(k_to_host<uint8_t>, dim3(1), dim3(256), 0, stream, (const uint8_t *)dev, pinned->dev,

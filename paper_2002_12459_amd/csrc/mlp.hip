@@ -206,7 +206,7 @@ Thresholds select_thresholds(const Ctx &c, const TwoPathSummary &s, const jp_opt
     features16(s, f);
     for (int i = 0; i < kFeatures; ++i) in[i] = (f[i] - sel.mean[i]) / sel.scale[i];
     DBuf<float> io = c.buf<float>(kFeatures + kSelectorCells);
-    JP_HIP(hipMemcpyAsync(io.get(), in, sizeof(in), hipMemcpyHostToDevice, c.stream));
+    c.upload(io.get(), in, sizeof(in));
     mlp_forward(c, sel.params.get(), sel.n_out, io.get(), 1, io.get() + kFeatures);
     float score[kSelectorCells];
     c.load_n(score, io.get() + kFeatures, kSelectorCells);

@@ -169,4 +169,8 @@ void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u
 
 constexpr int64_t kBmmPadK = 128;  // K padding of the heavy matrices (bytes)
 
+// Shape class of a product (log2 buckets of u, w and the row stride): the key
+// under which JP_BMM_AUTO keeps its kernel choice.
+uint64_t product_shape_class(int64_t u, int64_t w, int64_t ld);
+
 }  // namespace jp

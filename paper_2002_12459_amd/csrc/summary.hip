@@ -243,7 +243,15 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     int64_t hn[2];
     std::vector<int64_t> r, e;
     bool fetched = false;
-    if (c.pinned && c.pinned->host && c.pinned->bytes >= 64) {
+    if (c.replay) {  // a plan is recorded or captured: every read-back goes through load_n
+        c.load_n(hn, S.get(), 2);
+        JP_CHECK(hn[1] <= a.big_cap, JP_EINTERNAL, "degree index overflow list exceeds its bound");
+        r.resize(3 * hn[0]);
+        e.resize(2 * hn[1]);
+        c.load_n(r.data(), rec.get(), r.size());
+        c.load_n(e.data(), big.get(), e.size(), true);  // appended with atomics: any order
+        fetched = true;
+    } else if (c.pinned && c.pinned->host && c.pinned->bytes >= 64) {
         const int64_t cap = (int64_t)(c.pinned->bytes / sizeof(int64_t));
         hipLaunchKernelGGL(k_index_to_host, dim3(64), dim3(256), 0, c.stream, (const int64_t *)S.get(),
                            (const int64_t *)rec.get(), (const int64_t *)big.get(), a.big_cap, cap,
