@@ -290,7 +290,17 @@ def dense_leg(h, edges, steps):
     r = h.two_path_result(x, y, x, y, timing=True)
     sp = r.stats
     r.free()
-    return {"workload": f"dense-core self-join: 8 communities of 4096 x ids by 2048 y ids, edge probability 0.25 "
+    # the same product with fp16 operands and fp32 accumulation (exact: v < 2^24)
+    h.two_path_result(x, y, x, y, bmm="f16").free()
+    r = h.two_path_result(x, y, x, y, bmm="f16", timing=True)
+    sf = r.stats
+    nf = r.n
+    r.free()
+    if nf != n:
+        raise RuntimeError(f"fp16 product output size {nf} differs from {n}")
+    f16 = {"ms_bmm": sf["ms_bmm"], "tops": sf["bmm_ops"] / (sf["ms_bmm"] * 1e-3) / 1e12 if sf["ms_bmm"] > 0 else None,
+           "peak_tops": 2500.0, "ms_total": sf["ms_total"]}
+    return {"f16_product": f16, "workload": f"dense-core self-join: 8 communities of 4096 x ids by 2048 y ids, edge probability 0.25 "
                         f"({int(x.numel())} edges), cost-model thresholds",
             "n_out": n, "closed_form_n_out": 8 * 4096 * 4096, "J": st["J"], "ms_per_step": dt * 1e3,
             "pairs_per_s": n / dt, "delta1": st["delta1"], "delta2": st["delta2"], "u": sp["u"], "v": sp["v"],

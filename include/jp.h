@@ -50,7 +50,7 @@ typedef enum jp_status {
     JP_ENOMEM = 2,      /* device allocation failed */
     JP_EHIP = 3,        /* a HIP runtime call failed; message has hipGetErrorString */
     JP_ECAPACITY = 4,   /* a caller-supplied capacity was too small; the needed size is reported */
-    JP_EPRECISION = 5,  /* a reduced-precision product was requested where counts could exceed its exact range */
+    JP_EPRECISION = 5,  /* JP_BMM_F16 was requested where counts could reach 2^24 (v, or ld, >= 2^24) */
     JP_EINTERNAL = 6    /* internal consistency check failed */
 } jp_status;
 
@@ -69,7 +69,8 @@ typedef enum jp_bmm_kind {
     JP_BMM_I8_MFMA = 1,  /* int8 inputs, int32 accumulation on the matrix cores; tile by shape */
     JP_BMM_BITPOP = 2,   /* bit-packed rows, AND + popcount on the vector units */
     JP_BMM_I8_T128 = 3,  /* int8 MFMA, 128 x 128 block tiles */
-    JP_BMM_I8_T256 = 4   /* int8 MFMA, 256 x 256 block tiles */
+    JP_BMM_I8_T256 = 4,  /* int8 MFMA, 256 x 256 block tiles */
+    JP_BMM_F16 = 5       /* 0/1 operands as fp16, fp32 accumulation (exact below 2^24; JP_EPRECISION otherwise) */
 } jp_bmm_kind;
 
 /* Which y-degree decides whether y is heavy (two-path).  MAX: y is heavy when

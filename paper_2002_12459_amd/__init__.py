@@ -33,7 +33,7 @@ N_CELLS = 65
 
 DELTA_INF = 2**63 - 1
 STRATEGY = {"auto": 0, "cost": 0, "theory": 1, "fixed": 2, "light": 3, "mlp": 4}
-BMM = {"auto": 0, "i8": 1, "bitpop": 2, "i8_t128": 3, "i8_t256": 4}
+BMM = {"auto": 0, "i8": 1, "bitpop": 2, "i8_t128": 3, "i8_t256": 4, "f16": 5}
 Y_RULE = {"max": 0, "r_only": 1}
 DEDUP = {"auto": 0, "global": 1, "segmented": 2}
 STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ECAPACITY",

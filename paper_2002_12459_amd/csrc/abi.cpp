@@ -148,7 +148,7 @@ jp_status validate_options(jp_handle *h, const jp_options &o) {
         h->err = "FIXED thresholds must be >= 1";
         return JP_EINVAL;
     }
-    if (o.bmm < JP_BMM_AUTO || o.bmm > JP_BMM_I8_T256 || o.y_rule < JP_Y_RULE_MAX ||
+    if (o.bmm < JP_BMM_AUTO || o.bmm > JP_BMM_F16 || o.y_rule < JP_Y_RULE_MAX ||
         o.y_rule > JP_Y_RULE_R_ONLY || o.dedup < JP_DEDUP_AUTO || o.dedup > JP_DEDUP_SEGMENTED) {
         h->err = "bad option value";
         return JP_EINVAL;
@@ -970,9 +970,13 @@ jp_status jp_bool_matmul(jp_handle *h, const int8_t *A, const int8_t *Bt, int64_
     if (!h) return JP_EINVAL;
     if (u < 0 || w < 0 || k < 0 || cap < 0 || !nnz || ld < k || ld % jp::kBmmPadK != 0 ||
         bad_col(A, u * ld) || bad_col(Bt, w * ld) || bad_col(rows, cap) || bad_col(cols, cap) ||
-        kind < JP_BMM_AUTO || kind > JP_BMM_I8_T256) {
+        kind < JP_BMM_AUTO || kind > JP_BMM_F16) {
         h->err = "bad argument to jp_bool_matmul (ld must be >= k and a multiple of 128)";
         return JP_EINVAL;
+    }
+    if (kind == JP_BMM_F16 && ld >= (int64_t(1) << 24)) {
+        h->err = "fp16 product: counts may reach 2^24, beyond fp32's exact range";
+        return JP_EPRECISION;
     }
     int64_t count = 0;
     double t = 0;

@@ -465,6 +465,140 @@ __global__ __launch_bounds__(256) void k_emit_bitmap(const uint32_t *bitmap, int
     }
 }
 
+// ---- fp16 MFMA kernel ----------------------------------------------------------
+// The 128 x 128 block tile of k_bmm_i8 with fp16 operands: the 0/1 bytes
+// staged from global memory become fp16 ones and zeros in LDS, and
+// v_mfma_f32_16x16x32_f16 accumulates in fp32.  Every partial sum is an
+// integer of at most the row length, so the fp32 counts are exact while that
+// is below 2^24 (the caller checks).  The int8 storage of the matrices is
+// kept; only the LDS tile is twice as wide.
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int kF16Stride = 2 * BK + 32;                  // bytes per LDS row: 128 fp16 values + pad
+constexpr int kF16Lds = (BM + BN) * kF16Stride;          // dynamic LDS of one workgroup
+
+// Four 0/1 bytes -> four fp16 (1.0 = 0x3C00), as two words.
+__device__ __forceinline__ void bytes_to_f16(uint32_t w, uint32_t &lo, uint32_t &hi) {
+    lo = ((w & 1u) | ((w & 0x100u) << 8)) * 0x3C00u;
+    hi = (((w >> 16) & 1u) | ((w >> 8) & 0x10000u)) * 0x3C00u;
+}
+
+template <class ARows, class BRows, class Emit>
+__global__ __launch_bounds__(256) void k_bmm_f16(ARows arows, BRows brows, int64_t u, int64_t w, int64_t ld,
+                                                 int64_t tiles_m, int64_t tiles_n, Emit emit, int64_t cap,
+                                                 unsigned long long *count) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t lds16[];
+    uint8_t *sA = lds16, *sB = lds16 + BM * kF16Stride;
+    __shared__ uint32_t sh_cnt[4];
+    __shared__ unsigned long long sh_base;
+    const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
+    const int wm = wv >> 1, wn = wv & 1;
+    const int lr = tid / 8, lc = (tid % 8) * 16;
+    const int fr = lane % 16, fq = lane / 16;
+    const int64_t total = tiles_m * tiles_n;
+    for (int64_t bid = blockIdx.x; bid < xcd_padded(total); bid += gridDim.x) {
+        const int64_t item = xcd_item(bid, total);
+        if (item < 0) continue;  // padding (uniform per workgroup)
+        int64_t tm, tn;
+        tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
+        const int64_t row0 = tm * BM, col0 = tn * BN;
+        v4i ra[4], rb[4];
+        auto load_stage = [&](int64_t k0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t r = row0 + lr + 32 * q;
+                ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
+                const int64_t c = col0 + lr + 32 * q;
+                rb[q] = c < w ? brows.load(c, k0 + lc) : v4i{0, 0, 0, 0};
+            }
+        };
+        auto store_row = [&](uint8_t *base, v4i v) {
+            uint32_t h[8];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) bytes_to_f16((uint32_t)v[i], h[2 * i], h[2 * i + 1]);
+            *(v4i *)base = v4i{(int)h[0], (int)h[1], (int)h[2], (int)h[3]};
+            *(v4i *)(base + 16) = v4i{(int)h[4], (int)h[5], (int)h[6], (int)h[7]};
+        };
+        f4 acc[4][4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) acc[f][g] = f4{0.f, 0.f, 0.f, 0.f};
+        load_stage(0);
+        for (int64_t k0 = 0; k0 < ld; k0 += BK) {
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                store_row(sA + (lr + 32 * q) * kF16Stride + 2 * lc, ra[q]);
+                store_row(sB + (lr + 32 * q) * kF16Stride + 2 * lc, rb[q]);
+            }
+            __syncthreads();
+            if (k0 + BK < ld) load_stage(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 32) {
+                half8 a[4], b[4];
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+                    a[f] = *(const half8 *)(sA + (wm * 64 + f * 16 + fr) * kF16Stride + 2 * kk + 16 * fq);
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+                    b[g] = *(const half8 *)(sB + (wn * 64 + g * 16 + fr) * kF16Stride + 2 * kk + 16 * fq);
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+                        acc[f][g] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[f], b[g], acc[f][g], 0, 0, 0);
+            }
+        }
+        // Epilogue as in k_bmm_i8: C[row][col], row = 4 (lane / 16) + r, col = lane % 16.
+        uint32_t mine = 0;
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = row0 + wm * 64 + f * 16 + fq * 4 + r;
+                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
+                    mine += (acc[f][g][r] > 0.5f && i < u && j < w) ? 1u : 0u;
+                }
+        const uint32_t incl = wave_incl_scan(mine);
+        const uint32_t wtot = wave_lane(incl, kWave - 1);
+        const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
+        if (base < 0) continue;
+        int64_t pos = base + (incl - mine);
+#pragma unroll
+        for (int f = 0; f < 4; ++f)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t i = row0 + wm * 64 + f * 16 + fq * 4 + r;
+                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
+                    if (acc[f][g][r] > 0.5f && i < u && j < w) {
+                        if (pos < cap) emit(pos, i, j, (uint32_t)(acc[f][g][r] + 0.5f));
+                        ++pos;
+                    }
+                }
+    }
+}
+
+template <class ARows, class BRows, class Emit>
+void launch_bmm_f16(const Ctx &c, ARows arows, BRows brows, int64_t u, int64_t w, int64_t ld, Emit emit, int64_t cap,
+                    unsigned long long *count_dev) {
+    JP_CHECK(ld % kBmmPadK == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 128");
+    JP_CHECK(ld < (int64_t(1) << 24), JP_EPRECISION, "fp16 product: counts may reach 2^24, beyond fp32's exact range");
+    c.zero(count_dev, 1);
+    if (u <= 0 || w <= 0 || ld <= 0) return;
+    const int64_t tm = ceil_div(u, BM), tn = ceil_div(w, BN);
+    const int64_t total = xcd_padded(tm * tn);
+    constexpr int64_t kMaxGrid = 1ll << 22;  // multiple of 8
+    const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
+    hipLaunchKernelGGL((k_bmm_f16<ARows, BRows, Emit>), dim3(grid_x(blocks, 256)), dim3(256), kF16Lds, c.stream, arows,
+                       brows, u, w, ld, tm, tn, emit, cap, count_dev);
+    JP_HIP(hipGetLastError());
+}
+
 template <class ARows, class BRows, class Emit>
 void launch_bmm_rows(const Ctx &c, ARows arows, BRows brows, int64_t u, int64_t w, int64_t ld, Emit emit, int64_t cap,
                      unsigned long long *count_dev) {
@@ -639,7 +773,7 @@ void launch_bitpop(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, i
 // (large tiles need both sides to fill several 256-row tiles); AUTO also
 // races the popcount kernel against the int8 kernel once per shape class on
 // the handle (autotune), keeping the faster.
-enum class BmmVariant { T128, T256, BITPOP };
+enum class BmmVariant { T128, T256, BITPOP, F16 };
 
 static BmmVariant by_shape(int64_t u, int64_t w) {
     return (u >= 1024 && w >= 1024) ? BmmVariant::T256 : BmmVariant::T128;
@@ -651,6 +785,7 @@ static void run_variant(const Ctx &c, BmmVariant v, const int8_t *A, const int8_
     switch (v) {
         case BmmVariant::T256: launch_bmm_big(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
         case BmmVariant::BITPOP: launch_bitpop(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
+        case BmmVariant::F16: launch_bmm_f16(c, PlainRows{A, ld}, PlainRows{Bt, ld}, u, w, ld, emit, cap, count_dev); break;
         default: launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, emit, cap, count_dev); break;
     }
 }
@@ -675,6 +810,7 @@ static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int
         case JP_BMM_I8_T256: v = BmmVariant::T256; break;
         case JP_BMM_BITPOP: v = BmmVariant::BITPOP; break;
         case JP_BMM_I8_MFMA: v = by_shape(u, w); break;
+        case JP_BMM_F16: v = BmmVariant::F16; break;
         default: {
             v = by_shape(u, w);
             // race once per shape class (products too small to matter are not raced)
@@ -704,7 +840,8 @@ static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int
             }
         }
     }
-    if (c.bmm_used) *c.bmm_used = v == BmmVariant::BITPOP ? JP_BMM_BITPOP : JP_BMM_I8_MFMA;
+    if (c.bmm_used)
+        *c.bmm_used = v == BmmVariant::BITPOP ? JP_BMM_BITPOP : (v == BmmVariant::F16 ? JP_BMM_F16 : JP_BMM_I8_MFMA);
     run_variant(c, v, A, Bt, u, w, ld, emit, cap, count_dev);
 }
 
@@ -738,7 +875,7 @@ void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int
 // rows as they are loaded.  Nonzeros become k-tuple keys (xof[t][a_t] << s[t]).
 template <class K, int G, int H>
 static void star_product(const Ctx &c, const int8_t *const *M, const int64_t *u, int64_t ld, const int32_t *const *xof,
-                         const int *s, void *keys, int64_t cap, unsigned long long *count_dev) {
+                         const int *s, void *keys, int64_t cap, unsigned long long *count_dev, bool f16) {
     TupleRows<G> a;
     TupleRows<H> b;
     TupleEmit<K, G, H> e;
@@ -760,29 +897,30 @@ static void star_product(const Ctx &c, const int8_t *const *M, const int64_t *u,
         e.s[t] = s[t];
     }
     e.keys = (K *)keys;
-    launch_bmm_rows(c, a, b, rows_a, rows_b, ld, e, cap, count_dev);
+    if (f16) launch_bmm_f16(c, a, b, rows_a, rows_b, ld, e, cap, count_dev);
+    else launch_bmm_rows(c, a, b, rows_a, rows_b, ld, e, cap, count_dev);
 }
 
 template <class K>
 static void star_product_k(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
                            const int32_t *const *xof, const int *s, void *keys, int64_t cap,
-                           unsigned long long *count_dev) {
+                           unsigned long long *count_dev, bool f16) {
     switch (k) {
-        case 3: star_product<K, 2, 1>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
-        case 4: star_product<K, 2, 2>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
-        case 5: star_product<K, 3, 2>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
-        case 6: star_product<K, 3, 3>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
-        case 7: star_product<K, 4, 3>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
-        case 8: star_product<K, 4, 4>(c, M, u, ld, xof, s, keys, cap, count_dev); break;
+        case 3: star_product<K, 2, 1>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
+        case 4: star_product<K, 2, 2>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
+        case 5: star_product<K, 3, 2>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
+        case 6: star_product<K, 3, 3>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
+        case 7: star_product<K, 4, 3>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
+        case 8: star_product<K, 4, 4>(c, M, u, ld, xof, s, keys, cap, count_dev, f16); break;
         default: fail(JP_EINTERNAL, "star product needs 3 <= k <= 8");
     }
 }
 
 void star_bmm_keys(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
                    const int32_t *const *xof, const int *s, void *keys, bool wide, int64_t cap,
-                   unsigned long long *count_dev) {
-    if (wide) star_product_k<unsigned __int128>(c, k, M, u, ld, xof, s, keys, cap, count_dev);
-    else star_product_k<uint64_t>(c, k, M, u, ld, xof, s, keys, cap, count_dev);
+                   unsigned long long *count_dev, bool f16) {
+    if (wide) star_product_k<unsigned __int128>(c, k, M, u, ld, xof, s, keys, cap, count_dev, f16);
+    else star_product_k<uint64_t>(c, k, M, u, ld, xof, s, keys, cap, count_dev, f16);
 }
 
 }  // namespace jp

@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void k_star_expand(BoxArgs a) {
 // Heavy product of the star query (bmm.hip).
 void star_bmm_keys(const Ctx &c, int k, const int8_t *const *M, const int64_t *u, int64_t ld,
                    const int32_t *const *xof, const int *s, void *keys, bool wide, int64_t cap,
-                   unsigned long long *count_dev);
+                   unsigned long long *count_dev, bool f16);
 
 namespace {
 
@@ -625,6 +625,8 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
     int64_t nnz = 0;
     int ev_b0 = ev_light, ev_b1 = ev_light;
     if (has_heavy) {
+        JP_CHECK(o.bmm != JP_BMM_F16 || v < (int64_t(1) << 24), JP_EPRECISION,
+                 "fp16 product: counts may reach 2^24 (heavy y), beyond fp32's exact range");
         const int64_t ld = ceil_div(v, kBmmPadK) * kBmmPadK;
         DBuf<int8_t> M[kMaxStar];
         const int8_t *Mp[kMaxStar];
@@ -646,11 +648,11 @@ jp_result *run_star(const Ctx &c, int k, const int32_t *const *X, const int32_t 
         }
         ev_b0 = tl.mark();
         star_bmm_keys(c, k, Mp, u, ld, xp, shift, cand.get() + (size_t)J_L * ksz, wide, cap_h,
-                      (unsigned long long *)(S + 10));
+                      (unsigned long long *)(S + 10), o.bmm == JP_BMM_F16);
         ev_b1 = tl.mark();
         nnz = c.load(S + 10);
         JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "star heavy product produced more nonzeros than its bound");
-        st.bmm = JP_BMM_I8_MFMA;
+        st.bmm = o.bmm == JP_BMM_F16 ? JP_BMM_F16 : JP_BMM_I8_MFMA;
         st.bmm_ops = 2.0 * rows_v * (double)v * rows_w;
     }
     st.nnz_heavy = nnz;

@@ -862,6 +862,8 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     DBuf<int32_t> need_y;  // per heavy y: 1 if a heavy x meets it
     int64_t ld = 0;
     if (has_heavy) {
+        JP_CHECK(o.bmm != JP_BMM_F16 || v < (int64_t(1) << 24), JP_EPRECISION,
+                 "fp16 product: counts may reach 2^24 (heavy y), beyond fp32's exact range");
         ld = ceil_div(v, kBmmPadK) * kBmmPadK;
         M1 = c.buf<int8_t>((size_t)(u * ld));
         M2t = c.buf<int8_t>((size_t)(w * ld));

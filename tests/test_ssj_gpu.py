@@ -77,7 +77,8 @@ def test_random_small(jp, key_width, seed, d):
 
 
 @pytest.mark.parametrize("kw", [{}, {"strategy": "light"}, {"delta1": 30, "delta2": 8},
-                                {"delta1": 30, "delta2": 8, "bmm": "bitpop"}, {"delta1": 5, "delta2": 3}])
+                                {"delta1": 30, "delta2": 8, "bmm": "bitpop"}, {"delta1": 30, "delta2": 8, "bmm": "f16"},
+                                {"delta1": 5, "delta2": 3}])
 def test_zipf(jp, kw):
     rx, ry = datagen.zipf_edges(30_000, 3_000, 600, 1.2, 31)
     sz, sy = datagen.zipf_edges(30_000, 3_000, 600, 1.2, 32)

@@ -167,7 +167,7 @@ def test_random_small_star_k(jp, k, seed):
 
 
 @pytest.mark.parametrize("kw", [dict(strategy="light"), dict(strategy="auto"), dict(delta1=50, delta2=6),
-                                dict(delta1=10, delta2=4)])
+                                dict(delta1=10, delta2=4), dict(delta1=10, delta2=4, bmm="f16")])
 def test_star4_zipf(jp, kw):
     """Four 20K-edge Zipf(1.2) relations with independent y orders (J = 4.6M)."""
     rels = [datagen.zipf_edges(20_000, 5_000, 2_000, 1.2, 50 + i) for i in range(4)]

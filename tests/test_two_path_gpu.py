@@ -130,7 +130,7 @@ def test_zipf_scaled(jp, scale):
         np.testing.assert_array_equal(z, ez, err_msg=str(kw))
 
 
-@pytest.mark.parametrize("bmm", ["auto", "i8_t128", "i8_t256", "bitpop"])
+@pytest.mark.parametrize("bmm", ["auto", "i8_t128", "i8_t256", "bitpop", "f16"])
 def test_communities_dense_heavy(jp, bmm):
     """Dense communities: the heavy product carries most of the output."""
     # p = 0.5 over 150 y per community: two x of a community miss a common y
@@ -138,10 +138,10 @@ def test_communities_dense_heavy(jp, bmm):
     x, y = datagen.communities(4, 300, 150, 0.5, seed=5)
     st = check_equal(jp, x, y, x, y, delta1=10, delta2=10, bmm=bmm)
     assert st["nnz_heavy"] > 0 and st["n_out"] == 4 * 300 * 300
-    assert st["bmm"] == (2 if bmm == "bitpop" else (1 if bmm != "auto" else st["bmm"]))
+    assert st["bmm"] == {"bitpop": 2, "f16": 5}.get(bmm, 1 if bmm != "auto" else st["bmm"])
 
 
-@pytest.mark.parametrize("kind", ["i8", "i8_t128", "i8_t256", "bitpop", "auto"])
+@pytest.mark.parametrize("kind", ["i8", "i8_t128", "i8_t256", "bitpop", "f16", "auto"])
 @pytest.mark.parametrize("u,w,k", [(1, 1, 1), (37, 130, 200), (128, 128, 128), (257, 129, 1000), (600, 515, 77),
                                    (1100, 1300, 390), (513, 2049, 256), (1, 1, 5000), (100, 90, 20000),
                                    (129, 300, 9000)])
@@ -168,7 +168,7 @@ def test_bool_matmul_counts_do_not_overflow(jp):
     A = torch.ones((u, k), dtype=torch.int8).cuda()
     B = torch.zeros((w, k), dtype=torch.int8)
     B[::2] = 1
-    for kind in ("i8_t128", "i8_t256", "bitpop"):
+    for kind in ("i8_t128", "i8_t256", "bitpop", "f16"):
         rows, cols, _ = jp.default_handle(0).bool_matmul(A, B.cuda(), kind=kind)
         assert rows.numel() == u * (w // 2)
         assert set(cols.cpu().numpy().tolist()) == set(range(0, w, 2))
@@ -184,7 +184,7 @@ def test_bool_matmul_more_tiles_than_one_grid(jp):
     idx = torch.arange(u, device="cuda")
     A[idx, idx % 128] = 1
     per = np.bincount(np.arange(u) % 128, minlength=128).astype(np.int64)
-    for kind in ("i8_t128", "i8_t256", "bitpop"):
+    for kind in ("i8_t128", "i8_t256", "bitpop", "f16"):
         nnz, _ = jp.default_handle(0).bool_matmul_count(A, A, kind=kind)
         assert nnz == int((per * per).sum()), kind
 
@@ -299,3 +299,22 @@ def test_device_summary_drives_the_same_choice(jp, inst):
     assert np.isclose(f[15], np.log(1 + s["z"][0][-1]), rtol=1e-5)
     # and the whole pipeline under the optimizer's thresholds is exact
     check_equal(jp, rx, ry, sz, sy, strategy="auto")
+
+
+def test_f16_product_refuses_counts_beyond_its_exact_range(jp):
+    """fp16 operands with fp32 accumulation are exact below 2^24: a product
+    whose inner dimension reaches 2^24 is refused before any launch."""
+    import torch
+    A = torch.zeros((1, 1 << 24), dtype=torch.int8, device="cuda")
+    with pytest.raises(jp.JoinProjectError) as e:
+        jp.default_handle(0).bool_matmul_count(A, A, kind="f16")
+    assert e.value.status == 5  # JP_EPRECISION
+    nnz, _ = jp.default_handle(0).bool_matmul_count(A[:, :(1 << 24) - 128], A[:, :(1 << 24) - 128], kind="f16")
+    assert nnz == 0
+
+
+def test_f16_product_end_to_end(jp):
+    rx, ry = datagen.zipf_edges(40_000, 4_000, 800, 1.1, 81)
+    sz, sy = datagen.zipf_edges(40_000, 4_000, 800, 1.1, 82)
+    st = check_equal(jp, rx, ry, sz, sy, delta1=20, delta2=8, bmm="f16")
+    assert st["bmm"] == 5 and st["nnz_heavy"] > 0
