@@ -305,7 +305,9 @@ def dense_leg(h, edges, steps):
             "n_out": n, "closed_form_n_out": 8 * 4096 * 4096, "J": st["J"], "ms_per_step": dt * 1e3,
             "pairs_per_s": n / dt, "delta1": st["delta1"], "delta2": st["delta2"], "u": sp["u"], "v": sp["v"],
             "w": sp["w"], "ms_bmm": sp["ms_bmm"],
-            "bmm_tops": sp["bmm_ops"] / (sp["ms_bmm"] * 1e-3) / 1e12 if sp["ms_bmm"] > 0 else None}
+            "bmm_tops": sp["bmm_ops"] / (sp["ms_bmm"] * 1e-3) / 1e12 if sp["ms_bmm"] > 0 else None,
+            "bmm_ops_executed": sp["bmm_ops"], "bmm_ops_full_product": 2.0 * sp["u"] * sp["v"] * sp["w"],
+            "note": "self-join: M2^T = M1, the product runs on the tiles on and above the diagonal (mirrored)"}
 
 
 def main():

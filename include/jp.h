@@ -116,7 +116,8 @@ typedef struct jp_stats {
     int64_t J_H;                 /* heavy witnesses (covered by the product) */
     int64_t nnz_heavy;           /* nonzero entries of the heavy product */
     int64_t n_out;               /* distinct output tuples */
-    double bmm_ops;              /* 2*u*v*w (star: 2*u1*u2*v*u3) */
+    double bmm_ops;              /* operations the product ran: 2*u*v*w (star: 2*u1*u2*v*u3); a self-join
+                                    product on the tiles on and above the diagonal counts only those */
     double ms_ingest;            /* index build: dedup, semijoin, ranks, CSR, degrees */
     double ms_plan;              /* threshold choice + partition */
     double ms_light;             /* light witness enumeration */

@@ -309,24 +309,39 @@ constexpr int kStageBytes = (BM2 + BN2) * BK2;  // 64 KB: A rows then B rows
 
 __device__ __forceinline__ int swz(int r, int c) { return r * BK2 + ((c ^ (r & 7)) << 4); }
 
+// Upper-triangle tile t (column by column: (0,0), (0,1), (1,1), (0,2), ...)
+// of a symmetric product.
+__device__ __forceinline__ void tri_tile(int64_t t, int64_t *tm, int64_t *tn) {
+    int64_t c = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+    while ((c + 1) * (c + 2) / 2 <= t) ++c;
+    while (c * (c + 1) / 2 > t) --c;
+    *tn = c;
+    *tm = t - c * (c + 1) / 2;
+}
+
+// sym: A == Bt (a self-join's C = M1 M1^T, symmetric): only tiles with
+// tm <= tn are computed, and a nonzero of a tile off the diagonal is
+// emitted as (i, j) and (j, i).
 template <class Emit>
 __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ A, const int8_t *__restrict__ Bt,
                                                      int64_t u, int64_t w, int64_t ld, int64_t tiles_m,
                                                      int64_t tiles_n, Emit emit, int64_t cap,
-                                                     unsigned long long *count) {
+                                                     unsigned long long *count, bool sym) {
     extern __shared__ __attribute__((aligned(16))) int8_t lds[];  // 2 stages
     __shared__ uint32_t sh_cnt[kBig / kWave];
     __shared__ unsigned long long sh_base;
     const int tid = threadIdx.x, lane = lane_id(), wv = tid / kWave;
     const int wm = wv >> 2, wn = wv & 3;
     const int fr = lane % 16, fq = lane / 16;
-    const int64_t total = tiles_m * tiles_n;
+    const int64_t total = sym ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
     const int64_t nk = ld / BK2;
     for (int64_t bid = blockIdx.x; bid < xcd_padded(total); bid += gridDim.x) {
         const int64_t item = xcd_item(bid, total);
         if (item < 0) continue;  // padding (uniform per workgroup)
         int64_t tm, tn;
-        tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
+        if (sym) tri_tile(item, &tm, &tn);
+        else tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
+        const uint32_t mult = (sym && tm != tn) ? 2u : 1u;  // uniform per workgroup
         const int64_t row0 = tm * BM2, col0 = tn * BN2;
         // Stage s: 4096 chunks of 16 bytes, 8 rounds of 512; chunk P holds
         // (row P / 8, K chunk (P % 8) ^ (row & 7)); rows 0..255 are A, 256..511 B.
@@ -397,7 +412,7 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                 for (int r = 0; r < 4; ++r) {
                     const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
                     const int64_t j = col0 + wn * 64 + g * 16 + fr;
-                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
+                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? mult : 0u;
                 }
         const uint32_t incl = wave_incl_scan(mine);
         const uint32_t wtot = wave_lane(incl, kWave - 1);
@@ -414,7 +429,8 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
                     const int64_t j = col0 + wn * 64 + g * 16 + fr;
                     if (acc[f][g][r] > 0 && i < u && j < w) {
                         if (pos < cap) emit(pos, i, j, (uint32_t)acc[f][g][r]);
-                        ++pos;
+                        if (mult == 2u && pos + 1 < cap) emit(pos + 1, j, i, (uint32_t)acc[f][g][r]);
+                        pos += mult;
                     }
                 }
     }
@@ -422,16 +438,17 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
 
 template <class Emit>
 void launch_bmm_big(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, Emit emit,
-                    int64_t cap, unsigned long long *count_dev) {
+                    int64_t cap, unsigned long long *count_dev, bool sym = false) {
     JP_CHECK(ld % BK2 == 0, JP_EINTERNAL, "heavy matrix stride must be a multiple of 128");
+    JP_CHECK(!sym || (A == Bt && u == w), JP_EINTERNAL, "a symmetric product needs A == Bt");
     c.zero(count_dev, 1);
     if (u <= 0 || w <= 0 || ld <= 0) return;
     const int64_t tm = ceil_div(u, BM2), tn = ceil_div(w, BN2);
-    const int64_t total = xcd_padded(tm * tn);
+    const int64_t total = xcd_padded(sym ? tm * (tm + 1) / 2 : tm * tn);
     constexpr int64_t kMaxGrid = 1ll << 21;  // multiple of 8
     const int64_t blocks = total < kMaxGrid ? total : kMaxGrid;
     hipLaunchKernelGGL((k_bmm_i8_big<Emit>), dim3(grid_x(blocks, kBig)), dim3(kBig), 2 * kStageBytes, c.stream, A,
-                       Bt, u, w, ld, tm, tn, emit, cap, count_dev);
+                       Bt, u, w, ld, tm, tn, emit, cap, count_dev, sym);
     JP_HIP(hipGetLastError());
 }
 
@@ -781,9 +798,12 @@ static BmmVariant by_shape(int64_t u, int64_t w) {
 
 template <class Emit>
 static void run_variant(const Ctx &c, BmmVariant v, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w,
-                        int64_t ld, Emit emit, int64_t cap, unsigned long long *count_dev) {
+                        int64_t ld, Emit emit, int64_t cap, unsigned long long *count_dev, bool sym = false) {
     switch (v) {
-        case BmmVariant::T256: launch_bmm_big(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
+        case BmmVariant::T256:
+            launch_bmm_big(c, A, Bt, u, w, ld, emit, cap, count_dev, sym);
+            if (sym && c.bmm_sym) *c.bmm_sym = true;
+            break;
         case BmmVariant::BITPOP: launch_bitpop(c, A, Bt, u, w, ld, emit, cap, count_dev); break;
         case BmmVariant::F16: launch_bmm_f16(c, PlainRows{A, ld}, PlainRows{Bt, ld}, u, w, ld, emit, cap, count_dev); break;
         default: launch_bmm(c, PlainRows{A, ld}, Bt, u, w, ld, emit, cap, count_dev); break;
@@ -803,7 +823,7 @@ static uint64_t shape_class(int64_t u, int64_t w, int64_t ld) {
 
 template <class Emit>
 static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
-                            int kind, Emit emit, int64_t cap, unsigned long long *count_dev) {
+                            int kind, Emit emit, int64_t cap, unsigned long long *count_dev, bool sym = false) {
     BmmVariant v;
     switch (kind) {
         case JP_BMM_I8_T128: v = BmmVariant::T128; break;
@@ -825,7 +845,7 @@ static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int
                     for (BmmVariant q : cand) {
                         EventPair ev;
                         JP_HIP(hipEventRecord(ev.a, c.stream));
-                        run_variant(c, q, A, Bt, u, w, ld, emit, 0, count_dev);  // count only
+                        run_variant(c, q, A, Bt, u, w, ld, emit, 0, count_dev, sym);  // count only
                         JP_HIP(hipEventRecord(ev.b, c.stream));
                         JP_HIP(hipEventSynchronize(ev.b));
                         float ms = 0;
@@ -842,7 +862,7 @@ static void bool_matmul_any(const Ctx &c, const int8_t *A, const int8_t *Bt, int
     }
     if (c.bmm_used)
         *c.bmm_used = v == BmmVariant::BITPOP ? JP_BMM_BITPOP : (v == BmmVariant::F16 ? JP_BMM_F16 : JP_BMM_I8_MFMA);
-    run_variant(c, v, A, Bt, u, w, ld, emit, cap, count_dev);
+    run_variant(c, v, A, Bt, u, w, ld, emit, cap, count_dev, sym);
 }
 
 void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
@@ -852,21 +872,21 @@ void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t 
 
 void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,
-                      unsigned long long *count_dev) {
-    bool_matmul_any(c, A, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev);
+                      unsigned long long *count_dev, bool sym) {
+    bool_matmul_any(c, A, Bt, u, w, ld, kind, KeyEmit{rowmap, colmap, shift, keys}, cap, count_dev, sym);
 }
 
 void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
                             int kind, const int32_t *rowmap, const int32_t *colmap, int shift, int wshift, void *keys,
-                            bool wide, int64_t cap, unsigned long long *count_dev) {
+                            bool wide, int64_t cap, unsigned long long *count_dev, bool sym) {
     if (wide)
         bool_matmul_any(c, A, Bt, u, w, ld, kind,
                         CountKeyEmit<unsigned __int128>{rowmap, colmap, shift, wshift, (unsigned __int128 *)keys}, cap,
-                        count_dev);
+                        count_dev, sym);
     else
         bool_matmul_any(c, A, Bt, u, w, ld, kind, CountKeyEmit<uint64_t>{rowmap, colmap, shift, wshift,
                                                                           (uint64_t *)keys},
-                        cap, count_dev);
+                        cap, count_dev, sym);
 }
 
 // Star query heavy product C = V x W^T (Section 3.2) over k factor matrices

@@ -376,6 +376,7 @@ struct Ctx {
     const Selector *sel = nullptr;        // learned threshold selector of the handle (may be empty)
     std::map<uint64_t, int> *tune = nullptr;  // product kernel per shape class, raced once (handle-owned)
     mutable int *bmm_used = nullptr;          // where to report the product kernel used (may be null)
+    mutable bool *bmm_sym = nullptr;          // set when a symmetric product ran on half its tiles (may be null)
 
     template <class T>
     DBuf<T> buf(size_t n) const {

@@ -161,11 +161,14 @@ void bool_matmul_pairs(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t 
 // key of the pair with its count (u64 keys, or 128-bit keys when wide).
 void bool_matmul_count_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld,
                             int kind, const int32_t *rowmap, const int32_t *colmap, int shift, int wshift, void *keys,
-                            bool wide, int64_t cap, unsigned long long *count_dev);
+                            bool wide, int64_t cap, unsigned long long *count_dev, bool sym = false);
 // Same, emitting packed keys (rowmap[i] << shift) | colmap[j] (u64).
+// sym: A == Bt and u == w (a self-join): the product is symmetric, and the
+// 256 x 256 kernel computes only the tiles on and above the diagonal,
+// emitting each nonzero of an off-diagonal tile twice (mirrored).
 void bool_matmul_keys(const Ctx &c, const int8_t *A, const int8_t *Bt, int64_t u, int64_t w, int64_t ld, int kind,
                       const int32_t *rowmap, const int32_t *colmap, int shift, uint64_t *keys, int64_t cap,
-                      unsigned long long *count_dev);
+                      unsigned long long *count_dev, bool sym = false);
 
 constexpr int64_t kBmmPadK = 128;  // K padding of the heavy matrices (bytes)
 

@@ -558,6 +558,16 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     return true;
 }
 
+// Operations the product kernel executed: 2 u v w, or for a symmetric
+// product on the tiles on and above the diagonal (256 x 256 tiles) the
+// fraction T (T + 1) / 2 of the T^2 tiles.
+static double product_ops(int64_t u, int64_t v, int64_t w, bool sym_done) {
+    const double full = 2.0 * (double)u * (double)v * (double)w;
+    if (!sym_done) return full;
+    const double t = (double)ceil_div(u, 256);
+    return full * (t * (t + 1) / 2) / (t * t);
+}
+
 // ---- overlap output (set similarity join) ---------------------------------
 // Every distinct pair with its number of witnesses |N_R(x) & N_S(z)|: the
 // light witnesses and the heavy product partition the full join (Algorithm 1),
@@ -571,6 +581,7 @@ struct OverlapIn {
     int64_t J_L = 0, cap_h = 0;
     bool has_heavy = false;
     const int8_t *M1 = nullptr, *M2t = nullptr;
+    bool sym = false;  // M2t == M1 (self-join)
     int64_t u = 0, v = 0, w = 0, ld = 0;
     const int32_t *x_of_hx = nullptr, *z_of_hz = nullptr;
     int bmm_kind = 0;
@@ -648,14 +659,16 @@ static void overlap_output(const Ctx &c, const OverlapIn &in, jp_result *res, jp
     int64_t nnz = 0;
     if (in.has_heavy) {
         int used = JP_BMM_I8_MFMA;
+        bool sym_done = false;
         Ctx cb = c;
         cb.bmm_used = &used;
+        cb.bmm_sym = &sym_done;
         bool_matmul_count_keys(cb, in.M1, in.M2t, in.u, in.w, in.ld, in.bmm_kind, in.x_of_hx, in.z_of_hz, in.bz, wb,
-                               cand.get() + in.J_L, sizeof(K) == 16, in.cap_h, (unsigned long long *)(S + 17));
+                               cand.get() + in.J_L, sizeof(K) == 16, in.cap_h, (unsigned long long *)(S + 17), in.sym);
         nnz = c.load(S + 17);
         JP_CHECK(nnz <= in.cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
         st.bmm = used;
-        st.bmm_ops = 2.0 * (double)in.u * (double)in.v * (double)in.w;
+        st.bmm_ops = product_ops(in.u, in.v, in.w, sym_done);
     }
     st.nnz_heavy = nnz;
     const int64_t total = in.J_L + nnz;
@@ -861,15 +874,18 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     DBuf<int8_t> M1, M2t;
     DBuf<int32_t> need_y;  // per heavy y: 1 if a heavy x meets it
     int64_t ld = 0;
+    // A self-join (R and S the same columns) has heavy z = heavy x and
+    // M2^T = M1: the product is M1 M1^T, computed on half its tiles.
+    const bool sym = sum.self_join && u == w;
     if (has_heavy) {
         JP_CHECK(o.bmm != JP_BMM_F16 || v < (int64_t(1) << 24), JP_EPRECISION,
                  "fp16 product: counts may reach 2^24 (heavy y), beyond fp32's exact range");
         ld = ceil_div(v, kBmmPadK) * kBmmPadK;
         M1 = c.buf<int8_t>((size_t)(u * ld));
-        M2t = c.buf<int8_t>((size_t)(w * ld));
+        if (!sym) M2t = c.buf<int8_t>((size_t)(w * ld));
         need_y = c.buf<int32_t>(v);
         c.zero(M1.get(), (size_t)(u * ld));
-        c.zero(M2t.get(), (size_t)(w * ld));
+        if (!sym) c.zero(M2t.get(), (size_t)(w * ld));
         c.zero(need_y.get(), (size_t)v);
         int8_t *m1 = M1.get(), *m2 = M2t.get();
         int32_t *nd = need_y.get();
@@ -886,11 +902,13 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
                 }
             }
         });
-        for_each(c, n_s2, [=] __device__(int64_t e) {
-            const int32_t cc = hz[as[e]], b = hy[syr[e]];
-            if ((cc >= 0) & (b >= 0)) m2[(int64_t)(cc >= 0 ? cc : 0) * ldl + (b >= 0 ? b : 0)] = 1;
-        });
+        if (!sym)
+            for_each(c, n_s2, [=] __device__(int64_t e) {
+                const int32_t cc = hz[as[e]], b = hy[syr[e]];
+                if ((cc >= 0) & (b >= 0)) m2[(int64_t)(cc >= 0 ? cc : 0) * ldl + (b >= 0 ? b : 0)] = 1;
+            });
     }
+    const int8_t *M2use = sym ? M1.get() : M2t.get();
     // Witness lists.  zlist = N_S(y) for all y (adj_s, or the z offsets of
     // the same tuples), then for heavy y the light-z part of N_S(y) (what an
     // R tuple with heavy x and heavy y still meets; empty for heavy y that no
@@ -1016,7 +1034,8 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         in.cap_h = cap_h;
         in.has_heavy = has_heavy;
         in.M1 = M1.get();
-        in.M2t = M2t.get();
+        in.M2t = M2use;
+        in.sym = sym;
         in.u = u;
         in.v = v;
         in.w = w;
@@ -1063,10 +1082,12 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             hk = c.buf<uint64_t>(std::max<int64_t>(cap_h, 1));
             ev_bmm0 = tl.mark();
             int used = JP_BMM_I8_MFMA;
+            bool sym_done = false;
             Ctx cb = c;
             cb.bmm_used = &used;
-            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), zcol, bz, hk.get(),
-                             cap_h, (unsigned long long *)(S + 17));
+            cb.bmm_sym = &sym_done;
+            bool_matmul_keys(cb, M1.get(), M2use, u, w, ld, o.bmm, x_of_hx.get(), zcol, bz, hk.get(), cap_h,
+                             (unsigned long long *)(S + 17), sym);
             ev_bmm1 = tl.mark();
             nnz = c.load(S + 17);
             JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
@@ -1074,7 +1095,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
             hks = radix_sort(c, hk.get(), hk_tmp.get(), nnz, bx + bz);
             dump(c, "heavy keys", hks, nnz);
             st.bmm = used;
-            st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+            st.bmm_ops = product_ops(u, v, w, sym_done);
         }
         M1.reset();
         M2t.reset();
@@ -1133,16 +1154,18 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         if (has_heavy) {
             ev_bmm0 = tl.mark();
             int used = JP_BMM_I8_MFMA;
+            bool sym_done = false;
             Ctx cb = c;
             cb.bmm_used = &used;
-            bool_matmul_keys(cb, M1.get(), M2t.get(), u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
-                             cand.get() + J_L, cap_h, (unsigned long long *)(S + 17));
+            cb.bmm_sym = &sym_done;
+            bool_matmul_keys(cb, M1.get(), M2use, u, w, ld, o.bmm, x_of_hx.get(), z_of_hz.get(), bz,
+                             cand.get() + J_L, cap_h, (unsigned long long *)(S + 17), sym);
             ev_bmm1 = tl.mark();
             nnz = c.load(S + 17);
             JP_CHECK(nnz <= cap_h, JP_EINTERNAL, "heavy product produced more nonzeros than its bound");
             dump(c, "heavy keys", cand.get() + J_L, nnz);
             st.bmm = used;
-            st.bmm_ops = 2.0 * (double)u * (double)v * (double)w;
+            st.bmm_ops = product_ops(u, v, w, sym_done);
         }
         M1.reset();
         M2t.reset();

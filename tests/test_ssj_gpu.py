@@ -103,3 +103,13 @@ def test_arguments(jp):
     assert e.value.status == 1
     x, z, n, _ = h.ssj(dev([]), dev([]), a, a, min_overlap=2)
     assert x.numel() == z.numel() == n.numel() == 0
+
+
+@pytest.mark.parametrize("bmm", ["i8_t256", "auto", "i8_t128"])
+def test_self_join_symmetric_product_counts(jp, bmm):
+    """Self-join (R and S the same columns): the product is M1 M1^T computed
+    on the tiles on and above the diagonal, mirrored; overlaps stay exact."""
+    x, y = datagen.communities(4, 300, 150, 0.5, seed=6)
+    for c in (1, 40, 80):
+        st = check(jp, x, y, x, y, c, c == 40, delta1=10, delta2=10, bmm=bmm)
+        assert st["u"] == st["w"] == 1200 and st["nnz_heavy"] > 0

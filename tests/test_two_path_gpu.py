@@ -318,3 +318,14 @@ def test_f16_product_end_to_end(jp):
     sz, sy = datagen.zipf_edges(40_000, 4_000, 800, 1.1, 82)
     st = check_equal(jp, rx, ry, sz, sy, delta1=20, delta2=8, bmm="f16")
     assert st["bmm"] == 5 and st["nnz_heavy"] > 0
+
+
+def test_self_join_symmetric_product_many_tiles(jp):
+    """A self-join whose heavy part spans 6 x 6 tiles of 256: the product runs
+    on the 21 tiles on and above the diagonal and mirrors the rest."""
+    x, y = datagen.communities(6, 250, 100, 0.5, seed=9)
+    st = check_equal(jp, x, y, x, y, delta1=10, delta2=10, bmm="i8_t256")
+    assert st["u"] == st["w"] == 1500 and st["nnz_heavy"] == 6 * 250 * 250
+    # the same relation passed as two different column pairs: no symmetry assumed
+    st2 = check_equal(jp, x, y, x.copy(), y.copy(), delta1=10, delta2=10, bmm="i8_t256")
+    assert st2["nnz_heavy"] == st["nnz_heavy"]
