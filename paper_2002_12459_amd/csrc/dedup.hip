@@ -170,17 +170,106 @@ __device__ __forceinline__ uint32_t block_excl_max(uint32_t v, uint32_t *lds) {
     return r;
 }
 
-__device__ __forceinline__ uint16_t &ctr(uint32_t *cnt, int d, int t) {
-    const int ci = d * kDT + t;
-    return reinterpret_cast<uint16_t *>(cnt)[2 * cpad(ci >> 1) + (ci & 1)];
+// Thread t's counter of digit d is counter d * kDT + t: the 16-bit half
+// (t & 1) of word cpad((d * kDT + t) / 2) = d * kDigitWords + t / 2 + t / 32
+// (kDT / 2 is a multiple of 16, so the digit's part of the pad splits off).
+static_assert(kDT % 32 == 0, "counter word split");
+constexpr int kDigitWords = kDT / 2 + kDT / 32;
+
+// One LSD pass over digit (k >> shift) & (kRD - 1) of the unit's keys.
+// STR: the keys are in the striped layout (slot j of thread t holds position
+// j * kDT + t) and positions from nn on are not counted; otherwise the
+// layout is t * kDI + j and every slot is counted: slots from nn on hold
+// 0xffffffff, which sorts after every key of the sorted bits (its bits above
+// them are ones) or, where those bits tie, keeps its place after the keys
+// (ties keep their order, and those slots are last).  Leaves the layout
+// t * kDI + j, with 0xffffffff from nn on.
+template <bool STR>
+__device__ __forceinline__ void unit_pass(uint32_t (&k)[kDI], int nn, int shift, bool clear_after, uint32_t *sk,
+                                          uint32_t *cnt, uint32_t *lds_scan) {
+    const int tid = threadIdx.x;
+    const int tword = (tid >> 1) + (tid >> 5);
+    const int tsh = 16 * (tid & 1);
+    // count with LDS atomics that return the old value: the updates of one
+    // thread issue back to back instead of as dependent read-modify-writes (a
+    // thread's counter stays below 2^16)
+    uint16_t loc[kDI];
+#pragma unroll
+    for (int j = 0; j < kDI; ++j) {
+        const int d = (int)((k[j] >> shift) & (kRD - 1));
+        const bool valid = !STR || j * kDT + tid < nn;
+        const uint32_t old = atomicAdd(&cnt[d * kDigitWords + tword], (valid ? 1u : 0u) << tsh);
+        loc[j] = (uint16_t)(old >> tsh);
+    }
+    __syncthreads();
+    // raking exclusive scan over [digit][thread]: thread t owns `per`
+    // consecutive counter words (two 16-bit counters each)
+    constexpr int per = kCntWords / kDT;
+    constexpr int kGrp = 8;
+    static_assert(per % kGrp == 0, "whole groups");
+    uint32_t s = 0;
+#pragma unroll
+    for (int g = 0; g < per; g += kGrp) {
+        uint32_t wv[kGrp];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) s += (wv[i] & 0xffffu) + (wv[i] >> 16);
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
+    // write-back in groups of eight words as well: the group's reads are
+    // issued together, then its writes (one LDS round trip per group)
+#pragma unroll
+    for (int g = 0; g < per; g += kGrp) {
+        uint32_t wv[kGrp];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
+#pragma unroll
+        for (int i = 0; i < kGrp; ++i) {
+            const uint32_t lo = wv[i] & 0xffffu, hi = wv[i] >> 16;
+            const uint32_t q0 = run, q1 = run + lo;
+            run += lo + hi;
+            cnt[cpad(tid * per + g + i)] = (q0 & 0xffffu) | (q1 << 16);
+        }
+    }
+    __syncthreads();
+    // scatter without branches, in groups whose counter reads issue together
+    // (a striped slot past nn writes the last row's pad word, which no key
+    // slot uses)
+    constexpr int kScatGrp = 5;
+    static_assert(kDI % kScatGrp == 0, "whole groups");
+#pragma unroll
+    for (int g = 0; g < kDI; g += kScatGrp) {
+        uint32_t cb[kScatGrp];
+#pragma unroll
+        for (int i = 0; i < kScatGrp; ++i)
+            cb[i] = (cnt[(int)((k[g + i] >> shift) & (kRD - 1)) * kDigitWords + tword] >> tsh) & 0xffffu;
+#pragma unroll
+        for (int i = 0; i < kScatGrp; ++i) {
+            const int j = g + i;
+            const uint32_t dst = cb[i] + loc[j];
+            const int slot = kpad(dst < (uint32_t)kDCap ? (int)dst : 0);
+            sk[(STR && j * kDT + tid >= nn) ? kSkWords - 1 : slot] = k[j];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kDI; ++j) {
+        const uint32_t v = sk[kpad(tid * kDI + j)];
+        k[j] = (STR && tid * kDI + j >= nn) ? 0xffffffffu : v;
+    }
+    if (clear_after)
+        for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
+    __syncthreads();
 }
 
 // Sorts the nn keys in k[] on their low B bits by LSD radix sort in LDS:
 // 5-bit digits, per-thread 16-bit counters updated by LDS atomics, raking
 // scan.  Thread t's slot j holds key t*kDI + j of the current order (valid
-// below nn), or, when `striped`, key j*kDT + t (valid below nn) on entry;
-// every pass leaves the first layout.  Leaves the distinct keys in
-// sk[kpad(0 .. result)), in order.
+// below nn; 0xffffffff from nn on), or, when `striped`, key j*kDT + t (valid
+// below nn) on entry; every pass leaves the first layout.  Leaves the
+// distinct keys in sk[kpad(0 .. result)), in order.
 __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int B, uint32_t *sk, uint32_t *cnt,
                                                 uint32_t *lds_scan, PhaseClock &pc, bool striped = false) {
     const int tid = threadIdx.x;
@@ -189,84 +278,12 @@ __device__ __forceinline__ uint32_t sort_unique(uint32_t (&k)[kDI], int nn, int 
     // for the next (no barrier of their own)
     for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
     __syncthreads();
-    for (int pass = 0; pass < passes; ++pass) {
-        const bool str = striped && pass == 0;
-        const int shift = pass * kRB;
-        // count with LDS atomics that return the old value: the updates of
-        // one thread issue back to back instead of as dependent
-        // read-modify-writes (a thread's counter stays below 2^16)
-        uint16_t loc[kDI];
-#pragma unroll
-        for (int j = 0; j < kDI; ++j) {
-            const int p = str ? j * kDT + tid : tid * kDI + j;
-            const int d = (int)((k[j] >> shift) & (kRD - 1));
-            const int ci = d * kDT + tid;
-            const int sh = 16 * (ci & 1);
-            const uint32_t old = atomicAdd(&cnt[cpad(ci >> 1)], (p < nn ? 1u : 0u) << sh);
-            loc[j] = (uint16_t)(old >> sh);
-        }
-        __syncthreads();
-        // raking exclusive scan over [digit][thread]: thread t owns `per`
-        // consecutive counter words (two 16-bit counters each)
-        constexpr int per = kCntWords / kDT;
-        constexpr int kGrp = 8;
-        static_assert(per % kGrp == 0, "whole groups");
-        uint32_t s = 0;
-#pragma unroll
-        for (int g = 0; g < per; g += kGrp) {
-            uint32_t wv[kGrp];
-#pragma unroll
-            for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
-#pragma unroll
-            for (int i = 0; i < kGrp; ++i) s += (wv[i] & 0xffffu) + (wv[i] >> 16);
-        }
-        uint32_t all;
-        uint32_t run = block_excl_scan<kDT>(s, lds_scan, &all);
-        // write-back in groups of eight words as well: the group's reads are
-        // issued together, then its writes (one LDS round trip per group)
-#pragma unroll
-        for (int g = 0; g < per; g += kGrp) {
-            uint32_t wv[kGrp];
-#pragma unroll
-            for (int i = 0; i < kGrp; ++i) wv[i] = cnt[cpad(tid * per + g + i)];
-#pragma unroll
-            for (int i = 0; i < kGrp; ++i) {
-                const uint32_t lo = wv[i] & 0xffffu, hi = wv[i] >> 16;
-                const uint32_t q0 = run, q1 = run + lo;
-                run += lo + hi;
-                cnt[cpad(tid * per + g + i)] = (q0 & 0xffffu) | (q1 << 16);
-            }
-        }
-        __syncthreads();
-        // scatter without branches, in groups whose counter reads issue
-        // together: a slot past nn writes the last row's pad word, which no
-        // key slot uses
-        constexpr int kScatGrp = 5;
-        static_assert(kDI % kScatGrp == 0, "whole groups");
-#pragma unroll
-        for (int g = 0; g < kDI; g += kScatGrp) {
-            uint32_t cb[kScatGrp];
-#pragma unroll
-            for (int i = 0; i < kScatGrp; ++i) cb[i] = ctr(cnt, (int)((k[g + i] >> shift) & (kRD - 1)), tid);
-#pragma unroll
-            for (int i = 0; i < kScatGrp; ++i) {
-                const int j = g + i;
-                const int p = str ? j * kDT + tid : tid * kDI + j;
-                const uint32_t dst = cb[i] + loc[j];
-                const int slot = p < nn ? kpad(dst < (uint32_t)kDCap ? (int)dst : 0) : kSkWords - 1;
-                sk[slot] = k[j];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kDI; ++j) {
-            const int p = tid * kDI + j;
-            k[j] = p < nn ? sk[kpad(p)] : 0xffffffffu;
-        }
-        if (pass + 1 < passes)
-            for (int i = tid; i < kCntPadded; i += kDT) cnt[i] = 0;
-        __syncthreads();
+    int pass = 0;
+    if (striped) {
+        unit_pass<true>(k, nn, 0, passes > 1, sk, cnt, lds_scan);
+        pass = 1;
     }
+    for (; pass < passes; ++pass) unit_pass<false>(k, nn, pass * kRB, pass + 1 < passes, sk, cnt, lds_scan);
     pc.mark(kPhSort);
     // first of every run of equal keys, compacted into sk in order
     uint32_t flags = 0, mine = 0;
