@@ -16,6 +16,9 @@ witness count, heavy product nonzeros) against the paper's definitions:
   degree indexes, and Algorithm 2's cost-based threshold search (the paper
   prints no numbers for it; tests/test_planner_cpu.py pins it to searches
   worked out by hand).
+* A sampled output-size estimate (a selector input; not in the paper):
+  draws of x values by the splitmix64 generator, exact distinct z per drawn
+  x, scaled to all x.
 
 Readings of the paper where it is ambiguous (y classification shared by both
 relations with the larger degree deciding, light means degree <= threshold,
@@ -346,3 +349,44 @@ def algorithm2(s, cal):
     if not prev < light_only:
         return None, None, light_only, light_only
     return d1, d2, prev, light_only
+
+
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """Steele, Lea and Flood's SplitMix64 output function applied to state
+    x + 0x9e3779b97f4a7c15 (the generator's next value for state x)."""
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def sampled_out_estimate(rx, ry, sz, sy, seed: int, draws: int = 1024):
+    """Sampled |OUT| estimate.  After set semantics and dangling-tuple
+    removal (reduce_two_path), the distinct x values in ascending order are
+    x_0 < ... < x_{n-1}; draw i (0 <= i < k, k = min(draws, n)) picks x of
+    index splitmix64(seed + i) mod n (with replacement); D is the sum over
+    the draws of |{c : exists b, (x, b) in R, (c, b) in S}|.  Returns
+    (D, k, n) and the estimate D n / k."""
+    rx, ry, sz, sy = reduce_two_path(rx, ry, sz, sy)
+    xs = np.unique(rx)
+    n = int(xs.size)
+    if n == 0:
+        return 0, 0, 0, 0.0
+    k = min(int(draws), n)
+    nbr = {}
+    for a, b in zip(rx.tolist(), ry.tolist()):
+        nbr.setdefault(a, []).append(b)
+    zs_of_y = {}
+    for c, b in zip(sz.tolist(), sy.tolist()):
+        zs_of_y.setdefault(b, set()).add(c)
+    D = 0
+    for i in range(k):
+        x = int(xs[splitmix64((seed + i) & MASK64) % n])
+        reach = set()
+        for b in nbr[x]:
+            reach |= zs_of_y[b]
+        D += len(reach)
+    return D, k, n, D * n / k

@@ -571,3 +571,35 @@ def test_bsi_matches_brute_force_and_the_example():
         got = oracle.bsi(rx, ry, sz, sy, tx, tz)
         assert got.tolist() == [(a, b) in ov for a, b in zip(tx.tolist(), tz.tolist())]
     assert oracle.bsi(rx, ry, sz, sy, [], []).size == 0
+
+
+# ---------------------------------------------------------------------------
+# Sampled output-size estimate (a selector input): its generator pinned to
+# SplitMix64's published first outputs, the estimate to a closed form and to
+# the exact |OUT| it approaches over many seeds.
+# ---------------------------------------------------------------------------
+
+def test_splitmix64_reference_outputs():
+    # SplitMix64 seeded with 0: state advances by 0x9e3779b97f4a7c15 per call
+    # (Steele, Lea, Flood; the reference sequence for seed 0)
+    outs = [ref.splitmix64(i * 0x9E3779B97F4A7C15 & ref.MASK64) for i in range(3)]
+    assert outs == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+def test_sampled_estimate_closed_form_on_communities():
+    # c communities of m sets over g elements, each set holding all g: every x
+    # reaches exactly m z, so every draw counts m and the estimate is c m^2
+    c_, m, g = 6, 9, 4
+    xs = np.repeat(np.arange(c_ * m), g)
+    ys = (np.arange(c_ * m)[:, None] // m * g + np.arange(g)[None, :]).ravel()
+    for seed in (0, 7, 123456789):
+        D, k, n, est = ref.sampled_out_estimate(xs, ys, xs, ys, seed)
+        assert (k, n) == (c_ * m, c_ * m) and D == k * m and est == c_ * m * m
+
+
+def test_sampled_estimate_is_unbiased():
+    rx, ry = datagen.zipf_edges(1500, 400, 60, 1.1, 91)
+    sz, sy = datagen.zipf_edges(1500, 400, 60, 1.1, 92)
+    out = oracle.two_path(rx, ry, sz, sy)[0].size
+    ests = [ref.sampled_out_estimate(rx, ry, sz, sy, seed, draws=64)[3] for seed in range(300)]
+    assert abs(np.mean(ests) / out - 1) < 0.03
