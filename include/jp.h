@@ -98,7 +98,8 @@ typedef struct jp_options {
     uint64_t flags;     /* JP_FLAG_* */
 } jp_options;
 
-#define JP_FLAG_TIMING 1ull /* record per-phase device times (HIP events) */
+#define JP_FLAG_TIMING 1ull      /* record per-phase device times (HIP events) */
+#define JP_FLAG_SAMPLED_OUT 2ull /* compute the sampled output-size estimate (always done for AUTO_MLP) */
 
 /* Statistics of one evaluation.  Sizes refer to the relations after duplicate
  * removal and after dropping tuples whose y appears in only one relation. */
@@ -128,6 +129,11 @@ typedef struct jp_stats {
     double ms_kernel_dedup;      /* per-x duplicate-removal kernel alone (segmented strategy) */
     double dedup_alg_bytes;      /* its algorithmic HBM bytes: 4 per witness read + 4 per distinct pair key written */
     int64_t dedup_units;         /* on-chip units it processed */
+    double out_est;              /* Section 5 output-size estimate */
+    double out_sampled;          /* sampled estimate (0 when not computed): with k = sample_draws x ranks drawn
+                                    as splitmix64(seed + i) mod dom_x, i < k, and D = sample_distinct the sum of
+                                    the distinct z each reaches, D * dom_x / k */
+    int64_t sample_draws, sample_distinct;
 } jp_stats;
 
 typedef struct jp_handle jp_handle;

@@ -39,6 +39,7 @@ DEDUP = {"auto": 0, "global": 1, "segmented": 2}
 STATUS = {0: "JP_OK", 1: "JP_EINVAL", 2: "JP_ENOMEM", 3: "JP_EHIP", 4: "JP_ECAPACITY",
           5: "JP_EPRECISION", 6: "JP_EINTERNAL"}
 FLAG_TIMING = 1
+FLAG_SAMPLED_OUT = 2
 
 
 class JoinProjectError(RuntimeError):
@@ -60,7 +61,8 @@ class Stats(ctypes.Structure):
                [(n, ctypes.c_double) for n in ("bmm_ops", "ms_ingest", "ms_plan", "ms_light", "ms_heavy",
                                                "ms_bmm", "ms_dedup", "ms_total", "ms_kernel_dedup",
                                                "dedup_alg_bytes")] + \
-               [("dedup_units", ctypes.c_int64)]
+               [("dedup_units", ctypes.c_int64), ("out_est", ctypes.c_double), ("out_sampled", ctypes.c_double),
+                ("sample_draws", ctypes.c_int64), ("sample_distinct", ctypes.c_int64)]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}
@@ -442,7 +444,7 @@ class Handle:
         s = torch.cuda.current_stream(self.device)
         self._check(_load().jp_set_stream(self._p, ctypes.c_void_p(s.cuda_stream)))
 
-    def _options(self, delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed):
+    def _options(self, delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed, sampled_out=False):
         o = Options()
         _load().jp_default_options(ctypes.byref(o))
         if delta1 is not None or delta2 is not None or strategy == "fixed":
@@ -457,16 +459,16 @@ class Handle:
         o.dedup = DEDUP[dedup]
         if seed is not None:
             o.seed = seed
-        o.flags = FLAG_TIMING if timing else 0
+        o.flags = (FLAG_TIMING if timing else 0) | (FLAG_SAMPLED_OUT if sampled_out else 0)
         return o
 
     def two_path_result(self, rx, ry, sz, sy, delta1=None, delta2=None, strategy=None, bmm="auto",
-                        y_rule="max", dedup="auto", timing=False, seed=None) -> Result:
+                        y_rule="max", dedup="auto", timing=False, seed=None, sampled_out=False) -> Result:
         rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
         if rx.numel() != ry.numel() or sz.numel() != sy.numel():
             raise ValueError("column lengths differ")
         self._bind_stream()
-        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed)
+        o = self._options(delta1, delta2, strategy, bmm, y_rule, dedup, timing, seed, sampled_out)
         out = ctypes.c_void_p()
         self._check(_load().jp_two_path(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy), sz.numel(),
                                         ctypes.byref(o), ctypes.byref(out)))
@@ -681,11 +683,11 @@ class Handle:
         self._check(_load().jp_get_calibration(self._p, ctypes.byref(c)))
         return c.as_dict()
 
-    def plan_two_path(self, rx, ry, sz, sy, strategy="auto", y_rule="max"):
+    def plan_two_path(self, rx, ry, sz, sy, strategy="auto", y_rule="max", seed=None):
         """Thresholds the optimizer picks (None = infinity) and the 16 selector features."""
         rx, ry, sz, sy = (_col(t, n) for t, n in ((rx, "r_x"), (ry, "r_y"), (sz, "s_z"), (sy, "s_y")))
         self._bind_stream()
-        o = self._options(None, None, strategy, "auto", y_rule, "auto", False, None)
+        o = self._options(None, None, strategy, "auto", y_rule, "auto", False, seed)
         d1, d2 = ctypes.c_int64(), ctypes.c_int64()
         f = (ctypes.c_float * 16)()
         self._check(_load().jp_plan_two_path(self._p, _ptr(rx), _ptr(ry), rx.numel(), _ptr(sz), _ptr(sy),

@@ -37,7 +37,9 @@ struct TwoPathSummary {
     int64_t n_r = 0, n_s = 0, dom_x = 0, dom_y = 0, dom_z = 0;
     int64_t J = 0;
     bool self_join = false;
-    double out_est = 0;   // output-size estimate
+    double out_est = 0;   // output-size estimate (Section 5)
+    double out_sampled = 0;  // sampled estimate (selector input); 0 when not computed
+    int64_t sample_distinct = 0, sample_draws = 0;
     bool have_indexes = false;
     HostIndex y;          // key degree of y; sum = deg_R(y) deg_S(y)
     HostIndex x;          // deg_R(x); sum = witnesses of x
@@ -125,6 +127,14 @@ struct Ingest {
 
 // Builds the Section 5 degree indexes of an indexed instance (summary.hip).
 void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummary &s);
+
+// Sampled output size of an indexed instance (summary.hip): the distinct z
+// reached by `draws` x ranks drawn with splitmix64 from `seed` (see there).
+struct SampledOut {
+    int64_t distinct = 0, draws = 0;
+};
+SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max_draws = 1024,
+                       int64_t cap = int64_t(1) << 26);
 
 // Set similarity output of a two-path instance (Section 2.1): pairs whose
 // sets share at least min_c elements, with the overlap as a third column;

@@ -222,7 +222,7 @@ void features16(const TwoPathSummary &s, float *f) {
     const jp_degree_index yr = s.yr.view(), ys = s.ys.view();
     f[0] = (float)std::log((double)std::max<int64_t>(s.n_r, 1));
     f[1] = (float)std::log((double)std::max<int64_t>(s.n_s, 1));
-    f[2] = (float)std::log(1.0 + s.out_est);
+    f[2] = (float)std::log(1.0 + (s.out_sampled > 0 ? s.out_sampled : s.out_est));
     const double qs[5] = {0.5, 0.9, 0.99, 0.999, 1.0};
     for (int i = 0; i < 5; ++i) {
         f[3 + i] = (float)std::log(1.0 + quantile(yr, qs[i]));

@@ -308,4 +308,103 @@ void summarize_two_path(const Ctx &c, const Ingest &g, int y_rule, TwoPathSummar
     }
 }
 
+// ---- sampled output size ---------------------------------------------------
+// A selector input (not part of the paper's method): k = min(draws, dom_x)
+// draws of an x rank, draw i taking rank splitmix64(seed + i) mod dom_x (x
+// ranks follow x values, so rank r is the r-th smallest x kept), and the
+// exact number of distinct z each drawn x reaches, summed over the draws.
+// The draws' candidate z are gathered as (draw, z) keys, sorted and counted
+// distinct.  A prefix of the draws whose candidates exceed `cap` is dropped
+// (at least one draw is kept; if that alone exceeds 4 cap, nothing is
+// counted and draws = 0).
+
+__device__ __forceinline__ uint64_t splitmix64_next(uint64_t x) {
+    uint64_t z = x + 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max_draws, int64_t cap) {
+    SampledOut r;
+    const int64_t n = g.dom_x;
+    if (n <= 0 || max_draws <= 0) return r;
+    int64_t k = std::min(max_draws, n);
+    DBuf<int32_t> xr = c.buf<int32_t>((size_t)k);
+    DBuf<int64_t> cnt = c.buf<int64_t>((size_t)k), coff = c.buf<int64_t>((size_t)k + 1);
+    DBuf<int64_t> tcnt = c.buf<int64_t>((size_t)k), toff = c.buf<int64_t>((size_t)k + 1);
+    {
+        int32_t *x = xr.get();
+        int64_t *ct = cnt.get(), *tc = tcnt.get();
+        const int64_t *ox = g.off_x.get(), *oy = g.off_y.get();
+        const int32_t *ar = g.adj_r.get();
+        const uint64_t sd = seed;
+        for_each(c, k, [=] __device__(int64_t i) {
+            const int32_t xi = (int32_t)(splitmix64_next(sd + (uint64_t)i) % (uint64_t)n);
+            x[i] = xi;
+            int64_t t = 0;
+            for (int64_t e = ox[xi]; e < ox[xi + 1]; ++e) t += oy[ar[e] + 1] - oy[ar[e]];
+            ct[i] = t;
+            tc[i] = ox[xi + 1] - ox[xi];
+        });
+        scan_exclusive(c, k, ArrayGet{ct}, ArrayPut{coff.get()}, coff.get() + k);
+    }
+    std::vector<int64_t> hoff((size_t)k + 1);
+    c.load_n(hoff.data(), coff.get(), hoff.size());
+    if (hoff[k] > cap) {  // keep the longest prefix of draws within the cap
+        int64_t kk = (int64_t)(std::upper_bound(hoff.begin(), hoff.end(), cap) - hoff.begin()) - 1;
+        kk = std::max<int64_t>(kk, 1);
+        if (hoff[kk] > 4 * cap) return r;
+        k = kk;
+    }
+    const int64_t T = hoff[k];
+    r.draws = k;
+    if (T == 0) return r;
+    // (draw, tuple) pairs, then candidates by pair
+    scan_exclusive(c, k, ArrayGet{tcnt.get()}, ArrayPut{toff.get()}, toff.get() + k);
+    const int64_t P = c.load(toff.get() + k);
+    DBuf<int32_t> pdraw = c.buf<int32_t>((size_t)P);
+    DBuf<int64_t> ptup = c.buf<int64_t>((size_t)P), poff = c.buf<int64_t>((size_t)P + 1);
+    {
+        const int32_t *x = xr.get();
+        const int64_t *to = toff.get(), *ox = g.off_x.get();
+        int32_t *pd = pdraw.get();
+        int64_t *pt = ptup.get();
+        const int64_t kd = k;
+        for_each(c, P, [=] __device__(int64_t p) {
+            const int64_t i = upper_bound_dev(to, (int64_t)0, kd, p) - 1;
+            pd[p] = (int32_t)i;
+            pt[p] = ox[x[i]] + (p - to[i]);
+        });
+        const int64_t *oy = g.off_y.get();
+        const int32_t *ar = g.adj_r.get();
+        const int64_t *ptc = pt;
+        scan_exclusive(
+            c, P, [=] __device__(int64_t p) -> int64_t { return oy[ar[ptc[p]] + 1] - oy[ar[ptc[p]]]; },
+            ArrayPut{poff.get()}, poff.get() + P);
+    }
+    const int bz = bits_for((uint64_t)std::max<int64_t>(g.dom_z - 1, 1));
+    const int bd = bits_for((uint64_t)std::max<int64_t>(k - 1, 1));
+    DBuf<uint64_t> keys = c.buf<uint64_t>((size_t)T), tmp = c.buf<uint64_t>((size_t)T);
+    {
+        const int64_t *po = poff.get(), *pt = ptup.get(), *oy = g.off_y.get();
+        const int32_t *pd = pdraw.get(), *ar = g.adj_r.get(), *as = g.adj_s.get();
+        uint64_t *ky = keys.get();
+        const int64_t np = P;
+        const int bzs = bz;
+        for_each(c, T, [=] __device__(int64_t o) {
+            const int64_t p = upper_bound_dev(po, (int64_t)0, np, o) - 1;
+            const int64_t z = as[oy[ar[pt[p]]] + (o - po[p])];
+            ky[o] = ((uint64_t)pd[p] << bzs) | (uint64_t)z;
+        });
+    }
+    const uint64_t *sk = radix_sort(c, keys.get(), tmp.get(), T, bd + bz);
+    DBuf<int64_t> nd = c.buf<int64_t>(1);
+    compact(
+        c, T, [=] __device__(int64_t i) { return i == 0 || sk[i] != sk[i > 0 ? i - 1 : 0]; },
+        [=] __device__(int64_t, int64_t) {}, nd.get());
+    r.distinct = c.load(nd.get());
+    return r;
+}
+
 }  // namespace jp

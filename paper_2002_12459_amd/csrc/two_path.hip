@@ -795,6 +795,16 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     sum.out_est = estimate_out(dom_x, dom_z, J, std::max(n_r2, n_s2));
     if (o.strategy == JP_STRATEGY_AUTO_COST || o.strategy == JP_STRATEGY_AUTO_MLP)
         summarize_two_path(c, g, o.y_rule, sum);
+    if (o.strategy == JP_STRATEGY_AUTO_MLP || (o.flags & JP_FLAG_SAMPLED_OUT)) {
+        const SampledOut so = sampled_out(c, g, o.seed);
+        sum.sample_draws = so.draws;
+        sum.sample_distinct = so.distinct;
+        if (so.draws > 0) sum.out_sampled = (double)so.distinct * (double)dom_x / (double)so.draws;
+    }
+    st.out_est = sum.out_est;
+    st.out_sampled = sum.out_sampled;
+    st.sample_draws = sum.sample_draws;
+    st.sample_distinct = sum.sample_distinct;
     Thresholds th = select_thresholds(c, sum, o);
     st.delta1 = th.d1;
     st.delta2 = th.d2;
@@ -1232,6 +1242,10 @@ static bool summary_of(const Ctx &c, const int32_t *rx, const int32_t *ry, int64
     sum.self_join = (rx == sz && ry == sy && nr == ns);
     sum.out_est = estimate_out(g.dom_x, g.dom_z, g.J, std::max(g.n_r2, g.n_s2));
     summarize_two_path(c, g, o.y_rule, sum);
+    const SampledOut so = sampled_out(c, g, o.seed);
+    sum.sample_draws = so.draws;
+    sum.sample_distinct = so.distinct;
+    if (so.draws > 0) sum.out_sampled = (double)so.distinct * (double)g.dom_x / (double)so.draws;
     return true;
 }
 

@@ -65,8 +65,8 @@ def test_struct_layouts_match_header():
     import paper_2002_12459_amd as jp
     # jp_options: 2 x int64 + 4 x int32 + 2 x uint64
     assert ctypes.sizeof(jp.Options) == 48
-    # jp_stats: 7 int64, 4 int32, 8 int64, 10 double, 1 int64
-    assert ctypes.sizeof(jp.Stats) == 7 * 8 + 4 * 4 + 8 * 8 + 10 * 8 + 8
+    # jp_stats: 7 int64, 4 int32, 8 int64, 10 double, 1 int64, 2 double, 2 int64
+    assert ctypes.sizeof(jp.Stats) == 7 * 8 + 4 * 4 + 8 * 8 + 10 * 8 + 8 + 2 * 8 + 2 * 8
 
 
 def test_lookback_wait_hook_rejects_a_null_handle(lib):

@@ -329,3 +329,16 @@ def test_self_join_symmetric_product_many_tiles(jp):
     # the same relation passed as two different column pairs: no symmetry assumed
     st2 = check_equal(jp, x, y, x.copy(), y.copy(), delta1=10, delta2=10, bmm="i8_t256")
     assert st2["nnz_heavy"] == st["nnz_heavy"]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**63 + 5])
+def test_sampled_out_estimate_matches_the_restatement(jp, seed):
+    """The sampled output-size estimate (a selector input): the same draws of
+    x and the same exact distinct counts as the numpy restatement."""
+    cases = [datagen.zipf_edges(20_000, 3_000, 500, 1.2, 61) + datagen.zipf_edges(20_000, 3_000, 500, 1.2, 62),
+             datagen.random_small(600, 300, 40, seed=63, dup=True, signed=True) * 2]
+    for rx, ry, sz, sy in cases:
+        D, k, n, est = ref.sampled_out_estimate(rx, ry, sz, sy, seed)
+        x, z, st = run(jp, rx, ry, sz, sy, strategy="light", seed=seed, sampled_out=True)
+        assert (st["sample_distinct"], st["sample_draws"], st["dom_x"]) == (D, k, n)
+        assert st["out_sampled"] == pytest.approx(est, rel=1e-12)
