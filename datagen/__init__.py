@@ -36,6 +36,7 @@ __all__ = [
     "batch_instance",
     "selector_instance",
     "selector_instance_clustered",
+    "selector_instance_dense",
 ]
 
 
@@ -301,3 +302,45 @@ def selector_instance_clustered(i: int, lo: float = 1e5, hi: float = 1e7, seed0:
     sz = np.concatenate([dz, wz + ox]).astype(np.int32)
     sy = np.concatenate([dy, wy + oy]).astype(np.int32)
     return (rx, ry), (sz, sy), {"e": e, "f": f, "c": c, "m": m, "g": g, "p": p, "s": s}
+
+
+def selector_instance_dense(i: int, lo: float = 1e5, hi: float = 2e7, seed0: int = 50_000, jmax: float = 3e9):
+    """Instance i of the dense selector set: few large dense communities, the
+    shape of the paper's dense datasets and of Example 1, where a pair of
+    sets shares many elements (the case the matrix product serves).
+
+    |R| = |S| ~ E log-uniform in [lo, hi].  A fraction f ~ U[0.7, 1.0] of the
+    edges forms c ~ U{1..8} communities with edge probability p ~ U[0.1, 0.5]
+    and g = r / p^2 y-ids, where r ~ log-uniform [4, 128] is about the number
+    of elements two sets of a community share; each community has
+    m = f E p / (c r) x-ids (at least 2; fewer when the join size
+    f E m p would exceed jmax).  S uses the same y blocks with its own z
+    blocks and draws.  The rest is a Zipf part as in ``selector_instance``
+    on ids above the communities'.  Returns ((rx, ry), (sz, sy), params).
+    """
+    rng = np.random.default_rng(seed0 + i)
+    e = int(round(float(np.exp(rng.uniform(np.log(lo), np.log(hi))))))
+    f = float(rng.uniform(0.7, 1.0))
+    c = int(rng.integers(1, 9))
+    p = float(rng.uniform(0.1, 0.5))
+    r = float(np.exp(rng.uniform(np.log(4.0), np.log(128.0))))
+    g = max(2, int(round(r / (p * p))))
+    m = max(2, int(round(f * e / (c * g * p))))
+    m = max(2, min(m, int(jmax / max(f * e * p, 1.0))))
+    s = float(rng.uniform(0.5, 1.8))
+    sub = int(rng.integers(0, 2**31 - 1))
+    cx, cy = communities(c, m, g, p, seed=sub)
+    dz, dy = communities(c, m, g, p, seed=sub + 1)
+    es = max(1, e - cx.size)
+    nx = max(2, -(-es // 10))
+    ny = max(2, -(-es // 50))
+    es = min(es, nx * ny // 2)
+    (zx, zy) = zipf_edges(es, nx, ny, s, seed=sub + 2)
+    (wz, wy) = zipf_edges(es, nx, ny, s, seed=sub + 3)
+    ox, oy = c * m, c * g
+    rx = np.concatenate([cx, zx + ox]).astype(np.int32)
+    ry = np.concatenate([cy, zy + oy]).astype(np.int32)
+    sz = np.concatenate([dz, wz + ox]).astype(np.int32)
+    sy = np.concatenate([dy, wy + oy]).astype(np.int32)
+    return (rx, ry), (sz, sy), {"e": e, "f": f, "c": c, "m": m, "g": g, "p": p, "r": r, "s": s}
+

@@ -14,12 +14,15 @@ Algorithm 2 (Section 5), which stays the fallback.
     python -m paper_2002_12459_amd.selector train --data sweep*.jsonl --holdout-from 1000 \\
         --out selector_mi355x.json --report report.json
 
-Instances: two families, each indexed from 0.  "zipf":
+Instances: three families, each indexed from 0.  "zipf":
 ``datagen.selector_instance`` (|R| = |S| log-uniform, Zipf y degrees with
 exponent U[0.5, 1.8], x / y domains |R|/10 and |R|/50; the output is close to
 the join size, few duplicates).  "clustered":
 ``datagen.selector_instance_clustered`` (dense communities, as in the
-paper's Example 1, plus a Zipf part; many duplicate witnesses).
+paper's Example 1, plus a Zipf part; many duplicate witnesses).  "dense":
+``datagen.selector_instance_dense`` (a few large dense communities whose
+sets share tens to about a hundred elements: the shape of the paper's
+dense datasets, where the product pays).
 Instances whose full join J = sum_y deg_R(y) deg_S(y) exceeds ``--jmax`` are
 recorded as rejected and not timed: their run time is dominated by writing an
 output close to |dom x| |dom z| pairs whatever the thresholds.
@@ -54,6 +57,9 @@ def _generate(i, family, lo, hi, jmax):
     import datagen
     if family == "clustered":
         (rx, ry), (sz, sy), prm = datagen.selector_instance_clustered(i, lo=lo, hi=hi)
+        s = prm["s"]
+    elif family == "dense":
+        (rx, ry), (sz, sy), prm = datagen.selector_instance_dense(i, lo=lo, hi=hi, jmax=jmax)
         s = prm["s"]
     else:
         (rx, ry), (sz, sy), s = datagen.selector_instance(i, lo=lo, hi=hi)
@@ -99,7 +105,7 @@ def sweep(args):
 
     import paper_2002_12459_amd as jp
 
-    h = jp.Handle(0, selector=None)
+    h = jp.Handle(0, selector=None, allocator="builtin")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
     t_start = time.perf_counter()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
@@ -246,7 +252,7 @@ def train(args):
         with gzip.open(args.table_out, "wt") as fh:
             for r in recs:
                 fh.write(json.dumps({k: r.get(k, "zipf" if k == "family" else None) for k in keep}) + "\n")
-    hold = {"zipf": args.holdout_from, "clustered": args.holdout_from_clustered}
+    hold = {"zipf": args.holdout_from, "clustered": args.holdout_from_clustered, "dense": args.holdout_from_dense}
     tr = [r for r in recs if r["i"] < hold[_key(r)[0]]]
     te = [r for r in recs if r["i"] >= hold[_key(r)[0]]]
     every = max(2, int(round(1.0 / args.val_frac)))  # every k-th training instance validates
@@ -293,30 +299,16 @@ def train(args):
                 best_val, best_p = vr, p.clone()
     t_train = time.perf_counter() - t0
 
-    # Margin toward light only: a grid cell is picked only when its predicted
-    # log ratio beats light only by more than m.  m is chosen on the
-    # validation instances and folded into the output biases, so the library's
-    # argmin applies it.
-    nb3 = N_CELLS
-    yv = h.mlp_forward(best_p, xv).cpu().numpy()
-    margins = [0.0, 0.01, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0, 2.0]
-    scores = []
-    for m in margins:
-        ks = (yv + np.where(np.arange(nb3) < 64, m, 0.0)).argmin(axis=1)
-        scores.append(float(np.exp(np.mean([math.log(regret(r, int(k), args.skip_ratio)) for r, k in zip(val, ks)]))))
-    m_best = margins[int(np.argmin(scores))]
-    print(f"[train] light-only margin {m_best} (validation geo-regret {min(scores):.4f})", flush=True)
-    best_p[-nb3:-1] += m_best
     params = best_p.cpu().numpy().astype(np.float64)
     with open(args.out, "w") as fh:
         json.dump({"n_out": N_CELLS, "params": [float(x) for x in params], "mean": [float(x) for x in mean],
                    "scale": [float(x) for x in scale],
                    "meta": {"n_fit": len(fit), "n_val": len(val), "steps": args.steps, "lr": args.lr,
                             "skip_ratio": args.skip_ratio, "val_regret": best_val, "seed": args.seed,
-                            "light_margin": m_best, "val_regret_with_margin": min(scores),
                             "weighted": bool(args.weighted),
                             "holdout_from": args.holdout_from,
-                            "holdout_from_clustered": args.holdout_from_clustered}}, fh)
+                            "holdout_from_clustered": args.holdout_from_clustered,
+                            "holdout_from_dense": args.holdout_from_dense}}, fh)
     report = {"train_seconds": t_train, "log": log, "val_regret": best_val}
     if te:
         xt = norm(te)
@@ -349,7 +341,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2002_12459_amd.selector")
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("sweep")
-    a.add_argument("--family", choices=["zipf", "clustered"], default="zipf")
+    a.add_argument("--family", choices=["zipf", "clustered", "dense"], default="zipf")
     a.add_argument("--first", type=int, default=0)
     a.add_argument("--count", type=int, default=100)
     a.add_argument("--out", required=True)
@@ -367,6 +359,7 @@ def main(argv=None):
     b.add_argument("--data", nargs="+", required=True)
     b.add_argument("--holdout-from", type=int, default=1000, help="first held-out zipf instance")
     b.add_argument("--holdout-from-clustered", type=int, default=450, help="first held-out clustered instance")
+    b.add_argument("--holdout-from-dense", type=int, default=200, help="first held-out dense instance")
     b.add_argument("--val-frac", type=float, default=0.1)
     b.add_argument("--steps", type=int, default=4000)
     b.add_argument("--lr", type=float, default=3e-3)
