@@ -153,6 +153,10 @@ typedef struct jp_calibration {
     int32_t n_mm;      /* entries of the product time table */
     double mm_p[24];   /* table of M-hat(p, p, p): cube sizes p ... */
     double mm_s[24];   /* ... and measured seconds */
+    int32_t light_once; /* 1: each light witness is priced once: T_I (sum(y_D1) + sum(x_D2) (1 - sum(y_D1) / J)),
+                           the witnesses of light x at light y taken out of sum(x_D2) under independent
+                           x and y degree classes, and a plan without a product priced at J witnesses;
+                           0: T_I (sum(y_D1) + sum(x_D2)) as printed */
 } jp_calibration;
 
 /* Sorted degree vector with per-degree count and summed work: the indexes of

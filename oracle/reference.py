@@ -296,8 +296,17 @@ def algorithm2(s, cal):
     the largest key degree; the search stops when the cost does not decrease
     (literal) or strictly increases; the light cost is
       T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
-    and the heavy cost M-hat(u,v,w) + T_m (u v + w v); the result is the plain
-    join when J <= 20 N or when no candidate beats it.
+    and the heavy cost M-hat(u,v,w) + T_m (u v + w v), M-hat taken from the
+    nearest cube of the table scaled by u v w / p^3, or the smallest cube's
+    time when p is below it; the result is the plain
+    join when J <= 20 N or when no candidate beats it.  With light_once (a
+    reading of Section 5's sum indexes as counts of work done once per light
+    witness) the light-x term becomes sum(x_D2) (1 - sum(y_D1) / J): the
+    witnesses of light x at light y, already counted in sum(y_D1), are taken
+    out in the proportion they would have if x and y degree classes were
+    independent, and a plan without a product is priced at all J witnesses
+    (nothing leaves the light side).  A missing light_once means 0 (the
+    printed sum).
     Returns (delta1, delta2, cost, cost_light_only); None stands for infinity.
     """
     N = max(s["n_r"], s["n_s"])
@@ -307,6 +316,9 @@ def algorithm2(s, cal):
         if min(u, v, w) <= 0:
             return 0.0
         p = (u * v * w) ** (1.0 / 3.0)
+        j = int(np.argmin(cal["mm_p"]))
+        if p <= cal["mm_p"][j]:  # below the smallest measured cube: its time
+            return cal["mm_s"][j]
         i = int(np.argmin([abs(q - p) for q in cal["mm_p"]]))
         return cal["mm_s"][i] * (u * v * w) / cal["mm_p"][i] ** 3
 
@@ -315,8 +327,14 @@ def algorithm2(s, cal):
         cx, sx_ = _le(s["x"], d2)
         cc, _ = _le(s["xcdf"], d1)
         cz, _ = _le(s["z"], d2)
-        light = cal["t_witness"] * (sy_ + sx_) + cal["t_x"] * s["dom_x"] + cal["t_seq"] * cc * s["dom_x"]
         u, v, w = s["dom_x"] - cx, s["dom_y"] - cy, s["dom_z"] - cz
+        wit = sy_ + sx_
+        if cal.get("light_once", 0) and s["J"] > 0:
+            if u > 0 and v > 0 and w > 0:
+                wit = sy_ + sx_ * max(0.0, 1.0 - sy_ / s["J"])
+            else:  # no product: every witness stays light
+                wit = float(s["J"])
+        light = cal["t_witness"] * wit + cal["t_x"] * s["dom_x"] + cal["t_seq"] * cc * s["dom_x"]
         heavy = 0.0
         if u > 0 and v > 0 and w > 0:
             heavy = mm_hat(u, v, w) + cal["t_byte"] * (u * v + w * v)

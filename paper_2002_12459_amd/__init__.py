@@ -71,12 +71,13 @@ class Stats(ctypes.Structure):
 class Calibration(ctypes.Structure):
     _fields_ = [("t_witness", ctypes.c_double), ("t_seq", ctypes.c_double), ("t_byte", ctypes.c_double),
                 ("t_x", ctypes.c_double), ("eps", ctypes.c_double), ("literal", ctypes.c_int32),
-                ("n_mm", ctypes.c_int32), ("mm_p", ctypes.c_double * 24), ("mm_s", ctypes.c_double * 24)]
+                ("n_mm", ctypes.c_int32), ("mm_p", ctypes.c_double * 24), ("mm_s", ctypes.c_double * 24),
+                ("light_once", ctypes.c_int32)]
 
     def as_dict(self):
         return {"t_witness": self.t_witness, "t_seq": self.t_seq, "t_byte": self.t_byte, "t_x": self.t_x,
                 "eps": self.eps, "literal": self.literal, "mm_p": list(self.mm_p[: self.n_mm]),
-                "mm_s": list(self.mm_s[: self.n_mm])}
+                "mm_s": list(self.mm_s[: self.n_mm]), "light_once": self.light_once}
 
     @classmethod
     def from_dict(cls, d):
@@ -84,6 +85,7 @@ class Calibration(ctypes.Structure):
         for k in ("t_witness", "t_seq", "t_byte", "t_x", "eps"):
             setattr(c, k, float(d[k]))
         c.literal = int(d.get("literal", 0))
+        c.light_once = int(d.get("light_once", 0))
         c.n_mm = len(d["mm_p"])
         for i, (a, b) in enumerate(zip(d["mm_p"], d["mm_s"])):
             c.mm_p[i] = a

@@ -62,6 +62,7 @@ void default_calibration(jp_calibration *c) {
     c->t_x = 4.1686e-09;
     c->eps = 0.05;
     c->literal = 0;
+    c->light_once = 1;
     const double p[] = {1024, 2048, 4096, 8192, 12288, 16384, 20480};
     const double s[] = {2.4956e-05, 4.1555e-05, 1.3162e-04, 7.0919e-04, 2.2700e-03, 4.9962e-03, 9.9194e-03};
     c->n_mm = (int32_t)(sizeof(p) / sizeof(p[0]));
@@ -94,13 +95,18 @@ struct Index {
     int64_t max_deg() const { return n ? deg[n - 1] : 0; }
 };
 
-// M-hat(u, v, w): time of the nearest measured cube, scaled by u v w / p^3.
+// M-hat(u, v, w): time of the nearest measured cube, scaled by u v w / p^3;
+// below the smallest cube, that cube's time (a product launch costs at least
+// what the smallest measured one does: its tiles do not fill the GPU).
 double mm_hat(const jp_calibration &c, double u, double v, double w) {
     if (u <= 0 || v <= 0 || w <= 0 || c.n_mm <= 0) return 0.0;
     const double p = std::cbrt(u * v * w);
-    int best = 0;
-    for (int i = 1; i < c.n_mm; ++i)
+    int best = 0, small = 0;
+    for (int i = 1; i < c.n_mm; ++i) {
         if (std::fabs(c.mm_p[i] - p) < std::fabs(c.mm_p[best] - p)) best = i;
+        if (c.mm_p[i] < c.mm_p[small]) small = i;
+    }
+    if (p <= c.mm_p[small]) return c.mm_s[small];
     const double pb = c.mm_p[best];
     return c.mm_s[best] * (u * v * w) / (pb * pb * pb);
 }
@@ -113,11 +119,18 @@ struct CostModel {
     CostModel(const jp_two_path_summary &s_, const jp_calibration &c_)
         : s(s_), c(c_), Y(s_.y), X(s_.x), XC(s_.xcdf), Z(s_.z) {}
     double operator()(int64_t d1, int64_t d2, int64_t *uvw = nullptr) const {
-        // light: T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
-        const double light = c.t_witness * (Y.sum_le(d1) + X.sum_le(d2)) + c.t_x * (double)s.dom_x +
+        const int64_t u = s.dom_x - X.count_le(d2), v = s.dom_y - Y.count_le(d1), w = s.dom_z - Z.count_le(d2);
+        // light: T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|; with
+        // light_once the witnesses of light x at light y (already in sum(y_D1)) are taken
+        // out of sum(x_D2), estimated as sum(x_D2) sum(y_D1) / J, and a plan without a
+        // product leaves all J witnesses to the light side
+        const double sy = Y.sum_le(d1), sx = X.sum_le(d2);
+        double wit = sy + sx;
+        if (c.light_once && s.J > 0)
+            wit = (u > 0 && v > 0 && w > 0) ? sy + sx * std::max(0.0, 1.0 - sy / (double)s.J) : (double)s.J;
+        const double light = c.t_witness * wit + c.t_x * (double)s.dom_x +
                              c.t_seq * (double)XC.count_le(d1) * (double)s.dom_x;
         // heavy: M-hat(u, v, w) + allocation of the heavy matrices
-        const int64_t u = s.dom_x - X.count_le(d2), v = s.dom_y - Y.count_le(d1), w = s.dom_z - Z.count_le(d2);
         if (uvw) {
             uvw[0] = u;
             uvw[1] = v;

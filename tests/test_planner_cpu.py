@@ -16,6 +16,7 @@ def cals():
     yield base
     lit = dict(base, literal=1)
     yield lit
+    yield dict(base, light_once=0)
     cheap_mm = dict(base, mm_s=[s * 1e-3 for s in base["mm_s"]], t_byte=0.0)
     yield cheap_mm
     dear_mm = dict(base, mm_s=[s * 1e6 for s in base["mm_s"]])
@@ -113,6 +114,47 @@ def test_algorithm2_hand_worked_search(impl):
         d1, d2, c, clo = plan(s, _hand_cal(literal))
         assert (d1, d2) == want, (literal, d1, d2)
         assert c == pytest.approx(212.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_light_once(impl):
+    """The light-x term counted once.  J = 5000; key degrees 2 (x3, sum 12)
+    and 50 (x2, sum 4988); nine x of degree 1 (4900 witnesses) and one of
+    degree 30 (100 witnesses), z alike; T_I = 1, product u v w.
+
+    Printed sum (light_once 0): light only 5000 + 5000 = 10000; (50, 5)
+    5000 + 4900 = 9900; (25, 2) 12 + 4900 + product 1*2*1 = 4914, the same
+    to (3, 1); (1, 1) 0 + 4900 + 1*5*1 = 4905, lower again, and the search
+    ends there: (1, 1).
+    Counted once: light only 5000 + 5000 (1 - 1) = 5000; (50, 5) 5000 +
+    4900 * 0 = 5000; (25, 2) 12 + 4900 (1 - 12/5000) + 2 = 4902.24, the same
+    to (3, 1); (1, 1) 0 + 4900 + 5 = 4905 is higher: stop at (3, 1)."""
+    i64 = lambda *v: np.array(v, dtype=np.int64)
+    f64 = lambda *v: np.array(v, dtype=np.float64)
+    s = dict(_hand_summary(), y=(i64(2, 50), i64(3, 2), f64(12.0, 4988.0)),
+             x=(i64(1, 30), i64(9, 1), f64(4900.0, 100.0)), z=(i64(1, 30), i64(9, 1), None))
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    d1, d2, c, clo = plan(s, dict(_hand_cal(0), light_once=0))
+    assert (d1, d2) == (1, 1)
+    assert c == pytest.approx(4905.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
+    d1, d2, c, clo = plan(s, dict(_hand_cal(0), light_once=1))
+    assert (d1, d2) == (3, 1)
+    assert c == pytest.approx(4902.24, rel=1e-12) and clo == pytest.approx(5000.0, rel=1e-12)
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_product_floor(impl):
+    """A product below the table's smallest cube costs that cube's time.
+    Table: one cube p = 10 at 1000.  (50, 5): 5600, no product.  (25, 2):
+    u v w = 200, p = 5.8 < 10, so 12 + 1000 = 1012 (scaled, it would be
+    12 + 1000 * 200 / 1000 = 212); the same to (3, 1); (1, 1): u v w = 500,
+    p = 7.9, 0 + 1000 = 1000, lower: the search ends at (1, 1).  Scaled
+    down, (1, 1) would cost 500 > 212 and the search would stop at (3, 1)."""
+    s = _hand_summary()
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    d1, d2, c, clo = plan(s, dict(_hand_cal(0), mm_p=[10.0], mm_s=[1000.0]))
+    assert (d1, d2) == (1, 1)
+    assert c == pytest.approx(1000.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
 
 
 @pytest.mark.parametrize("impl", ["library", "restatement"])

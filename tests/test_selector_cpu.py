@@ -38,7 +38,8 @@ def _load():
 
 def _holdout(w, recs):
     meta = w["meta"]
-    lim = {"zipf": meta["holdout_from"], "clustered": meta["holdout_from_clustered"]}
+    lim = {"zipf": meta["holdout_from"], "clustered": meta["holdout_from_clustered"],
+           "dense": meta.get("holdout_from_dense", 0)}
     return [r for r in recs if r["i"] >= lim[r.get("family", "zipf")]]
 
 
@@ -85,3 +86,21 @@ def test_selector_beats_the_cost_model_on_held_out_instances():
     for fam in sorted({r.get("family", "zipf") for r in te}):
         sel = [i for i, r in enumerate(te) if r.get("family", "zipf") == fam]
         assert _geo([mlp_regret[i] for i in sel]) <= 1.15, fam
+
+
+def _light_only(r):
+    """The light-only cell (no heavy part) is the last of the 65."""
+    return r["t"][-1]
+
+
+def test_selector_is_no_worse_than_light_only_where_the_product_pays():
+    """On held-out instances where some plan with a heavy part beats light
+    only by more than 10%, the selector's pick must on average beat light only."""
+    w, recs = _load()
+    te = [r for r in _holdout(w, recs) if _light_only(r) is not None and _best(r) < 0.9 * _light_only(r)]
+    if len(te) < 5:
+        pytest.skip(f"only {len(te)} held-out instances where the product pays")
+    skip = w["meta"]["skip_ratio"]
+    ks = _picks(w, te)
+    ratio = [(skip * _best(r) if r["t"][k] is None else r["t"][k]) / _light_only(r) for r, k in zip(te, ks)]
+    assert _geo(ratio) < 1.0, _geo(ratio)
