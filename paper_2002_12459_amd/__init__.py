@@ -123,6 +123,12 @@ def _load():
             return _lib
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2002_12459_amd.build.build()")
+        # torch first: it brings its own HIP runtime, and a process that has
+        # loaded the system one before it finds no GPU through torch
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
