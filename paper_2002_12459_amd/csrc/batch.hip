@@ -115,6 +115,58 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_keys(const BatchDesc *d, 
         out[base + e] = inst_key(i, col[e]);
 }
 
+// Combined ids of the output back to each instance's own ids.  Block b
+// takes outputs [b * kSliceChunk, (b + 1) * kSliceChunk): one search finds
+// the instances whose slices meet the chunk, their slice starts are staged
+// in LDS, and each output finds its instance there (the last whose slice
+// starts at or before it; instances with empty slices precede the one that
+// holds the output).  bd: slice starts, n_inst + 1 entries, bd[n_inst] = n.
+constexpr int64_t kSliceChunk = 4096;
+constexpr int kSliceStage = 256;
+__global__ __launch_bounds__(kBatchBlock) void k_batch_unshift(int32_t *X, int32_t *Z, int64_t n, const int64_t *bd,
+                                                               int n_inst, const int64_t *add) {
+    __shared__ int64_t sb[kSliceStage];
+    __shared__ int sh_i0, sh_cnt;
+    const int64_t k0 = (int64_t)blockIdx.x * kSliceChunk;
+    const int64_t k1 = k0 + kSliceChunk < n ? k0 + kSliceChunk : n;
+    auto last_at_or_before = [&](int lo, int hi, int64_t k) {  // last i in [lo, hi] with bd[i] <= k (bd[lo] <= k)
+        while (lo < hi) {
+            const int mid = lo + (hi - lo + 1) / 2;
+            if (bd[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    if (threadIdx.x == 0) {
+        const int i0 = last_at_or_before(0, n_inst, k0);
+        sh_i0 = i0;
+        sh_cnt = last_at_or_before(i0, n_inst, k1 - 1) - i0 + 1;
+    }
+    __syncthreads();
+    const int i0 = sh_i0, cnt = sh_cnt;
+    if (cnt <= kSliceStage) {
+        for (int t = threadIdx.x; t < cnt; t += kBatchBlock) sb[t] = bd[i0 + t];
+        __syncthreads();
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += kBatchBlock) {
+            int lo = 0, hi = cnt - 1;
+            while (lo < hi) {
+                const int mid = lo + (hi - lo + 1) / 2;
+                if (sb[mid] <= k) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t i = i0 + lo;
+            X[k] = (int32_t)((int64_t)X[k] - add[3 * i]);
+            Z[k] = (int32_t)((int64_t)Z[k] - add[3 * i + 2]);
+        }
+    } else {  // more instances meet the chunk than LDS stages: search bd itself
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += kBatchBlock) {
+            const int64_t i = last_at_or_before(i0, i0 + cnt - 1, k);
+            X[k] = (int32_t)((int64_t)X[k] - add[3 * i]);
+            Z[k] = (int32_t)((int64_t)Z[k] - add[3 * i + 2]);
+        }
+    }
+}
+
 // Dense ranks of (instance, id) keys: sorted distinct keys in *uniq, their count returned.
 struct RankTable {
     DBuf<uint64_t> uniq;
@@ -290,18 +342,9 @@ jp_result *run_two_path_batch(const Ctx &c, int n_inst, const jp_instance *inst,
             Z[k] = (int32_t)((uint32_t)uz[Z[k]] ^ 0x80000000u);
         });
     } else {
-        const int64_t *ad = addd.get();
-        const int ni = n_inst;
-        for_each(c, n, [=] __device__(int64_t k) {
-            int64_t lo = 0, hi = ni;  // instance: last i with bd[i] <= k
-            while (lo < hi) {
-                const int64_t mid = lo + (hi - lo + 1) / 2;
-                if (bd[mid] <= k) lo = mid;
-                else hi = mid - 1;
-            }
-            X[k] = (int32_t)((int64_t)X[k] - ad[3 * lo]);
-            Z[k] = (int32_t)((int64_t)Z[k] - ad[3 * lo + 2]);
-        });
+        hipLaunchKernelGGL(k_batch_unshift, dim3(grid_x(ceil_div(n, kSliceChunk), kBatchBlock)), dim3(kBatchBlock), 0,
+                           c.stream, X, Z, n, (const int64_t *)bd, n_inst, (const int64_t *)addd.get());
+        JP_HIP(hipGetLastError());
     }
     c.load_n(res->batch_off.data(), bd, (size_t)n_inst + 1);
     JP_CHECK(res->batch_off[n_inst] == n, JP_EINTERNAL, "batched output slices do not cover the output");
