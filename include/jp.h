@@ -157,6 +157,8 @@ typedef struct jp_calibration {
                            the witnesses of light x at light y taken out of sum(x_D2) under independent
                            x and y degree classes, and a plan without a product priced at J witnesses;
                            0: T_I (sum(y_D1) + sum(x_D2)) as printed */
+    int32_t k_pad;      /* > 1: the product's inner dimension v is priced padded to a multiple of k_pad (the
+                           matrices are u x v_pad and w x v_pad and the product runs over v_pad); 0 or 1: v */
 } jp_calibration;
 
 /* Sorted degree vector with per-degree count and summed work: the indexes of
@@ -278,14 +280,26 @@ jp_status jp_plan_cells(jp_handle *h, const int32_t *r_x, const int32_t *r_y, in
                         const int64_t *delta1, const int64_t *delta2, double *est_seconds, int64_t *heavy_dims);
 
 /*
+ * The heavy part of Algorithm 2's cost (Section 5) for heavy dimensions
+ * u, v, w: M-hat(u, v, w) plus the heavy matrices' bytes, in seconds, with
+ * the calibration cal (NULL: the library's default).  0 when u, v or w is 0.
+ * The learned selector takes a grid cell only when this is below the
+ * light-only plan's estimate.  Host only; no GPU needed.
+ */
+double jp_heavy_cost(const jp_calibration *cal, int64_t u, int64_t v, int64_t w);
+
+/*
  * Learned threshold selector (strategy AUTO_MLP).  It replaces Algorithm 2's
  * search (Section 5) by a fixed-size multilayer perceptron; any thresholds
  * keep the result exact (Section 3.1), so only the run time depends on it.
  *
  * Network: the 16 features of jp_plan_two_path, normalised as
  * (f - mean) / scale, then 16 -> 64 (ReLU) -> 64 (ReLU) -> n_out, fp32.
- * Output k is the predicted log run-time ratio of threshold cell k; the cell
- * with the smallest output is used.  Parameters are one flat fp32 array:
+ * Output k is the predicted log run-time ratio of threshold cell k.  The
+ * candidates are the light-only cell and every cell whose heavy part alone
+ * (jp_heavy_cost of its u, v, w) is estimated below the light-only plan's
+ * Algorithm 2 cost; the candidate with the smallest output is used.
+ * Parameters are one flat fp32 array:
  * W1[64][16], b1[64], W2[64][64], b2[64], W3[n_out][64], b3[n_out]
  * (jp_mlp_param_count(n_out) floats).
  */

@@ -298,7 +298,8 @@ def algorithm2(s, cal):
       T_I sum(y_D1) + T_I sum(x_D2) + T_m |dom x| + T_s cdfx(y_D1) |dom x|
     and the heavy cost M-hat(u,v,w) + T_m (u v + w v), M-hat taken from the
     nearest cube of the table scaled by u v w / p^3, or the smallest cube's
-    time when p is below it; the result is the plain
+    time when p is below it, and v priced as the next multiple of k_pad when
+    k_pad > 1 (missing k_pad: v itself); the result is the plain
     join when J <= 20 N or when no candidate beats it.  With light_once (a
     reading of Section 5's sum indexes as counts of work done once per light
     witness) the light-x term becomes sum(x_D2) (1 - sum(y_D1) / J): the
@@ -311,6 +312,11 @@ def algorithm2(s, cal):
     """
     N = max(s["n_r"], s["n_s"])
     out = max(s["out_est"], 1.0)
+
+    kp = int(cal.get("k_pad", 1))
+
+    def padded(v):  # the product's inner dimension as priced (k_pad > 1: next multiple)
+        return -(-v // kp) * kp if kp > 1 else v
 
     def mm_hat(u, v, w):
         if min(u, v, w) <= 0:
@@ -337,7 +343,8 @@ def algorithm2(s, cal):
         light = cal["t_witness"] * wit + cal["t_x"] * s["dom_x"] + cal["t_seq"] * cc * s["dom_x"]
         heavy = 0.0
         if u > 0 and v > 0 and w > 0:
-            heavy = mm_hat(u, v, w) + cal["t_byte"] * (u * v + w * v)
+            vp = padded(v)
+            heavy = mm_hat(u, vp, w) + cal["t_byte"] * (u * vp + w * vp)
         return light + heavy
 
     big = 1 << 62

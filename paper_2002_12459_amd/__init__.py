@@ -72,12 +72,12 @@ class Calibration(ctypes.Structure):
     _fields_ = [("t_witness", ctypes.c_double), ("t_seq", ctypes.c_double), ("t_byte", ctypes.c_double),
                 ("t_x", ctypes.c_double), ("eps", ctypes.c_double), ("literal", ctypes.c_int32),
                 ("n_mm", ctypes.c_int32), ("mm_p", ctypes.c_double * 24), ("mm_s", ctypes.c_double * 24),
-                ("light_once", ctypes.c_int32)]
+                ("light_once", ctypes.c_int32), ("k_pad", ctypes.c_int32)]
 
     def as_dict(self):
         return {"t_witness": self.t_witness, "t_seq": self.t_seq, "t_byte": self.t_byte, "t_x": self.t_x,
                 "eps": self.eps, "literal": self.literal, "mm_p": list(self.mm_p[: self.n_mm]),
-                "mm_s": list(self.mm_s[: self.n_mm]), "light_once": self.light_once}
+                "mm_s": list(self.mm_s[: self.n_mm]), "light_once": self.light_once, "k_pad": self.k_pad}
 
     @classmethod
     def from_dict(cls, d):
@@ -86,6 +86,7 @@ class Calibration(ctypes.Structure):
             setattr(c, k, float(d[k]))
         c.literal = int(d.get("literal", 0))
         c.light_once = int(d.get("light_once", 0))
+        c.k_pad = int(d.get("k_pad", 1))
         c.n_mm = len(d["mm_p"])
         for i, (a, b) in enumerate(zip(d["mm_p"], d["mm_s"])):
             c.mm_p[i] = a
@@ -188,6 +189,8 @@ def _load():
                                       ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double),
                                       ctypes.POINTER(i64)]
         lib.jp_selector_cells.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.jp_heavy_cost.argtypes = [ctypes.POINTER(Calibration), i64, i64, i64]
+        lib.jp_heavy_cost.restype = ctypes.c_double
         lib.jp_selector_cells.restype = ctypes.c_int32
         lib.jp_mlp_param_count.argtypes = [ctypes.c_int32]
         lib.jp_mlp_param_count.restype = i64
@@ -830,6 +833,19 @@ def selector_cells(features):
 
 def mlp_param_count(n_out=N_CELLS):
     return int(_load().jp_mlp_param_count(n_out))
+
+
+def heavy_cost(u, v, w, cal=None):
+    """Heavy part of Algorithm 2's cost for dimensions (u, v, w), seconds
+    (M-hat plus the heavy matrices' bytes; calibration dict or None)."""
+    c = None if cal is None else (cal if isinstance(cal, Calibration) else Calibration.from_dict(cal))
+    return float(_load().jp_heavy_cost(ctypes.byref(c) if c is not None else None, int(u), int(v), int(w)))
+
+
+def selector_candidates(est_light, heavy):
+    """Cells the selector may take: light only (the last) and every cell whose
+    heavy-part estimate is below the light-only plan's estimate."""
+    return [k == len(heavy) - 1 or h < est_light for k, h in enumerate(heavy)]
 
 
 def default_calibration():

@@ -828,6 +828,12 @@ jp_status jp_plan_cells(jp_handle *h, const int32_t *r_x, const int32_t *r_y, in
     });
 }
 
+double jp_heavy_cost(const jp_calibration *cal, int64_t u, int64_t v, int64_t w) {
+    jp_calibration d;
+    if (!cal) jp::default_calibration(&d);
+    return jp::heavy_cost(cal ? *cal : d, u, v, w);
+}
+
 int32_t jp_selector_cells(const float *features, int64_t *delta1, int64_t *delta2) {
     if (!features || !delta1 || !delta2) return 0;
     jp::selector_cells(features, delta1, delta2);

@@ -210,11 +210,20 @@ Thresholds select_thresholds(const Ctx &c, const TwoPathSummary &s, const jp_opt
     mlp_forward(c, sel.params.get(), sel.n_out, io.get(), 1, io.get() + kFeatures);
     float score[kSelectorCells];
     c.load_n(score, io.get() + kFeatures, kSelectorCells);
-    int best = 0;
-    for (int k = 1; k < kSelectorCells; ++k)
-        if (score[k] < score[best]) best = k;
     int64_t d1[kSelectorCells], d2[kSelectorCells];
     selector_cells(f, d1, d2);
+    // Candidates: light only, and every cell whose heavy part alone is
+    // estimated below the whole light-only plan (a cell whose product costs
+    // more than evaluating everything light cannot win).
+    const jp_two_path_summary v = s.view();
+    const double light = plan_cost(v, cal, JP_DELTA_INF, JP_DELTA_INF, nullptr);
+    int best = kSelectorCells - 1;
+    for (int k = 0; k + 1 < kSelectorCells; ++k) {
+        int64_t uvw[3] = {0, 0, 0};
+        (void)plan_cost(v, cal, d1[k], d2[k], uvw);
+        if (heavy_cost(cal, uvw[0], uvw[1], uvw[2]) >= light) continue;
+        if (score[k] < score[best]) best = k;
+    }
     Thresholds th;
     th.d1 = d1[best];
     th.d2 = d2[best];

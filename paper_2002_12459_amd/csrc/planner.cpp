@@ -56,15 +56,16 @@ void default_calibration(jp_calibration *c) {
     // measured on MI355X with this library (paper_2002_12459_amd.calibrate):
     // light witness cost, per-x index cost, heavy-matrix bytes, and the int8
     // product on p x p x p operands; replaced at run time by jp_set_calibration
-    c->t_witness = 2.5188e-11;
+    c->t_witness = 1.3522e-11;
     c->t_seq = 0.0;
-    c->t_byte = 2.5000e-13;
-    c->t_x = 4.1686e-09;
+    c->t_byte = 3.0775e-13;
+    c->t_x = 1.7849e-09;
     c->eps = 0.05;
     c->literal = 0;
     c->light_once = 1;
+    c->k_pad = 128;  // the heavy matrices' stride and the product's K stage
     const double p[] = {1024, 2048, 4096, 8192, 12288, 16384, 20480};
-    const double s[] = {2.4956e-05, 4.1555e-05, 1.3162e-04, 7.0919e-04, 2.2700e-03, 4.9962e-03, 9.9194e-03};
+    const double s[] = {3.4316e-05, 4.8074e-05, 7.7510e-05, 4.8934e-04, 1.5718e-03, 3.8439e-03, 7.8472e-03};
     c->n_mm = (int32_t)(sizeof(p) / sizeof(p[0]));
     for (int i = 0; i < c->n_mm; ++i) {
         c->mm_p[i] = p[i];
@@ -111,6 +112,16 @@ double mm_hat(const jp_calibration &c, double u, double v, double w) {
     return c.mm_s[best] * (u * v * w) / (pb * pb * pb);
 }
 
+}  // namespace
+
+double heavy_cost(const jp_calibration &c, int64_t u, int64_t v, int64_t w) {
+    if (u <= 0 || v <= 0 || w <= 0) return 0.0;
+    const double vp = c.k_pad > 1 ? (double)((v + c.k_pad - 1) / c.k_pad * c.k_pad) : (double)v;
+    return mm_hat(c, (double)u, vp, (double)w) + c.t_byte * ((double)u * vp + (double)w * vp);
+}
+
+namespace {
+
 // Algorithm 2's cost of a threshold pair on one instance's indexes.
 struct CostModel {
     const jp_two_path_summary &s;
@@ -136,10 +147,7 @@ struct CostModel {
             uvw[1] = v;
             uvw[2] = w;
         }
-        double heavy = 0.0;
-        if (u > 0 && v > 0 && w > 0)
-            heavy = mm_hat(c, (double)u, (double)v, (double)w) + c.t_byte * ((double)u * v + (double)w * v);
-        return light + heavy;
+        return light + heavy_cost(c, u, v, w);
     }
 };
 

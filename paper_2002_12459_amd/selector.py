@@ -148,6 +148,7 @@ def sweep(args):
         est, dims = h.plan_cells(*R, d1s, d2s)
         rec["features"] = feats
         rec["cells"] = [[a, b] for a, b in zip(d1s, d2s)]
+        rec.update(_cell_estimates(h, est, dims))
         t = [None] * N_CELLS
         full = [False] * N_CELLS
         t_light, st, full[64] = run(args.reps, strategy="light")
@@ -191,9 +192,38 @@ def sweep(args):
     h.close()
 
 
+def _cell_estimates(h, est, dims):
+    """Cost-model seconds of every cell and of its heavy part alone (the
+    selector's candidate rule compares the latter with the light-only cell's
+    estimate), with the handle's calibration."""
+    import paper_2002_12459_amd as jp
+    cal = h.get_calibration()
+    return {"est": [float(e) for e in est], "heavy": [jp.heavy_cost(u, v, w, cal) for u, v, w in dims],
+            "uvw": [list(d) for d in dims]}
+
+
+def candidates(rec):
+    """Cells the selector may take on a swept instance (all when the record
+    holds no estimates)."""
+    import paper_2002_12459_amd as jp
+    if "heavy" not in rec:
+        return [True] * N_CELLS
+    return jp.selector_candidates(rec["est"][N_CELLS - 1], rec["heavy"])
+
+
+def masked_argmin(scores, recs):
+    """Per row, the candidate cell with the smallest score."""
+    import numpy as np
+    s = np.array(scores, dtype=np.float64, copy=True)
+    for i, r in enumerate(recs):
+        s[i, ~np.asarray(candidates(r))] = np.inf
+    return s.argmin(axis=1)
+
+
 def retime(args):
     """Time the cost model's plan again on instances already swept (after a
-    change of the cost model), keeping every other column."""
+    change of the cost model or its calibration), and recompute the cells'
+    cost-model estimates, keeping every other column."""
     import multiprocessing as mp
 
     recs = [r for r in load_records(args.data) if r.get("family", "zipf") == args.family and "t" in r]
@@ -216,6 +246,10 @@ def retime(args):
         if data is None:
             continue
         R = tuple(T(a) for a in data)
+        d1s = [c[0] for c in rec["cells"]]
+        d2s = [c[1] for c in rec["cells"]]
+        est, dims = h.plan_cells(*R, d1s, d2s)
+        rec.update(_cell_estimates(h, est, dims))
         r = h.two_path_result(*R, strategy="auto")
         st = r.stats
         r.free()
@@ -300,7 +334,8 @@ def train(args):
     recs = [r for r in load_records(args.data) if not r.get("rejected")]
     if args.table_out:
         import gzip
-        keep = ("family", "i", "n", "s", "J", "n_out", "features", "t", "auto", "theory", "sqrtN")
+        keep = ("family", "i", "n", "s", "J", "n_out", "features", "t", "auto", "theory", "sqrtN", "est", "heavy",
+                "uvw")
         with gzip.open(args.table_out, "wt") as fh:
             for r in recs:
                 fh.write(json.dumps({k: r.get(k, "zipf" if k == "family" else None) for k in keep}) + "\n")
@@ -321,34 +356,37 @@ def train(args):
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
     xf, tf = norm(fit), dev(Y(fit))
     # errors near an instance's best cells decide its pick: weight each target
-    # by exp(-target) (1 at the best cell, 1/e at a cell e times slower)
-    wf = torch.exp(-tf) if args.weighted else torch.ones_like(tf)
+    # by exp(-target / tau) (1 at the best cell, 1/e at a cell e^tau times slower)
+    wf = torch.exp(-tf / args.weight_tau) if args.weighted else torch.ones_like(tf)
     xv = norm(val)
-    p = dev(_init_params(args.seed))
-    m = torch.zeros_like(p)
-    v = torch.zeros_like(p)
-    grad = torch.empty_like(p)
-    loss = torch.empty(1, dtype=torch.float32, device="cuda")
 
-    def picks(params, xs):
-        return h.mlp_forward(params, xs).argmin(dim=1).cpu().numpy()
+    def picks(params, xs, rs):
+        return masked_argmin(h.mlp_forward(params, xs).cpu().numpy(), rs)
 
     def geo_regret(params, rs, xs):
-        ks = picks(params, xs)
+        ks = picks(params, xs, rs)
         return float(np.exp(np.mean([math.log(regret(r, int(k), args.skip_ratio)) for r, k in zip(rs, ks)])))
 
-    best_p, best_val, log = p.clone(), geo_regret(p, val, xv), []
+    # one run per seed; the parameters with the best validation regret over
+    # all runs and checkpoints are kept
+    best_p, best_val, best_seed, log = None, math.inf, None, []
     t0 = time.perf_counter()
-    for step in range(1, args.steps + 1):
-        lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / args.steps))
-        h.mlp_grad(p, xf, tf, wf, grad=grad, loss=loss)
-        h.mlp_adam(p, m, v, grad, step, lr=lr)
-        if step % args.eval_every == 0 or step == args.steps:
-            vr = geo_regret(p, val, xv)
-            log.append({"step": step, "loss": float(loss.item()), "val_regret": vr})
-            print(f"[train] step {step}: loss {loss.item():.4f} val geo-regret {vr:.4f}", flush=True)
-            if vr < best_val:
-                best_val, best_p = vr, p.clone()
+    for seed in range(args.seed, args.seed + args.seeds):
+        p = dev(_init_params(seed))
+        m = torch.zeros_like(p)
+        v = torch.zeros_like(p)
+        grad = torch.empty_like(p)
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        for step in range(1, args.steps + 1):
+            lr = args.lr * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / args.steps))
+            h.mlp_grad(p, xf, tf, wf, grad=grad, loss=loss)
+            h.mlp_adam(p, m, v, grad, step, lr=lr)
+            if step % args.eval_every == 0 or step == args.steps:
+                vr = geo_regret(p, val, xv)
+                log.append({"seed": seed, "step": step, "loss": float(loss.item()), "val_regret": vr})
+                print(f"[train] seed {seed} step {step}: loss {loss.item():.4f} val geo-regret {vr:.4f}", flush=True)
+                if vr < best_val:
+                    best_val, best_p, best_seed = vr, p.clone(), seed
     t_train = time.perf_counter() - t0
 
     params = best_p.cpu().numpy().astype(np.float64)
@@ -356,15 +394,16 @@ def train(args):
         json.dump({"n_out": N_CELLS, "params": [float(x) for x in params], "mean": [float(x) for x in mean],
                    "scale": [float(x) for x in scale],
                    "meta": {"n_fit": len(fit), "n_val": len(val), "steps": args.steps, "lr": args.lr,
-                            "skip_ratio": args.skip_ratio, "val_regret": best_val, "seed": args.seed,
-                            "weighted": bool(args.weighted),
+                            "skip_ratio": args.skip_ratio, "val_regret": best_val, "seed": best_seed,
+                            "seeds": [args.seed, args.seed + args.seeds], "weighted": bool(args.weighted),
+                            "weight_tau": args.weight_tau,
                             "holdout_from": args.holdout_from,
                             "holdout_from_clustered": args.holdout_from_clustered,
                             "holdout_from_dense": args.holdout_from_dense}}, fh)
     report = {"train_seconds": t_train, "log": log, "val_regret": best_val}
     if te:
         xt = norm(te)
-        ks = picks(best_p, xt)
+        ks = picks(best_p, xt, te)
         best = lambda r: min(x for x in r["t"] if x is not None)
         rows = {"mlp": [regret(r, int(k), args.skip_ratio) for r, k in zip(te, ks)]}
         for name in ("auto", "theory", "sqrtN"):
@@ -427,7 +466,9 @@ def main(argv=None):
     b.add_argument("--eval-every", type=int, default=100)
     b.add_argument("--skip-ratio", type=float, default=30.0)
     b.add_argument("--seed", type=int, default=0)
-    b.add_argument("--weighted", type=int, default=1, help="weight targets by exp(-target)")
+    b.add_argument("--weighted", type=int, default=1, help="weight targets by exp(-target / tau)")
+    b.add_argument("--weight-tau", type=float, default=0.3)
+    b.add_argument("--seeds", type=int, default=5, help="runs from seeds seed .. seed + seeds - 1")
     b.add_argument("--out", required=True)
     b.add_argument("--report", default=None)
     b.add_argument("--table-out", default=None, help="write the clean sweep table (gzip JSON lines) here")

@@ -140,7 +140,14 @@ def test_auto_mlp_picks_a_best_scored_cell_and_stays_exact(jp):
     cells = list(zip(*jp.selector_cells(feats)))
     inf = jp.DELTA_INF
     picked = (st["delta1"] if st["delta1"] != inf else None, st["delta2"] if st["delta2"] != inf else None)
-    ok = [c for c, s in zip(cells, score) if s <= score.min() + 1e-4]
+    # candidates: light only and the cells whose heavy part alone is
+    # estimated below the light-only plan (the library's rule)
+    d1s, d2s = jp.selector_cells(feats)
+    est, dims = hd.plan_cells(dev(rx), dev(ry), dev(sz), dev(sy), d1s, d2s)
+    cal = hd.get_calibration()
+    cand = jp.selector_candidates(est[-1], [jp.heavy_cost(u, v, w, cal) for u, v, w in dims])
+    best = min(s for s, ok in zip(score, cand) if ok)
+    ok = [c for c, s, q in zip(cells, score, cand) if q and s <= best + 1e-4]
     assert picked in ok
     # the planning entry point makes the same choice
     d1, d2, _ = hd.plan_two_path(dev(rx), dev(ry), dev(sz), dev(sy), strategy="mlp")
@@ -150,6 +157,39 @@ def test_auto_mlp_picks_a_best_scored_cell_and_stays_exact(jp):
     _, _, st2 = hd.two_path(dev(rx), dev(ry), dev(sz), dev(sy), strategy="mlp")
     assert st2["strategy"] == 0
     assert (st2["delta1"], st2["delta2"]) == (d1a if d1a is not None else inf, d2a if d2a is not None else inf)
+    hd.close()
+
+
+def test_auto_mlp_skips_cells_whose_product_alone_exceeds_light_only(jp):
+    """A network whose lowest score is on a cell that the candidate rule
+    excludes (its heavy part alone estimated above the light-only plan)
+    does not get that cell."""
+    (rx, ry), (sz, sy), _ = datagen.selector_instance(3, lo=5e3, hi=2e4)
+    hd = jp.Handle(0, selector=None)
+    _, _, feats = hd.plan_two_path(dev(rx), dev(ry), dev(sz), dev(sy))
+    d1s, d2s = jp.selector_cells(feats)
+    est, dims = hd.plan_cells(dev(rx), dev(ry), dev(sz), dev(sy), d1s, d2s)
+    cal = hd.get_calibration()
+    heavy = [jp.heavy_cost(u, v, w, cal) for u, v, w in dims]
+    cand = jp.selector_candidates(est[-1], heavy)
+    excluded = [k for k, q in enumerate(cand) if not q]
+    if not excluded:
+        hd.close()
+        pytest.skip("no cell of this instance is excluded")
+    k = 65
+    p = np.zeros(mlp.param_count(k))
+    W1, b1, W2, b2, W3, b3 = mlp.unpack(p, k)
+    b3[:] = 0.0
+    b3[excluded[0]] = -100.0  # the excluded cell scores lowest by far
+    alt = next(j for j, q in enumerate(cand) if q and j != 64) if any(cand[:64]) else 64
+    b3[alt] = -50.0            # the best candidate
+    hd.set_selector(mlp.pack(W1, b1, W2, b2, W3, b3).tolist(), np.zeros(16).tolist(), np.ones(16).tolist())
+    x, z, st = hd.two_path(dev(rx), dev(ry), dev(sz), dev(sy), strategy="mlp")
+    inf = jp.DELTA_INF
+    got = (None if st["delta1"] == inf else st["delta1"], None if st["delta2"] == inf else st["delta2"])
+    assert got == (d1s[alt], d2s[alt])
+    ex, ez = oracle.two_path(rx, ry, sz, sy)
+    assert np.array_equal(x.cpu().numpy(), ex) and np.array_equal(z.cpu().numpy(), ez)
     hd.close()
 
 

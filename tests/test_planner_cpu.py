@@ -238,3 +238,38 @@ def test_library_out_estimate_by_hand():
     assert jp.estimate_out(5, 1000, 2000, 100) == pytest.approx(np.sqrt(400.0 * 2000.0), rel=1e-12)
     assert jp.estimate_out(5, 1000, 1000, 10) == pytest.approx(1000.0, rel=1e-12)
     assert jp.estimate_out(5, 5, 0, 10) == 0.0
+
+
+def test_heavy_cost_terms():
+    """jp_heavy_cost: M-hat (nearest cube scaled, floored at the smallest)
+    plus T_m per byte of the u x v and w x v matrices; 0 without a product."""
+    cal = dict(_hand_cal(0), mm_p=[10.0, 100.0], mm_s=[5.0, 2000.0], t_byte=0.5)
+    assert jp.heavy_cost(0, 10, 10, cal) == 0.0 and jp.heavy_cost(10, 0, 10, cal) == 0.0
+    # p = 80: nearest cube 100, scaled 2000 * 80^3 / 100^3 = 1024; bytes 0.5 * (80*80 + 80*80) = 6400
+    assert jp.heavy_cost(80, 80, 80, cal) == pytest.approx(1024.0 + 6400.0, rel=1e-12)
+    # p = 2: below the smallest cube, its time 5; bytes 0.5 * (2*2 + 2*2) = 4
+    assert jp.heavy_cost(2, 2, 2, cal) == pytest.approx(5.0 + 4.0, rel=1e-12)
+
+
+def test_selector_candidates_rule():
+    assert jp.selector_candidates(10.0, [1.0, 10.0, 11.0, 0.0, 99.0]) == [True, False, False, True, True]
+
+
+@pytest.mark.parametrize("impl", ["library", "restatement"])
+def test_algorithm2_hand_worked_padded_inner_dimension(impl):
+    """The product priced on v padded to a multiple of k_pad = 4.  The hand
+    summary's (25, 2) has u v w = 10 x 2 x 10: padded 10 x 4 x 10 = 400, so
+    12 + 400 = 412; the same to (3, 1); (1, 1) has v = 5, padded 8:
+    0 + 800 > 412, so the search stops at (3, 1) with cost 412."""
+    s = _hand_summary()
+    plan = jp.plan_summary if impl == "library" else ref.algorithm2
+    d1, d2, c, clo = plan(s, dict(_hand_cal(0), k_pad=4))
+    assert (d1, d2) == (3, 1)
+    assert c == pytest.approx(412.0, rel=1e-12) and clo == pytest.approx(10000.0, rel=1e-12)
+
+
+def test_heavy_cost_pads_the_inner_dimension():
+    cal = dict(_hand_cal(0), mm_p=[1.0], mm_s=[1.0], t_byte=1.0, k_pad=128)
+    # v = 1 is priced as 128: M-hat 3 * 128 * 3 = 1152, bytes 3 * 128 + 3 * 128 = 768
+    assert jp.heavy_cost(3, 1, 3, cal) == pytest.approx(1152.0 + 768.0, rel=1e-12)
+    assert jp.heavy_cost(3, 1, 3, dict(cal, k_pad=1)) == pytest.approx(9.0 + 6.0, rel=1e-12)

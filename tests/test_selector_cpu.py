@@ -43,10 +43,23 @@ def _holdout(w, recs):
     return [r for r in recs if r["i"] >= lim[r.get("family", "zipf")]]
 
 
+def _candidates(r):
+    """The library's rule: light only (cell 64) and every cell whose heavy
+    part's estimate is below the light-only plan's estimate."""
+    if "heavy" not in r:
+        return np.ones(65, dtype=bool)
+    h = np.asarray(r["heavy"], dtype=np.float64)
+    ok = h < r["est"][64]
+    ok[64] = True
+    return ok
+
+
 def _picks(w, recs):
     x = np.asarray([r["features"] for r in recs], dtype=np.float32)
     xin = (x - np.asarray(w["mean"], np.float32)) / np.asarray(w["scale"], np.float32)
     y, _ = mlp.forward(np.asarray(w["params"], np.float64), w["n_out"], xin.astype(np.float64))
+    for i, r in enumerate(recs):
+        y[i, ~_candidates(r)] = np.inf
     return y.argmin(axis=1)
 
 
