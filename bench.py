@@ -12,10 +12,17 @@ output in HBM).
 A second leg measures the batched mode on the serving-style set: 512
 independent two-path instances, edge counts log-uniform in [1K, 1M], Zipf
 exponent U[0.6, 1.6], evaluated in one call; it is reported under "batched"
-next to the time of the same instances evaluated one call each.  Further
-legs: the star query over three 2M-edge Zipf(1.3) relations ("star"), and a
-dense-core self-join of 8 communities ("dense_core"), where the cost model
-sends most witnesses to the matrix product.
+next to the time of the same instances evaluated one call each, and as a
+captured plan replayed as one HIP graph.  Further legs: the same 10M input
+with the learned selector's thresholds ("selector") and at forced thresholds
+that give the int8 product a large shape ("heavy_bmm"); the star query over
+three 2M-edge Zipf(1.3) relations ("star") and a 4-relation star
+("star_k4"); a dense-core self-join of 8 communities ("dense_core"), where
+the cost model sends most witnesses to the matrix product; the set
+similarity join at overlap >= 2 ("ssj") and batched set intersection
+("bsi") on the 10M input; the paper's five-run, middle-three timing
+("paper_protocol"); the whole output against the oracle ("parity"); and the
+oracle itself on the host cores ("cpu_baseline").
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 Prints one JSON line.
@@ -40,8 +47,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
 # profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
 # whose SHA-256 is given (None: not measured for the current source).
-DEDUP_TRAFFIC = {"sha256": "af19fdffbaab20918b65d1b099140e1e5a69e58e2c9d16c4241f78bd584c2654",
-                 "bytes_per_launch": 1843326376}
+DEDUP_TRAFFIC = {"sha256": "3ecd75e9fcfd9cef0e8ca4b49ef2d1592582a37e4c198e0a9dadd4cd68d0e37f",
+                 "bytes_per_launch": 1844427157}
 
 
 def dedup_traffic():
