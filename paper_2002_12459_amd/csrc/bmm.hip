@@ -57,29 +57,45 @@ struct CountKeyEmit {  // nonzero (i, j) -> ((rowmap[i] << shift | colmap[j]) <<
     }
 };
 
-// Row sources of the A operand: 16 bytes of row r starting at byte k.
+// Row sources of an operand.  row(r) resolves row r once (per tile); load(h,
+// k) then returns its 16 bytes starting at byte k.
 struct PlainRows {  // A stored row-major
     const int8_t *A;
     int64_t ld;
-    __device__ v4i load(int64_t r, int64_t k) const { return *(const v4i *)(A + r * ld + k); }
+    struct Row {
+        const int8_t *p;
+    };
+    __device__ Row row(int64_t r) const { return Row{A + r * ld}; }
+    __device__ v4i load(const Row &h, int64_t k) const { return *(const v4i *)(h.p + k); }
 };
 // Row (a_0, ..., a_{N-1}) of a product of N factor matrices (the V and W of
 // the star query, Section 3.2): the AND of the factors' rows M_i[a_i, :] (0/1
 // bytes), with r = mixed-radix number of the a_i over the factor heights
 // u_i, the last factor varying fastest.  V and W are never stored.
+// The mixed-radix decode (integer divisions) happens once per row in row();
+// each 16-byte load is then N loads and ANDs.
 template <int N>
 struct TupleRows {
     const int8_t *M[N];
     int64_t u[N];
     int64_t ld;
-    __device__ v4i load(int64_t r, int64_t k) const {
-        v4i acc = {-1, -1, -1, -1};
+    struct Row {
+        const int8_t *p[N];
+    };
+    __device__ Row row(int64_t r) const {
+        Row h;
 #pragma unroll
         for (int i = N - 1; i >= 0; --i) {
             const int64_t a = i > 0 ? r % u[i] : r;
             if (i > 0) r /= u[i];
-            acc &= *(const v4i *)(M[i] + a * ld + k);
+            h.p[i] = M[i] + a * ld;
         }
+        return h;
+    }
+    __device__ v4i load(const Row &h, int64_t k) const {
+        v4i acc = {-1, -1, -1, -1};
+#pragma unroll
+        for (int i = 0; i < N; ++i) acc &= *(const v4i *)(h.p[i] + k);
         return acc;
     }
 };
@@ -196,14 +212,22 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_
         const int64_t kbeg = (item % nchunks) * kchunk;
         const int64_t kend = kbeg + kchunk < ld ? kbeg + kchunk : ld;
         const int64_t row0 = tm * BM, col0 = tn * BN;
+        // this thread's 4 A rows and 4 B rows, resolved once for the tile
+        // (rows past the edge resolve row 0 and load zeros)
+        typename ARows::Row ha[4];
+        typename BRows::Row hb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = row0 + lr + 32 * q, c = col0 + lr + 32 * q;
+            ha[q] = arows.row(r < u ? r : 0);
+            hb[q] = brows.row(c < w ? c : 0);
+        }
         v4i ra[4], rb[4];
         auto load_stage = [&](int64_t k0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                int64_t r = row0 + lr + 32 * q;
-                ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
-                int64_t c = col0 + lr + 32 * q;
-                rb[q] = c < w ? brows.load(c, k0 + lc) : v4i{0, 0, 0, 0};
+                ra[q] = row0 + lr + 32 * q < u ? arows.load(ha[q], k0 + lc) : v4i{0, 0, 0, 0};
+                rb[q] = col0 + lr + 32 * q < w ? brows.load(hb[q], k0 + lc) : v4i{0, 0, 0, 0};
             }
         };
         auto store_stage = [&]() {
@@ -519,14 +543,20 @@ __global__ __launch_bounds__(256) void k_bmm_f16(ARows arows, BRows brows, int64
         int64_t tm, tn;
         tile_of_block(item, tiles_m, tiles_n, &tm, &tn);
         const int64_t row0 = tm * BM, col0 = tn * BN;
+        typename ARows::Row ha[4];
+        typename BRows::Row hb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t r = row0 + lr + 32 * q, c = col0 + lr + 32 * q;
+            ha[q] = arows.row(r < u ? r : 0);
+            hb[q] = brows.row(c < w ? c : 0);
+        }
         v4i ra[4], rb[4];
         auto load_stage = [&](int64_t k0) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int64_t r = row0 + lr + 32 * q;
-                ra[q] = r < u ? arows.load(r, k0 + lc) : v4i{0, 0, 0, 0};
-                const int64_t c = col0 + lr + 32 * q;
-                rb[q] = c < w ? brows.load(c, k0 + lc) : v4i{0, 0, 0, 0};
+                ra[q] = row0 + lr + 32 * q < u ? arows.load(ha[q], k0 + lc) : v4i{0, 0, 0, 0};
+                rb[q] = col0 + lr + 32 * q < w ? brows.load(hb[q], k0 + lc) : v4i{0, 0, 0, 0};
             }
         };
         auto store_row = [&](uint8_t *base, v4i v) {
