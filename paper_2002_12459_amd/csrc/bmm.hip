@@ -268,7 +268,23 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_
         }
 
         // Epilogue: C[row][col] with row = 4*(lane/16) + r inside the 16x16
-        // block, col = lane % 16.  Count this lane's nonzeros, one atomic per tile.
+        // block, col = lane % 16.  Entries past the matrix edge are dropped
+        // first (edge tiles only); the counts are >= 0, so min(count, 1) is
+        // the nonzero test.  One atomic per tile; a wave without a nonzero
+        // skips the emission.
+        {
+            const int rlim = (int)(u - row0 < BM ? u - row0 : BM), clim = (int)(w - col0 < BN ? w - col0 : BN);
+            if (rlim < BM || clim < BN) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (!(wm * 64 + f * 16 + (lane / 16) * 4 + r < rlim && wn * 64 + g * 16 + (lane % 16) < clim))
+                                acc[f][g][r] = 0;
+            }
+        }
         if (bitmap) {
 #pragma unroll
             for (int f = 0; f < 4; ++f)
@@ -278,7 +294,7 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_
                     for (int r = 0; r < 4; ++r) {
                         const int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
                         const int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
-                        if (acc[f][g][r] > 0 && i < u && j < w) {
+                        if (acc[f][g][r] > 0) {
                             const int64_t b = i * w + j;
                             atomicOr(&bitmap[b >> 5], 1u << (b & 31));
                         }
@@ -291,15 +307,11 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_
 #pragma unroll
             for (int g = 0; g < 4; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
-                    int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
-                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? 1u : 0u;
-                }
+                for (int r = 0; r < 4; ++r) mine += (uint32_t)min(acc[f][g][r], 1);
         uint32_t incl = wave_incl_scan(mine);
         uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
-        if (base < 0) continue;
+        if (base < 0 || wtot == 0) continue;
         int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int f = 0; f < 4; ++f)
@@ -307,9 +319,9 @@ __global__ __launch_bounds__(256) void k_bmm_i8(ARows arows, BRows brows, int64_
             for (int g = 0; g < 4; ++g)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
-                    int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
-                    if (acc[f][g][r] > 0 && i < u && j < w) {
+                    if (acc[f][g][r] > 0) {
+                        const int64_t i = row0 + wm * 64 + f * 16 + (lane / 16) * 4 + r;
+                        const int64_t j = col0 + wn * 64 + g * 16 + (lane % 16);
                         if (pos < cap) emit(pos, i, j, (uint32_t)acc[f][g][r]);
                         ++pos;
                     }
@@ -426,22 +438,34 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
             }
         }
 
-        // Epilogue as in the 128 x 128 kernel.
-        uint32_t mine = 0;
+        // Epilogue as in the 128 x 128 kernel, in tile-local 32-bit
+        // coordinates: rows and columns past the matrix edge are cut by two
+        // limits (the tile size for interior tiles).  A wave without a
+        // nonzero skips the emission.
+        const int rlim = (int)(u - row0 < BM2 ? u - row0 : BM2), clim = (int)(w - col0 < BN2 ? w - col0 : BN2);
+        const bool interior = rlim == BM2 && clim == BN2;  // uniform per workgroup
+        const int ib = wm * 128 + fq * 4, jb = wn * 64 + fr;
+        if (!interior) {  // edge tile: entries past the matrix edge are dropped
+#pragma unroll
+            for (int f = 0; f < 8; ++f)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (!(ib + f * 16 + r < rlim && jb + g * 16 < clim)) acc[f][g][r] = 0;
+        }
+        uint32_t mine = 0;  // counts are >= 0: min(count, 1) is the nonzero test
 #pragma unroll
         for (int f = 0; f < 8; ++f)
 #pragma unroll
             for (int g = 0; g < 4; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
-                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
-                    mine += (acc[f][g][r] > 0 && i < u && j < w) ? mult : 0u;
-                }
+                for (int r = 0; r < 4; ++r) mine += (uint32_t)min(acc[f][g][r], 1);
+        mine *= mult;
         const uint32_t incl = wave_incl_scan(mine);
         const uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<kBig / kWave>(wtot, count, sh_cnt, &sh_base);
-        if (base < 0) continue;
+        if (base < 0 || wtot == 0) continue;
         int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int f = 0; f < 8; ++f)
@@ -449,9 +473,8 @@ __global__ __launch_bounds__(kBig) void k_bmm_i8_big(const int8_t *__restrict__ 
             for (int g = 0; g < 4; ++g)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t i = row0 + wm * 128 + f * 16 + fq * 4 + r;
-                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
-                    if (acc[f][g][r] > 0 && i < u && j < w) {
+                    if (acc[f][g][r] > 0) {
+                        const int64_t i = row0 + ib + f * 16 + r, j = col0 + jb + g * 16;
                         if (pos < cap) emit(pos, i, j, (uint32_t)acc[f][g][r]);
                         if (mult == 2u && pos + 1 < cap) emit(pos + 1, j, i, (uint32_t)acc[f][g][r]);
                         pos += mult;
@@ -598,21 +621,30 @@ __global__ __launch_bounds__(256) void k_bmm_f16(ARows arows, BRows brows, int64
             }
         }
         // Epilogue as in k_bmm_i8: C[row][col], row = 4 (lane / 16) + r, col = lane % 16.
+        {
+            const int rlim = (int)(u - row0 < BM ? u - row0 : BM), clim = (int)(w - col0 < BN ? w - col0 : BN);
+            if (rlim < BM || clim < BN) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f)
+#pragma unroll
+                    for (int g = 0; g < 4; ++g)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (!(wm * 64 + f * 16 + fq * 4 + r < rlim && wn * 64 + g * 16 + fr < clim))
+                                acc[f][g][r] = 0.0f;
+            }
+        }
         uint32_t mine = 0;
 #pragma unroll
         for (int f = 0; f < 4; ++f)
 #pragma unroll
             for (int g = 0; g < 4; ++g)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t i = row0 + wm * 64 + f * 16 + fq * 4 + r;
-                    const int64_t j = col0 + wn * 64 + g * 16 + fr;
-                    mine += (acc[f][g][r] > 0.5f && i < u && j < w) ? 1u : 0u;
-                }
+                for (int r = 0; r < 4; ++r) mine += acc[f][g][r] > 0.5f ? 1u : 0u;
         const uint32_t incl = wave_incl_scan(mine);
         const uint32_t wtot = wave_lane(incl, kWave - 1);
         const int64_t base = tile_reserve<4>(wtot, count, sh_cnt, &sh_base);
-        if (base < 0) continue;
+        if (base < 0 || wtot == 0) continue;
         int64_t pos = base + (incl - mine);
 #pragma unroll
         for (int f = 0; f < 4; ++f)
@@ -622,7 +654,7 @@ __global__ __launch_bounds__(256) void k_bmm_f16(ARows arows, BRows brows, int64
                 for (int r = 0; r < 4; ++r) {
                     const int64_t i = row0 + wm * 64 + f * 16 + fq * 4 + r;
                     const int64_t j = col0 + wn * 64 + g * 16 + fr;
-                    if (acc[f][g][r] > 0.5f && i < u && j < w) {
+                    if (acc[f][g][r] > 0.5f) {
                         if (pos < cap) emit(pos, i, j, (uint32_t)(acc[f][g][r] + 0.5f));
                         ++pos;
                     }
