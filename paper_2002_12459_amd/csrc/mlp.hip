@@ -215,13 +215,13 @@ Thresholds select_thresholds(const Ctx &c, const TwoPathSummary &s, const jp_opt
     // Candidates: light only, and every cell whose heavy part alone is
     // estimated below the whole light-only plan (a cell whose product costs
     // more than evaluating everything light cannot win).
-    const jp_two_path_summary v = s.view();
-    const double light = plan_cost(v, cal, JP_DELTA_INF, JP_DELTA_INF, nullptr);
+    double cost[kSelectorCells];
+    int64_t uvw[3 * kSelectorCells];
+    plan_costs(s.view(), cal, kSelectorCells, d1, d2, cost, uvw);
+    const double light = cost[kSelectorCells - 1];
     int best = kSelectorCells - 1;
     for (int k = 0; k + 1 < kSelectorCells; ++k) {
-        int64_t uvw[3] = {0, 0, 0};
-        (void)plan_cost(v, cal, d1[k], d2[k], uvw);
-        if (heavy_cost(cal, uvw[0], uvw[1], uvw[2]) >= light) continue;
+        if (heavy_cost(cal, uvw[3 * k], uvw[3 * k + 1], uvw[3 * k + 2]) >= light) continue;
         if (score[k] < score[best]) best = k;
     }
     Thresholds th;

@@ -101,6 +101,9 @@ void default_calibration(jp_calibration *c);
 void features16(const TwoPathSummary &s, float *f);
 // Algorithm 2's cost of one threshold pair and the heavy dimensions u, v, w.
 double plan_cost(const jp_two_path_summary &s, const jp_calibration &c, int64_t d1, int64_t d2, int64_t *uvw);
+// The same for n pairs at once (cost and / or uvw may be null).
+void plan_costs(const jp_two_path_summary &s, const jp_calibration &c, int n, const int64_t *d1, const int64_t *d2,
+                double *cost, int64_t *uvw);
 // Its heavy part alone: M-hat(u, v, w) plus the heavy matrices' bytes (0 without a product).
 double heavy_cost(const jp_calibration &c, int64_t u, int64_t v, int64_t w);
 // Threshold choice for any strategy, running the selector for AUTO_MLP when

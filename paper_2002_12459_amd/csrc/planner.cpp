@@ -157,6 +157,18 @@ double plan_cost(const jp_two_path_summary &s, const jp_calibration &c, int64_t 
     return CostModel(s, c)(d1, d2, uvw);
 }
 
+void plan_costs(const jp_two_path_summary &s, const jp_calibration &c, int n, const int64_t *d1, const int64_t *d2,
+                double *cost, int64_t *uvw) {
+    const CostModel cm(s, c);  // the indexes' prefix tables, built once for all pairs
+    for (int i = 0; i < n; ++i) {
+        int64_t t[3] = {0, 0, 0};
+        const double v = cm(d1[i], d2[i], t);
+        if (cost) cost[i] = v;
+        if (uvw)
+            for (int j = 0; j < 3; ++j) uvw[3 * i + j] = t[j];
+    }
+}
+
 PlanResult algorithm2(const jp_two_path_summary &s, const jp_calibration &c) {
     PlanResult r;
     const int64_t N = std::max(s.n_r, s.n_s);

@@ -325,6 +325,69 @@ __device__ __forceinline__ uint64_t splitmix64_next(uint64_t x) {
     return z ^ (z >> 31);
 }
 
+// Draws kept under the cap: the longest prefix of draws whose candidates
+// total at most cap, at least the first draw, none if that one alone passes
+// 4 cap (coff: exclusive prefix of the draws' candidate counts).
+__device__ __forceinline__ bool draw_kept(const int64_t *coff, int64_t i, int64_t cap) {
+    return coff[i + 1] <= cap || (i == 0 && coff[1] <= 4 * cap);
+}
+
+// Distinct z of each kept draw when the z domain fits one LDS bitmap: one
+// workgroup per draw marks its candidates (its R tuples' lists, 256 tuples
+// at a time, the candidates of those lists spread over the threads) and
+// counts the set bits.  Adds the counts to *dsum and the kept draws to *kept.
+constexpr int64_t kSampleBitmapBits = int64_t(1) << 20;
+constexpr int kSampleBlock = 256;
+__global__ __launch_bounds__(kSampleBlock) void k_sample_distinct(const int32_t *xr, const int64_t *coff, int64_t cap,
+                                                                  const int64_t *ox, const int32_t *ar,
+                                                                  const int64_t *oy, const int32_t *as, int64_t dom_z,
+                                                                  unsigned long long *dsum, unsigned long long *kept) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int64_t lpre[kSampleBlock + 1], lbase[kSampleBlock];
+    __shared__ int64_t lds64[kSampleBlock / kWave + 1];
+    const int64_t i = blockIdx.x;
+    if (!draw_kept(coff, i, cap)) return;  // uniform per workgroup
+    const int tid = threadIdx.x;
+    const int nw = (int)((dom_z + 31) / 32);
+    for (int t = tid; t < nw; t += kSampleBlock) bm[t] = 0;
+    const int32_t x = xr[i];
+    const int64_t e0 = ox[x], e1 = ox[x + 1];
+    for (int64_t c0 = e0; c0 < e1; c0 += kSampleBlock) {
+        const int64_t e = c0 + tid;
+        int64_t len = 0, base = 0;
+        if (e < e1) {
+            const int32_t y = ar[e];
+            base = oy[y];
+            len = oy[y + 1] - base;
+        }
+        int64_t tot;
+        const int64_t pre = block_excl_scan<kSampleBlock>(len, lds64, &tot);
+        lpre[tid] = pre;
+        lbase[tid] = base;
+        if (tid == 0) lpre[kSampleBlock] = tot;
+        __syncthreads();  // also orders the bitmap clear before the first marks
+        const int nl = (int)(e1 - c0 < kSampleBlock ? e1 - c0 : kSampleBlock);
+        for (int64_t q = tid; q < tot; q += kSampleBlock) {
+            int lo = 0, hi = nl - 1;  // the list holding candidate q: last l with lpre[l] <= q
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (lpre[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int32_t z = as[lbase[lo] + (q - lpre[lo])];
+            atomicOr(&bm[z >> 5], 1u << (z & 31));
+        }
+        __syncthreads();  // lpre / lbase are refilled by the next chunk
+    }
+    uint32_t cnt = 0;
+    for (int t = tid; t < nw; t += kSampleBlock) cnt += (uint32_t)__popc(bm[t]);
+    const int64_t d = block_sum<kSampleBlock>((int64_t)cnt, lds64);
+    if (tid == 0) {
+        atomicAdd(dsum, (unsigned long long)d);
+        atomicAdd(kept, 1ull);
+    }
+}
+
 SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max_draws, int64_t cap) {
     SampledOut r;
     const int64_t n = g.dom_x;
@@ -348,6 +411,23 @@ SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max
             tc[i] = ox[xi + 1] - ox[xi];
         });
         scan_exclusive(c, k, ArrayGet{ct}, ArrayPut{coff.get()}, coff.get() + k);
+    }
+    if (g.dom_z <= kSampleBitmapBits) {
+        // one LDS bitmap per draw: the cap rule applied on the device, one read-back
+        DBuf<int64_t> S2 = c.buf<int64_t>(2);
+        c.zero(S2.get(), 2);
+        const size_t lds = (size_t)((g.dom_z + 31) / 32) * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_sample_distinct, dim3(grid_x(k, kSampleBlock)), dim3(kSampleBlock), lds, c.stream,
+                           (const int32_t *)xr.get(), (const int64_t *)coff.get(), cap, (const int64_t *)g.off_x.get(),
+                           (const int32_t *)g.adj_r.get(), (const int64_t *)g.off_y.get(),
+                           (const int32_t *)g.adj_s.get(), g.dom_z, (unsigned long long *)S2.get(),
+                           (unsigned long long *)(S2.get() + 1));
+        JP_HIP(hipGetLastError());
+        int64_t h[2];
+        c.load_n(h, S2.get(), 2);
+        r.distinct = h[0];
+        r.draws = h[1];
+        return r;
     }
     std::vector<int64_t> hoff((size_t)k + 1);
     c.load_n(hoff.data(), coff.get(), hoff.size());

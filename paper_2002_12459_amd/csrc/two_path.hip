@@ -1270,13 +1270,14 @@ void plan_cells(const Ctx &c, const int32_t *rx, const int32_t *ry, int64_t nr, 
     jp_calibration cal_default;
     if (!c.cal) default_calibration(&cal_default);
     const jp_calibration &cal = c.cal ? *c.cal : cal_default;
-    const jp_two_path_summary v = sum.view();
-    for (int32_t i = 0; i < n_cells; ++i) {
-        int64_t uvw[3] = {0, 0, 0};
-        const double t = any ? plan_cost(v, cal, d1[i], d2[i], uvw) : 0.0;
-        if (est_seconds) est_seconds[i] = t;
-        if (heavy_dims)
-            for (int j = 0; j < 3; ++j) heavy_dims[3 * i + j] = uvw[j];
+    if (any) {
+        plan_costs(sum.view(), cal, n_cells, d1, d2, est_seconds, heavy_dims);
+    } else {
+        for (int32_t i = 0; i < n_cells; ++i) {
+            if (est_seconds) est_seconds[i] = 0.0;
+            if (heavy_dims)
+                for (int j = 0; j < 3; ++j) heavy_dims[3 * i + j] = 0;
+        }
     }
 }
 

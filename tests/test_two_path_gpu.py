@@ -336,9 +336,15 @@ def test_sampled_out_estimate_matches_the_restatement(jp, seed):
     """The sampled output-size estimate (a selector input): the same draws of
     x and the same exact distinct counts as the numpy restatement."""
     cases = [datagen.zipf_edges(20_000, 3_000, 500, 1.2, 61) + datagen.zipf_edges(20_000, 3_000, 500, 1.2, 62),
-             datagen.random_small(600, 300, 40, seed=63, dup=True, signed=True) * 2]
+             datagen.random_small(600, 300, 40, seed=63, dup=True, signed=True) * 2,
+             ]
+    if seed == 0:  # more than 2^20 distinct z: a device sort counts the draws, not LDS bitmaps
+        cases.append(datagen.zipf_edges(3_000, 3_000, 500, 1.2, 64) +
+                     datagen.zipf_edges(3_000_000, 2_000_000, 500, 0.8, 65))
     for rx, ry, sz, sy in cases:
         D, k, n, est = ref.sampled_out_estimate(rx, ry, sz, sy, seed)
         x, z, st = run(jp, rx, ry, sz, sy, strategy="light", seed=seed, sampled_out=True)
         assert (st["sample_distinct"], st["sample_draws"], st["dom_x"]) == (D, k, n)
+        if len(sz) > 1_000_000:
+            assert st["dom_z"] > 1 << 20
         assert st["out_sampled"] == pytest.approx(est, rel=1e-12)
