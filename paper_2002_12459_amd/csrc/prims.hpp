@@ -373,6 +373,19 @@ struct KeyArray {
     __device__ K operator()(int64_t i) const { return p[i]; }
 };
 
+// Workgroups are dealt to the 8 XCDs round-robin by block index.  The radix
+// kernels give XCD r (blocks b with b % 8 == r) the r-th eighth of the tiles,
+// a contiguous run: the digit-major count and offset tables hold the entries
+// of consecutive tiles in one cache line, and with the run on one XCD that
+// line is written and read through one L2 instead of up to eight.  Grids are
+// padded to a multiple of 8; a padding block returns -1.
+__device__ __forceinline__ int64_t rs_tile(int64_t b, int64_t ntiles) {
+    const int64_t per = (ntiles + 7) / 8;
+    const int64_t t = (b & 7) * per + (b >> 3);
+    return t < ntiles ? t : -1;
+}
+inline int64_t rs_grid(int64_t ntiles) { return 8 * ((ntiles + 7) / 8); }
+
 // Per-tile digit counts, digit-major: counts[d * ntiles + tile].  Keys are
 // read coalesced (each wave takes 64 consecutive keys per step) and counted
 // with LDS atomic adds into kRsHistCopies copies of the histogram, lane l
@@ -387,9 +400,10 @@ __global__ __launch_bounds__(kRsBlock) void k_rs_hist(Src keys, int64_t n, int s
     static_assert(kRsBlock == 256, "one digit per thread in the final sum");
     constexpr int kStride = 257;
     __shared__ uint32_t h[kRsHistCopies * kStride];
+    const int64_t tile = rs_tile(blockIdx.x, ntiles);
+    if (tile < 0) return;  // grid padding (uniform per workgroup)
     for (int i = threadIdx.x; i < kRsHistCopies * kStride; i += kRsBlock) h[i] = 0;
     __syncthreads();
-    const int64_t tile = blockIdx.x;
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t wbase = tile * kRsTile + (int64_t)w * kWave * kRsItems;
     uint32_t *mine = h + (lane % kRsHistCopies) * kStride;
@@ -425,7 +439,8 @@ __global__ __launch_bounds__(kRsBlock, sizeof(K) <= 8 ? 4 : 2) void k_rs_scatter
     __shared__ uint32_t bstart[257];  // start of each digit's run in the tile, bstart[256] = tile size
     __shared__ int64_t goff[256];
     __shared__ uint32_t lds_scan[W + 1];
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = rs_tile(blockIdx.x, ntiles);
+    if (tile < 0) return;  // grid padding (uniform per workgroup)
     const int64_t tbase = tile * kRsTile;
     const int w = threadIdx.x / kWave, lane = lane_id();
     K k[kRsItems];
@@ -496,14 +511,14 @@ __global__ __launch_bounds__(kRsBlock, sizeof(K) <= 8 ? 4 : 2) void k_rs_scatter
 // One stable pass on the digit at `shift`: keys from src into dst.
 template <class K, class Src>
 void radix_pass(const Ctx &c, Src src, K *dst, int64_t n, int shift, uint32_t *counts, int64_t *offs, int64_t nt) {
-    hipLaunchKernelGGL((k_rs_hist<K, Src>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, src, n, shift, counts,
-                       nt);
+    hipLaunchKernelGGL((k_rs_hist<K, Src>), dim3(grid_x(rs_grid(nt), kRsBlock)), dim3(kRsBlock), 0, c.stream, src, n,
+                       shift, counts, nt);
     JP_HIP(hipGetLastError());
     const uint32_t *cp = counts;
     scan_exclusive(
         c, 256 * nt, [=] __device__(int64_t i) -> int64_t { return (int64_t)cp[i]; }, ArrayPut{offs});
-    hipLaunchKernelGGL((k_rs_scatter<K, Src>), dim3(grid_x(nt, kRsBlock)), dim3(kRsBlock), 0, c.stream, src, dst, n, shift,
-                       (const int64_t *)offs, nt);
+    hipLaunchKernelGGL((k_rs_scatter<K, Src>), dim3(grid_x(rs_grid(nt), kRsBlock)), dim3(kRsBlock), 0, c.stream, src, dst,
+                       n, shift, (const int64_t *)offs, nt);
     JP_HIP(hipGetLastError());
 }
 
