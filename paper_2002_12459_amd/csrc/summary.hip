@@ -338,6 +338,7 @@ __device__ __forceinline__ bool draw_kept(const int64_t *coff, int64_t i, int64_
 // counts the set bits.  Adds the counts to *dsum and the kept draws to *kept.
 constexpr int64_t kSampleBitmapBits = int64_t(1) << 20;
 constexpr int kSampleBlock = 256;
+constexpr int kSampleMarkBatch = 8;  // candidates per thread with loads in flight together
 __global__ __launch_bounds__(kSampleBlock) void k_sample_distinct(const int32_t *xr, const int64_t *coff, int64_t cap,
                                                                   const int64_t *ox, const int32_t *ar,
                                                                   const int64_t *oy, const int32_t *as, int64_t dom_z,
@@ -367,15 +368,26 @@ __global__ __launch_bounds__(kSampleBlock) void k_sample_distinct(const int32_t 
         if (tid == 0) lpre[kSampleBlock] = tot;
         __syncthreads();  // also orders the bitmap clear before the first marks
         const int nl = (int)(e1 - c0 < kSampleBlock ? e1 - c0 : kSampleBlock);
-        for (int64_t q = tid; q < tot; q += kSampleBlock) {
-            int lo = 0, hi = nl - 1;  // the list holding candidate q: last l with lpre[l] <= q
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) / 2;
-                if (lpre[mid] <= q) lo = mid;
-                else hi = mid - 1;
+        // kSampleMarkBatch candidates per thread and round, their loads issued
+        // together (a draw can reach long lists); slots past the end read the
+        // last candidate and mark nothing
+        for (int64_t q0 = tid; q0 < tot; q0 += (int64_t)kSampleBlock * kSampleMarkBatch) {
+            int32_t z[kSampleMarkBatch];
+#pragma unroll
+            for (int r = 0; r < kSampleMarkBatch; ++r) {
+                const int64_t q1 = q0 + (int64_t)r * kSampleBlock;
+                const int64_t q = q1 < tot ? q1 : tot - 1;
+                int lo = 0, hi = nl - 1;  // the list holding candidate q: last l with lpre[l] <= q
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) / 2;
+                    if (lpre[mid] <= q) lo = mid;
+                    else hi = mid - 1;
+                }
+                z[r] = as[lbase[lo] + (q - lpre[lo])];
             }
-            const int32_t z = as[lbase[lo] + (q - lpre[lo])];
-            atomicOr(&bm[z >> 5], 1u << (z & 31));
+#pragma unroll
+            for (int r = 0; r < kSampleMarkBatch; ++r)
+                if (q0 + (int64_t)r * kSampleBlock < tot) atomicOr(&bm[z[r] >> 5], 1u << (z[r] & 31));
         }
         __syncthreads();  // lpre / lbase are refilled by the next chunk
     }
