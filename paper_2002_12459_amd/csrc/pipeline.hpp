@@ -125,9 +125,15 @@ struct Ingest {
     int64_t n_r2 = 0, n_s2 = 0, dom_x = 0, dom_y = 0, dom_z = 0, J = 0;
     int64_t x_dense_base = INT64_MIN, z_dense_base = INT64_MIN;  // see SegDedupIn
     int64_t zmin = 0, zspan = 0;                                  // range of the z ids kept
-    DBuf<int32_t> r_xr, adj_r, adj_s, s2_y, dRy, dSz, xorig, zorig;
-    DBuf<uint32_t> s2_zoff;  // z - zmin of every kept S tuple, in adj_s order
+    int64_t n_in = 0;                                             // input tuples, |R| + |S|
+    DBuf<int32_t> r_xr, adj_r, s2_y, dRy, dSz, xorig, zorig;
+    DBuf<uint32_t> s2_zoff;  // z - zmin of every kept S tuple, y-major
+    DBuf<uint32_t> zs;       // the distinct z - zmin, ascending (dom_z)
     DBuf<int64_t> off_x, off_y;
+    // z rank of every kept S tuple (y-major), built on first use: an
+    // evaluation that works in z offsets without a heavy part never reads it.
+    const int32_t *adj_s(const Ctx &c) const;
+    mutable DBuf<int32_t> adj_s_;
 };
 
 // Builds the Section 5 degree indexes of an indexed instance (summary.hip).

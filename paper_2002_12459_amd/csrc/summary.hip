@@ -432,7 +432,7 @@ SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max
         hipLaunchKernelGGL(k_sample_distinct, dim3(grid_x(k, kSampleBlock)), dim3(kSampleBlock), lds, c.stream,
                            (const int32_t *)xr.get(), (const int64_t *)coff.get(), cap, (const int64_t *)g.off_x.get(),
                            (const int32_t *)g.adj_r.get(), (const int64_t *)g.off_y.get(),
-                           (const int32_t *)g.adj_s.get(), g.dom_z, (unsigned long long *)S2.get(),
+                           g.adj_s(c), g.dom_z, (unsigned long long *)S2.get(),
                            (unsigned long long *)(S2.get() + 1));
         JP_HIP(hipGetLastError());
         int64_t h[2];
@@ -480,7 +480,7 @@ SampledOut sampled_out(const Ctx &c, const Ingest &g, uint64_t seed, int64_t max
     DBuf<uint64_t> keys = c.buf<uint64_t>((size_t)T), tmp = c.buf<uint64_t>((size_t)T);
     {
         const int64_t *po = poff.get(), *pt = ptup.get(), *oy = g.off_y.get();
-        const int32_t *pd = pdraw.get(), *ar = g.adj_r.get(), *as = g.adj_s.get();
+        const int32_t *pd = pdraw.get(), *ar = g.adj_r.get(), *as = g.adj_s(c);
         uint64_t *ky = keys.get();
         const int64_t np = P;
         const int bzs = bz;

@@ -451,22 +451,29 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             S + 7);
     }
     // ---- x ranks and the x-major CSR of R -----------------------------------------
+    // One scan of the first-of-x flags over the x-major tuples gives every
+    // tuple its x rank and, at the first tuple of each x, that x's id and
+    // CSR offset.
     DBuf<int32_t> xorig = c.buf<int32_t>(n_r2);
     DBuf<int64_t> off_x = c.buf<int64_t>(n_r2 + 1);
+    DBuf<int32_t> r_xr = c.buf<int32_t>(n_r2);
     {
         const uint32_t *xs = r2_x.get();
-        int32_t *xo = xorig.get();
+        int32_t *xo = xorig.get(), *xr = r_xr.get();
         int64_t *ox = off_x.get();
         const int64_t xm = xmin;
-        compact_v(
+        scan_exclusive_v(
             c, n_r2,
             [=] __device__(int64_t i) {
                 const uint32_t k = xs[i];
-                return Pick<uint32_t>{i == 0 || k != xs[i - 1], k};
+                return Sum<uint32_t>{(i == 0 || k != xs[i - 1]) ? 1 : 0, k};
             },
-            [=] __device__(int64_t i, int64_t p, uint32_t k) {
-                xo[p] = (int32_t)((int64_t)k + xm);
-                ox[p] = i;
+            [=] __device__(int64_t i, int64_t p, const Sum<uint32_t> &it) {
+                xr[i] = (int32_t)(p + it.add - 1);
+                if (it.add) {
+                    xo[p] = (int32_t)((int64_t)it.v + xm);
+                    ox[p] = i;
+                }
             },
             S + 8);
     }
@@ -490,41 +497,20 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     c.load_n(h9, S + 7, 4);
     const int64_t dom_z = h9[0], dom_x = h9[1], J = h9[3];
     JP_CHECK(h9[2] == dom_y, JP_EINTERNAL, "y offsets disagree with the number of y");
-    DBuf<int32_t> r_xr = c.buf<int32_t>(n_r2);
     {
-        const uint32_t *xs = r2_x.get();
-        int32_t *xr = r_xr.get();
         int64_t *ox = off_x.get();
         const int64_t nx = dom_x, nr2 = n_r2;
-        auto newx = [=] __device__(int64_t i) -> int64_t { return (i == 0 || xs[i] != xs[i - 1]) ? 1 : 0; };
-        scan_exclusive_v(c, n_r2, newx, [=] __device__(int64_t i, int64_t p, int64_t v) { xr[i] = (int32_t)(p + v - 1); });
         for_each(c, 1, [=] __device__(int64_t) { ox[nx] = nr2; });
     }
     r2_x.reset();
-    // ---- S y-major CSR with z ranks --------------------------------------------
+    // ---- z id of every z rank (the per-tuple z ranks are built on first use) ----
     DBuf<int32_t> zorig = c.buf<int32_t>(dom_z);
-    DBuf<int32_t> adj_s = c.buf<int32_t>(n_s2);
     {
         const uint32_t *zs = ZS.get();
         int32_t *zo = zorig.get();
-        const int64_t zm = zmin, nz = dom_z;
+        const int64_t zm = zmin;
         for_each(c, dom_z, [=] __device__(int64_t r) { zo[r] = (int32_t)((int64_t)zs[r] + zm); });
-        const uint32_t *sz2 = s2_z.get();
-        int32_t *as = adj_s.get();
-        const int64_t zspan = zmax - zmin + 1;
-        if (dense_range_ok(zspan, nr + ns)) {
-            // every z of S is among the distinct z: a table entry per distinct z suffices
-            DBuf<int32_t> zmap = c.buf<int32_t>((size_t)zspan);
-            int32_t *zmp = zmap.get();
-            for_each(c, nz, [=] __device__(int64_t r) { zmp[zs[r]] = (int32_t)r; });
-            const int32_t *zmc = zmp;
-            for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = zmc[sz2[e]]; });
-        } else {
-            for_each(c, n_s2,
-                     [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zs, (int64_t)0, nz, sz2[e]); });
-        }
     }
-    ZS.reset();
     // ---- degrees (run lengths of the sorts above) and the full join size J ------
     DBuf<int32_t> dSz = c.buf<int32_t>(dom_z);
     {
@@ -542,7 +528,8 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     g.J = J;
     g.r_xr = std::move(r_xr);
     g.adj_r = std::move(adj_r);
-    g.adj_s = std::move(adj_s);
+    g.zs = std::move(ZS);
+    g.n_in = nr + ns;
     g.s2_zoff = std::move(s2_z);
     g.s2_y = std::move(s2_y);
     g.dRy = std::move(dRy);
@@ -556,6 +543,30 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
     g.off_x = std::move(off_x);
     g.off_y = std::move(off_y);
     return true;
+}
+
+const int32_t *Ingest::adj_s(const Ctx &c) const {
+    if (adj_s_.get() || n_s2 <= 0) return adj_s_.get();
+    DBuf<int32_t> out = c.buf<int32_t>(n_s2);
+    int32_t *as = out.get();
+    const uint32_t *zsr = zs.get(), *sz2 = s2_zoff.get();
+    const int64_t nz = dom_z;
+    if (nz == zspan) {
+        // every offset of the z range occurs, so a z's rank is its offset
+        JP_HIP(hipMemcpyAsync(as, sz2, (size_t)n_s2 * sizeof(int32_t), hipMemcpyDeviceToDevice, c.stream));
+    } else if (dense_range_ok(zspan, n_in)) {
+        // rank of every z offset from a table over the range (every z of S is
+        // among the distinct z, so only their entries are written)
+        DBuf<int32_t> zmap = c.buf<int32_t>((size_t)zspan);
+        int32_t *zmp = zmap.get();
+        for_each(c, nz, [=] __device__(int64_t r) { zmp[zsr[r]] = (int32_t)r; });
+        const int32_t *zmc = zmp;
+        for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = zmc[sz2[e]]; });
+    } else {
+        for_each(c, n_s2, [=] __device__(int64_t e) { as[e] = (int32_t)lower_bound_dev(zsr, (int64_t)0, nz, sz2[e]); });
+    }
+    adj_s_ = std::move(out);
+    return adj_s_.get();
 }
 
 // Operations the product kernel executed: 2 u v w, or for a symmetric
@@ -752,7 +763,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     Ingest g;
     if (!ingest_two_path(c, rx, ry, nr, sz, sy, ns, g, S)) return finish_empty();
     const int64_t n_r2 = g.n_r2, n_s2 = g.n_s2, dom_x = g.dom_x, dom_y = g.dom_y, dom_z = g.dom_z, J = g.J;
-    DBuf<int32_t> &r_xr = g.r_xr, &adj_r = g.adj_r, &adj_s = g.adj_s, &s2_y = g.s2_y, &dRy = g.dRy,
+    DBuf<int32_t> &r_xr = g.r_xr, &adj_r = g.adj_r, &s2_y = g.s2_y, &dRy = g.dRy,
                   &dSz = g.dSz, &xorig = g.xorig, &zorig = g.zorig;
     DBuf<int64_t> &off_x = g.off_x, &off_y = g.off_y;
     const int ev_ingest = tl.mark();
@@ -761,7 +772,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         check_range(c, (w + ": r_xr").c_str(), r_xr.get(), n_r2, 0, dom_x);
         check_monotone(c, (w + ": r_xr order").c_str(), r_xr.get(), n_r2, 0, -1);
         check_range(c, (w + ": adj_r").c_str(), adj_r.get(), n_r2, 0, dom_y);
-        check_range(c, (w + ": adj_s").c_str(), adj_s.get(), n_s2, 0, dom_z);
+        if (checks_on()) check_range(c, (w + ": adj_s").c_str(), g.adj_s(c), n_s2, 0, dom_z);
         check_monotone(c, (w + ": off_x").c_str(), off_x.get(), dom_x + 1, 0, n_r2);
         check_monotone(c, (w + ": off_y").c_str(), off_y.get(), dom_y + 1, 0, n_s2);
         check_range(c, (w + ": s2_y").c_str(), s2_y.get(), n_s2, 0, dom_y);
@@ -771,7 +782,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     dump(c, "adj_r", adj_r.get(), n_r2);
     dump(c, "off_x", off_x.get(), dom_x + 1);
     dump(c, "off_y", off_y.get(), dom_y + 1);
-    dump(c, "adj_s", adj_s.get(), n_s2);
+    if (dump_on()) dump(c, "adj_s", g.adj_s(c), n_s2);
     dump(c, "s2_y", s2_y.get(), n_s2);
     dump(c, "dRy", dRy.get(), dom_y);
     dump(c, "dSz", dSz.get(), dom_z);
@@ -899,7 +910,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         c.zero(need_y.get(), (size_t)v);
         int8_t *m1 = M1.get(), *m2 = M2t.get();
         int32_t *nd = need_y.get();
-        const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = adj_s.get();
+        const int32_t *xr = r_xr.get(), *ar = adj_r.get(), *syr = s2_y.get(), *as = g.adj_s(c);
         const int32_t *hx = hx_of_x.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
         const int64_t ldl = ld;
         for_each(c, n_r2, [=] __device__(int64_t e) {
@@ -925,7 +936,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
     // heavy x meets, since no tuple reads it).
     DBuf<int64_t> lz_off;
     DBuf<int32_t> zlist_own;
-    const int32_t *zfull = z_off ? reinterpret_cast<const int32_t *>(g.s2_zoff.get()) : adj_s.get();
+    const int32_t *zfull = z_off ? reinterpret_cast<const int32_t *>(g.s2_zoff.get()) : g.adj_s(c);
     const int32_t *zlist = zfull;
     int64_t zlist_n = n_s2;
     if (has_heavy) {
@@ -934,7 +945,7 @@ jp_result *run_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, int6
         // that y's list start.
         lz_off = c.buf<int64_t>(v + 1);
         int64_t *lo = lz_off.get();
-        const int32_t *syr = s2_y.get(), *as = adj_s.get(), *hy = hy_of_y.get(), *hz = hz_of_z.get();
+        const int32_t *syr = s2_y.get(), *as = g.adj_s(c), *hy = hy_of_y.get(), *hz = hz_of_z.get();
         const int32_t *ndc = need_y.get();
         zlist_own = c.buf<int32_t>(2 * n_s2);
         int32_t *zl = zlist_own.get();
