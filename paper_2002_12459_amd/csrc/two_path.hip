@@ -333,18 +333,27 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
         for_each(c, ny_s, [=] __device__(int64_t j) { ymp[ys[j]] = yr[j]; });
     }
     // S tuples kept, y-major: y rank + z offset.  Without the dense table the
-    // y rank comes from the tuple's run index among the distinct y of S.
+    // y rank comes from the tuple's run index among the distinct y of S.  A y
+    // is kept with all its tuples, so the first kept tuple of a y is the first
+    // of its run: it also writes that y's CSR offset (bit 63 of the value).
     DBuf<int32_t> s2_y = c.buf<int32_t>(n_s1);
     DBuf<uint32_t> s2_z = c.buf<uint32_t>(n_s1);
+    DBuf<int64_t> off_y = c.buf<int64_t>(ny_s + 1);  // dom_y + 1 used
     {
         const uint64_t *s = s1.get();
         const int zbs = zb;
         const uint64_t zm = zmask;
         int32_t *oy = s2_y.get();
         uint32_t *oz = s2_z.get();
+        int64_t *offy = off_y.get();
         auto emit = [=] __device__(int64_t, int64_t p, uint64_t v) {
-            oy[p] = (int32_t)(v >> 32);
+            const int32_t r = (int32_t)((v >> 32) & 0x7fffffffu);
+            oy[p] = r;
             oz[p] = (uint32_t)v;
+            if (v >> 63) offy[r] = p;
+        };
+        auto first_y = [=] __device__(int64_t i, uint64_t k) -> uint64_t {
+            return (i == 0 || (k >> zbs) != (s[i - 1] >> zbs)) ? (1ull << 63) : 0ull;
         };
         if (y_dense) {
             const int32_t *ymc = ymap.get();
@@ -353,7 +362,8 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
                 [=] __device__(int64_t i) {
                     const uint64_t k = s[i];
                     const int32_t r = ymc[k >> zbs];
-                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(k & zm)};
+                    return Pick<uint64_t>{r >= 0, first_y(i, k) | ((uint64_t)(uint32_t)r << 32) |
+                                                      (uint64_t)(uint32_t)(k & zm)};
                 },
                 emit, S + 5);
         } else {
@@ -368,8 +378,10 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             compact_v(
                 c, n_s1,
                 [=] __device__(int64_t i) {
+                    const uint64_t k = s[i];
                     const int32_t r = yr[sg[i]];
-                    return Pick<uint64_t>{r >= 0, ((uint64_t)(uint32_t)r << 32) | (uint64_t)(uint32_t)(s[i] & zm)};
+                    return Pick<uint64_t>{r >= 0, first_y(i, k) | ((uint64_t)(uint32_t)r << 32) |
+                                                      (uint64_t)(uint32_t)(k & zm)};
                 },
                 emit, S + 5);
         }
@@ -477,15 +489,10 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             },
             S + 8);
     }
-    // ---- y-major CSR offsets of S and the full join size J (no host values needed)
-    DBuf<int64_t> off_y = c.buf<int64_t>(dom_y + 1);
+    // ---- end of the y-major CSR offsets of S and the full join size J ----------
     {
-        const int32_t *syr = s2_y.get();
         int64_t *oy = off_y.get();
         const int64_t ny = dom_y, ns2 = n_s2;
-        compact(
-            c, n_s2, [=] __device__(int64_t e) { return e == 0 || syr[e] != syr[e - 1]; },
-            [=] __device__(int64_t e, int64_t p) { oy[p] = e; }, S + 9);
         for_each(c, 1, [=] __device__(int64_t) { oy[ny] = ns2; });
         const int32_t *d1 = dRy.get();
         const int64_t *oyc = oy;
@@ -493,10 +500,9 @@ static bool ingest_two_path(const Ctx &c, const int32_t *rx, const int32_t *ry, 
             c, dom_y, [=] __device__(int64_t y) -> int64_t { return (int64_t)d1[y] * (oyc[y + 1] - oyc[y]); },
             (unsigned long long *)(S + 10));
     }
-    int64_t h9[4];
-    c.load_n(h9, S + 7, 4);
-    const int64_t dom_z = h9[0], dom_x = h9[1], J = h9[3];
-    JP_CHECK(h9[2] == dom_y, JP_EINTERNAL, "y offsets disagree with the number of y");
+    int64_t h9[3];
+    c.load_scalars({S + 7, S + 8, S + 10}, h9);
+    const int64_t dom_z = h9[0], dom_x = h9[1], J = h9[2];
     {
         int64_t *ox = off_x.get();
         const int64_t nx = dom_x, nr2 = n_r2;
