@@ -337,7 +337,7 @@ __device__ __forceinline__ bool draw_kept(const int64_t *coff, int64_t i, int64_
 // at a time, the candidates of those lists spread over the threads) and
 // counts the set bits.  Adds the counts to *dsum and the kept draws to *kept.
 constexpr int64_t kSampleBitmapBits = int64_t(1) << 20;
-constexpr int kSampleBlock = 256;
+constexpr int kSampleBlock = 1024;  // one workgroup per CU fits the bitmap: all its threads for one draw
 constexpr int kSampleMarkBatch = 8;  // candidates per thread with loads in flight together
 __global__ __launch_bounds__(kSampleBlock) void k_sample_distinct(const int32_t *xr, const int64_t *coff, int64_t cap,
                                                                   const int64_t *ox, const int32_t *ar,
