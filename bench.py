@@ -47,8 +47,8 @@ INT8_PEAK_TOPS = 5000.0        # MI355X dense int8 MFMA, TOP/s
 # reads half of the copy's 1 GiB: x2; WRITE_SIZE reads it in full: x1); see
 # profiles/k_dedup_two_path_10M_traffic.md.  Valid only for the dedup source
 # whose SHA-256 is given (None: not measured for the current source).
-DEDUP_TRAFFIC = {"sha256": "3ecd75e9fcfd9cef0e8ca4b49ef2d1592582a37e4c198e0a9dadd4cd68d0e37f",
-                 "bytes_per_launch": 1844427157}
+DEDUP_TRAFFIC = {"sha256": "41f302bc8b638cc89b25e2ae8f9053f0aadcc4924c5f44146ce085e63f9e39ff",
+                 "bytes_per_launch": 1844558510}
 
 
 def dedup_traffic():

@@ -787,15 +787,13 @@ void segmented_dedup(const Ctx &c, const SegDedupIn &in, DBuf<int32_t> *out_x, D
             c.zero(ho, dom_x + 1);
         }
     }
-    // candidates before every x
+    // candidates before every x: the light candidates before x's first R
+    // tuple (the tuples are x-major) plus the heavy nonzeros before x
     DBuf<int64_t> toff = c.buf<int64_t>(dom_x + 1);
     {
         const int64_t *ox = in.off_x, *eo = in.eoff, *ho = hoff.get();
-        auto tx = [=] __device__(int64_t x) -> int64_t {
-            return (eo[ox[x + 1]] - eo[ox[x]]) + (ho[x + 1] - ho[x]);
-        };
         int64_t *to = toff.get();
-        scan_exclusive(c, dom_x, tx, ArrayPut{to}, to + dom_x);
+        for_each(c, dom_x + 1, [=] __device__(int64_t x) { to[x] = eo[ox[x]] + ho[x]; });
     }
 
     // Units in x order.  A small x starts a packed unit when it is the first
